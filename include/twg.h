@@ -1,0 +1,247 @@
+/*
+ * twg.h -- C ABI of libtwg.so: harmonic potential fields on time-warped grids
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Farzan & DeSouza, "Path Planning in Dynamic Environments Using
+ * Time-Warped Grids and a Parallel Implementation".  The library computes the
+ * data-parallel part of each replanning step of Algorithm 1:
+ *   twg_rasterize  -- "Map Update": time rings around the robot, Kalman
+ *                     prediction of every moving obstacle to its ring's
+ *                     horizon, and marking of the predicted poses.
+ *   hpf_relax      -- "Path Planning", harmonic potential: Laplace's equation
+ *                     (Eqs. 1-2) relaxed to convergence with Dirichlet goal,
+ *                     obstacle and wall values.
+ *   hpf_descend    -- index matrix (Eq. 3) and steepest-descent path.
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers unless marked "host".  The caller
+ *     owns every buffer it passes; the library never frees caller memory.  The
+ *     context owns only its scratch buffers (allocated at first use of a size,
+ *     released by twg_ctx_destroy).
+ *   - Grids are row-major, x fastest: a[y * pitch + x], pitch >= nx, in
+ *     elements of the array's type.  1 <= nx, ny <= 32767.
+ *   - The potential is stored as psi = 1 - phi, phi being the paper's
+ *     potential: the goal holds psi = 1, obstacles and walls psi = 0, free
+ *     space starts at psi = 0.5 (phi = 0.5).  The equation is linear, so psi
+ *     is harmonic where phi is; the goal-side values keep FP32 relative
+ *     precision far from the goal, where phi approaches 1.
+ *   - A neighbour outside the grid acts as a fixed cell with psi = 0.
+ *   - Every call is ordered on `stream` (a hipStream_t; NULL = the null
+ *     stream).  Calls documented as "blocking" also wait for their own work.
+ *   - Return value: 0 = TWG_OK; > 0 = finished with a non-fatal outcome;
+ *     < 0 = error, outputs undefined.  twg_last_error() describes the last
+ *     error or outcome of a context in words.
+ */
+#ifndef TWG_H
+#define TWG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define TWG_OK 0
+#define TWG_NOT_CONVERGED 1   /* max_sweeps reached; the partial field is returned */
+#define TWG_NO_PATH 2         /* descent met a cell with no strictly better neighbour */
+#define TWG_START_BLOCKED 3   /* the start cell is not FREE or GOAL */
+#define TWG_NET_FALLBACK 4    /* learned warm start rejected; the plain initial field was used */
+#define TWG_PATH_TRUNCATED 5  /* the path buffer filled before the goal */
+#define TWG_EINVAL (-1)       /* invalid argument (checked on the host before any launch) */
+#define TWG_ENOMEM (-2)       /* scratch allocation failed */
+#define TWG_EDEVICE (-3)      /* a HIP call failed */
+#define TWG_EUNSUPPORTED (-4) /* valid but unsupported option */
+
+/* ---- cell classes (uint8 class map) ------------------------------------- */
+#define TWG_CELL_FREE 0  /* relaxed */
+#define TWG_CELL_OBST 1  /* obstacle, static or predicted: psi = 0 (phi = 1) */
+#define TWG_CELL_WALL 2  /* border wall: psi = 0 */
+#define TWG_CELL_GOAL 3  /* goal: psi = 1 (phi = 0) */
+#define TWG_CELL_FIXED 4 /* Dirichlet cell holding the value the caller put in psi */
+
+typedef struct twg_ctx twg_ctx;
+
+typedef struct {
+    int32_t nx, ny; /* cells */
+    int32_t pitch;  /* row stride in elements, >= nx */
+} twg_grid;
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t twg_version(void);
+
+/* Create a context bound to HIP device `device`; *out receives it.
+ * Errors: TWG_EINVAL (out NULL, no such device), TWG_EDEVICE. */
+int32_t twg_ctx_create(twg_ctx **out, int32_t device);
+
+/* Wait for the device, free the context's scratch and the context. */
+int32_t twg_ctx_destroy(twg_ctx *ctx);
+
+/* Text of the last error or non-fatal outcome of ctx ("" if none).  The
+ * string belongs to ctx and is valid until its next call. */
+const char *twg_last_error(const twg_ctx *ctx);
+
+/* ========================================================================= */
+/* Map update: time rings, prediction, marking                               */
+/* ========================================================================= */
+
+typedef struct {
+    int32_t robot_x, robot_y; /* robot cell (ring centre); inside the grid */
+    int32_t goal_x, goal_y;   /* goal cell; inside the grid */
+    int32_t ring_width;       /* W >= 1, cells per time ring */
+    int32_t border_walls;     /* 1: cells on the grid border are WALL */
+    double robot_speed;       /* v_r > 0, cells per step */
+} twg_raster_params;
+
+/* twg_rasterize -- class map of one replanning step (Algorithm 1, "Map
+ * Update"; section "Time-Warped Grid"; section "Integration of Kalman Filter
+ * with Time-Warps").
+ *
+ * Every cell (x, y) lies in time ring
+ *     j = floor(sqrt((x - robot_x)^2 + (y - robot_y)^2) / W)
+ * (concentric rings of width W around the robot: the isotropic case of the
+ * warp ellipses of Eqs. 14-15), computed exactly in integers.  Ring j's
+ * horizon is t_j = j W / robot_speed steps: the time the robot needs to reach
+ * the ring.  Obstacle i's constant-velocity Kalman state is predicted to t_j
+ * by Eq. (9) with the state matrix of time step t_j: mu = p + t_j v (each
+ * product and sum rounded once, FP64).  The cell is occupied by obstacle i
+ * when its centre lies in the disc of radius r_i around mu, tested exactly in
+ * Q.8 fixed point: C = rint(256 mu), R = rint(256 r) (round half to even) and
+ * (256 x - C_x)^2 + (256 y - C_y)^2 <= R^2 in 64-bit integers.  A cell thus
+ * sees every obstacle at the pose predicted for the time the robot would get
+ * there.  Class, by precedence: WALL (border, if border_walls), GOAL (the goal
+ * cell), OBST (static_occ nonzero, or occupied), FREE.
+ *
+ *   pos, vel   n_obs x 2 doubles [x, y] (device): position in cells, velocity
+ *              in cells per step.  Obstacles with a non-finite predicted
+ *              position, or with |256 mu| >= 2^40, are ignored.
+ *   radius     n_obs doubles (device), cells.  An obstacle whose radius is not
+ *              a finite number in [0, 1e6] is ignored.
+ *   static_occ optional uint8 map (device, pitch g.pitch): nonzero = static
+ *              obstacle.  NULL = none.
+ *   cls        out uint8 class map (device, pitch g.pitch).
+ *   ring       optional out uint16 ring map (device, pitch g.pitch), or NULL.
+ * Asynchronous.  Errors: TWG_EINVAL for a bad grid, robot or goal outside the
+ * grid, W < 1, non-positive or non-finite speed, n_obs < 0, NULL cls, or
+ * n_obs > 0 with NULL pos/vel/radius. */
+int32_t twg_rasterize(twg_ctx *ctx, twg_grid g, int32_t n_obs, const double *pos,
+                      const double *vel, const double *radius, const uint8_t *static_occ,
+                      const twg_raster_params *params, uint8_t *cls, uint16_t *ring,
+                      void *stream);
+
+/* ========================================================================= */
+/* Harmonic potential                                                        */
+/* ========================================================================= */
+
+#define HPF_INIT_KEEP 0 /* free cells keep the values in psi */
+#define HPF_INIT_HALF 1 /* free cells start at phi = psi = 0.5 (the paper's choice) */
+#define HPF_INIT_ZERO 2 /* free cells start at psi = 0 (phi = 1) */
+
+typedef struct {
+    double tol;              /* stop when max over FREE cells of |avg4(psi) - psi|,
+                                evaluated in FP64, is <= tol (default 1e-6) */
+    double tol_cert;         /* > 0: with polish, also require the certified error
+                                bound residual * wbound <= tol_cert */
+    int64_t max_sweeps;      /* cap on FP32 sweeps of the field (0 = 10^7) */
+    float omega;             /* SOR factor in (0, 2); 0 = the open-rectangle optimum */
+    int32_t init;            /* HPF_INIT_* */
+    int32_t polish;          /* 0: FP32 only; 1: FP64 defect-correction polish */
+    int32_t sweeps_per_pass; /* red-black sweeps per tile load, 1..16; 0 = tuned */
+    int32_t check_passes;    /* passes between residual checks; 0 = adaptive */
+    int32_t reserved;
+} hpf_params;
+
+typedef struct {
+    int64_t sweeps;        /* FP32 red-black sweeps on the field */
+    int64_t polish_sweeps; /* FP32 sweeps on corrections */
+    double residual;       /* FP64 residual of the returned field (psi64 if polished) */
+    double residual32;     /* FP64 residual of the FP32 field after the FP32 phase */
+    double cert_bound;     /* residual * wbound: bound on |psi - psi*| (max principle) */
+    double wbound;         /* ((min(nx, ny) + 1)^2) / 2 >= ||(I - J)^-1 1||inf */
+    float omega;           /* SOR factor used */
+    int32_t status;        /* TWG_OK or TWG_NOT_CONVERGED */
+    int32_t polish_rounds; /* defect-correction rounds */
+    int32_t checks;        /* residual read-backs */
+} hpf_stats;
+
+/* hpf_relax -- converge the harmonic potential of one grid (Eqs. 1-2,
+ * boundary values of section "Harmonic Potential Fields", Algorithm 1 "Path
+ * Planning").
+ *
+ * Solves the discrete Laplace equation psi = avg4(psi) on FREE cells, where
+ * avg4 is the mean of the four neighbours (Eq. 1), with Dirichlet values on
+ * every other cell: OBST and WALL 0, GOAL 1, FIXED the input value.  The
+ * iteration is red-black SOR (red = (x + y) even first; each FREE cell set to
+ * psi + omega (avg4(psi) - psi), summed as ((E + W) + (S + N)) / 4) in FP32,
+ * several sweeps per tile load.  It stops when the FP64 residual
+ * r = max |avg4(psi) - psi| over FREE cells is <= tol.  Because
+ * |psi - psi*| <= r * ||(I - J)^-1 1||inf (discrete maximum principle), the
+ * residual certifies the error; with polish = 1 the field is then refined by
+ * FP64 defect correction (FP64 residual, FP32 correction solve, FP64 update)
+ * until r <= tol and r * wbound <= tol_cert, and the result is written to
+ * psi64 (and rounded into psi).
+ *
+ *   cls    uint8 class map (device, pitch g.pitch).
+ *   psi    in/out FP32 field (device, pitch g.pitch): FIXED cells must hold their
+ *          values; with HPF_INIT_KEEP the FREE cells hold the initial field.
+ *   psi64  FP64 field (device, pitch g.pitch) written when polish = 1; may be
+ *          NULL when polish = 0.
+ *   stats  host pointer or NULL.
+ * Blocking: returns after the field is final (it reads residuals back).
+ * Returns TWG_OK or TWG_NOT_CONVERGED; errors TWG_EINVAL (bad grid, NULL
+ * arrays, tol <= 0, omega outside [0, 2), polish without psi64, bad
+ * sweeps_per_pass), TWG_ENOMEM, TWG_EDEVICE. */
+int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, double *psi64,
+                  const hpf_params *params, hpf_stats *stats, void *stream);
+
+/* hpf_sweeps -- exactly `sweeps` red-black SOR sweeps of the same update as
+ * hpf_relax, with an optional FP32 source f (psi + omega (avg4(psi) + f - psi);
+ * NULL = 0), no convergence test.  tiled = 0 runs one launch per colour
+ * (each colour in place); tiled = 1 runs sweeps_per_pass sweeps per tile load
+ * and gives bit-identical results.  Asynchronous.  Errors: TWG_EINVAL. */
+int32_t hpf_sweeps(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, const float *f,
+                   float omega, int32_t sweeps, int32_t tiled, int32_t sweeps_per_pass,
+                   void *stream);
+
+/* hpf_residual -- max over FREE cells of |avg4(u) + f - u| in FP64, where u
+ * is psi64 if it is not NULL, else psi (FP32 values, FP64 arithmetic); f is
+ * an optional FP32 source (NULL = 0).  *out is a host double.  Blocking. */
+int32_t hpf_residual(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi,
+                     const double *psi64, const float *f, double *out, void *stream);
+
+/* ========================================================================= */
+/* Descent                                                                   */
+/* ========================================================================= */
+
+typedef struct {
+    int32_t start_x, start_y; /* start cell (the robot) */
+    int32_t cap;              /* capacity of path_xy in cells, >= 1 */
+    int32_t reserved;
+} hpf_descend_params;
+
+/* hpf_index_matrix -- index matrix of Eq. (3): for every cell, the direction
+ * of its FREE or GOAL neighbour with the lowest phi (highest psi), looked at
+ * in the order E (x+1) = 0, W (x-1) = 1, S (y+1) = 2, N (y-1) = 3, the first
+ * one winning a tie; 4 when no neighbour has a strictly higher psi than the
+ * cell.  Compares psi64 if it is not NULL, else psi.  idx is a uint8 map
+ * (device, pitch g.pitch).  Asynchronous.  Errors: TWG_EINVAL. */
+int32_t hpf_index_matrix(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi,
+                         const double *psi64, uint8_t *idx, void *stream);
+
+/* hpf_descend -- steepest-descent path (Algorithm 1: index matrix, then the
+ * path from the robot's position).  From the start, repeatedly moves to the
+ * neighbour given by the index matrix until a GOAL cell.  path_xy receives
+ * (x, y) int32 pairs (device, 2 * cap), starting with the start cell.
+ * info (device, 2 int32) receives [length, status] with status TWG_OK,
+ * TWG_START_BLOCKED, TWG_NO_PATH (a cell with no strictly better neighbour:
+ * the goal is unreachable or the field is not resolved there) or
+ * TWG_PATH_TRUNCATED.  Asynchronous.  Errors: TWG_EINVAL (bad grid, start
+ * outside the grid, cap < 1, NULL arrays). */
+int32_t hpf_descend(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi,
+                    const double *psi64, const hpf_descend_params *params, int32_t *path_xy,
+                    int32_t *info, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TWG_H */

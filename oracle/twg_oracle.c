@@ -204,6 +204,10 @@ static int disc_covers(int32_t x, int32_t y, int64_t cx, int64_t cy, int64_t R)
     return dx * dx + dy * dy <= R * R;
 }
 
+/* An obstacle radius is usable when it is a finite number in [0, 1e6]
+ * cells; other obstacles are skipped (input-validity rule of the library). */
+static int radius_ok(double r) { return r >= 0.0 && r <= 1e6; }
+
 static uint8_t base_class(int32_t nx, int32_t ny, int32_t x, int32_t y,
                           int32_t xg, int32_t yg, int32_t border_walls)
 {
@@ -234,6 +238,7 @@ void orc_rasterize_allpairs(int32_t nx, int32_t ny, int32_t xr, int32_t yr,
                 for (int32_t i = 0; i < n_obs; ++i) {
                     double mu[2];
                     int64_t cx, cy;
+                    if (!radius_ok(rad[i])) continue;
                     orc_predict_mean(&pos[2 * i], &vel[2 * i], t, mu);
                     if (!q8(mu[0], &cx) || !q8(mu[1], &cy)) continue;
                     int64_t R = (int64_t)nearbyint(256.0 * rad[i]);
@@ -261,6 +266,7 @@ void orc_rasterize_perobs(int32_t nx, int32_t ny, int32_t xr, int32_t yr,
     int32_t J = orc_num_rings(nx, ny, xr, yr, W);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t i = 0; i < n_obs; ++i) {
+        if (!radius_ok(rad[i])) continue;
         int64_t R = (int64_t)nearbyint(256.0 * rad[i]);
         for (int32_t j = 0; j < J; ++j) {
             double mu[2];

@@ -1,0 +1,427 @@
+// C ABI of libtwg.so: argument checks, scratch management and the host-side
+// convergence control of the relaxation.  The arithmetic runs in the kernels
+// of raster.hip, relax.hip and descend.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "twg_internal.h"
+
+namespace twg {
+
+int set_err(twg_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int ensure(twg_ctx *ctx, void **buf, size_t *have, size_t need)
+{
+    if (*have >= need) return TWG_OK;
+    if (*buf) {
+        hipDeviceSynchronize();
+        hipFree(*buf);
+        *buf = nullptr;
+        *have = 0;
+    }
+    need = (need + 4095) & ~size_t(4095);
+    if (hipMalloc(buf, need) != hipSuccess) {
+        *buf = nullptr;
+        return set_err(ctx, TWG_ENOMEM, "scratch allocation of " + std::to_string(need) + " bytes failed");
+    }
+    *have = need;
+    return TWG_OK;
+}
+
+int check_grid(twg_ctx *ctx, const twg_grid &g)
+{
+    if (g.nx < 1 || g.ny < 1 || g.nx > 32767 || g.ny > 32767)
+        return set_err(ctx, TWG_EINVAL, "grid sides must be in [1, 32767]");
+    if (g.pitch < g.nx) return set_err(ctx, TWG_EINVAL, "pitch must be >= nx");
+    return TWG_OK;
+}
+
+}  // namespace twg
+
+using namespace twg;
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+double bits_to_double(unsigned long long b)
+{
+    double d;
+    std::memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+// Optimal SOR factor of the open rectangle: Jacobi spectral radius of the
+// 5-point average with fixed values outside an nx-by-ny grid, then Young's
+// formula omega = 2 / (1 + sqrt(1 - rho^2)).
+double omega_open(int nx, int ny)
+{
+    const double pi = 3.14159265358979323846;
+    const double rho = 0.5 * (std::cos(pi / (nx + 1)) + std::cos(pi / (ny + 1)));
+    return 2.0 / (1.0 + std::sqrt(std::max(0.0, 1.0 - rho * rho)));
+}
+
+// Sweeps per tile load and rows per tile for a grid (fixed table; the
+// autotuner may override through hpf_params.sweeps_per_pass).
+void default_tiling(int nx, int ny, int *S, int *RH)
+{
+    const long long cells = (long long)nx * ny;
+    if (cells >= (1LL << 22)) { *S = 4; *RH = 32; }
+    else if (cells >= (1LL << 18)) { *S = 4; *RH = 16; }
+    else { *S = 2; *RH = 8; }
+}
+
+struct Runner {
+    twg_ctx *ctx;
+    twg_grid g;
+    const uint8_t *cls;
+    hipStream_t st;
+    int checks = 0;
+
+    int residual32(const float *u, const float *f, double *out)
+    {
+        int rc = launch_zero_words(ctx->words, 1, st);
+        if (!rc) rc = launch_resid_f32(cls, u, f, g.nx, g.ny, g.pitch, ctx->words, st);
+        if (!rc) rc = readback(1);
+        if (rc) return set_err(ctx, rc, "residual kernel failed");
+        *out = bits_to_double(ctx->host_words[0]);
+        return TWG_OK;
+    }
+
+    int readback(int n)
+    {
+        if (hipMemcpyAsync(ctx->host_words, ctx->words, n * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, st) != hipSuccess)
+            return TWG_EDEVICE;
+        if (hipStreamSynchronize(st) != hipSuccess) return TWG_EDEVICE;
+        ++checks;
+        return TWG_OK;
+    }
+
+    // `sweeps` FP32 sweeps on a <-> b, S per pass (remainder one per pass);
+    // on return *a holds the newest field.
+    int sweep32(float **a, float **b, const float *f, float omega, int S, int RH, int64_t sweeps)
+    {
+        const Geometry geo = stream_geometry(g.nx, g.ny, S, RH);
+        const Geometry geo1 = stream_geometry(g.nx, g.ny, 1, RH);
+        int64_t done = 0;
+        while (done < sweeps) {
+            const bool full = sweeps - done >= S;
+            int rc = launch_stream_f32(*a, *b, cls, f, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, st);
+            if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
+            std::swap(*a, *b);
+            done += full ? S : 1;
+        }
+        return TWG_OK;
+    }
+
+    // FP32 red-black SOR on `field` (ping-pong with ctx->alt) until the FP64
+    // residual is <= tol, the sweep budget is spent, or progress stalls.
+    int solve32(float *field, const float *f, float omega, int S, int RH, double tol,
+                int64_t max_sweeps, int check_passes, int64_t *sweeps_out, double *res_out,
+                bool *converged)
+    {
+        const size_t bytes = (size_t)g.pitch * g.ny * sizeof(float);
+        int rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, bytes);
+        if (rc) return rc;
+        float *a = field, *b = reinterpret_cast<float *>(ctx->alt);
+        double r;
+        rc = residual32(a, f, &r);
+        if (rc) return rc;
+        const double r_init = r;
+        int64_t done = 0;
+        int stalls = 0;
+        double rate = std::max((double)omega - 1.0, 0.5);  // per-sweep guess before any measurement
+        *converged = false;
+        while (true) {
+            if (std::isnan(r)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
+            if (r <= tol) { *converged = true; break; }
+            if (done >= max_sweeps) break;
+            int64_t chunk;
+            if (check_passes > 0) {
+                chunk = (int64_t)check_passes * S;
+            } else {
+                double want = std::log(tol / r) / std::log(rate);
+                chunk = (int64_t)std::ceil(want * (checks <= 1 ? 0.8 : 1.05)) + S;
+                chunk = std::max<int64_t>(chunk, 8 * S);
+            }
+            chunk = std::min(chunk, max_sweeps - done);
+            const double r_prev = r;
+            rc = sweep32(&a, &b, f, omega, S, RH, chunk);
+            if (rc) return rc;
+            done += chunk;
+            rc = residual32(a, f, &r);
+            if (rc) return rc;
+            if (r < r_prev * 0.999) {
+                stalls = 0;
+                const double q = std::pow(r / r_prev, 1.0 / (double)chunk);
+                if (q > 0.0 && q < 1.0) rate = q;
+            } else if (++stalls >= 3) {
+                break;  // FP32 rounding floor or no convergence
+            }
+        }
+        (void)r_init;
+        if (a != field) {
+            rc = launch_copy_f32(a, field, g.nx, g.ny, g.pitch, st);
+            if (rc) return set_err(ctx, rc, "copy launch failed");
+        }
+        *sweeps_out = done;
+        *res_out = r;
+        return TWG_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int32_t twg_version(void) { return 100; }
+
+int32_t twg_ctx_create(twg_ctx **out, int32_t device)
+{
+    if (!out) return TWG_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TWG_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return TWG_EDEVICE;
+    twg_ctx *ctx = new twg_ctx();
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+    if (hipMalloc(&ctx->words, kWords * sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc(&ctx->host_words, kWords * sizeof(unsigned long long), hipHostMallocDefault) !=
+            hipSuccess) {
+        twg_ctx_destroy(ctx);
+        return TWG_ENOMEM;
+    }
+    *out = ctx;
+    return TWG_OK;
+}
+
+int32_t twg_ctx_destroy(twg_ctx *ctx)
+{
+    if (!ctx) return TWG_EINVAL;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    void *bufs[] = {ctx->alt, ctx->pol, ctx->alt64, ctx->pairs, ctx->idxbuf, ctx->words};
+    for (void *b : bufs)
+        if (b) hipFree(b);
+    if (ctx->host_words) hipHostFree(ctx->host_words);
+    delete ctx;
+    return TWG_OK;
+}
+
+const char *twg_last_error(const twg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t twg_rasterize(twg_ctx *ctx, twg_grid g, int32_t n_obs, const double *pos, const double *vel,
+                      const double *radius, const uint8_t *static_occ, const twg_raster_params *p,
+                      uint8_t *cls, uint16_t *ring, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!p || !cls) return set_err(ctx, TWG_EINVAL, "params and cls are required");
+    if (n_obs < 0) return set_err(ctx, TWG_EINVAL, "n_obs < 0");
+    if (n_obs > 0 && (!pos || !vel || !radius))
+        return set_err(ctx, TWG_EINVAL, "obstacle arrays are required when n_obs > 0");
+    if (p->robot_x < 0 || p->robot_y < 0 || p->robot_x >= g.nx || p->robot_y >= g.ny)
+        return set_err(ctx, TWG_EINVAL, "robot outside the grid");
+    if (p->goal_x < 0 || p->goal_y < 0 || p->goal_x >= g.nx || p->goal_y >= g.ny)
+        return set_err(ctx, TWG_EINVAL, "goal outside the grid");
+    if (p->ring_width < 1) return set_err(ctx, TWG_EINVAL, "ring_width < 1");
+    if (!(p->robot_speed > 0.0) || !std::isfinite(p->robot_speed))
+        return set_err(ctx, TWG_EINVAL, "robot_speed must be positive and finite");
+    hipSetDevice(ctx->device);
+    return launch_rasterize(ctx, g, n_obs, pos, vel, radius, static_occ, *p, cls, ring,
+                            as_stream(stream));
+}
+
+int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, double *psi64,
+                  const hpf_params *params, hpf_stats *stats, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!cls || !psi || !params) return set_err(ctx, TWG_EINVAL, "cls, psi and params are required");
+    hpf_params p = *params;
+    if (!(p.tol > 0.0)) return set_err(ctx, TWG_EINVAL, "tol must be > 0");
+    if (!(p.omega >= 0.0f && p.omega < 2.0f)) return set_err(ctx, TWG_EINVAL, "omega must be in [0, 2)");
+    if (p.init < HPF_INIT_KEEP || p.init > HPF_INIT_ZERO) return set_err(ctx, TWG_EINVAL, "bad init mode");
+    if (p.polish && !psi64) return set_err(ctx, TWG_EINVAL, "polish needs psi64");
+    if (p.sweeps_per_pass && !stream_depth_supported(p.sweeps_per_pass))
+        return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
+    if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
+    hipSetDevice(ctx->device);
+    hipStream_t st = as_stream(stream);
+    const float omega = p.omega > 0.0f ? p.omega : (float)omega_open(g.nx, g.ny);
+    int S, RH;
+    default_tiling(g.nx, g.ny, &S, &RH);
+    if (p.sweeps_per_pass) S = p.sweeps_per_pass;
+    const double wb = std::pow((double)std::min(g.nx, g.ny) + 1.0, 2) / 2.0;
+
+    Runner run{ctx, g, cls, st};
+    hpf_stats s;
+    std::memset(&s, 0, sizeof s);
+    s.omega = omega;
+    s.wbound = wb;
+
+    rc = launch_field_init(cls, psi, g.nx, g.ny, g.pitch, p.init, st);
+    if (rc) return set_err(ctx, rc, "init launch failed");
+    bool conv = false;
+    rc = run.solve32(psi, nullptr, omega, S, RH, p.tol, p.max_sweeps, p.check_passes, &s.sweeps,
+                     &s.residual32, &conv);
+    if (rc) return rc;
+    s.residual = s.residual32;
+    s.status = conv ? TWG_OK : TWG_NOT_CONVERGED;
+
+    if (p.polish) {
+        // FP64 defect correction: r = avg4(psi64) - psi64 in FP64, solve
+        // (I - J) e = r in FP32 (e = 0 on fixed cells), psi64 += e.
+        const size_t n32 = (size_t)g.pitch * g.ny;
+        rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n32 * sizeof(float));
+        if (rc) return rc;
+        float *r32 = reinterpret_cast<float *>(ctx->pol);
+        float *e = r32 + n32;
+        rc = launch_widen(psi, psi64, g.nx, g.ny, g.pitch, st);
+        if (rc) return set_err(ctx, rc, "widen launch failed");
+        bool done = false;
+        double r64 = 0.0;
+        for (int round = 0; round < 12; ++round) {
+            rc = launch_zero_words(ctx->words, 1, st);
+            if (!rc) rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->words, st);
+            if (!rc) rc = run.readback(1);
+            if (rc) return set_err(ctx, rc, "defect kernel failed");
+            r64 = bits_to_double(ctx->host_words[0]);
+            if (std::isnan(r64)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
+            if (r64 <= p.tol && (p.tol_cert <= 0.0 || r64 * wb <= p.tol_cert)) { done = true; break; }
+            rc = launch_fill_f32(e, 0.0f, g.nx, g.ny, g.pitch, st);
+            if (rc) return set_err(ctx, rc, "fill launch failed");
+            // correction solve to a residual well below the defect
+            const double target = std::max(r64 * 1e-4, 1e-30);
+            int64_t sw = 0;
+            double re = 0.0;
+            bool cconv = false;
+            rc = run.solve32(e, r32, omega, S, RH, target, p.max_sweeps, 0, &sw, &re, &cconv);
+            if (rc) return rc;
+            s.polish_sweeps += sw;
+            rc = launch_update64(cls, psi64, e, psi, g.nx, g.ny, g.pitch, st);
+            if (rc) return set_err(ctx, rc, "update launch failed");
+            s.polish_rounds = round + 1;
+        }
+        s.residual = r64;
+        s.status = done ? TWG_OK : TWG_NOT_CONVERGED;
+        hipStreamSynchronize(st);
+    }
+    s.cert_bound = s.residual * wb;
+    s.checks = run.checks;
+    if (stats) *stats = s;
+    if (s.status == TWG_NOT_CONVERGED)
+        set_err(ctx, TWG_NOT_CONVERGED, "relaxation stopped before reaching the tolerance");
+    return s.status;
+}
+
+int32_t hpf_sweeps(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, const float *f,
+                   float omega, int32_t sweeps, int32_t tiled, int32_t sweeps_per_pass, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!cls || !psi) return set_err(ctx, TWG_EINVAL, "cls and psi are required");
+    if (sweeps < 0) return set_err(ctx, TWG_EINVAL, "sweeps < 0");
+    if (!(omega > 0.0f && omega < 2.0f)) return set_err(ctx, TWG_EINVAL, "omega must be in (0, 2)");
+    hipSetDevice(ctx->device);
+    hipStream_t st = as_stream(stream);
+    if (!tiled) {
+        for (int k = 0; k < sweeps; ++k)
+            for (int color = 0; color < 2; ++color) {
+                rc = launch_sweep_color_f32(cls, psi, f, g.nx, g.ny, g.pitch, omega, color, st);
+                if (rc) return set_err(ctx, rc, "sweep launch failed");
+            }
+        return TWG_OK;
+    }
+    int S = sweeps_per_pass, RH;
+    int dS;
+    default_tiling(g.nx, g.ny, &dS, &RH);
+    if (!S) S = dS;
+    if (!stream_depth_supported(S))
+        return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
+    rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, (size_t)g.pitch * g.ny * sizeof(float));
+    if (rc) return rc;
+    Runner run{ctx, g, cls, st};
+    float *a = psi, *b = reinterpret_cast<float *>(ctx->alt);
+    rc = run.sweep32(&a, &b, f, omega, S, RH, sweeps);
+    if (rc) return rc;
+    if (a != psi) {
+        rc = launch_copy_f32(a, psi, g.nx, g.ny, g.pitch, st);
+        if (rc) return set_err(ctx, rc, "copy launch failed");
+    }
+    return TWG_OK;
+}
+
+int32_t hpf_residual(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi,
+                     const double *psi64, const float *f, double *out, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!cls || (!psi && !psi64) || !out) return set_err(ctx, TWG_EINVAL, "missing argument");
+    hipSetDevice(ctx->device);
+    hipStream_t st = as_stream(stream);
+    rc = launch_zero_words(ctx->words, 1, st);
+    if (!rc)
+        rc = psi64 ? launch_resid_f64(cls, psi64, f, g.nx, g.ny, g.pitch, ctx->words, st)
+                   : launch_resid_f32(cls, psi, f, g.nx, g.ny, g.pitch, ctx->words, st);
+    Runner run{ctx, g, cls, st};
+    if (!rc) rc = run.readback(1);
+    if (rc) return set_err(ctx, rc, "residual kernel failed");
+    *out = bits_to_double(ctx->host_words[0]);
+    return TWG_OK;
+}
+
+int32_t hpf_index_matrix(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi,
+                         const double *psi64, uint8_t *idx, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!cls || (!psi && !psi64) || !idx) return set_err(ctx, TWG_EINVAL, "missing argument");
+    hipSetDevice(ctx->device);
+    rc = launch_index(cls, psi, psi64, idx, g.nx, g.ny, g.pitch, as_stream(stream));
+    return rc ? set_err(ctx, rc, "index launch failed") : TWG_OK;
+}
+
+int32_t hpf_descend(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi,
+                    const double *psi64, const hpf_descend_params *p, int32_t *path_xy,
+                    int32_t *info, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!cls || (!psi && !psi64) || !p || !path_xy || !info)
+        return set_err(ctx, TWG_EINVAL, "missing argument");
+    if (p->cap < 1) return set_err(ctx, TWG_EINVAL, "cap < 1");
+    if (p->start_x < 0 || p->start_y < 0 || p->start_x >= g.nx || p->start_y >= g.ny)
+        return set_err(ctx, TWG_EINVAL, "start outside the grid");
+    hipSetDevice(ctx->device);
+    hipStream_t st = as_stream(stream);
+    rc = ensure(ctx, &ctx->idxbuf, &ctx->idxbuf_bytes, (size_t)g.pitch * g.ny);
+    if (rc) return rc;
+    uint8_t *idx = reinterpret_cast<uint8_t *>(ctx->idxbuf);
+    rc = launch_index(cls, psi, psi64, idx, g.nx, g.ny, g.pitch, st);
+    if (!rc) rc = launch_walk(cls, idx, g.nx, g.ny, g.pitch, p->start_x, p->start_y, p->cap, path_xy,
+                              info, st);
+    return rc ? set_err(ctx, rc, "descent launch failed") : TWG_OK;
+}
+
+}  // extern "C"

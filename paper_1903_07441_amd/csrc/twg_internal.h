@@ -1,0 +1,88 @@
+// Internal declarations shared by the HIP translation units of libtwg.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "twg.h"
+
+struct twg_ctx {
+    int device = 0;
+    int num_cu = 0;
+    std::string err;
+    // FP32 ping-pong partner of a relaxed field
+    void *alt = nullptr;
+    size_t alt_bytes = 0;
+    // defect-correction buffers: FP32 defect, FP32 correction, its partner
+    void *pol = nullptr;
+    size_t pol_bytes = 0;
+    // FP64 ping-pong partner (FP64 sweeps)
+    void *alt64 = nullptr;
+    size_t alt64_bytes = 0;
+    // (obstacle, ring) work list of the rasteriser and its counter
+    void *pairs = nullptr;
+    size_t pairs_bytes = 0;
+    // index matrix of hpf_descend
+    void *idxbuf = nullptr;
+    size_t idxbuf_bytes = 0;
+    // small device words: residual maxima (uint64 bit patterns), counters
+    unsigned long long *words = nullptr;
+    // pinned host mirror of `words`
+    unsigned long long *host_words = nullptr;
+};
+
+namespace twg {
+
+constexpr int kWords = 64;
+
+int set_err(twg_ctx *ctx, int code, const std::string &msg);
+int ensure(twg_ctx *ctx, void **buf, size_t *have, size_t need);
+int check_grid(twg_ctx *ctx, const twg_grid &g);
+
+// relax.hip
+struct Geometry {
+    int S;       // sweeps per tile load
+    int RH;      // output rows per tile (even)
+    int strips;  // tiles across
+    int segs;    // tiles down
+    int tiles;
+};
+Geometry stream_geometry(int nx, int ny, int S, int RH);
+int launch_field_init(const uint8_t *cls, float *psi, int nx, int ny, int pitch, int mode,
+                      hipStream_t st);
+int launch_sweep_color_f32(const uint8_t *cls, float *psi, const float *f, int nx, int ny, int pitch,
+                           float omega, int color, hipStream_t st);
+int launch_sweep_color_f64(const uint8_t *cls, double *psi, const double *f, int nx, int ny,
+                           int pitch, double omega, int color, hipStream_t st);
+bool stream_depth_supported(int S);
+int launch_stream_f32(const float *src, float *dst, const uint8_t *cls, const float *f, int nx,
+                      int ny, int pitch, float omega, const Geometry &geo, hipStream_t st);
+int launch_stream_f64(const double *src, double *dst, const uint8_t *cls, const double *f, int nx,
+                      int ny, int pitch, double omega, const Geometry &geo, hipStream_t st);
+int launch_resid_f32(const uint8_t *cls, const float *u, const float *f, int nx, int ny, int pitch,
+                     unsigned long long *out, hipStream_t st);
+int launch_resid_f64(const uint8_t *cls, const double *u, const float *f, int nx, int ny, int pitch,
+                     unsigned long long *out, hipStream_t st);
+int launch_defect64(const uint8_t *cls, const double *u, float *r32, int nx, int ny, int pitch,
+                    unsigned long long *out, hipStream_t st);
+int launch_update64(const uint8_t *cls, double *u, const float *e, float *psi, int nx, int ny,
+                    int pitch, hipStream_t st);
+int launch_widen(const float *psi, double *u, int nx, int ny, int pitch, hipStream_t st);
+int launch_fill_f32(float *a, float v, int nx, int ny, int pitch, hipStream_t st);
+int launch_copy_f32(const float *src, float *dst, int nx, int ny, int pitch, hipStream_t st);
+int launch_zero_words(unsigned long long *w, int n, hipStream_t st);
+
+// raster.hip
+int launch_rasterize(twg_ctx *ctx, const twg_grid &g, int n_obs, const double *pos,
+                     const double *vel, const double *rad, const uint8_t *static_occ,
+                     const twg_raster_params &p, uint8_t *cls, uint16_t *ring, hipStream_t st);
+
+// descend.hip
+int launch_index(const uint8_t *cls, const float *psi, const double *psi64, uint8_t *idx, int nx,
+                 int ny, int pitch, hipStream_t st);
+int launch_walk(const uint8_t *cls, const uint8_t *idx, int nx, int ny, int pitch, int sx, int sy,
+                int cap, int32_t *path, int32_t *info, hipStream_t st);
+
+}  // namespace twg

@@ -1,0 +1,223 @@
+"""ctypes binding of libtwg.so (C ABI in include/twg.h).
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of the computation runs in the library's HIP kernels.
+Importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtwg.so")
+
+OK, NOT_CONVERGED, NO_PATH, START_BLOCKED, NET_FALLBACK, PATH_TRUNCATED = 0, 1, 2, 3, 4, 5
+EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4
+FREE, OBST, WALL, GOAL, FIXED = 0, 1, 2, 3, 4
+INIT_KEEP, INIT_HALF, INIT_ZERO = 0, 1, 2
+
+i32, i64, f32, f64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_void_p
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", i32), ("ny", i32), ("pitch", i32)]
+
+
+class RasterParams(ctypes.Structure):
+    _fields_ = [("robot_x", i32), ("robot_y", i32), ("goal_x", i32), ("goal_y", i32),
+                ("ring_width", i32), ("border_walls", i32), ("robot_speed", f64)]
+
+
+class HpfParams(ctypes.Structure):
+    _fields_ = [("tol", f64), ("tol_cert", f64), ("max_sweeps", i64), ("omega", f32),
+                ("init", i32), ("polish", i32), ("sweeps_per_pass", i32), ("check_passes", i32),
+                ("reserved", i32)]
+
+
+class HpfStats(ctypes.Structure):
+    _fields_ = [("sweeps", i64), ("polish_sweeps", i64), ("residual", f64), ("residual32", f64),
+                ("cert_bound", f64), ("wbound", f64), ("omega", f32), ("status", i32),
+                ("polish_rounds", i32), ("checks", i32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DescendParams(ctypes.Structure):
+    _fields_ = [("start_x", i32), ("start_y", i32), ("cap", i32), ("reserved", i32)]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_1903_07441_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    sigs = {
+        "twg_version": (i32, []),
+        "twg_ctx_create": (i32, [P(vp), i32]),
+        "twg_ctx_destroy": (i32, [vp]),
+        "twg_last_error": (ctypes.c_char_p, [vp]),
+        "twg_rasterize": (i32, [vp, Grid, i32, vp, vp, vp, vp, P(RasterParams), vp, vp, vp]),
+        "hpf_relax": (i32, [vp, Grid, vp, vp, vp, P(HpfParams), P(HpfStats), vp]),
+        "hpf_sweeps": (i32, [vp, Grid, vp, vp, vp, f32, i32, i32, i32, vp]),
+        "hpf_residual": (i32, [vp, Grid, vp, vp, vp, vp, P(f64), vp]),
+        "hpf_index_matrix": (i32, [vp, Grid, vp, vp, vp, vp, vp]),
+        "hpf_descend": (i32, [vp, Grid, vp, vp, vp, P(DescendParams), vp, vp, vp]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error", "twg_rasterize",
+            "hpf_relax", "hpf_sweeps", "hpf_residual", "hpf_index_matrix", "hpf_descend")
+
+
+class TwgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libtwg error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _grid_of(t):
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("grid arrays must be 2-D [ny, >= nx] with unit x stride")
+    if not t.is_cuda:
+        raise ValueError("grid arrays must be device tensors")
+    return t.shape[1], t.shape[0], t.stride(0)
+
+
+class Context:
+    """Owns one twg_ctx on a HIP device."""
+
+    def __init__(self, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        h = ctypes.c_void_p()
+        rc = lib.twg_ctx_create(ctypes.byref(h), int(device))
+        if rc != OK:
+            raise TwgError(rc, "twg_ctx_create failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib.twg_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=(OK,)):
+        if rc not in allow:
+            msg = lib.twg_last_error(self.h)
+            raise TwgError(rc, msg.decode() if msg else "")
+        return rc
+
+    @staticmethod
+    def grid(nx, ny, pitch):
+        return Grid(int(nx), int(ny), int(pitch))
+
+    # ---- map update ------------------------------------------------------
+    def rasterize(self, nx, ny, robot, goal, pos, vel, rad, W=8, robot_speed=1.0,
+                  border_walls=True, static_occ=None, cls=None, ring=None, want_ring=True):
+        dev = torch.device("cuda", self.device)
+        if cls is None:
+            cls = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
+        if ring is None and want_ring:
+            ring = torch.empty((ny, nx), dtype=torch.uint16, device=dev)
+        gx, gy, pitch = _grid_of(cls)
+        assert (gx, gy) == (nx, ny)
+        n = int(rad.numel()) if rad is not None else 0
+        for t in (pos, vel, rad):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError("obstacle arrays must be contiguous float64 device tensors")
+        if ring is not None and ring.stride(0) != pitch:
+            raise ValueError("ring map must share the class map's pitch")
+        if static_occ is not None and static_occ.stride(0) != pitch:
+            raise ValueError("static map must share the class map's pitch")
+        p = RasterParams(int(robot[0]), int(robot[1]), int(goal[0]), int(goal[1]), int(W),
+                         int(bool(border_walls)), float(robot_speed))
+        rc = lib.twg_rasterize(self.h, Grid(nx, ny, pitch), n, _ptr(pos), _ptr(vel), _ptr(rad),
+                               _ptr(static_occ), ctypes.byref(p), _ptr(cls), _ptr(ring), _stream())
+        self._check(rc)
+        return cls, ring
+
+    # ---- relaxation --------------------------------------------------------
+    def relax(self, cls, psi, psi64=None, tol=1e-6, tol_cert=0.0, max_sweeps=0, omega=0.0,
+              init=INIT_HALF, polish=False, sweeps_per_pass=0, check_passes=0):
+        nx, ny, pitch = _grid_of(psi)
+        if psi.dtype != torch.float32 or cls.dtype != torch.uint8 or cls.stride(0) != pitch:
+            raise ValueError("psi must be float32 and share its pitch with the uint8 class map")
+        if psi64 is not None and (psi64.dtype != torch.float64 or psi64.stride(0) != pitch):
+            raise ValueError("psi64 must be float64 with the same pitch")
+        prm = HpfParams(float(tol), float(tol_cert), int(max_sweeps), float(omega), int(init),
+                        int(bool(polish)), int(sweeps_per_pass), int(check_passes), 0)
+        st = HpfStats()
+        rc = lib.hpf_relax(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(psi64),
+                           ctypes.byref(prm), ctypes.byref(st), _stream())
+        self._check(rc, allow=(OK, NOT_CONVERGED))
+        return st.as_dict()
+
+    def sweeps(self, cls, psi, omega, n, tiled=True, sweeps_per_pass=0, f=None):
+        nx, ny, pitch = _grid_of(psi)
+        rc = lib.hpf_sweeps(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(f), float(omega),
+                            int(n), int(bool(tiled)), int(sweeps_per_pass), _stream())
+        self._check(rc)
+
+    def residual(self, cls, psi=None, psi64=None, f=None):
+        t = psi if psi is not None else psi64
+        nx, ny, pitch = _grid_of(t)
+        out = ctypes.c_double()
+        rc = lib.hpf_residual(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(psi64), _ptr(f),
+                              ctypes.byref(out), _stream())
+        self._check(rc)
+        return out.value
+
+    # ---- descent -----------------------------------------------------------
+    def index_matrix(self, cls, psi=None, psi64=None, idx=None):
+        t = psi if psi is not None else psi64
+        nx, ny, pitch = _grid_of(t)
+        if idx is None:
+            idx = torch.empty_strided((ny, nx), (pitch, 1), dtype=torch.uint8, device=t.device)
+        rc = lib.hpf_index_matrix(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(psi64),
+                                  _ptr(idx), _stream())
+        self._check(rc)
+        return idx
+
+    def descend(self, cls, psi=None, psi64=None, start=(0, 0), cap=None, path=None, info=None):
+        """Returns (path tensor [cap, 2] int32, info tensor [2] int32 = [len, status]);
+        both stay on the device (the call is asynchronous)."""
+        t = psi if psi is not None else psi64
+        nx, ny, pitch = _grid_of(t)
+        if cap is None:
+            cap = nx * ny
+        if path is None:
+            path = torch.empty((cap, 2), dtype=torch.int32, device=t.device)
+        if info is None:
+            info = torch.empty(2, dtype=torch.int32, device=t.device)
+        p = DescendParams(int(start[0]), int(start[1]), int(cap), 0)
+        rc = lib.hpf_descend(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(psi64),
+                             ctypes.byref(p), _ptr(path), _ptr(info), _stream())
+        self._check(rc)
+        return path, info
+
+
+def version() -> int:
+    return int(lib.twg_version())

@@ -18,3 +18,23 @@ def orc():
     import oracle
     oracle._load()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_07441_amd import twg
+    c = twg.Context(0)
+    yield c
+    c.close()
+
+
+def scenario_tensors(sc, device="cuda"):
+    """Obstacle arrays of a scenario dict as float64 device tensors."""
+    import torch
+    pos = torch.as_tensor(sc["pos"], dtype=torch.float64).reshape(-1, 2).contiguous().to(device)
+    vel = torch.as_tensor(sc["vel"], dtype=torch.float64).reshape(-1, 2).contiguous().to(device)
+    rad = torch.as_tensor(sc["rad"], dtype=torch.float64).contiguous().to(device)
+    return pos, vel, rad

@@ -1,0 +1,95 @@
+"""GPU parity of the index matrix (Eq. 3) and the descent walk."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1903_07441_amd import scenarios
+from test_gpu_relax import gpu_relax, random_classes, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_descend(ctx, c, psi_t, start, cap=None, use64=False):
+    if use64:
+        path, info = ctx.descend(c, psi64=psi_t, start=start, cap=cap)
+    else:
+        path, info = ctx.descend(c, psi=psi_t, start=start, cap=cap)
+    torch.cuda.synchronize()
+    n, status = info.cpu().tolist()
+    return status, path[:n].cpu().numpy()
+
+
+@pytest.mark.parametrize("name,idx", [("static64", 0), ("static64", 5), ("warped512", 0)])
+def test_index_and_path_parity(ctx, orc, name, idx):
+    sc = scenarios.scenario(name, idx)
+    cls, _ = orc.rasterize(sc)
+    st, psi, psi64, c = gpu_relax(ctx, cls, tol=1e-6, polish=True, tol_cert=1e-7)
+    for use64, field in ((False, psi), (True, psi64)):
+        t = to_dev(field) if not use64 else to_dev(field, dtype=torch.float64)
+        kw = dict(psi64=t) if use64 else dict(psi=t)
+        idx_gpu = ctx.index_matrix(c, **kw)
+        torch.cuda.synchronize()
+        want = orc.index_matrix(cls, field.astype(np.float64))
+        np.testing.assert_array_equal(idx_gpu.cpu().numpy(), want)
+        s_gpu, p_gpu = gpu_descend(ctx, c, t, sc["robot"], use64=use64)
+        s_orc, p_orc = orc.descend(cls, field.astype(np.float64), sc["robot"])
+        assert s_gpu == s_orc
+        np.testing.assert_array_equal(p_gpu, p_orc)
+        if orc.goal_reachable(cls, sc["robot"]):
+            assert s_gpu == 0 and cls[p_gpu[-1][1], p_gpu[-1][0]] == 3
+
+
+def test_descent_2048_reaches_goal(ctx, orc):
+    sc = scenarios.scenario("replan2048", 0)
+    cls, _ = orc.rasterize(sc)
+    st, psi, psi64, c = gpu_relax(ctx, cls, tol=1e-6, polish=True, tol_cert=5e-7)
+    t = to_dev(psi64, dtype=torch.float64)
+    s_gpu, p_gpu = gpu_descend(ctx, c, t, sc["robot"], use64=True)
+    s_orc, p_orc = orc.descend(cls, psi64, sc["robot"])
+    assert s_gpu == s_orc
+    np.testing.assert_array_equal(p_gpu, p_orc)
+    print(f"2048 descent status={s_gpu} length={len(p_gpu)} reachable={orc.goal_reachable(cls, sc['robot'])}",
+          flush=True)
+
+
+def test_descent_outcomes(ctx, orc):
+    rng = np.random.default_rng(0)
+    cls = random_classes(rng, 80, 60, p=0.1)
+    gy, gx = np.argwhere(cls == 3)[0]
+    # enclose the goal: NO_PATH from outside
+    enc = cls.copy()
+    enc[gy - 1:gy + 2, gx - 1:gx + 2] = np.where(enc[gy - 1:gy + 2, gx - 1:gx + 2] == 3, 3, 1)
+    st, psi, psi64, c = gpu_relax(ctx, enc, tol=1e-6)
+    free = np.argwhere(enc == 0)
+    y0, x0 = free[len(free) // 2]
+    s, p = gpu_descend(ctx, c, to_dev(psi), (x0, y0))
+    assert s == 2 and len(p) >= 1
+    # start on an obstacle
+    oy, ox = np.argwhere(enc == 1)[0]
+    s, p = gpu_descend(ctx, c, to_dev(psi), (ox, oy))
+    assert s == 3 and len(p) == 0
+    # start on the goal
+    s, p = gpu_descend(ctx, c, to_dev(psi), (gx, gy))
+    assert s == 0 and len(p) == 1
+    # truncated
+    st, psi, _, c = gpu_relax(ctx, cls, tol=1e-7)
+    far = np.argwhere(cls == 0)
+    dist = np.abs(far[:, 0] - gy) + np.abs(far[:, 1] - gx)
+    y1, x1 = far[np.argmax(dist)]
+    s_full, p_full = gpu_descend(ctx, c, to_dev(psi), (x1, y1))
+    s_orc, p_orc = orc.descend(cls, psi.astype(np.float64), (x1, y1))
+    assert s_full == s_orc and np.array_equal(p_full, p_orc)
+    if s_full == 0 and len(p_full) > 3:
+        s, p = gpu_descend(ctx, c, to_dev(psi), (x1, y1), cap=3)
+        assert s == 5 and len(p) == 3
+        np.testing.assert_array_equal(p, p_full[:3])
+
+
+def test_descend_rejects_bad_arguments(ctx):
+    from paper_1903_07441_amd import twg
+    c = to_dev(np.zeros((10, 10), np.uint8))
+    psi = to_dev(np.zeros((10, 10), np.float32))
+    with pytest.raises(twg.TwgError):
+        ctx.descend(c, psi=psi, start=(10, 0))
+    with pytest.raises(twg.TwgError):
+        ctx.descend(c, psi=psi, start=(0, 0), cap=0)

@@ -1,0 +1,95 @@
+"""GPU parity of twg_rasterize against the oracle: bit-exact class and ring maps."""
+import numpy as np
+import pytest
+import torch
+
+from conftest import scenario_tensors
+from paper_1903_07441_amd import scenarios
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_raster(ctx, sc, pitch=None, static=None, border=True):
+    nx, ny = sc["nx"], sc["ny"]
+    pitch = pitch or nx
+    cls = torch.full((ny, pitch), 77, dtype=torch.uint8, device="cuda")[:, :nx]
+    ring = torch.full((ny, pitch), 7, dtype=torch.int16, device="cuda").view(torch.uint16)[:, :nx]
+    st = None
+    if static is not None:
+        st = torch.zeros((ny, pitch), dtype=torch.uint8, device="cuda")[:, :nx]
+        st.copy_(torch.as_tensor(static))
+    pos, vel, rad = scenario_tensors(sc)
+    ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"],
+                  robot_speed=sc["vr"], border_walls=border, static_occ=st, cls=cls, ring=ring)
+    torch.cuda.synchronize()
+    return cls.cpu().numpy(), ring.cpu().numpy().astype(np.uint16)
+
+
+@pytest.mark.parametrize("name,idx", [("static64", 0), ("static64", 1), ("static64", 2),
+                                      ("warped512", 0), ("warped512", 1), ("learn256", 3)])
+def test_raster_parity_configs(ctx, orc, name, idx):
+    sc = scenarios.scenario(name, idx)
+    print(f"raster parity {name}[{idx}] seed={sc['seed']}", flush=True)
+    want_cls, want_ring = orc.rasterize(sc, "perobs")
+    got_cls, got_ring = gpu_raster(ctx, sc)
+    np.testing.assert_array_equal(got_ring, want_ring)
+    np.testing.assert_array_equal(got_cls, want_cls)
+
+
+def test_raster_parity_full_size_2048(ctx, orc):
+    # 2048 x 2048, 500 moving discs: the replanning workload at full size
+    sc = scenarios.scenario("replan2048", 0)
+    print("raster parity replan2048[0]", flush=True)
+    want_cls, want_ring = orc.rasterize(sc, "perobs")
+    got_cls, got_ring = gpu_raster(ctx, sc)
+    np.testing.assert_array_equal(got_ring, want_ring)
+    np.testing.assert_array_equal(got_cls, want_cls)
+    assert (got_cls == 1).sum() > 10000
+
+
+def test_raster_pitch_static_and_no_border(ctx, orc):
+    sc = scenarios.custom(301, 173, 40, rad=(2.0, 9.0), vel_sigma=1.0, seed=42, W=5, vr=0.7)
+    rng = np.random.default_rng(1)
+    static = (rng.uniform(size=(173, 301)) < 0.05).astype(np.uint8)
+    for border in (True, False):
+        want, want_ring = orc.rasterize(sc, "allpairs", static_occ=static, border_walls=border)
+        got, got_ring = gpu_raster(ctx, sc, pitch=320, static=static, border=border)
+        np.testing.assert_array_equal(got, want)
+        np.testing.assert_array_equal(got_ring, want_ring)
+
+
+def test_raster_edge_cases(ctx, orc):
+    # tiny grids, no obstacles, huge ring width, far-away and invalid discs
+    cases = [
+        scenarios.custom(3, 3, 0, seed=1),
+        scenarios.custom(5, 2, 2, seed=2, W=1),
+        dict(scenarios.custom(17, 9, 3, seed=3), W=1000),
+        scenarios.custom(130, 70, 25, rad=(0.0, 30.0), vel_sigma=3.0, seed=4, W=2, vr=3.0),
+    ]
+    far = scenarios.custom(40, 40, 3, seed=5)
+    far["pos"][0] = [1e12, -1e12]         # beyond the Q.8 range: ignored
+    far["vel"][1] = [np.nan, 0.0]         # non-finite prediction: ignored (ring 0 too)
+    far["rad"][2] = -1.0                  # invalid radius: ignored
+    cases.append(far)
+    for sc in cases:
+        sc["robot"] = np.minimum(sc["robot"], [sc["nx"] - 1, sc["ny"] - 1])
+        sc["goal"] = np.minimum(sc["goal"], [sc["nx"] - 1, sc["ny"] - 1])
+        want, want_ring = orc.rasterize(sc, "allpairs")
+        got, got_ring = gpu_raster(ctx, sc)
+        np.testing.assert_array_equal(got, want)
+        np.testing.assert_array_equal(got_ring, want_ring)
+
+
+def test_raster_rejects_bad_arguments(ctx):
+    from paper_1903_07441_amd import twg
+    sc = scenarios.custom(20, 20, 2, seed=0)
+    pos, vel, rad = scenario_tensors(sc)
+    with pytest.raises(twg.TwgError) as e:
+        ctx.rasterize(20, 20, (25, 3), (4, 4), pos, vel, rad)
+    assert e.value.code == twg.EINVAL
+    with pytest.raises(twg.TwgError) as e:
+        ctx.rasterize(20, 20, (3, 3), (4, 4), pos, vel, rad, W=0)
+    assert e.value.code == twg.EINVAL
+    with pytest.raises(twg.TwgError) as e:
+        ctx.rasterize(20, 20, (3, 3), (4, 4), pos, vel, rad, robot_speed=0.0)
+    assert e.value.code == twg.EINVAL
