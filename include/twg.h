@@ -203,6 +203,20 @@ int32_t hpf_sweeps(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, con
                    float omega, int32_t sweeps, int32_t tiled, int32_t sweeps_per_pass,
                    void *stream);
 
+/* hpf_autotune -- measure the relaxation kernel on grid g and class map cls
+ * and remember, for grids of this exact size, the fastest tiling and an SOR
+ * factor; later hpf_relax calls on this context with sweeps_per_pass = 0
+ * and omega = 0 use them.  Tilings: sweeps per tile load S in
+ * {1, 2, 3, 4, 6, 8} x output rows per tile RH in {8, 16, 32, 64, 128}, each
+ * timed with HIP events over repeated passes on context scratch.  Factors:
+ * omega = 2 / (1 + c sin(pi / (n + 1))), n = max(nx, ny), c in
+ * {0.7, 1, 1.4, 2, 2.8, 4}; the one with the smallest residual after a fixed
+ * number of sweeps from the half-initialised field wins (obstacles shrink the
+ * effective domain, so the best factor is below the open-rectangle one).
+ * out (host, optional) receives [S, RH, omega, cell-updates per second].
+ * Blocking.  Errors: TWG_EINVAL, TWG_ENOMEM, TWG_EDEVICE. */
+int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, void *stream);
+
 /* hpf_residual -- max over FREE cells of |avg4(u) + f - u| in FP64, where u
  * is psi64 if it is not NULL, else psi (FP32 values, FP64 arithmetic); f is
  * an optional FP32 source (NULL = 0).  *out is a host double.  Blocking. */

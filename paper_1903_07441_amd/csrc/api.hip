@@ -38,6 +38,8 @@ int check_grid(twg_ctx *ctx, const twg_grid &g)
     if (g.nx < 1 || g.ny < 1 || g.nx > 32767 || g.ny > 32767)
         return set_err(ctx, TWG_EINVAL, "grid sides must be in [1, 32767]");
     if (g.pitch < g.nx) return set_err(ctx, TWG_EINVAL, "pitch must be >= nx");
+    if ((long long)g.pitch * g.ny >= (1LL << 31))
+        return set_err(ctx, TWG_EINVAL, "pitch * ny must be below 2^31 elements");
     return TWG_OK;
 }
 
@@ -74,6 +76,20 @@ void default_tiling(int nx, int ny, int *S, int *RH)
     if (cells >= (1LL << 22)) { *S = 4; *RH = 32; }
     else if (cells >= (1LL << 18)) { *S = 4; *RH = 16; }
     else { *S = 2; *RH = 8; }
+}
+
+// Tiling and SOR factor for a grid: the autotuned entry of this size if the
+// context has one, else the fixed table and the open-rectangle optimum.
+void tiling_for(twg_ctx *ctx, int nx, int ny, int *S, int *RH, float *omega)
+{
+    default_tiling(nx, ny, S, RH);
+    *omega = (float)omega_open(nx, ny);
+    auto it = ctx->tuned.find({nx, ny});
+    if (it != ctx->tuned.end()) {
+        *S = it->second.S;
+        *RH = it->second.RH;
+        if (it->second.omega > 0.0f) *omega = it->second.omega;
+    }
 }
 
 struct Runner {
@@ -260,9 +276,10 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
     if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
     hipSetDevice(ctx->device);
     hipStream_t st = as_stream(stream);
-    const float omega = p.omega > 0.0f ? p.omega : (float)omega_open(g.nx, g.ny);
     int S, RH;
-    default_tiling(g.nx, g.ny, &S, &RH);
+    float omega_t;
+    tiling_for(ctx, g.nx, g.ny, &S, &RH, &omega_t);
+    const float omega = p.omega > 0.0f ? p.omega : omega_t;
     if (p.sweeps_per_pass) S = p.sweeps_per_pass;
     const double wb = std::pow((double)std::min(g.nx, g.ny) + 1.0, 2) / 2.0;
 
@@ -293,6 +310,8 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
         if (rc) return set_err(ctx, rc, "widen launch failed");
         bool done = false;
         double r64 = 0.0;
+        // residual the result must reach: tol, and tol_cert / wbound if set
+        const double need = p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / wb) : p.tol;
         for (int round = 0; round < 12; ++round) {
             rc = launch_zero_words(ctx->words, 1, st);
             if (!rc) rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->words, st);
@@ -300,11 +319,13 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
             if (rc) return set_err(ctx, rc, "defect kernel failed");
             r64 = bits_to_double(ctx->host_words[0]);
             if (std::isnan(r64)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
-            if (r64 <= p.tol && (p.tol_cert <= 0.0 || r64 * wb <= p.tol_cert)) { done = true; break; }
+            if (r64 <= need) { done = true; break; }
             rc = launch_fill_f32(e, 0.0f, g.nx, g.ny, g.pitch, st);
             if (rc) return set_err(ctx, rc, "fill launch failed");
-            // correction solve to a residual well below the defect
-            const double target = std::max(r64 * 1e-4, 1e-30);
+            // correction solve: at most four decades per round (the FP32
+            // correction keeps about that much relative accuracy), and no
+            // further than a third of what is still needed
+            const double target = std::max(r64 * 1e-4, need / 3.0);
             int64_t sw = 0;
             double re = 0.0;
             bool cconv = false;
@@ -327,6 +348,84 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
     return s.status;
 }
 
+int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!cls) return set_err(ctx, TWG_EINVAL, "cls is required");
+    hipSetDevice(ctx->device);
+    hipStream_t st = as_stream(stream);
+    const size_t n32 = (size_t)g.pitch * g.ny;
+    rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, n32 * sizeof(float));
+    if (!rc) rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n32 * sizeof(float));
+    if (rc) return rc;
+    float *a = reinterpret_cast<float *>(ctx->pol);
+    float *b = reinterpret_cast<float *>(ctx->alt);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return set_err(ctx, TWG_EDEVICE, "event creation failed");
+    Runner run{ctx, g, cls, st};
+    const double cells = (double)g.nx * g.ny;
+    // 1. tiling: fastest cell-update rate
+    const int Ss[] = {1, 2, 3, 4, 6, 8};
+    const int RHs[] = {8, 16, 32, 64, 128};
+    twg_tuning best;
+    const float om0 = (float)omega_open(g.nx, g.ny);
+    for (int S : Ss)
+        for (int RH : RHs) {
+            if (RH > 2 * g.ny && RH > 8) continue;
+            rc = launch_fill_f32(a, 0.5f, g.nx, g.ny, g.pitch, st);
+            if (!rc) rc = launch_field_init(cls, a, g.nx, g.ny, g.pitch, HPF_INIT_KEEP, st);
+            if (rc) break;
+            float *x = a, *y = b;
+            rc = run.sweep32(&x, &y, nullptr, om0, S, RH, 2 * S);  // warm-up
+            if (rc) break;
+            // passes for about 2 ms at 1e12 cell-updates/s
+            int passes = (int)std::min(400.0, std::max(4.0, 2e9 / (cells * S)));
+            passes += passes & 1;
+            hipEventRecord(e0, st);
+            rc = run.sweep32(&x, &y, nullptr, om0, S, RH, (int64_t)passes * S);
+            hipEventRecord(e1, st);
+            if (rc || hipEventSynchronize(e1) != hipSuccess) { rc = rc ? rc : TWG_EDEVICE; break; }
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            const double cups = cells * S * passes / (ms * 1e-3);
+            if (cups > best.cups) { best.S = S; best.RH = RH; best.cups = cups; }
+        }
+    // 2. SOR factor: smallest residual after a fixed number of sweeps
+    if (!rc) {
+        const double pi = 3.14159265358979323846;
+        const int n = std::max(g.nx, g.ny);
+        const double cs[] = {0.7, 1.0, 1.4, 2.0, 2.8, 4.0};
+        const int64_t sweeps = std::max<int64_t>(64, (int64_t)(1.5 * n));
+        double best_r = INFINITY;
+        for (double c : cs) {
+            const float om = (float)(2.0 / (1.0 + c * std::sin(pi / (n + 1))));
+            rc = launch_field_init(cls, a, g.nx, g.ny, g.pitch, HPF_INIT_HALF, st);
+            if (rc) break;
+            float *x = a, *y = b;
+            rc = run.sweep32(&x, &y, nullptr, om, best.S, best.RH, sweeps);
+            double r;
+            if (!rc) rc = run.residual32(x, nullptr, &r);
+            if (rc) break;
+            if (r < best_r) { best_r = r; best.omega = om; }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return set_err(ctx, rc, "autotune failed");
+    ctx->tuned[{g.nx, g.ny}] = best;
+    if (out) {
+        out[0] = best.S;
+        out[1] = best.RH;
+        out[2] = best.omega;
+        out[3] = best.cups;
+    }
+    return TWG_OK;
+}
+
 int32_t hpf_sweeps(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, const float *f,
                    float omega, int32_t sweeps, int32_t tiled, int32_t sweeps_per_pass, void *stream)
 {
@@ -347,9 +446,9 @@ int32_t hpf_sweeps(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, con
             }
         return TWG_OK;
     }
-    int S = sweeps_per_pass, RH;
-    int dS;
-    default_tiling(g.nx, g.ny, &dS, &RH);
+    int S = sweeps_per_pass, RH, dS;
+    float om_unused;
+    tiling_for(ctx, g.nx, g.ny, &dS, &RH, &om_unused);
     if (!S) S = dS;
     if (!stream_depth_supported(S))
         return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");

@@ -29,32 +29,25 @@ namespace {
 constexpr int kWave = 64;
 
 // ---- arithmetic shared by the untiled and the streamed kernels ----------
-__device__ __forceinline__ float hpf_update(float old, float ew, float sn, float w, float f)
+// FP32: d = avg4 (+ f) - old with the exact quarter folded into one fma,
+// then old + w * d in a second fma.
+template <bool RHS>
+__device__ __forceinline__ float upd(float old, float ew, float sn, float w, float f)
 {
-    float g = __builtin_fmaf(0.25f, ew + sn, f);
-    return __builtin_fmaf(w, g - old, old);
+    const float s = ew + sn;
+    const float d = RHS ? __builtin_fmaf(0.25f, s, f) - old : __builtin_fmaf(0.25f, s, -old);
+    return __builtin_fmaf(w, d, old);
 }
 
 // FP64: unfused, in the order of the definition (this file is compiled with
 // contraction off), so one sweep reproduces a plain FP64 sweep bit for bit.
 template <bool RHS>
-__device__ __forceinline__ double hpf_update64(double old, double ew, double sn, double w, double f)
+__device__ __forceinline__ double upd(double old, double ew, double sn, double w, double f)
 {
     double g = (ew + sn) * 0.25;
     if (RHS) g = g + f;
-    double d = g - old;
+    const double d = g - old;
     return old + w * d;
-}
-
-template <bool RHS>
-__device__ __forceinline__ float upd(float old, float ew, float sn, float w, float f)
-{
-    return hpf_update(old, ew, sn, w, RHS ? f : 0.0f);
-}
-template <bool RHS>
-__device__ __forceinline__ double upd(double old, double ew, double sn, double w, double f)
-{
-    return hpf_update64<RHS>(old, ew, sn, w, f);
 }
 
 // ---- wave-wide DPP shifts (gfx9 wave_shr:1 / wave_shl:1) ----------------
@@ -92,6 +85,10 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 }
 
 // ---- streamed temporal-blocked red-black SOR ----------------------------
+// Rows are prefetched one window (NW rows) ahead into a register queue, so a
+// load has NW row-steps of arithmetic to arrive.  Loads use clamped (always
+// in-bounds) addresses; cells outside the grid are zeroed with a fixed-cell
+// factor when they are taken from the queue.
 template <typename T, int S, bool RHS>
 __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T *__restrict__ dst,
                                                     const uint8_t *__restrict__ cls,
@@ -99,24 +96,49 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
                                                     int pitch, T omega, int strips, int RH,
                                                     int tiles)
 {
-    constexpr int NW = 2 * S + 2;      // rolling window of rows
+    constexpr int NW = 2 * S + 2;      // rolling window of rows (even)
     constexpr int VW = 128 - 4 * S;    // columns written per strip
     const int lane = threadIdx.x & (kWave - 1);
-    const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    // everything that depends only on the tile is wave-uniform: keep it scalar
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
     if (tile >= tiles) return;  // whole wave
     const int strip = tile % strips, seg = tile / strips;
-    const int xa = strip * VW - 2 * S + 2 * lane;  // lane's first (even) column
+    const int x0 = strip * VW - 2 * S;             // first (even) column of the strip
     const int ybeg = seg * RH;
     const int yend = min(ybeg + RH, ny);
     const int r0 = ybeg - 2 * S;                   // first row streamed (even)
     const int T_rows = (yend - ybeg) + 4 * S;
+    // per-lane constants
+    const int xa = x0 + 2 * lane;
     const bool in0 = xa >= 0 && xa < nx, in1 = xa + 1 >= 0 && xa + 1 < nx;
+    const int xc0 = min(max(xa, 0), nx - 1), xc1 = min(max(xa + 1, 0), nx - 1);
+    const T om0 = in0 ? omega : T(0), om1 = in1 ? omega : T(0);
     const bool writer = lane >= S && lane < kWave - S;
+
+    T qv0[NW], qv1[NW], qf0[NW], qf1[NW];
+    uint32_t qc0[NW], qc1[NW];
+    auto fetch = [&](int slot, int t) {
+        const int yc = min(max(r0 + t, 0), ny - 1);
+        const T *ps = src + yc * pitch;
+        const uint8_t *pc = cls + yc * pitch;
+        qv0[slot] = ps[xc0];
+        qv1[slot] = ps[xc1];
+        qc0[slot] = pc[xc0];
+        qc1[slot] = pc[xc1];
+        if (RHS) {
+            const T *pf = f + yc * pitch;
+            qf0[slot] = pf[xc0];
+            qf1[slot] = pf[xc1];
+        }
+    };
 
     T R[NW], B[NW], wR[NW], wB[NW], fR[NW], fB[NW];
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
         R[i] = B[i] = wR[i] = wB[i] = fR[i] = fB[i] = T(0);
+        qf0[i] = qf1[i] = T(0);
+        fetch(i, i);
     }
 
     for (int base = 0; base < T_rows; base += NW) {
@@ -126,19 +148,17 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
             if (t < T_rows) {
                 const int y = r0 + t;  // parity of y == parity of u
                 T v0 = T(0), v1 = T(0), w0 = T(0), w1 = T(0), f0 = T(0), f1 = T(0);
-                if (y >= 0 && y < ny) {
-                    const size_t row = (size_t)y * pitch;
-                    if (in0) {
-                        v0 = src[row + xa];
-                        w0 = cls[row + xa] == TWG_CELL_FREE ? omega : T(0);
-                        if (RHS) f0 = f[row + xa];
-                    }
-                    if (in1) {
-                        v1 = src[row + xa + 1];
-                        w1 = cls[row + xa + 1] == TWG_CELL_FREE ? omega : T(0);
-                        if (RHS) f1 = f[row + xa + 1];
+                if (y >= 0 && y < ny) {  // uniform
+                    v0 = in0 ? qv0[u] : T(0);
+                    v1 = in1 ? qv1[u] : T(0);
+                    w0 = qc0[u] == TWG_CELL_FREE ? om0 : T(0);
+                    w1 = qc1[u] == TWG_CELL_FREE ? om1 : T(0);
+                    if (RHS) {
+                        f0 = in0 ? qf0[u] : T(0);
+                        f1 = in1 ? qf1[u] : T(0);
                     }
                 }
+                if (t + NW < T_rows) fetch(u, t + NW);
                 if ((u & 1) == 0) {  // even row: red = first column
                     R[u] = v0; B[u] = v1; wR[u] = w0; wB[u] = w1; fR[u] = f0; fB[u] = f1;
                 } else {
@@ -161,14 +181,14 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
                         B[s] = upd<RHS>(B[s], ew, sn, wB[s], fB[s]);
                     }
                 }
-                const int ys = y - 2 * S;  // row finished by this step
-                if (writer && ys >= ybeg && ys < yend) {
+                const int ys = y - 2 * S;  // row finished by this step (uniform test)
+                if (ys >= ybeg && ys < yend) {
                     const int s = (u - 2 * S + 4 * NW) % NW;
-                    const size_t row = (size_t)ys * pitch;
+                    T *pd = dst + ys * pitch;
                     const T o0 = (s & 1) == 0 ? R[s] : B[s];
                     const T o1 = (s & 1) == 0 ? B[s] : R[s];
-                    if (in0) dst[row + xa] = o0;
-                    if (in1) dst[row + xa + 1] = o1;
+                    if (writer && in0) pd[xa] = o0;
+                    if (writer && in1) pd[xa + 1] = o1;
                 }
             }
         }

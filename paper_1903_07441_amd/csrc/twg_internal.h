@@ -4,12 +4,23 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <utility>
 
 #include "twg.h"
 
+struct twg_tuning {
+    int S = 0;        // sweeps per tile load
+    int RH = 0;       // output rows per tile
+    float omega = 0;  // 0 = open-rectangle optimum
+    double cups = 0;  // measured cell-updates per second
+};
+
 struct twg_ctx {
     int device = 0;
+    // autotuned tiling per grid size (nx, ny)
+    std::map<std::pair<int, int>, twg_tuning> tuned;
     int num_cu = 0;
     std::string err;
     // FP32 ping-pong partner of a relaxed field

@@ -35,16 +35,24 @@ SEED_BASE = {"static64": 1000, "warped512": 2000, "batch": 3000, "learn256": 400
              "replan2048": 5000}
 
 
+def _cell(rng, n):
+    """A coordinate one cell inside the border, or anywhere on grids too
+    narrow to have an inside."""
+    return int(rng.integers(1, n - 1)) if n >= 3 else int(rng.integers(0, n))
+
+
 def _draw(rng, nx, ny, n_obs, rad_spec, vel_sigma, W=8, vr=1.0):
     (lo, hi), share, alt = rad_spec
-    robot = np.array([rng.integers(1, nx - 1), rng.integers(1, ny - 1)], dtype=np.int32)
-    goal = np.array([rng.integers(1, nx - 1), rng.integers(1, ny - 1)], dtype=np.int32)
-    while goal[0] == robot[0] and goal[1] == robot[1]:
-        goal = np.array([rng.integers(1, nx - 1), rng.integers(1, ny - 1)], dtype=np.int32)
+    robot = np.array([_cell(rng, nx), _cell(rng, ny)], dtype=np.int32)
+    goal = np.array([_cell(rng, nx), _cell(rng, ny)], dtype=np.int32)
+    for _ in range(64):  # tiny grids may have a single candidate cell
+        if goal[0] != robot[0] or goal[1] != robot[1]:
+            break
+        goal = np.array([_cell(rng, nx), _cell(rng, ny)], dtype=np.int32)
     pos = np.empty((n_obs, 2))
     rad = np.empty(n_obs)
     for i in range(n_obs):
-        while True:
+        for _ in range(100):  # bounded: on tiny grids the start may end up covered
             p = np.array([rng.uniform(0, nx), rng.uniform(0, ny)])
             if alt is not None and rng.uniform() < share:
                 r = rng.uniform(*alt)

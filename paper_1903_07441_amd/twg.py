@@ -63,6 +63,7 @@ def _load():
         "hpf_relax": (i32, [vp, Grid, vp, vp, vp, P(HpfParams), P(HpfStats), vp]),
         "hpf_sweeps": (i32, [vp, Grid, vp, vp, vp, f32, i32, i32, i32, vp]),
         "hpf_residual": (i32, [vp, Grid, vp, vp, vp, vp, P(f64), vp]),
+        "hpf_autotune": (i32, [vp, Grid, vp, vp, vp]),
         "hpf_index_matrix": (i32, [vp, Grid, vp, vp, vp, vp, vp]),
         "hpf_descend": (i32, [vp, Grid, vp, vp, vp, P(DescendParams), vp, vp, vp]),
     }
@@ -75,7 +76,8 @@ def _load():
 
 lib = _load()
 EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error", "twg_rasterize",
-            "hpf_relax", "hpf_sweeps", "hpf_residual", "hpf_index_matrix", "hpf_descend")
+            "hpf_relax", "hpf_sweeps", "hpf_residual", "hpf_autotune", "hpf_index_matrix",
+            "hpf_descend")
 
 
 class TwgError(RuntimeError):
@@ -180,6 +182,15 @@ class Context:
         rc = lib.hpf_sweeps(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(f), float(omega),
                             int(n), int(bool(tiled)), int(sweeps_per_pass), _stream())
         self._check(rc)
+
+    def autotune(self, cls):
+        """Tune tiling and SOR factor for grids of cls's size; returns
+        dict(S, RH, omega, cups)."""
+        nx, ny, pitch = _grid_of(cls)
+        out = (ctypes.c_double * 4)()
+        rc = lib.hpf_autotune(self.h, Grid(nx, ny, pitch), _ptr(cls), out, _stream())
+        self._check(rc)
+        return dict(S=int(out[0]), RH=int(out[1]), omega=float(out[2]), cups=float(out[3]))
 
     def residual(self, cls, psi=None, psi64=None, f=None):
         t = psi if psi is not None else psi64
