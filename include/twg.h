@@ -149,6 +149,12 @@ typedef struct {
     int32_t sweeps_per_pass; /* red-black sweeps per tile load, 1..16; 0 = tuned */
     int32_t check_passes;    /* passes between residual checks; 0 = adaptive */
     int32_t reserved;
+    double rel_tol;          /* > 0: also stop only when max over FREE cells with
+                                |psi| >= 1e-30 of |avg4(psi) - psi| / |psi| is <= rel_tol
+                                (a "descent-grade" field: far from the goal psi can be
+                                ~1e-13 and absolute tolerances do not resolve its
+                                gradient; components without a goal decay towards 0 and
+                                drop out below 1e-30, so bound the run with max_sweeps) */
 } hpf_params;
 
 typedef struct {
@@ -162,6 +168,7 @@ typedef struct {
     int32_t status;        /* TWG_OK or TWG_NOT_CONVERGED */
     int32_t polish_rounds; /* defect-correction rounds */
     int32_t checks;        /* residual read-backs */
+    double residual_rel;   /* max |r| / |psi| over FREE cells with |psi| >= 1e-30 (FP32 phase) */
 } hpf_stats;
 
 /* hpf_relax -- converge the harmonic potential of one grid (Eqs. 1-2,

@@ -99,13 +99,15 @@ struct Runner {
     hipStream_t st;
     int checks = 0;
 
-    int residual32(const float *u, const float *f, double *out)
+    // FP64 residual of an FP32 field: *out = max |r|, *rel = max |r| / |u|
+    int residual32(const float *u, const float *f, double *out, double *rel = nullptr)
     {
-        int rc = launch_zero_words(ctx->words, 1, st);
+        int rc = launch_zero_words(ctx->words, 2, st);
         if (!rc) rc = launch_resid_f32(cls, u, f, g.nx, g.ny, g.pitch, ctx->words, st);
-        if (!rc) rc = readback(1);
+        if (!rc) rc = readback(2);
         if (rc) return set_err(ctx, rc, "residual kernel failed");
         *out = bits_to_double(ctx->host_words[0]);
+        if (rel) *rel = bits_to_double(ctx->host_words[1]);
         return TWG_OK;
     }
 
@@ -137,57 +139,67 @@ struct Runner {
     }
 
     // FP32 red-black SOR on `field` (ping-pong with ctx->alt) until the FP64
-    // residual is <= tol, the sweep budget is spent, or progress stalls.
+    // residual is <= tol (and, if rel_tol > 0, the relative residual is <=
+    // rel_tol), the sweep budget is spent, or progress stalls.
     int solve32(float *field, const float *f, float omega, int S, int RH, double tol,
                 int64_t max_sweeps, int check_passes, int64_t *sweeps_out, double *res_out,
-                bool *converged)
+                bool *converged, double rel_tol = 0.0, double *rel_out = nullptr)
     {
         const size_t bytes = (size_t)g.pitch * g.ny * sizeof(float);
         int rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, bytes);
         if (rc) return rc;
         float *a = field, *b = reinterpret_cast<float *>(ctx->alt);
-        double r;
-        rc = residual32(a, f, &r);
+        double r, rr;
+        rc = residual32(a, f, &r, &rr);
         if (rc) return rc;
-        const double r_init = r;
         int64_t done = 0;
         int stalls = 0;
-        double rate = std::max((double)omega - 1.0, 0.5);  // per-sweep guess before any measurement
+        // per-sweep contraction guesses before any measurement
+        double rate = std::max((double)omega - 1.0, 0.5), rate_rel = rate;
         *converged = false;
         while (true) {
-            if (std::isnan(r)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
-            if (r <= tol) { *converged = true; break; }
+            if (std::isnan(r) || std::isnan(rr))
+                return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
+            const bool abs_ok = r <= tol, rel_ok = rel_tol <= 0.0 || rr <= rel_tol;
+            if (abs_ok && rel_ok) { *converged = true; break; }
             if (done >= max_sweeps) break;
             int64_t chunk;
             if (check_passes > 0) {
                 chunk = (int64_t)check_passes * S;
             } else {
-                double want = std::log(tol / r) / std::log(rate);
+                double want = abs_ok ? 0.0 : std::log(tol / r) / std::log(rate);
+                if (!rel_ok) want = std::max(want, std::log(rel_tol / rr) / std::log(rate_rel));
                 chunk = (int64_t)std::ceil(want * (checks <= 1 ? 0.8 : 1.05)) + S;
                 chunk = std::max<int64_t>(chunk, 8 * S);
             }
             chunk = std::min(chunk, max_sweeps - done);
-            const double r_prev = r;
+            const double r_prev = r, rr_prev = rr;
             rc = sweep32(&a, &b, f, omega, S, RH, chunk);
             if (rc) return rc;
             done += chunk;
-            rc = residual32(a, f, &r);
+            rc = residual32(a, f, &r, &rr);
             if (rc) return rc;
+            bool progress = false;
             if (r < r_prev * 0.999) {
-                stalls = 0;
+                progress = true;
                 const double q = std::pow(r / r_prev, 1.0 / (double)chunk);
                 if (q > 0.0 && q < 1.0) rate = q;
-            } else if (++stalls >= 3) {
-                break;  // FP32 rounding floor or no convergence
             }
+            if (rel_tol > 0.0 && rr < rr_prev * 0.999) {
+                progress = true;
+                const double q = std::pow(rr / rr_prev, 1.0 / (double)chunk);
+                if (q > 0.0 && q < 1.0) rate_rel = q;
+            }
+            if (progress) stalls = 0;
+            else if (++stalls >= 3) break;  // rounding floor or no convergence
         }
-        (void)r_init;
         if (a != field) {
             rc = launch_copy_f32(a, field, g.nx, g.ny, g.pitch, st);
             if (rc) return set_err(ctx, rc, "copy launch failed");
         }
         *sweeps_out = done;
         *res_out = r;
+        if (rel_out) *rel_out = rr;
         return TWG_OK;
     }
 };
@@ -292,8 +304,9 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
     rc = launch_field_init(cls, psi, g.nx, g.ny, g.pitch, p.init, st);
     if (rc) return set_err(ctx, rc, "init launch failed");
     bool conv = false;
+    if (!(p.rel_tol >= 0.0)) return set_err(ctx, TWG_EINVAL, "rel_tol must be >= 0");
     rc = run.solve32(psi, nullptr, omega, S, RH, p.tol, p.max_sweeps, p.check_passes, &s.sweeps,
-                     &s.residual32, &conv);
+                     &s.residual32, &conv, p.rel_tol, &s.residual_rel);
     if (rc) return rc;
     s.residual = s.residual32;
     s.status = conv ? TWG_OK : TWG_NOT_CONVERGED;
@@ -313,7 +326,7 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
         // residual the result must reach: tol, and tol_cert / wbound if set
         const double need = p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / wb) : p.tol;
         for (int round = 0; round < 12; ++round) {
-            rc = launch_zero_words(ctx->words, 1, st);
+            rc = launch_zero_words(ctx->words, 2, st);
             if (!rc) rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->words, st);
             if (!rc) rc = run.readback(1);
             if (rc) return set_err(ctx, rc, "defect kernel failed");
@@ -475,7 +488,7 @@ int32_t hpf_residual(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *
     if (!cls || (!psi && !psi64) || !out) return set_err(ctx, TWG_EINVAL, "missing argument");
     hipSetDevice(ctx->device);
     hipStream_t st = as_stream(stream);
-    rc = launch_zero_words(ctx->words, 1, st);
+    rc = launch_zero_words(ctx->words, 2, st);
     if (!rc)
         rc = psi64 ? launch_resid_f64(cls, psi64, f, g.nx, g.ny, g.pitch, ctx->words, st)
                    : launch_resid_f32(cls, psi, f, g.nx, g.ny, g.pitch, ctx->words, st);

@@ -227,8 +227,9 @@ __device__ __forceinline__ double block_max(double v)
 }
 
 // Residual |avg4(u) + f - u| over FREE cells; the max's bit pattern goes to
-// *out by atomicMax (non-negative doubles order like their bit patterns; a
-// NaN anywhere yields a NaN pattern, which is larger than +inf).
+// out[0] by atomicMax (non-negative doubles order like their bit patterns; a
+// NaN anywhere yields a NaN pattern, which is larger than +inf).  out[1]
+// receives max |r| / |u| over FREE cells with |u| >= 1e-30.
 template <typename T, bool RHS, bool WRITE_R32>
 __global__ __launch_bounds__(256) void k_resid(const uint8_t *__restrict__ cls,
                                                const T *__restrict__ u, const float *__restrict__ f,
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(256) void k_resid(const uint8_t *__restrict__ cls,
                                                unsigned long long *out)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    double m = 0.0;
+    double m = 0.0, mr = 0.0;
     for (int y = blockIdx.y * 4 + (threadIdx.x >> 6); y < ny; y += gridDim.y * 4) {
         if (x >= nx) break;
         const size_t i = (size_t)y * pitch + x;
@@ -248,13 +249,21 @@ __global__ __launch_bounds__(256) void k_resid(const uint8_t *__restrict__ cls,
             const double n = y > 0 ? (double)u[i - pitch] : 0.0;
             double g = ((e + w) + (s + n)) * 0.25;
             if (RHS) g = g + (double)f[i];
-            r = g - (double)u[i];
+            const double c = (double)u[i];
+            r = g - c;
+            const double ac = fabs(c);
+            if (ac >= 1e-30) mr = nanmax(mr, fabs(r) / ac);
         }
         if (WRITE_R32) r32[i] = (float)r;
         m = nanmax(m, fabs(r));
     }
     m = block_max(m);
-    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+    __syncthreads();
+    mr = block_max(mr);
+    if (threadIdx.x == 0) {
+        atomicMax(out, (unsigned long long)__double_as_longlong(m));
+        atomicMax(out + 1, (unsigned long long)__double_as_longlong(mr));
+    }
 }
 
 // ---- element-wise helpers --------------------------------------------------

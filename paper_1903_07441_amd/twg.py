@@ -33,13 +33,13 @@ class RasterParams(ctypes.Structure):
 class HpfParams(ctypes.Structure):
     _fields_ = [("tol", f64), ("tol_cert", f64), ("max_sweeps", i64), ("omega", f32),
                 ("init", i32), ("polish", i32), ("sweeps_per_pass", i32), ("check_passes", i32),
-                ("reserved", i32)]
+                ("reserved", i32), ("rel_tol", f64)]
 
 
 class HpfStats(ctypes.Structure):
     _fields_ = [("sweeps", i64), ("polish_sweeps", i64), ("residual", f64), ("residual32", f64),
                 ("cert_bound", f64), ("wbound", f64), ("omega", f32), ("status", i32),
-                ("polish_rounds", i32), ("checks", i32)]
+                ("polish_rounds", i32), ("checks", i32), ("residual_rel", f64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -163,14 +163,15 @@ class Context:
 
     # ---- relaxation --------------------------------------------------------
     def relax(self, cls, psi, psi64=None, tol=1e-6, tol_cert=0.0, max_sweeps=0, omega=0.0,
-              init=INIT_HALF, polish=False, sweeps_per_pass=0, check_passes=0):
+              init=INIT_HALF, polish=False, sweeps_per_pass=0, check_passes=0, rel_tol=0.0):
         nx, ny, pitch = _grid_of(psi)
         if psi.dtype != torch.float32 or cls.dtype != torch.uint8 or cls.stride(0) != pitch:
             raise ValueError("psi must be float32 and share its pitch with the uint8 class map")
         if psi64 is not None and (psi64.dtype != torch.float64 or psi64.stride(0) != pitch):
             raise ValueError("psi64 must be float64 with the same pitch")
         prm = HpfParams(float(tol), float(tol_cert), int(max_sweeps), float(omega), int(init),
-                        int(bool(polish)), int(sweeps_per_pass), int(check_passes), 0)
+                        int(bool(polish)), int(sweeps_per_pass), int(check_passes), 0,
+                        float(rel_tol))
         st = HpfStats()
         rc = lib.hpf_relax(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(psi64),
                            ctypes.byref(prm), ctypes.byref(st), _stream())

@@ -93,3 +93,23 @@ def test_descend_rejects_bad_arguments(ctx):
         ctx.descend(c, psi=psi, start=(10, 0))
     with pytest.raises(twg.TwgError):
         ctx.descend(c, psi=psi, start=(0, 0), cap=0)
+
+
+def test_descent_grade_field_reaches_goal_2048(ctx, orc):
+    # scenario 1: the goal is reachable, but psi at the robot is ~1e-13; the
+    # relative-residual stop makes the field resolve the descent direction
+    sc = scenarios.scenario("replan2048", 1)
+    cls, _ = orc.rasterize(sc)
+    assert orc.goal_reachable(cls, sc["robot"])
+    st, psi, psi64, c = gpu_relax(ctx, cls, tol=1e-6, polish=True, tol_cert=5e-7, rel_tol=1e-4)
+    print(f"descent-grade stats={st}", flush=True)
+    assert st["status"] == 0 and st["residual_rel"] <= 1e-4
+    t = to_dev(psi64, dtype=torch.float64)
+    s_gpu, p_gpu = gpu_descend(ctx, c, t, sc["robot"], use64=True)
+    s_orc, p_orc = orc.descend(cls, psi64, sc["robot"])
+    assert s_gpu == s_orc
+    np.testing.assert_array_equal(p_gpu, p_orc)
+    print(f"descent status={s_gpu} length={len(p_gpu)}", flush=True)
+    assert s_gpu == 0
+    steps = np.abs(np.diff(p_gpu, axis=0)).sum(axis=1)
+    assert np.all(steps == 1) and cls[p_gpu[-1][1], p_gpu[-1][0]] == 3
