@@ -210,6 +210,15 @@ int32_t hpf_sweeps(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, con
                    float omega, int32_t sweeps, int32_t tiled, int32_t sweeps_per_pass,
                    void *stream);
 
+/* hpf_sweeps64 -- exactly `sweeps` red-black SOR sweeps of an FP64 field
+ * psi64, the update evaluated unfused in the order of the definition
+ * (g = ((E + W) + (S + N)) * 0.25, psi + omega * (g - psi)), so one sweep
+ * matches a plain FP64 sweep bit for bit.  tiled = 0: one launch per colour;
+ * tiled = 1: sweeps_per_pass (1, 2, 3, 4, 6 or 8; 0 = 4) sweeps per tile
+ * load, bit-identical.  Asynchronous.  Errors: TWG_EINVAL. */
+int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64, double omega,
+                     int32_t sweeps, int32_t tiled, int32_t sweeps_per_pass, void *stream);
+
 /* hpf_autotune -- measure the relaxation kernel on grid g and class map cls
  * and remember, for grids of this exact size, the fastest tiling and an SOR
  * factor; later hpf_relax calls on this context with sweeps_per_pass = 0

@@ -478,6 +478,48 @@ int32_t hpf_sweeps(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, con
     return TWG_OK;
 }
 
+int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64, double omega,
+                     int32_t sweeps, int32_t tiled, int32_t sweeps_per_pass, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!cls || !psi64) return set_err(ctx, TWG_EINVAL, "cls and psi64 are required");
+    if (sweeps < 0) return set_err(ctx, TWG_EINVAL, "sweeps < 0");
+    if (!(omega > 0.0 && omega < 2.0)) return set_err(ctx, TWG_EINVAL, "omega must be in (0, 2)");
+    hipSetDevice(ctx->device);
+    hipStream_t st = as_stream(stream);
+    if (!tiled) {
+        for (int k = 0; k < sweeps; ++k)
+            for (int color = 0; color < 2; ++color) {
+                rc = launch_sweep_color_f64(cls, psi64, nullptr, g.nx, g.ny, g.pitch, omega, color, st);
+                if (rc) return set_err(ctx, rc, "sweep launch failed");
+            }
+        return TWG_OK;
+    }
+    const int S = sweeps_per_pass ? sweeps_per_pass : 4;
+    if (!stream_depth_supported(S))
+        return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
+    rc = ensure(ctx, &ctx->alt64, &ctx->alt64_bytes, (size_t)g.pitch * g.ny * sizeof(double));
+    if (rc) return rc;
+    double *a = psi64, *b = reinterpret_cast<double *>(ctx->alt64);
+    const int RH = 32;
+    const Geometry geo = stream_geometry(g.nx, g.ny, S, RH), geo1 = stream_geometry(g.nx, g.ny, 1, RH);
+    for (int64_t done = 0; done < sweeps;) {
+        const bool full = sweeps - done >= S;
+        rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, st);
+        if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
+        std::swap(a, b);
+        done += full ? S : 1;
+    }
+    if (a != psi64 &&
+        hipMemcpy2DAsync(psi64, (size_t)g.pitch * 8, a, (size_t)g.pitch * 8, (size_t)g.nx * 8, g.ny,
+                         hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return set_err(ctx, TWG_EDEVICE, "copy failed");
+    return TWG_OK;
+}
+
 int32_t hpf_residual(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi,
                      const double *psi64, const float *f, double *out, void *stream)
 {

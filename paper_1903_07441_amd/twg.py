@@ -64,6 +64,7 @@ def _load():
         "hpf_sweeps": (i32, [vp, Grid, vp, vp, vp, f32, i32, i32, i32, vp]),
         "hpf_residual": (i32, [vp, Grid, vp, vp, vp, vp, P(f64), vp]),
         "hpf_autotune": (i32, [vp, Grid, vp, vp, vp]),
+        "hpf_sweeps64": (i32, [vp, Grid, vp, vp, f64, i32, i32, i32, vp]),
         "hpf_index_matrix": (i32, [vp, Grid, vp, vp, vp, vp, vp]),
         "hpf_descend": (i32, [vp, Grid, vp, vp, vp, P(DescendParams), vp, vp, vp]),
     }
@@ -76,7 +77,7 @@ def _load():
 
 lib = _load()
 EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error", "twg_rasterize",
-            "hpf_relax", "hpf_sweeps", "hpf_residual", "hpf_autotune", "hpf_index_matrix",
+            "hpf_relax", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune", "hpf_index_matrix",
             "hpf_descend")
 
 
@@ -182,6 +183,12 @@ class Context:
         nx, ny, pitch = _grid_of(psi)
         rc = lib.hpf_sweeps(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(f), float(omega),
                             int(n), int(bool(tiled)), int(sweeps_per_pass), _stream())
+        self._check(rc)
+
+    def sweeps64(self, cls, psi64, omega, n, tiled=True, sweeps_per_pass=0):
+        nx, ny, pitch = _grid_of(psi64)
+        rc = lib.hpf_sweeps64(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi64), float(omega), int(n),
+                              int(bool(tiled)), int(sweeps_per_pass), _stream())
         self._check(rc)
 
     def autotune(self, cls):

@@ -200,3 +200,23 @@ def test_relax_not_converged_and_errors(ctx):
     with pytest.raises(twg.TwgError) as e:
         ctx.relax(c, psi, None, sweeps_per_pass=5)
     assert e.value.code == twg.EINVAL
+
+
+@pytest.mark.parametrize("nx,ny,pitch", [(96, 80, 96), (301, 129, 320), (3, 40, 4)])
+@pytest.mark.parametrize("S", [1, 3, 4])
+def test_fp64_sweep_bit_exact_vs_oracle(ctx, orc, nx, ny, pitch, S):
+    # P11: the GPU's FP64 red-black sweep equals the oracle's FP64 sweep bit for bit
+    rng = np.random.default_rng(nx + S)
+    cls = random_classes(rng, nx, ny, walls=nx > 2, fixed=0.02)
+    psi0 = orc.field_init(cls, rng.uniform(size=(ny, nx)), orc.INIT_KEEP)
+    want = psi0.copy()
+    for _ in range(2 * S):
+        want = orc.sor_sweep(cls, want, 1.87)
+    c = to_dev(cls, pitch)
+    a = to_dev(psi0, pitch, dtype=torch.float64)
+    b = to_dev(psi0, pitch, dtype=torch.float64)
+    ctx.sweeps64(c, a, 1.87, 2 * S, tiled=False)
+    ctx.sweeps64(c, b, 1.87, 2 * S, tiled=True, sweeps_per_pass=S)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a.cpu().numpy(), want)
+    np.testing.assert_array_equal(b.cpu().numpy(), want)
