@@ -201,6 +201,27 @@ typedef struct {
 int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, double *psi64,
                   const hpf_params *params, hpf_stats *stats, void *stream);
 
+typedef struct {
+    int32_t nx, ny, pitch; /* as twg_grid */
+    int32_t reserved;
+    int64_t offset; /* element offset of this grid's arrays from the batch base pointers */
+} twg_grid_desc;
+
+/* hpf_relax_batched -- hpf_relax (FP32 phase) for n independent grids of any
+ * sizes at once.  Every pass is ONE launch over the tiles of all grids still
+ * above tolerance, and the FP64 residuals of all grids are reduced in one
+ * launch; a grid drops out of the pass sequence as soon as it meets tol (and
+ * rel_tol, if set).  Grid k's class map and field start at element offset
+ * grids[k].offset of cls and psi (the grids must not overlap).  Sweeps per
+ * tile load come from the autotuned entry of the largest grid (or
+ * params->sweeps_per_pass); each grid's SOR factor is params->omega, else its
+ * size's autotuned factor, else its open-rectangle optimum.  polish must be 0.
+ * stats: host array of n entries, or NULL.  Blocking.  Returns TWG_OK when
+ * every grid converged, else TWG_NOT_CONVERGED.  Errors: TWG_EINVAL (n < 1,
+ * NULL arrays, a bad grid or offset, polish set), TWG_ENOMEM, TWG_EDEVICE. */
+int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, const uint8_t *cls,
+                          float *psi, const hpf_params *params, hpf_stats *stats, void *stream);
+
 /* hpf_sweeps -- exactly `sweeps` red-black SOR sweeps of the same update as
  * hpf_relax, with an optional FP32 source f (psi + omega (avg4(psi) + f - psi);
  * NULL = 0), no convergence test.  tiled = 0 runs one launch per colour

@@ -2,8 +2,10 @@
 // convergence control of the relaxation.  The arithmetic runs in the kernels
 // of raster.hip, relax.hip and descend.hip.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "twg_internal.h"
 
@@ -236,10 +238,11 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
     if (!ctx) return TWG_EINVAL;
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
-    void *bufs[] = {ctx->alt, ctx->pol, ctx->alt64, ctx->pairs, ctx->idxbuf, ctx->words};
+    void *bufs[] = {ctx->alt, ctx->pol, ctx->alt64, ctx->pairs, ctx->idxbuf, ctx->batch, ctx->words};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (ctx->host_words) hipHostFree(ctx->host_words);
+    if (ctx->batch_host) hipHostFree(ctx->batch_host);
     delete ctx;
     return TWG_OK;
 }
@@ -359,6 +362,233 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
     if (s.status == TWG_NOT_CONVERGED)
         set_err(ctx, TWG_NOT_CONVERGED, "relaxation stopped before reaching the tolerance");
     return s.status;
+}
+
+int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, const uint8_t *cls,
+                          float *psi, const hpf_params *params, hpf_stats *stats, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    if (n < 1 || !grids || !cls || !psi || !params)
+        return set_err(ctx, TWG_EINVAL, "n >= 1, grids, cls, psi and params are required");
+    hpf_params p = *params;
+    if (!(p.tol > 0.0)) return set_err(ctx, TWG_EINVAL, "tol must be > 0");
+    if (!(p.omega >= 0.0f && p.omega < 2.0f)) return set_err(ctx, TWG_EINVAL, "omega must be in [0, 2)");
+    if (p.init < HPF_INIT_KEEP || p.init > HPF_INIT_ZERO) return set_err(ctx, TWG_EINVAL, "bad init mode");
+    if (p.polish) return set_err(ctx, TWG_EINVAL, "the batched relaxation has no polish");
+    if (!(p.rel_tol >= 0.0)) return set_err(ctx, TWG_EINVAL, "rel_tol must be >= 0");
+    if (p.sweeps_per_pass && !stream_depth_supported(p.sweeps_per_pass))
+        return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
+    if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
+    int big = 0;
+    long long total = 0;
+    for (int k = 0; k < n; ++k) {
+        const twg_grid gk{grids[k].nx, grids[k].ny, grids[k].pitch};
+        int rc = check_grid(ctx, gk);
+        if (rc) return set_err(ctx, rc, "grid " + std::to_string(k) + ": " + ctx->err);
+        if (grids[k].offset < 0) return set_err(ctx, TWG_EINVAL, "negative offset");
+        total = std::max(total, (long long)grids[k].offset + (long long)grids[k].pitch * grids[k].ny);
+        if ((long long)grids[k].nx * grids[k].ny > (long long)grids[big].nx * grids[big].ny) big = k;
+    }
+    hipSetDevice(ctx->device);
+    hipStream_t st = as_stream(stream);
+    int S, RH;
+    float om_big;
+    tiling_for(ctx, grids[big].nx, grids[big].ny, &S, &RH, &om_big);
+    if (p.sweeps_per_pass) S = p.sweeps_per_pass;
+    const int VW = 128 - 4 * S;
+
+    // host descriptors, full tile and block lists
+    std::vector<BatchGrid> bg(n);
+    std::vector<int> tiles_of(n), blocks_of(n);
+    int max_tiles = 0, max_blocks = 0;
+    for (int k = 0; k < n; ++k) {
+        int s_, rh_;
+        float om;
+        tiling_for(ctx, grids[k].nx, grids[k].ny, &s_, &rh_, &om);
+        bg[k] = BatchGrid{grids[k].nx, grids[k].ny, grids[k].pitch, p.omega > 0.0f ? p.omega : om,
+                          (long long)grids[k].offset};
+        tiles_of[k] = ((grids[k].nx + VW - 1) / VW) * ((grids[k].ny + RH - 1) / RH);
+        blocks_of[k] = (grids[k].nx + 63) / 64;
+        max_tiles += tiles_of[k];
+        max_blocks += blocks_of[k];
+    }
+    // device layout: grids | tiles | blocks | n_tiles | words
+    auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t o_grids = 0, o_tiles = align(o_grids + n * sizeof(BatchGrid));
+    const size_t o_blocks = align(o_tiles + max_tiles * sizeof(BatchTile));
+    const size_t o_count = align(o_blocks + max_blocks * sizeof(int2));
+    const size_t o_words = align(o_count + sizeof(int));
+    const size_t bytes = align(o_words + 2 * n * sizeof(unsigned long long));
+    int rc = ensure(ctx, &ctx->batch, &ctx->batch_bytes, bytes);
+    if (!rc) rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, (size_t)total * sizeof(float));
+    if (rc) return rc;
+    if (ctx->batch_host_bytes < 2 * n * sizeof(unsigned long long)) {
+        if (ctx->batch_host) hipHostFree(ctx->batch_host);
+        ctx->batch_host = nullptr;
+        ctx->batch_host_bytes = 0;
+        if (hipHostMalloc(&ctx->batch_host, 2 * n * sizeof(unsigned long long), hipHostMallocDefault) !=
+            hipSuccess)
+            return set_err(ctx, TWG_ENOMEM, "pinned allocation failed");
+        ctx->batch_host_bytes = 2 * n * sizeof(unsigned long long);
+    }
+    char *base = reinterpret_cast<char *>(ctx->batch);
+    BatchGrid *d_grids = reinterpret_cast<BatchGrid *>(base + o_grids);
+    BatchTile *d_tiles = reinterpret_cast<BatchTile *>(base + o_tiles);
+    int2 *d_blocks = reinterpret_cast<int2 *>(base + o_blocks);
+    int *d_count = reinterpret_cast<int *>(base + o_count);
+    unsigned long long *d_words = reinterpret_cast<unsigned long long *>(base + o_words);
+    if (hipMemcpyAsync(d_grids, bg.data(), n * sizeof(BatchGrid), hipMemcpyHostToDevice, st) != hipSuccess)
+        return set_err(ctx, TWG_EDEVICE, "descriptor upload failed");
+
+    std::vector<char> active(n, 1);
+    std::vector<BatchTile> tl;
+    std::vector<int2> bl;
+    auto build_lists = [&](const std::vector<char> &sel) {
+        tl.clear();
+        bl.clear();
+        for (int k = 0; k < n; ++k) {
+            if (!sel[k]) continue;
+            const int strips = (grids[k].nx + VW - 1) / VW;
+            for (int y0 = 0; y0 < grids[k].ny; y0 += RH)
+                for (int sx = 0; sx < strips; ++sx)
+                    tl.push_back(BatchTile{k, sx * VW - 2 * S, y0, std::min(y0 + RH, grids[k].ny)});
+            for (int bx = 0; bx < blocks_of[k]; ++bx) bl.push_back(make_int2(k, bx));
+        }
+    };
+    auto upload_lists = [&]() -> int {
+        const int nt = (int)tl.size();
+        if ((!tl.empty() && hipMemcpyAsync(d_tiles, tl.data(), tl.size() * sizeof(BatchTile),
+                                           hipMemcpyHostToDevice, st) != hipSuccess) ||
+            (!bl.empty() && hipMemcpyAsync(d_blocks, bl.data(), bl.size() * sizeof(int2),
+                                           hipMemcpyHostToDevice, st) != hipSuccess) ||
+            hipMemcpyAsync(d_count, &nt, sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return TWG_EDEVICE;
+        return TWG_OK;
+    };
+    build_lists(active);
+    rc = upload_lists();
+    if (!rc) rc = launch_field_init_batch(cls, psi, d_grids, d_blocks, (int)bl.size(), p.init, st);
+    if (rc) return set_err(ctx, TWG_EDEVICE, "batch set-up failed");
+
+    std::vector<double> r(n), rr(n), rate(n), rate_rel(n);
+    std::vector<int64_t> sw(n, 0);
+    std::vector<int> stalls(n, 0);
+    std::vector<char> conv(n, 0), parity(n, 0);
+    for (int k = 0; k < n; ++k) rate[k] = rate_rel[k] = std::max((double)bg[k].omega - 1.0, 0.5);
+    float *cur = psi, *nxt = reinterpret_cast<float *>(ctx->alt);
+    int64_t done = 0;
+    int checks = 0;
+    auto check = [&]() -> int {
+        int e = launch_resid_batch(cls, cur, d_grids, d_blocks, (int)bl.size(), d_words, 2 * n, st);
+        if (e) return e;
+        if (hipMemcpyAsync(ctx->batch_host, d_words, 2 * n * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return TWG_EDEVICE;
+        ++checks;
+        return TWG_OK;
+    };
+    rc = check();
+    if (rc) return set_err(ctx, rc, "batched residual failed");
+    for (int k = 0; k < n; ++k) {
+        r[k] = bits_to_double(ctx->batch_host[2 * k]);
+        rr[k] = bits_to_double(ctx->batch_host[2 * k + 1]);
+    }
+    while (true) {
+        // retire converged, stalled or non-finite grids
+        bool changed = false;
+        int64_t chunk = INT64_MAX;
+        for (int k = 0; k < n; ++k) {
+            if (!active[k]) continue;
+            if (std::isnan(r[k]) || std::isnan(rr[k]))
+                return set_err(ctx, TWG_EINVAL, "non-finite value in grid " + std::to_string(k));
+            const bool ok = r[k] <= p.tol && (p.rel_tol <= 0.0 || rr[k] <= p.rel_tol);
+            if (ok || stalls[k] >= 3 || done >= p.max_sweeps) {
+                active[k] = 0;
+                conv[k] = ok;
+                parity[k] = cur != psi;
+                changed = true;
+                continue;
+            }
+            double want = r[k] <= p.tol ? 0.0 : std::log(p.tol / r[k]) / std::log(rate[k]);
+            if (p.rel_tol > 0.0 && rr[k] > p.rel_tol)
+                want = std::max(want, std::log(p.rel_tol / rr[k]) / std::log(rate_rel[k]));
+            int64_t c = (int64_t)std::ceil(want * (checks <= 1 ? 0.8 : 1.05));
+            if (p.check_passes > 0) c = (int64_t)p.check_passes * S;
+            chunk = std::min(chunk, std::max<int64_t>(c, 8 * S));
+        }
+        if (chunk == INT64_MAX) break;  // nothing active
+        if (changed) {
+            build_lists(active);
+            rc = upload_lists();
+            if (rc) return set_err(ctx, rc, "list upload failed");
+        }
+        chunk = std::min(chunk, p.max_sweeps - done);
+        const int64_t passes = (chunk + S - 1) / S;
+        for (int64_t q = 0; q < passes; ++q) {
+            rc = launch_stream_batch(cur, nxt, cls, d_grids, d_tiles, d_count, (int)tl.size(), S, st);
+            if (rc) return set_err(ctx, rc, "batched relaxation launch failed");
+            std::swap(cur, nxt);
+        }
+        done += passes * S;
+        rc = check();
+        if (rc) return set_err(ctx, rc, "batched residual failed");
+        for (int k = 0; k < n; ++k) {
+            if (!active[k]) continue;
+            sw[k] = done;
+            const double rn = bits_to_double(ctx->batch_host[2 * k]);
+            const double rrn = bits_to_double(ctx->batch_host[2 * k + 1]);
+            bool progress = false;
+            if (rn < r[k] * 0.999) {
+                progress = true;
+                const double q = std::pow(rn / r[k], 1.0 / (double)(passes * S));
+                if (q > 0.0 && q < 1.0) rate[k] = q;
+            }
+            if (p.rel_tol > 0.0 && rrn < rr[k] * 0.999) {
+                progress = true;
+                const double q = std::pow(rrn / rr[k], 1.0 / (double)(passes * S));
+                if (q > 0.0 && q < 1.0) rate_rel[k] = q;
+            }
+            stalls[k] = progress ? 0 : stalls[k] + 1;
+            r[k] = rn;
+            rr[k] = rrn;
+        }
+    }
+    // grids that stopped on an odd pass count hold their field in the partner buffer
+    std::vector<char> back(n);
+    bool any = false;
+    for (int k = 0; k < n; ++k) {
+        back[k] = parity[k];
+        any = any || parity[k];
+    }
+    if (any) {
+        build_lists(back);
+        rc = upload_lists();
+        if (!rc) rc = launch_copy_batch(reinterpret_cast<float *>(ctx->alt), psi, d_grids, d_blocks,
+                                        (int)bl.size(), st);
+        if (rc) return set_err(ctx, rc, "copy-back failed");
+    }
+    hipStreamSynchronize(st);
+    bool all = true;
+    for (int k = 0; k < n; ++k) {
+        all = all && conv[k];
+        if (stats) {
+            hpf_stats &s = stats[k];
+            std::memset(&s, 0, sizeof s);
+            s.sweeps = sw[k];
+            s.residual = s.residual32 = r[k];
+            s.residual_rel = rr[k];
+            s.wbound = std::pow((double)std::min(grids[k].nx, grids[k].ny) + 1.0, 2) / 2.0;
+            s.cert_bound = r[k] * s.wbound;
+            s.omega = bg[k].omega;
+            s.status = conv[k] ? TWG_OK : TWG_NOT_CONVERGED;
+            s.checks = checks;
+        }
+    }
+    if (!all) set_err(ctx, TWG_NOT_CONVERGED, "some grids stopped before reaching the tolerance");
+    return all ? TWG_OK : TWG_NOT_CONVERGED;
 }
 
 int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, void *stream)

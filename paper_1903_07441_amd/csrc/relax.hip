@@ -89,24 +89,17 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 // load has NW row-steps of arithmetic to arrive.  Loads use clamped (always
 // in-bounds) addresses; cells outside the grid are zeroed with a fixed-cell
 // factor when they are taken from the queue.
+// One wave relaxes one tile: output columns [x0 + 2S, x0 + 128 - 2S) and
+// rows [ybeg, yend) of a grid; x0 and ybeg are even, all tile values are
+// wave-uniform.
 template <typename T, int S, bool RHS>
-__global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T *__restrict__ dst,
-                                                    const uint8_t *__restrict__ cls,
-                                                    const T *__restrict__ f, int nx, int ny,
-                                                    int pitch, T omega, int strips, int RH,
-                                                    int tiles)
+__device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__restrict__ dst,
+                                            const uint8_t *__restrict__ cls,
+                                            const T *__restrict__ f, int nx, int ny, int pitch,
+                                            T omega, int x0, int ybeg, int yend)
 {
     constexpr int NW = 2 * S + 2;      // rolling window of rows (even)
-    constexpr int VW = 128 - 4 * S;    // columns written per strip
     const int lane = threadIdx.x & (kWave - 1);
-    // everything that depends only on the tile is wave-uniform: keep it scalar
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-    if (tile >= tiles) return;  // whole wave
-    const int strip = tile % strips, seg = tile / strips;
-    const int x0 = strip * VW - 2 * S;             // first (even) column of the strip
-    const int ybeg = seg * RH;
-    const int yend = min(ybeg + RH, ny);
     const int r0 = ybeg - 2 * S;                   // first row streamed (even)
     const int T_rows = (yend - ybeg) + 4 * S;
     // per-lane constants
@@ -195,6 +188,44 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
     }
 }
 
+template <typename T, int S, bool RHS>
+__global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T *__restrict__ dst,
+                                                    const uint8_t *__restrict__ cls,
+                                                    const T *__restrict__ f, int nx, int ny,
+                                                    int pitch, T omega, int strips, int RH,
+                                                    int tiles)
+{
+    constexpr int VW = 128 - 4 * S;  // columns written per strip
+    // everything that depends only on the tile is wave-uniform: keep it scalar
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    if (tile >= tiles) return;  // whole wave
+    const int strip = tile % strips, seg = tile / strips;
+    const int ybeg = seg * RH;
+    stream_tile<T, S, RHS>(src, dst, cls, f, nx, ny, pitch, omega, strip * VW - 2 * S, ybeg,
+                           min(ybeg + RH, ny));
+}
+
+// Batched form: the tiles of many grids in one launch.  Grid g's arrays start
+// at element offset desc.off of the batch base pointers; the tile count is
+// read from device memory so that one captured launch serves any active set.
+template <int S>
+__global__ __launch_bounds__(256) void k_sor_stream_batch(const float *__restrict__ src,
+                                                          float *__restrict__ dst,
+                                                          const uint8_t *__restrict__ cls,
+                                                          const BatchGrid *__restrict__ grids,
+                                                          const BatchTile *__restrict__ tiles,
+                                                          const int *__restrict__ n_tiles)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    if (tile >= *n_tiles) return;  // whole wave
+    const BatchTile t = tiles[tile];
+    const BatchGrid g = grids[t.grid];
+    stream_tile<float, S, false>(src + g.off, dst + g.off, cls + g.off, nullptr, g.nx, g.ny,
+                                 g.pitch, g.omega, t.x0, t.ybeg, t.yend);
+}
+
 // ---- untiled half-sweep: one colour, in place -----------------------------
 template <typename T, bool RHS>
 __global__ __launch_bounds__(256) void k_sweep_color(const uint8_t *__restrict__ cls, T *psi,
@@ -263,6 +294,84 @@ __global__ __launch_bounds__(256) void k_resid(const uint8_t *__restrict__ cls,
     if (threadIdx.x == 0) {
         atomicMax(out, (unsigned long long)__double_as_longlong(m));
         atomicMax(out + 1, (unsigned long long)__double_as_longlong(mr));
+    }
+}
+
+// Batched residual: block b handles 64 columns of one grid (all rows);
+// out[2 g] and out[2 g + 1] receive grid g's max |r| and max |r| / |u|.
+__global__ __launch_bounds__(256) void k_resid_batch(const uint8_t *__restrict__ cls,
+                                                     const float *__restrict__ u,
+                                                     const BatchGrid *__restrict__ grids,
+                                                     const int2 *__restrict__ blocks,
+                                                     unsigned long long *out)
+{
+    const int2 bk = blocks[blockIdx.x];
+    const BatchGrid g = grids[bk.x];
+    const uint8_t *c = cls + g.off;
+    const float *v = u + g.off;
+    const int x = bk.y * 64 + (threadIdx.x & 63);
+    double m = 0.0, mr = 0.0;
+    if (x < g.nx) {
+        for (int y = threadIdx.x >> 6; y < g.ny; y += 4) {
+            const size_t i = (size_t)y * g.pitch + x;
+            if (c[i] != TWG_CELL_FREE) continue;
+            const double e = x + 1 < g.nx ? (double)v[i + 1] : 0.0;
+            const double w = x > 0 ? (double)v[i - 1] : 0.0;
+            const double s = y + 1 < g.ny ? (double)v[i + g.pitch] : 0.0;
+            const double n = y > 0 ? (double)v[i - g.pitch] : 0.0;
+            const double cc = (double)v[i];
+            const double r = ((e + w) + (s + n)) * 0.25 - cc;
+            m = nanmax(m, fabs(r));
+            if (fabs(cc) >= 1e-30) mr = nanmax(mr, fabs(r) / fabs(cc));
+        }
+    }
+    m = block_max(m);
+    __syncthreads();
+    mr = block_max(mr);
+    if (threadIdx.x == 0) {
+        atomicMax(out + 2 * bk.x, (unsigned long long)__double_as_longlong(m));
+        atomicMax(out + 2 * bk.x + 1, (unsigned long long)__double_as_longlong(mr));
+    }
+}
+
+__global__ void k_field_init_batch(const uint8_t *__restrict__ cls, float *psi,
+                                   const BatchGrid *__restrict__ grids,
+                                   const int2 *__restrict__ blocks, int mode)
+{
+    const int2 bk = blocks[blockIdx.x];
+    const BatchGrid g = grids[bk.x];
+    const int x = bk.y * 64 + (threadIdx.x & 63);
+    if (x >= g.nx) return;
+    for (int y = threadIdx.x >> 6; y < g.ny; y += 4) {
+        const size_t i = g.off + (size_t)y * g.pitch + x;
+        switch (cls[i]) {
+        case TWG_CELL_OBST:
+        case TWG_CELL_WALL: psi[i] = 0.0f; break;
+        case TWG_CELL_GOAL: psi[i] = 1.0f; break;
+        case TWG_CELL_FREE:
+            if (mode == HPF_INIT_HALF) psi[i] = 0.5f;
+            else if (mode == HPF_INIT_ZERO) psi[i] = 0.0f;
+            break;
+        default: break;
+        }
+    }
+}
+
+__global__ void k_zero_words_n(unsigned long long *w, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) w[i] = 0ull;
+}
+
+__global__ void k_copy_batch(const float *__restrict__ s, float *__restrict__ d,
+                             const BatchGrid *__restrict__ grids, const int2 *__restrict__ blocks)
+{
+    const int2 bk = blocks[blockIdx.x];
+    const BatchGrid g = grids[bk.x];
+    const int x = bk.y * 64 + (threadIdx.x & 63);
+    if (x >= g.nx) return;
+    for (int y = threadIdx.x >> 6; y < g.ny; y += 4) {
+        const size_t i = g.off + (size_t)y * g.pitch + x;
+        d[i] = s[i];
     }
 }
 
@@ -363,6 +472,58 @@ int launch_stream(const T *src, T *dst, const uint8_t *cls, const T *f, int nx, 
 }
 
 }  // namespace
+
+int launch_stream_batch(const float *src, float *dst, const uint8_t *cls, const BatchGrid *grids,
+                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S,
+                        hipStream_t st)
+{
+    const int blocks = (max_tiles + 3) / 4;
+    if (blocks == 0) return TWG_OK;
+#define TWG_BATCH_CASE(SV)                                                                       \
+    case SV:                                                                                     \
+        hipLaunchKernelGGL(k_sor_stream_batch<SV>, dim3(blocks), dim3(256), 0, st, src, dst, cls, \
+                           grids, tiles, n_tiles);                                               \
+        break;
+    switch (S) {
+        TWG_BATCH_CASE(1)
+        TWG_BATCH_CASE(2)
+        TWG_BATCH_CASE(3)
+        TWG_BATCH_CASE(4)
+        TWG_BATCH_CASE(6)
+        TWG_BATCH_CASE(8)
+    default: return TWG_EUNSUPPORTED;
+    }
+#undef TWG_BATCH_CASE
+    return last_status();
+}
+
+int launch_resid_batch(const uint8_t *cls, const float *u, const BatchGrid *grids,
+                       const int2 *blocks, int n_blocks, unsigned long long *out, int n_words,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_words_n, dim3(std::max(1, std::min(64, (n_words + 255) / 256))),
+                       dim3(256), 0, st, out, n_words);
+    if (n_blocks > 0)
+        hipLaunchKernelGGL(k_resid_batch, dim3(n_blocks), dim3(256), 0, st, cls, u, grids, blocks, out);
+    return last_status();
+}
+
+int launch_field_init_batch(const uint8_t *cls, float *psi, const BatchGrid *grids,
+                            const int2 *blocks, int n_blocks, int mode, hipStream_t st)
+{
+    if (n_blocks > 0)
+        hipLaunchKernelGGL(k_field_init_batch, dim3(n_blocks), dim3(256), 0, st, cls, psi, grids,
+                           blocks, mode);
+    return last_status();
+}
+
+int launch_copy_batch(const float *src, float *dst, const BatchGrid *grids, const int2 *blocks,
+                      int n_blocks, hipStream_t st)
+{
+    if (n_blocks > 0)
+        hipLaunchKernelGGL(k_copy_batch, dim3(n_blocks), dim3(256), 0, st, src, dst, grids, blocks);
+    return last_status();
+}
 
 bool stream_depth_supported(int S) { return S == 1 || S == 2 || S == 3 || S == 4 || S == 6 || S == 8; }
 

@@ -38,6 +38,11 @@ struct twg_ctx {
     // index matrix of hpf_descend
     void *idxbuf = nullptr;
     size_t idxbuf_bytes = 0;
+    // batched relaxation: descriptors, tile and block lists, per-grid words
+    void *batch = nullptr;
+    size_t batch_bytes = 0;
+    unsigned long long *batch_host = nullptr;  // pinned mirror of the per-grid words
+    size_t batch_host_bytes = 0;
     // small device words: residual maxima (uint64 bit patterns), counters
     unsigned long long *words = nullptr;
     // pinned host mirror of `words`
@@ -47,6 +52,28 @@ struct twg_ctx {
 namespace twg {
 
 constexpr int kWords = 64;
+
+// one grid of a batch: arrays start at element offset `off` of the batch base
+struct BatchGrid {
+    int nx, ny, pitch;
+    float omega;
+    long long off;
+};
+// one tile of the batched relaxation kernel
+struct BatchTile {
+    int grid, x0, ybeg, yend;
+};
+
+int launch_stream_batch(const float *src, float *dst, const uint8_t *cls, const BatchGrid *grids,
+                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S,
+                        hipStream_t st);
+int launch_resid_batch(const uint8_t *cls, const float *u, const BatchGrid *grids,
+                       const int2 *blocks, int n_blocks, unsigned long long *out, int n_words,
+                       hipStream_t st);
+int launch_field_init_batch(const uint8_t *cls, float *psi, const BatchGrid *grids,
+                            const int2 *blocks, int n_blocks, int mode, hipStream_t st);
+int launch_copy_batch(const float *src, float *dst, const BatchGrid *grids, const int2 *blocks,
+                      int n_blocks, hipStream_t st);
 
 int set_err(twg_ctx *ctx, int code, const std::string &msg);
 int ensure(twg_ctx *ctx, void **buf, size_t *have, size_t need);

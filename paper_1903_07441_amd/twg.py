@@ -45,6 +45,10 @@ class HpfStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class GridDesc(ctypes.Structure):
+    _fields_ = [("nx", i32), ("ny", i32), ("pitch", i32), ("reserved", i32), ("offset", i64)]
+
+
 class DescendParams(ctypes.Structure):
     _fields_ = [("start_x", i32), ("start_y", i32), ("cap", i32), ("reserved", i32)]
 
@@ -62,6 +66,7 @@ def _load():
         "twg_rasterize": (i32, [vp, Grid, i32, vp, vp, vp, vp, P(RasterParams), vp, vp, vp]),
         "hpf_relax": (i32, [vp, Grid, vp, vp, vp, P(HpfParams), P(HpfStats), vp]),
         "hpf_sweeps": (i32, [vp, Grid, vp, vp, vp, f32, i32, i32, i32, vp]),
+        "hpf_relax_batched": (i32, [vp, i32, vp, vp, vp, P(HpfParams), vp, vp]),
         "hpf_residual": (i32, [vp, Grid, vp, vp, vp, vp, P(f64), vp]),
         "hpf_autotune": (i32, [vp, Grid, vp, vp, vp]),
         "hpf_sweeps64": (i32, [vp, Grid, vp, vp, f64, i32, i32, i32, vp]),
@@ -77,7 +82,7 @@ def _load():
 
 lib = _load()
 EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error", "twg_rasterize",
-            "hpf_relax", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune", "hpf_index_matrix",
+            "hpf_relax", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune", "hpf_index_matrix",
             "hpf_descend")
 
 
@@ -178,6 +183,28 @@ class Context:
                            ctypes.byref(prm), ctypes.byref(st), _stream())
         self._check(rc, allow=(OK, NOT_CONVERGED))
         return st.as_dict()
+
+    def relax_batched(self, cls_flat, psi_flat, descs, tol=1e-6, max_sweeps=0, omega=0.0,
+                      init=INIT_HALF, sweeps_per_pass=0, check_passes=0, rel_tol=0.0):
+        """Relax many grids packed in one flat uint8 class buffer and one flat
+        float32 field buffer; descs = [(nx, ny, pitch, offset), ...] (offsets in
+        elements).  Returns one stats dict per grid."""
+        if cls_flat.dtype != torch.uint8 or psi_flat.dtype != torch.float32:
+            raise ValueError("class buffer must be uint8 and field buffer float32")
+        if not (cls_flat.is_cuda and psi_flat.is_cuda):
+            raise ValueError("batch buffers must be device tensors")
+        n = len(descs)
+        arr = (GridDesc * n)(*[GridDesc(int(a), int(b), int(c), 0, int(d)) for a, b, c, d in descs])
+        for a, b, c, d in descs:
+            if d + c * b > min(cls_flat.numel(), psi_flat.numel()):
+                raise ValueError("a grid extends past the batch buffers")
+        prm = HpfParams(float(tol), 0.0, int(max_sweeps), float(omega), int(init), 0,
+                        int(sweeps_per_pass), int(check_passes), 0, float(rel_tol))
+        st = (HpfStats * n)()
+        rc = lib.hpf_relax_batched(self.h, n, arr, _ptr(cls_flat), _ptr(psi_flat), ctypes.byref(prm),
+                                   st, _stream())
+        self._check(rc, allow=(OK, NOT_CONVERGED))
+        return [x.as_dict() for x in st]
 
     def sweeps(self, cls, psi, omega, n, tiled=True, sweeps_per_pass=0, f=None):
         nx, ny, pitch = _grid_of(psi)
