@@ -1,0 +1,128 @@
+"""Pins of the FP64 reference network: library correlation, central finite
+differences, adjoint identities, bfloat16 rounding against torch's cast, the
+parameter count, and the first Adam step's closed form."""
+import numpy as np
+import pytest
+import scipy.signal
+import torch
+
+from oracle import unet
+
+
+def test_conv_is_cross_correlation_with_zero_padding():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(3, 9, 7))
+    w = rng.normal(size=(4, 3, 3, 3))
+    b = rng.normal(size=4)
+    got = unet.conv(x, w, b)
+    for o in range(4):
+        want = b[o] + sum(scipy.signal.correlate2d(x[c], w[o, c], mode="same") for c in range(3))
+        np.testing.assert_allclose(got[o], want, rtol=1e-12, atol=1e-12)
+    w1 = rng.normal(size=(2, 3, 1, 1))
+    np.testing.assert_allclose(unet.conv(x, w1, np.zeros(2)),
+                               np.einsum("oc,chw->ohw", w1[:, :, 0, 0], x), rtol=1e-12)
+
+
+def test_pool_and_up_adjoints():
+    rng = np.random.default_rng(1)
+    a = rng.normal(size=(3, 4, 6))
+    b = rng.normal(size=(3, 8, 12))
+    assert np.isclose((unet.up(a) * b).sum(), (a * unet.up_backward(b)).sum())
+    assert np.isclose((unet.pool(b) * a).sum(), (b * unet.pool_backward(a)).sum())
+    np.testing.assert_allclose(unet.pool(unet.up(a)), a)
+
+
+def test_conv_backward_adjoint():
+    rng = np.random.default_rng(2)
+    x = rng.normal(size=(5, 6, 8))
+    w = rng.normal(size=(3, 5, 3, 3))
+    d = rng.normal(size=(3, 6, 8))
+    dx, dw, db = unet.conv_backward(x, w, d)
+    # <conv(x) - b, d> is bilinear in (x, w)
+    lin = (unet.conv(x, w, np.zeros(3)) * d).sum()
+    assert np.isclose(lin, (dx * x).sum())
+    assert np.isclose(lin, (dw * w).sum())
+    np.testing.assert_allclose(db, d.sum(axis=(1, 2)))
+
+
+def test_parameter_count():
+    assert unet.n_params() == 443745
+    p = unet.init_params(0)
+    assert sum(v.size for v in p.values()) == 443745
+
+
+@pytest.mark.parametrize("val,want", [(1.0, 1.0), (1.0 + 2**-8, 1.0), (1.0 + 3 * 2**-8, 1.0 + 2**-6),
+                                      (-(1.0 + 2**-8 + 2**-20), -(1.0 + 2**-7))])
+def test_bf16_round_known_values(val, want):
+    # bfloat16 keeps 7 mantissa bits: ties go to the even mantissa
+    assert float(unet.bf16_round(np.array([val]))[0]) == want
+
+
+def test_bf16_round_matches_torch_cast():
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.normal(size=20000) * 10.0 ** rng.integers(-30, 30, size=20000),
+                        [0.0, -0.0, np.inf, -np.inf]]).astype(np.float32)
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    got = unet.bf16_round(x)
+    np.testing.assert_array_equal(got, want)
+    assert np.isnan(unet.bf16_round(np.array([np.nan]))[0])
+
+
+def test_gradients_central_differences():
+    rng = np.random.default_rng(4)
+    p = unet.init_params(5)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = rng.normal(size=p[k].shape) * 0.1
+    x = rng.uniform(size=(3, 16, 16))
+    t = rng.uniform(size=(16, 16))
+    m = rng.uniform(size=(16, 16)) < 0.8
+
+    def loss(pp, xx):
+        y, _ = unet.forward(pp, xx)
+        return unet.masked_mse(y, t, m)[0]
+
+    y, c = unet.forward(p, x)
+    _, dy = unet.masked_mse(y, t, m)
+    g = unet.backward(p, c, dy)
+    h = 1e-6
+    for k in p:
+        idxs = [tuple(rng.integers(0, s) for s in p[k].shape) for _ in range(3)]
+        for idx in idxs:
+            pp = {kk: vv.copy() for kk, vv in p.items()}
+            pp[k][idx] += h
+            lp = loss(pp, x)
+            pp[k][idx] -= 2 * h
+            lm = loss(pp, x)
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[k][idx]) <= 1e-6 * max(1e-3, abs(fd)) + 1e-9, (k, idx, fd, g[k][idx])
+    for _ in range(5):
+        idx = tuple(rng.integers(0, s) for s in x.shape)
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (loss(p, xp) - loss(p, xm)) / (2 * h)
+        assert abs(fd - g["x"][idx]) <= 1e-6 * max(1e-3, abs(fd)) + 1e-9
+
+
+def test_first_adam_step_closed_form():
+    # after one step m_hat = g and v_hat = g^2, so the update is lr * g / (|g| + eps)
+    p = {"a": np.array([1.0, -2.0, 3.0])}
+    g = {"a": np.array([0.5, -4.0, 1e-3])}
+    st = {}
+    q = unet.adam_step({"a": p["a"].copy()}, g, st, lr=0.01)
+    np.testing.assert_allclose(q["a"], p["a"] - 0.01 * g["a"] / (np.abs(g["a"]) + 1e-8), rtol=1e-12)
+
+
+def test_training_decreases_loss():
+    rng = np.random.default_rng(6)
+    p = unet.init_params(7)
+    xs = [rng.uniform(size=(3, 16, 16)) for _ in range(2)]
+    ts = [0.3 + 0.1 * x[0] for x in xs]
+    ms = [np.ones((16, 16), bool)] * 2
+    st = {}
+    l0, g = unet.loss_and_grads(p, xs, ts, ms)
+    for _ in range(10):
+        p = unet.adam_step(p, g, st, lr=2e-3)
+        l, g = unet.loss_and_grads(p, xs, ts, ms)
+    assert l < 0.5 * l0
