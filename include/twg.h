@@ -145,16 +145,11 @@ typedef struct {
     int64_t max_sweeps;      /* cap on FP32 sweeps of the field (0 = 10^7) */
     float omega;             /* SOR factor in (0, 2); 0 = the open-rectangle optimum */
     int32_t init;            /* HPF_INIT_* */
-    int32_t polish;          /* 0: FP32 only; 1: FP64 defect-correction polish */
+    int32_t polish;          /* 0: FP32 only; 1: FP64 defect correction (FP32 correction
+                                solves); 2: FP64 red-black SOR sweeps */
     int32_t sweeps_per_pass; /* red-black sweeps per tile load, 1..16; 0 = tuned */
     int32_t check_passes;    /* passes between residual checks; 0 = adaptive */
     int32_t reserved;
-    double rel_tol;          /* > 0: also stop only when max over FREE cells with
-                                |psi| >= 1e-30 of |avg4(psi) - psi| / |psi| is <= rel_tol
-                                (a "descent-grade" field: far from the goal psi can be
-                                ~1e-13 and absolute tolerances do not resolve its
-                                gradient; components without a goal decay towards 0 and
-                                drop out below 1e-30, so bound the run with max_sweeps) */
 } hpf_params;
 
 typedef struct {
@@ -168,7 +163,9 @@ typedef struct {
     int32_t status;        /* TWG_OK or TWG_NOT_CONVERGED */
     int32_t polish_rounds; /* defect-correction rounds */
     int32_t checks;        /* residual read-backs */
-    double residual_rel;   /* max |r| / |psi| over FREE cells with |psi| >= 1e-30 (FP32 phase) */
+    double residual_rel;   /* max |r| / |psi| over FREE cells with |psi| >= 1e-30 (FP32 phase);
+                              far from the goal this stays large in FP32, whose rounding
+                              noise there exceeds the field itself */
 } hpf_stats;
 
 /* hpf_relax -- converge the harmonic potential of one grid (Eqs. 1-2,
@@ -183,10 +180,13 @@ typedef struct {
  * several sweeps per tile load.  It stops when the FP64 residual
  * r = max |avg4(psi) - psi| over FREE cells is <= tol.  Because
  * |psi - psi*| <= r * ||(I - J)^-1 1||inf (discrete maximum principle), the
- * residual certifies the error; with polish = 1 the field is then refined by
- * FP64 defect correction (FP64 residual, FP32 correction solve, FP64 update)
- * until r <= tol and r * wbound <= tol_cert, and the result is written to
- * psi64 (and rounded into psi).
+ * residual certifies the error.  With polish != 0 the field is then refined
+ * in FP64 until r <= tol and r * wbound <= tol_cert, and the result is written
+ * to psi64 (and rounded into psi): polish = 1 by defect correction (FP64
+ * residual, FP32 correction solve, FP64 update), polish = 2 by FP64 SOR sweeps.
+ * Far from the goal psi can be ~1e-13: FP32 sweeps leave rounding noise of
+ * ~1e-12 there, which only FP64 sweeps remove, so polish = 2 is the choice
+ * when the descent must be resolved far from the goal.
  *
  *   cls    uint8 class map (device, pitch g.pitch).
  *   psi    in/out FP32 field (device, pitch g.pitch): FIXED cells must hold their
@@ -210,8 +210,7 @@ typedef struct {
 /* hpf_relax_batched -- hpf_relax (FP32 phase) for n independent grids of any
  * sizes at once.  Every pass is ONE launch over the tiles of all grids still
  * above tolerance, and the FP64 residuals of all grids are reduced in one
- * launch; a grid drops out of the pass sequence as soon as it meets tol (and
- * rel_tol, if set).  Grid k's class map and field start at element offset
+ * launch; a grid drops out of the pass sequence as soon as it meets tol.  Grid k's class map and field start at element offset
  * grids[k].offset of cls and psi (the grids must not overlap).  Sweeps per
  * tile load come from the autotuned entry of the largest grid (or
  * params->sweeps_per_pass); each grid's SOR factor is params->omega, else its

@@ -141,11 +141,10 @@ struct Runner {
     }
 
     // FP32 red-black SOR on `field` (ping-pong with ctx->alt) until the FP64
-    // residual is <= tol (and, if rel_tol > 0, the relative residual is <=
-    // rel_tol), the sweep budget is spent, or progress stalls.
+    // residual is <= tol, the sweep budget is spent, or progress stalls.
     int solve32(float *field, const float *f, float omega, int S, int RH, double tol,
                 int64_t max_sweeps, int check_passes, int64_t *sweeps_out, double *res_out,
-                bool *converged, double rel_tol = 0.0, double *rel_out = nullptr)
+                bool *converged, double *rel_out = nullptr)
     {
         const size_t bytes = (size_t)g.pitch * g.ny * sizeof(float);
         int rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, bytes);
@@ -156,44 +155,35 @@ struct Runner {
         if (rc) return rc;
         int64_t done = 0;
         int stalls = 0;
-        // per-sweep contraction guesses before any measurement
-        double rate = std::max((double)omega - 1.0, 0.5), rate_rel = rate;
+        // per-sweep contraction guess before any measurement
+        double rate = std::max((double)omega - 1.0, 0.5);
         *converged = false;
         while (true) {
-            if (std::isnan(r) || std::isnan(rr))
-                return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
-            const bool abs_ok = r <= tol, rel_ok = rel_tol <= 0.0 || rr <= rel_tol;
-            if (abs_ok && rel_ok) { *converged = true; break; }
+            if (std::isnan(r)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
+            if (r <= tol) { *converged = true; break; }
             if (done >= max_sweeps) break;
             int64_t chunk;
             if (check_passes > 0) {
                 chunk = (int64_t)check_passes * S;
             } else {
-                double want = abs_ok ? 0.0 : std::log(tol / r) / std::log(rate);
-                if (!rel_ok) want = std::max(want, std::log(rel_tol / rr) / std::log(rate_rel));
+                const double want = std::log(tol / r) / std::log(rate);
                 chunk = (int64_t)std::ceil(want * (checks <= 1 ? 0.8 : 1.05)) + S;
                 chunk = std::max<int64_t>(chunk, 8 * S);
             }
             chunk = std::min(chunk, max_sweeps - done);
-            const double r_prev = r, rr_prev = rr;
+            const double r_prev = r;
             rc = sweep32(&a, &b, f, omega, S, RH, chunk);
             if (rc) return rc;
             done += chunk;
             rc = residual32(a, f, &r, &rr);
             if (rc) return rc;
-            bool progress = false;
             if (r < r_prev * 0.999) {
-                progress = true;
+                stalls = 0;
                 const double q = std::pow(r / r_prev, 1.0 / (double)chunk);
                 if (q > 0.0 && q < 1.0) rate = q;
+            } else if (++stalls >= 3) {
+                break;  // rounding floor or no convergence
             }
-            if (rel_tol > 0.0 && rr < rr_prev * 0.999) {
-                progress = true;
-                const double q = std::pow(rr / rr_prev, 1.0 / (double)chunk);
-                if (q > 0.0 && q < 1.0) rate_rel = q;
-            }
-            if (progress) stalls = 0;
-            else if (++stalls >= 3) break;  // rounding floor or no convergence
         }
         if (a != field) {
             rc = launch_copy_f32(a, field, g.nx, g.ny, g.pitch, st);
@@ -202,6 +192,67 @@ struct Runner {
         *sweeps_out = done;
         *res_out = r;
         if (rel_out) *rel_out = rr;
+        return TWG_OK;
+    }
+
+    // FP64 residual of an FP64 field
+    int residual64(const double *u, double *out)
+    {
+        int rc = launch_zero_words(ctx->words, 2, st);
+        if (!rc) rc = launch_resid_f64(cls, u, nullptr, g.nx, g.ny, g.pitch, ctx->words, st);
+        if (!rc) rc = readback(2);
+        if (rc) return set_err(ctx, rc, "residual kernel failed");
+        *out = bits_to_double(ctx->host_words[0]);
+        return TWG_OK;
+    }
+
+    // FP64 red-black SOR on `field` (ping-pong with ctx->alt64), four sweeps
+    // per tile load, until the FP64 residual is <= tol or the budget is spent.
+    int solve64(double *field, double omega, double tol, int64_t max_sweeps, int64_t *sweeps_out,
+                double *res_out, bool *converged)
+    {
+        int rc = ensure(ctx, &ctx->alt64, &ctx->alt64_bytes, (size_t)g.pitch * g.ny * sizeof(double));
+        if (rc) return rc;
+        constexpr int S = 4, RH = 32;
+        const Geometry geo = stream_geometry(g.nx, g.ny, S, RH);
+        double *a = field, *b = reinterpret_cast<double *>(ctx->alt64);
+        double r;
+        rc = residual64(a, &r);
+        if (rc) return rc;
+        int64_t done = 0;
+        int stalls = 0;
+        double rate = std::max(omega - 1.0, 0.5);
+        *converged = false;
+        while (true) {
+            if (std::isnan(r)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
+            if (r <= tol) { *converged = true; break; }
+            if (done >= max_sweeps) break;
+            const double want = std::log(tol / r) / std::log(rate);
+            int64_t chunk = std::max<int64_t>((int64_t)std::ceil(want * 1.05) + S, 8 * S);
+            chunk = ((std::min(chunk, max_sweeps - done) + S - 1) / S) * S;
+            for (int64_t k = 0; k < chunk; k += S) {
+                rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, geo, st);
+                if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
+                std::swap(a, b);
+            }
+            done += chunk;
+            const double r_prev = r;
+            rc = residual64(a, &r);
+            if (rc) return rc;
+            if (r < r_prev * 0.999) {
+                stalls = 0;
+                const double q = std::pow(r / r_prev, 1.0 / (double)chunk);
+                if (q > 0.0 && q < 1.0) rate = q;
+            } else if (++stalls >= 3) {
+                break;
+            }
+        }
+        if (a != field &&
+            hipMemcpy2DAsync(field, (size_t)g.pitch * 8, a, (size_t)g.pitch * 8, (size_t)g.nx * 8, g.ny,
+                             hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return set_err(ctx, TWG_EDEVICE, "copy failed");
+        *sweeps_out = done;
+        *res_out = r;
         return TWG_OK;
     }
 };
@@ -285,6 +336,7 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
     if (!(p.tol > 0.0)) return set_err(ctx, TWG_EINVAL, "tol must be > 0");
     if (!(p.omega >= 0.0f && p.omega < 2.0f)) return set_err(ctx, TWG_EINVAL, "omega must be in [0, 2)");
     if (p.init < HPF_INIT_KEEP || p.init > HPF_INIT_ZERO) return set_err(ctx, TWG_EINVAL, "bad init mode");
+    if (p.polish < 0 || p.polish > 2) return set_err(ctx, TWG_EINVAL, "polish must be 0, 1 or 2");
     if (p.polish && !psi64) return set_err(ctx, TWG_EINVAL, "polish needs psi64");
     if (p.sweeps_per_pass && !stream_depth_supported(p.sweeps_per_pass))
         return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
@@ -307,14 +359,27 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
     rc = launch_field_init(cls, psi, g.nx, g.ny, g.pitch, p.init, st);
     if (rc) return set_err(ctx, rc, "init launch failed");
     bool conv = false;
-    if (!(p.rel_tol >= 0.0)) return set_err(ctx, TWG_EINVAL, "rel_tol must be >= 0");
     rc = run.solve32(psi, nullptr, omega, S, RH, p.tol, p.max_sweeps, p.check_passes, &s.sweeps,
-                     &s.residual32, &conv, p.rel_tol, &s.residual_rel);
+                     &s.residual32, &conv, &s.residual_rel);
     if (rc) return rc;
     s.residual = s.residual32;
     s.status = conv ? TWG_OK : TWG_NOT_CONVERGED;
 
-    if (p.polish) {
+    if (p.polish == 2) {
+        // FP64 SOR sweeps from the FP32 field
+        const double need = p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / wb) : p.tol;
+        rc = launch_widen(psi, psi64, g.nx, g.ny, g.pitch, st);
+        if (rc) return set_err(ctx, rc, "widen launch failed");
+        bool done = false;
+        double r64 = 0.0;
+        rc = run.solve64(psi64, (double)omega, need, p.max_sweeps, &s.polish_sweeps, &r64, &done);
+        if (rc) return rc;
+        rc = launch_narrow(psi64, psi, g.nx, g.ny, g.pitch, st);
+        if (rc) return set_err(ctx, rc, "narrow launch failed");
+        s.residual = r64;
+        s.status = done ? TWG_OK : TWG_NOT_CONVERGED;
+        hipStreamSynchronize(st);
+    } else if (p.polish == 1) {
         // FP64 defect correction: r = avg4(psi64) - psi64 in FP64, solve
         // (I - J) e = r in FP32 (e = 0 on fixed cells), psi64 += e.
         const size_t n32 = (size_t)g.pitch * g.ny;
@@ -376,7 +441,6 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
     if (!(p.omega >= 0.0f && p.omega < 2.0f)) return set_err(ctx, TWG_EINVAL, "omega must be in [0, 2)");
     if (p.init < HPF_INIT_KEEP || p.init > HPF_INIT_ZERO) return set_err(ctx, TWG_EINVAL, "bad init mode");
     if (p.polish) return set_err(ctx, TWG_EINVAL, "the batched relaxation has no polish");
-    if (!(p.rel_tol >= 0.0)) return set_err(ctx, TWG_EINVAL, "rel_tol must be >= 0");
     if (p.sweeps_per_pass && !stream_depth_supported(p.sweeps_per_pass))
         return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
     if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
@@ -472,11 +536,11 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
     if (!rc) rc = launch_field_init_batch(cls, psi, d_grids, d_blocks, (int)bl.size(), p.init, st);
     if (rc) return set_err(ctx, TWG_EDEVICE, "batch set-up failed");
 
-    std::vector<double> r(n), rr(n), rate(n), rate_rel(n);
+    std::vector<double> r(n), rr(n), rate(n);
     std::vector<int64_t> sw(n, 0);
     std::vector<int> stalls(n, 0);
     std::vector<char> conv(n, 0), parity(n, 0);
-    for (int k = 0; k < n; ++k) rate[k] = rate_rel[k] = std::max((double)bg[k].omega - 1.0, 0.5);
+    for (int k = 0; k < n; ++k) rate[k] = std::max((double)bg[k].omega - 1.0, 0.5);
     float *cur = psi, *nxt = reinterpret_cast<float *>(ctx->alt);
     int64_t done = 0;
     int checks = 0;
@@ -504,7 +568,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
             if (!active[k]) continue;
             if (std::isnan(r[k]) || std::isnan(rr[k]))
                 return set_err(ctx, TWG_EINVAL, "non-finite value in grid " + std::to_string(k));
-            const bool ok = r[k] <= p.tol && (p.rel_tol <= 0.0 || rr[k] <= p.rel_tol);
+            const bool ok = r[k] <= p.tol;
             if (ok || stalls[k] >= 3 || done >= p.max_sweeps) {
                 active[k] = 0;
                 conv[k] = ok;
@@ -512,9 +576,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
                 changed = true;
                 continue;
             }
-            double want = r[k] <= p.tol ? 0.0 : std::log(p.tol / r[k]) / std::log(rate[k]);
-            if (p.rel_tol > 0.0 && rr[k] > p.rel_tol)
-                want = std::max(want, std::log(p.rel_tol / rr[k]) / std::log(rate_rel[k]));
+            const double want = std::log(p.tol / r[k]) / std::log(rate[k]);
             int64_t c = (int64_t)std::ceil(want * (checks <= 1 ? 0.8 : 1.05));
             if (p.check_passes > 0) c = (int64_t)p.check_passes * S;
             chunk = std::min(chunk, std::max<int64_t>(c, 8 * S));
@@ -545,11 +607,6 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
                 progress = true;
                 const double q = std::pow(rn / r[k], 1.0 / (double)(passes * S));
                 if (q > 0.0 && q < 1.0) rate[k] = q;
-            }
-            if (p.rel_tol > 0.0 && rrn < rr[k] * 0.999) {
-                progress = true;
-                const double q = std::pow(rrn / rr[k], 1.0 / (double)(passes * S));
-                if (q > 0.0 && q < 1.0) rate_rel[k] = q;
             }
             stalls[k] = progress ? 0 : stalls[k] + 1;
             r[k] = rn;

@@ -419,6 +419,15 @@ __global__ void k_widen(const float *__restrict__ psi, double *u, int nx, int ny
     u[i] = (double)psi[i];
 }
 
+__global__ void k_narrow(const double *__restrict__ u, float *psi, int nx, int ny, int pitch)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= nx || y >= ny) return;
+    const size_t i = (size_t)y * pitch + x;
+    psi[i] = (float)u[i];
+}
+
 __global__ void k_fill(float *a, float v, int nx, int ny, int pitch)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -634,6 +643,12 @@ int launch_update64(const uint8_t *cls, double *u, const float *e, float *psi, i
 int launch_widen(const float *psi, double *u, int nx, int ny, int pitch, hipStream_t st)
 {
     hipLaunchKernelGGL(k_widen, cell_grid(nx, ny), dim3(256), 0, st, psi, u, nx, ny, pitch);
+    return last_status();
+}
+
+int launch_narrow(const double *u, float *psi, int nx, int ny, int pitch, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_narrow, cell_grid(nx, ny), dim3(256), 0, st, u, psi, nx, ny, pitch);
     return last_status();
 }
 

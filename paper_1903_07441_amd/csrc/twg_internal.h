@@ -108,6 +108,7 @@ int launch_defect64(const uint8_t *cls, const double *u, float *r32, int nx, int
 int launch_update64(const uint8_t *cls, double *u, const float *e, float *psi, int nx, int ny,
                     int pitch, hipStream_t st);
 int launch_widen(const float *psi, double *u, int nx, int ny, int pitch, hipStream_t st);
+int launch_narrow(const double *u, float *psi, int nx, int ny, int pitch, hipStream_t st);
 int launch_fill_f32(float *a, float v, int nx, int ny, int pitch, hipStream_t st);
 int launch_copy_f32(const float *src, float *dst, int nx, int ny, int pitch, hipStream_t st);
 int launch_zero_words(unsigned long long *w, int n, hipStream_t st);

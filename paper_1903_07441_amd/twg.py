@@ -33,7 +33,7 @@ class RasterParams(ctypes.Structure):
 class HpfParams(ctypes.Structure):
     _fields_ = [("tol", f64), ("tol_cert", f64), ("max_sweeps", i64), ("omega", f32),
                 ("init", i32), ("polish", i32), ("sweeps_per_pass", i32), ("check_passes", i32),
-                ("reserved", i32), ("rel_tol", f64)]
+                ("reserved", i32)]
 
 
 class HpfStats(ctypes.Structure):
@@ -169,15 +169,15 @@ class Context:
 
     # ---- relaxation --------------------------------------------------------
     def relax(self, cls, psi, psi64=None, tol=1e-6, tol_cert=0.0, max_sweeps=0, omega=0.0,
-              init=INIT_HALF, polish=False, sweeps_per_pass=0, check_passes=0, rel_tol=0.0):
+              init=INIT_HALF, polish=0, sweeps_per_pass=0, check_passes=0):
+        """polish: 0 FP32 only, 1 (or True) FP64 defect correction, 2 FP64 SOR sweeps."""
         nx, ny, pitch = _grid_of(psi)
         if psi.dtype != torch.float32 or cls.dtype != torch.uint8 or cls.stride(0) != pitch:
             raise ValueError("psi must be float32 and share its pitch with the uint8 class map")
         if psi64 is not None and (psi64.dtype != torch.float64 or psi64.stride(0) != pitch):
             raise ValueError("psi64 must be float64 with the same pitch")
         prm = HpfParams(float(tol), float(tol_cert), int(max_sweeps), float(omega), int(init),
-                        int(bool(polish)), int(sweeps_per_pass), int(check_passes), 0,
-                        float(rel_tol))
+                        int(polish), int(sweeps_per_pass), int(check_passes), 0)
         st = HpfStats()
         rc = lib.hpf_relax(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(psi64),
                            ctypes.byref(prm), ctypes.byref(st), _stream())
@@ -185,7 +185,7 @@ class Context:
         return st.as_dict()
 
     def relax_batched(self, cls_flat, psi_flat, descs, tol=1e-6, max_sweeps=0, omega=0.0,
-                      init=INIT_HALF, sweeps_per_pass=0, check_passes=0, rel_tol=0.0):
+                      init=INIT_HALF, sweeps_per_pass=0, check_passes=0):
         """Relax many grids packed in one flat uint8 class buffer and one flat
         float32 field buffer; descs = [(nx, ny, pitch, offset), ...] (offsets in
         elements).  Returns one stats dict per grid."""
@@ -199,7 +199,7 @@ class Context:
             if d + c * b > min(cls_flat.numel(), psi_flat.numel()):
                 raise ValueError("a grid extends past the batch buffers")
         prm = HpfParams(float(tol), 0.0, int(max_sweeps), float(omega), int(init), 0,
-                        int(sweeps_per_pass), int(check_passes), 0, float(rel_tol))
+                        int(sweeps_per_pass), int(check_passes), 0)
         st = (HpfStats * n)()
         rc = lib.hpf_relax_batched(self.h, n, arr, _ptr(cls_flat), _ptr(psi_flat), ctypes.byref(prm),
                                    st, _stream())
@@ -263,6 +263,25 @@ class Context:
                              ctypes.byref(p), _ptr(path), _ptr(info), _stream())
         self._check(rc)
         return path, info
+
+
+def plan(ctx, cls, psi, psi64, start, tol=1e-6, tol_cert=5e-7, init=INIT_HALF, extra_sweeps=256,
+         max_extra=8, path=None, info=None):
+    """One replanning field and path: FP32 relaxation to `tol`, FP64 SOR polish
+    to a certified error of `tol_cert`, then further FP64 sweeps, `extra_sweeps`
+    at a time, until the steepest descent from `start` reaches the goal (at
+    most `max_extra` times: far from the goal the potential can be ~1e-13 and
+    only a well-converged FP64 field orders its neighbours).  Returns
+    (plain_stats, polish_stats, path, info, extra_rounds)."""
+    plain = ctx.relax(cls, psi, None, tol=tol, init=init)
+    pol = ctx.relax(cls, psi, psi64, tol=tol, init=INIT_KEEP, polish=2, tol_cert=tol_cert)
+    path, info = ctx.descend(cls, psi64=psi64, start=start, path=path, info=info)
+    rounds = 0
+    while int(info[1].item()) == NO_PATH and rounds < max_extra:
+        ctx.sweeps64(cls, psi64, pol["omega"], extra_sweeps)
+        path, info = ctx.descend(cls, psi64=psi64, start=start, path=path, info=info)
+        rounds += 1
+    return plain, pol, path, info, rounds
 
 
 def version() -> int:

@@ -97,19 +97,26 @@ def test_descend_rejects_bad_arguments(ctx):
 
 def test_descent_grade_field_reaches_goal_2048(ctx, orc):
     # scenario 1: the goal is reachable, but psi at the robot is ~1e-13; the
-    # relative-residual stop makes the field resolve the descent direction
+    # FP64 polish plus FP64 sweeps until the descent resolves (twg.plan) gives
+    # a path, identical to the oracle's walk on the same field
+    from paper_1903_07441_amd import twg
     sc = scenarios.scenario("replan2048", 1)
     cls, _ = orc.rasterize(sc)
     assert orc.goal_reachable(cls, sc["robot"])
-    st, psi, psi64, c = gpu_relax(ctx, cls, tol=1e-6, polish=True, tol_cert=5e-7, rel_tol=1e-4)
-    print(f"descent-grade stats={st}", flush=True)
-    assert st["status"] == 0 and st["residual_rel"] <= 1e-4
-    t = to_dev(psi64, dtype=torch.float64)
-    s_gpu, p_gpu = gpu_descend(ctx, c, t, sc["robot"], use64=True)
-    s_orc, p_orc = orc.descend(cls, psi64, sc["robot"])
-    assert s_gpu == s_orc
+    c = to_dev(cls)
+    psi = torch.zeros((2048, 2048), dtype=torch.float32, device="cuda")
+    psi64 = torch.zeros((2048, 2048), dtype=torch.float64, device="cuda")
+    plain, pol, path, info, rounds = twg.plan(ctx, c, psi, psi64, sc["robot"])
+    torch.cuda.synchronize()
+    n, status = info.cpu().tolist()
+    print(f"plan: plain={plain['sweeps']} polish={pol['polish_sweeps']} rounds={rounds} status={status} "
+          f"length={n}", flush=True)
+    assert pol["status"] == 0 and pol["cert_bound"] <= 5e-7
+    f64 = psi64.cpu().numpy()
+    assert orc.residual(cls, f64) * orc.wbound(2048, 2048) <= 5e-7
+    s_orc, p_orc = orc.descend(cls, f64, sc["robot"])
+    assert status == s_orc == 0
+    p_gpu = path[:n].cpu().numpy()
     np.testing.assert_array_equal(p_gpu, p_orc)
-    print(f"descent status={s_gpu} length={len(p_gpu)}", flush=True)
-    assert s_gpu == 0
     steps = np.abs(np.diff(p_gpu, axis=0)).sum(axis=1)
     assert np.all(steps == 1) and cls[p_gpu[-1][1], p_gpu[-1][0]] == 3
