@@ -28,6 +28,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
+    summary, or None when the summary is for another kernel or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_sor_stream_replan2048.md")
+    src = os.path.join(ROOT, "paper_1903_07441_amd", "csrc", "sor_stream.hip")
+    try:
+        text = open(path).read().splitlines()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    kv = {}
+    for ln in text:
+        ln = ln.strip()
+        if ":" in ln and ln.split(":", 1)[0] in ("kernel", "source_sha256_16", "traffic_bytes_per_launch"):
+            k, v = ln.split(":", 1)
+            kv[k] = v.strip()
+    if kv.get("kernel") != kernel or kv.get("source_sha256_16") != sha:
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,10 +155,18 @@ def main():
     t_launch = e0.elapsed_time(e1) * 1e-3 / passes
     alg_bytes = BYTES_PER_CELL_UPDATE * cells * S
     achieved = alg_bytes / t_launch / 1e9
+    kname = f"k_sor_stream<float,{S},false>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"k_sor_stream<float,{S},false>", "launch_us": round(t_launch * 1e6, 2),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(kname),
+                "kernel": kname, "launch_us": round(t_launch * 1e6, 2),
                 "algorithmic_bytes_per_launch": alg_bytes}
+    # the same launch against the vector-ALU issue rate: 5 VALU instructions
+    # per cell-update (3 adds, 2 FMAs) are the minimum of the update; the chip
+    # issues 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s
+    valu_peak = 256 * 4 * 16 * 2.4e9
+    valu_ach = 5.0 * cells * S / t_launch
+    roofline_alu = {"bound": "alu", "achieved": round(valu_ach / 1e12, 3), "peak": round(valu_peak / 1e12, 3),
+                    "unit": "T VALU lane-instr/s", "frac": round(valu_ach / valu_peak, 4)}
 
     # ---- CPU baseline: the oracle on a bounded sample ----
     cpu = None
@@ -187,6 +218,7 @@ def main():
         "tuning": {"sweeps_per_pass": tuning["S"], "rows_per_tile": tuning["RH"],
                    "omega": round(tuning["omega"], 6)},
         "roofline": roofline,
+        "roofline_alu": roofline_alu,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
