@@ -291,6 +291,77 @@ int32_t hpf_descend(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *p
                     const double *psi64, const hpf_descend_params *params, int32_t *path_xy,
                     int32_t *info, void *stream);
 
+/* ========================================================================= */
+/* Learned warm start (not in the paper: an initial field for hpf_relax)     */
+/* ========================================================================= */
+
+/* A small encoder-decoder network (4 levels, 32 base channels, 443,745
+ * parameters) maps three input channels per cell -- occupancy (1 on OBST and
+ * WALL), Euclidean distance to the goal / (max(nx, ny) sqrt 2), ring number /
+ * largest ring -- to an initial psi.  Layers, in order (conv3 = 3x3
+ * cross-correlation with zero padding 1 and a bias; pool = 2x2 mean; up = 2x
+ * nearest; cat = channel concatenation):
+ *   e0 = relu(conv3(x, 3->32)); e1 = relu(conv3(pool(e0), 32->64));
+ *   e2 = relu(conv3(pool(e1), 64->128)); e3 = relu(conv3(pool(e2), 128->128));
+ *   d2 = relu(conv3(cat(up(e3), e2), 256->64)); d1 = relu(conv3(cat(up(d2), e1), 128->32));
+ *   d0 = relu(conv3(cat(up(d1), e0), 64->32)); y = conv1(d0, 32->1).
+ * Every stored activation and the input are rounded to bf16 (nearest even);
+ * products accumulate in FP32 on the matrix cores.  The relaxation always
+ * finishes from the network's field, so results keep hpf_relax's tolerance.
+ *
+ * Parameter vectors (device, FP32, TWG_UNET_NUM_PARAMS entries) list the
+ * layers in the order above, each as w[cout][cin][ky][kx] then b[cout].
+ * Images are [batch][H][W] (x: [batch][H][W][3]), contiguous, H and W
+ * multiples of 8, batch * H * W <= 2^28.  The network object owns its
+ * parameters, optimiser state and activation buffers (allocated on first use
+ * of a size); it must not be used by two streams at once. */
+#define TWG_UNET_NUM_PARAMS 443745
+typedef struct twg_unet twg_unet;
+
+int32_t twg_unet_num_params(void);
+
+/* Create a network on ctx's device with all parameters zero.  Errors:
+ * TWG_EINVAL, TWG_ENOMEM, TWG_EDEVICE. */
+int32_t twg_unet_create(twg_ctx *ctx, twg_unet **out);
+int32_t twg_unet_destroy(twg_unet *net);
+
+/* Load / read the parameters (device FP32 vector).  Loading resets the Adam
+ * state.  Asynchronous. */
+int32_t twg_unet_set_params(twg_unet *net, const float *params, void *stream);
+int32_t twg_unet_get_params(twg_unet *net, float *params, void *stream);
+
+/* y[b][h][w] = network output for input x[b][h][w][0..2] (device FP32).
+ * Asynchronous.  Errors: TWG_EINVAL (shape, NULL), TWG_ENOMEM. */
+int32_t twg_unet_forward(twg_unet *net, int32_t batch, int32_t H, int32_t W, const float *x, float *y,
+                         void *stream);
+
+/* Training loss and gradients: loss = mean over images of the mean over FREE
+ * cells (cls[b][h][w] == TWG_CELL_FREE, uint8, device) of (y - target)^2;
+ * *loss (device float) receives it.  The parameter gradients are kept for
+ * twg_unet_adam_step and, if grads is not NULL, written there (device FP32,
+ * parameter order).  Weight gradients are reduced in a fixed order
+ * (deterministic).  Asynchronous. */
+int32_t twg_unet_loss_grad(twg_unet *net, int32_t batch, int32_t H, int32_t W, const float *x,
+                           const float *target, const uint8_t *cls, float *loss, float *grads,
+                           void *stream);
+
+/* One Adam step (b1 0.9, b2 0.999, eps 1e-8) with the gradients of the last
+ * twg_unet_loss_grad.  Errors: TWG_EINVAL for lr outside (0, 1). */
+int32_t twg_unet_adam_step(twg_unet *net, float lr, void *stream);
+
+/* Network input channels of a grid, on an H x W frame (H >= ny, W >= nx,
+ * multiples of 8; frame cells outside the grid read as walls), written to x
+ * (device FP32 [H][W][3]).  ring may be NULL (ring channel 0).  Asynchronous. */
+int32_t twg_unet_features(twg_unet *net, twg_grid g, const uint8_t *cls, const uint16_t *ring,
+                          int32_t goal_x, int32_t goal_y, int32_t H, int32_t W, float *x, void *stream);
+
+/* Warm start of one grid: features, network, and the field written to psi
+ * (device FP32, pitch g.pitch): FREE cells clamp(y, 0, 1), OBST and WALL 0,
+ * GOAL 1, FIXED cells unchanged.  Follow with hpf_relax(init =
+ * HPF_INIT_KEEP).  Asynchronous. */
+int32_t twg_unet_warm_start(twg_unet *net, twg_grid g, const uint8_t *cls, const uint16_t *ring,
+                            int32_t goal_x, int32_t goal_y, float *psi, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,228 @@
+"""Train and evaluate the learned warm start on the GPU.
+
+The training set is made by the library itself: seeded 256 x 256 scenarios
+are rasterised (twg_rasterize), their fields relaxed (hpf_relax_batched), and
+the network input channels computed (twg_unet_features); the network is then
+trained with twg_unet_loss_grad / twg_unet_adam_step (masked MSE over FREE
+cells, Adam).  Evaluation relaxes held-out scenarios to residual 1e-6 from the
+plain initial fields and from the network's field and reports sweeps and time.
+
+    python -m paper_1903_07441_amd.learn --train 4096 --eval 64 --epochs 4 \\
+        --out paper_1903_07441_amd/weights/unet_learn256.npz
+
+Weights are stored as an .npz with one FP32 array ``params`` (the C ABI's
+parameter order) and a text array ``meta`` (JSON); load with
+``np.load(path)`` (no pickles).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import scenarios, twg
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "unet_learn256.npz")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def he_init(seed=0):
+    """He-uniform conv weights, zero biases, head scaled by 0.1 (parameter
+    order of the C ABI)."""
+    rng = np.random.default_rng(seed)
+    spec = [(3, 32, 3), (32, 64, 3), (64, 128, 3), (128, 128, 3), (256, 64, 3), (128, 32, 3), (64, 32, 3),
+            (32, 1, 1)]
+    parts = []
+    for i, (cin, cout, k) in enumerate(spec):
+        lim = math.sqrt(6.0 / (cin * k * k))
+        w = rng.uniform(-lim, lim, size=cout * cin * k * k)
+        if i == len(spec) - 1:
+            w *= 0.1
+        parts += [w, np.zeros(cout)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def save_weights(path, params, meta):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, params=np.asarray(params, dtype=np.float32), meta=np.array(json.dumps(meta)))
+
+
+def load_weights(path=DEFAULT_WEIGHTS):
+    with np.load(path, allow_pickle=False) as z:
+        return z["params"].astype(np.float32), json.loads(str(z["meta"]))
+
+
+def make_dataset(ctx, net, first, n, name="learn256", side=None):
+    """Rasterise scenarios first .. first + n - 1 of recipe `name`, compute the
+    network inputs, and keep class map, ring map and goal of each."""
+    dev = torch.device("cuda", ctx.device)
+    sc0 = scenarios.scenario(name, first, side=side)
+    H, W = sc0["ny"], sc0["nx"]
+    x = torch.empty((n, H, W, 3), dtype=torch.float32, device=dev)
+    cls = torch.empty((n, H, W), dtype=torch.uint8, device=dev)
+    ring = torch.empty((n, H, W), dtype=torch.uint16, device=dev)
+    goals = []
+    for k in range(n):
+        sc = scenarios.scenario(name, first + k, side=side)
+        pos = torch.as_tensor(sc["pos"], dtype=torch.float64).reshape(-1, 2).to(dev)
+        vel = torch.as_tensor(sc["vel"], dtype=torch.float64).reshape(-1, 2).to(dev)
+        rad = torch.as_tensor(sc["rad"], dtype=torch.float64).to(dev)
+        ctx.rasterize(W, H, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"], robot_speed=sc["vr"],
+                      cls=cls[k], ring=ring[k])
+        net.features(cls[k], ring[k], sc["goal"], H=H, W=W, out=x[k])
+        goals.append((int(sc["goal"][0]), int(sc["goal"][1])))
+        if (k + 1) % 2048 == 0:
+            log(f"  rasterised {k + 1}/{n}")
+    return dict(x=x, cls=cls, ring=ring, goals=goals, H=H, W=W, first=first, name=name)
+
+
+def relax_targets(ctx, data, tol=1e-7, chunk=256):
+    """Converged FP32 fields of every scenario (batched relaxation)."""
+    n, H, W = data["cls"].shape
+    psi = torch.empty((n, H, W), dtype=torch.float32, device=data["cls"].device)
+    cls_flat = data["cls"].view(-1)
+    psi_flat = psi.view(-1)
+    sweeps = []
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        descs = [(W, H, W, (k - s) * H * W) for k in range(s, e)]
+        st = ctx.relax_batched(cls_flat[s * H * W:e * H * W], psi_flat[s * H * W:e * H * W], descs, tol=tol)
+        sweeps += [d["sweeps"] for d in st]
+        if (e // chunk) % 8 == 0 or e == n:
+            log(f"  relaxed {e}/{n} (median sweeps {int(np.median(sweeps))})")
+    data["target"] = psi
+    return psi
+
+
+def train(net, data, epochs=4, batch=16, lr=1e-3, lr_min=2e-5, log_every=100):
+    """Adam over contiguous batches of the (already random) scenarios with a
+    cosine learning-rate decay.  Returns the loss history (per logged step)."""
+    n = data["x"].shape[0]
+    steps_per_epoch = n // batch
+    total = epochs * steps_per_epoch
+    loss = torch.empty(1, dtype=torch.float32, device=data["x"].device)
+    hist = []
+    t0 = time.perf_counter()
+    step = 0
+    for ep in range(epochs):
+        for b in range(steps_per_epoch):
+            s, e = b * batch, (b + 1) * batch
+            a = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / max(1, total)))
+            net.loss_grad(data["x"][s:e], data["target"][s:e], data["cls"][s:e], loss)
+            net.adam_step(a)
+            step += 1
+            if step % log_every == 0 or step == total:
+                v = float(loss.item())
+                hist.append((step, v))
+                log(f"  step {step}/{total} epoch {ep + 1} loss {v:.3e} lr {a:.2e} "
+                    f"({(time.perf_counter() - t0) / step * 1e3:.2f} ms/step)")
+    torch.cuda.synchronize()
+    return hist, (time.perf_counter() - t0) / max(1, total)
+
+
+def evaluate(ctx, net, data, tol=1e-6, reps=1):
+    """Relax every scenario of `data` to `tol` from the plain initial fields
+    (half and zero) and from the network's field; per-scenario sweeps and
+    times (the learned time includes features and network)."""
+    n, H, W = data["cls"].shape
+    dev = data["cls"].device
+    psi = torch.empty((H, W), dtype=torch.float32, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {"half": [], "zero": [], "learned": [], "net_ms": [], "net_err": []}
+    for k in range(n):
+        cls, ring, goal = data["cls"][k], data["ring"][k], data["goals"][k]
+        for mode, init in (("half", twg.INIT_HALF), ("zero", twg.INIT_ZERO)):
+            best = None
+            for _ in range(reps):
+                ev0.record()
+                st = ctx.relax(cls, psi, None, tol=tol, init=init)
+                ev1.record()
+                torch.cuda.synchronize()
+                ms = ev0.elapsed_time(ev1)
+                best = ms if best is None else min(best, ms)
+            out[mode].append((st["sweeps"], best, st["residual"]))
+        best = None
+        for _ in range(reps):
+            ev0.record()
+            net.warm_start(cls, ring, goal, psi)
+            ev1.record()
+            torch.cuda.synchronize()
+            net_ms = ev0.elapsed_time(ev1)
+            if "target" in data:
+                free = cls == twg.FREE
+                out["net_err"].append(float((psi - data["target"][k]).abs()[free].max().item()))
+            ev0.record()
+            net.warm_start(cls, ring, goal, psi)
+            st = ctx.relax(cls, psi, None, tol=tol, init=twg.INIT_KEEP)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            best = ms if best is None else min(best, ms)
+        out["learned"].append((st["sweeps"], best, st["residual"]))
+        out["net_ms"].append(net_ms)
+    summ = {}
+    for mode in ("half", "zero", "learned"):
+        a = np.array(out[mode])
+        summ[mode] = {"median_sweeps": float(np.median(a[:, 0])), "median_ms": float(np.median(a[:, 1])),
+                      "max_residual": float(np.max(a[:, 2]))}
+    summ["net_median_ms"] = float(np.median(out["net_ms"]))
+    if out["net_err"]:
+        summ["net_median_max_err"] = float(np.median(out["net_err"]))
+    best_plain = min(summ["half"]["median_sweeps"], summ["zero"]["median_sweeps"])
+    summ["sweep_ratio_plain_over_learned"] = best_plain / max(1.0, summ["learned"]["median_sweeps"])
+    best_plain_ms = min(summ["half"]["median_ms"], summ["zero"]["median_ms"])
+    summ["time_ratio_plain_over_learned"] = best_plain_ms / max(1e-9, summ["learned"]["median_ms"])
+    return summ
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=4096)
+    ap.add_argument("--eval", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--init", default=None, help="start from these weights instead of He init")
+    args = ap.parse_args()
+
+    torch.cuda.set_device(0)
+    ctx = twg.Context(0)
+    net = twg.UNet(ctx)
+    params = load_weights(args.init)[0] if args.init else he_init(args.seed)
+    net.set_params(torch.as_tensor(params))
+    t0 = time.perf_counter()
+    log(f"dataset: {args.train} training + {args.eval} held-out 256x256 scenarios")
+    tr = make_dataset(ctx, net, 0, args.train)
+    relax_targets(ctx, tr)
+    ev = make_dataset(ctx, net, 100000, args.eval)
+    relax_targets(ctx, ev)
+    t_data = time.perf_counter() - t0
+    log(f"dataset ready in {t_data:.1f} s")
+    before = evaluate(ctx, net, ev) if args.init is None else None
+    hist, ms_step = train(net, tr, epochs=args.epochs, batch=args.batch, lr=args.lr)
+    after = evaluate(ctx, net, ev)
+    meta = {"train_scenarios": [0, args.train], "eval_scenarios": [100000, 100000 + args.eval],
+            "recipe": "learn256", "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+            "ms_per_step": ms_step, "loss_history": hist, "eval": after}
+    save_weights(args.out, net.get_params().cpu().numpy(), meta)
+    print(json.dumps({"data_s": round(t_data, 1), "ms_per_train_step": round(ms_step * 1e3, 3),
+                      "final_loss": hist[-1][1] if hist else None, "eval_untrained": before,
+                      "eval_trained": after}), flush=True)
+    net.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

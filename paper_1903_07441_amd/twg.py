@@ -72,6 +72,16 @@ def _load():
         "hpf_sweeps64": (i32, [vp, Grid, vp, vp, f64, i32, i32, i32, vp]),
         "hpf_index_matrix": (i32, [vp, Grid, vp, vp, vp, vp, vp]),
         "hpf_descend": (i32, [vp, Grid, vp, vp, vp, P(DescendParams), vp, vp, vp]),
+        "twg_unet_num_params": (i32, []),
+        "twg_unet_create": (i32, [vp, P(vp)]),
+        "twg_unet_destroy": (i32, [vp]),
+        "twg_unet_set_params": (i32, [vp, vp, vp]),
+        "twg_unet_get_params": (i32, [vp, vp, vp]),
+        "twg_unet_forward": (i32, [vp, i32, i32, i32, vp, vp, vp]),
+        "twg_unet_loss_grad": (i32, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "twg_unet_adam_step": (i32, [vp, f32, vp]),
+        "twg_unet_features": (i32, [vp, Grid, vp, vp, i32, i32, i32, i32, vp, vp]),
+        "twg_unet_warm_start": (i32, [vp, Grid, vp, vp, i32, i32, vp, vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -82,8 +92,10 @@ def _load():
 
 lib = _load()
 EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error", "twg_rasterize",
-            "hpf_relax", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune", "hpf_index_matrix",
-            "hpf_descend")
+            "hpf_relax", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
+            "hpf_index_matrix", "hpf_descend", "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
+            "twg_unet_set_params", "twg_unet_get_params", "twg_unet_forward", "twg_unet_loss_grad",
+            "twg_unet_adam_step", "twg_unet_features", "twg_unet_warm_start")
 
 
 class TwgError(RuntimeError):
@@ -263,6 +275,104 @@ class Context:
                              ctypes.byref(p), _ptr(path), _ptr(info), _stream())
         self._check(rc)
         return path, info
+
+
+class UNet:
+    """The learned warm start's network (twg_unet_*): parameters, forward,
+    loss and gradients, Adam, features and warm start.  Tensors are device
+    tensors; images are [batch, H, W] and inputs [batch, H, W, 3]."""
+
+    def __init__(self, ctx: Context, params=None):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        ctx._check(lib.twg_unet_create(ctx.h, ctypes.byref(h)))
+        self.h = h
+        self.n_params = int(lib.twg_unet_num_params())
+        if params is not None:
+            self.set_params(params)
+
+    def close(self):
+        if self.h:
+            lib.twg_unet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self):
+        return torch.device("cuda", self.ctx.device)
+
+    def set_params(self, params):
+        t = torch.as_tensor(params, dtype=torch.float32).to(self._dev()).contiguous()
+        if t.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {t.numel()}")
+        self.ctx._check(lib.twg_unet_set_params(self.h, _ptr(t), _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    def get_params(self):
+        t = torch.empty(self.n_params, dtype=torch.float32, device=self._dev())
+        self.ctx._check(lib.twg_unet_get_params(self.h, _ptr(t), _stream()))
+        return t
+
+    @staticmethod
+    def _img(t, dtype, last=None):
+        if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous {dtype} device tensor")
+        if last is not None and t.shape[-1] != last:
+            raise ValueError(f"last dimension must be {last}")
+        return t
+
+    def forward(self, x, y=None):
+        x = self._img(x, torch.float32, 3)
+        B, H, W, _ = x.shape
+        if y is None:
+            y = torch.empty((B, H, W), dtype=torch.float32, device=x.device)
+        self.ctx._check(lib.twg_unet_forward(self.h, B, H, W, _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def loss_grad(self, x, target, cls, loss=None, grads=None):
+        x = self._img(x, torch.float32, 3)
+        B, H, W, _ = x.shape
+        self._img(target, torch.float32)
+        self._img(cls, torch.uint8)
+        if tuple(target.shape) != (B, H, W) or tuple(cls.shape) != (B, H, W):
+            raise ValueError("target and cls must be [batch, H, W]")
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        self.ctx._check(lib.twg_unet_loss_grad(self.h, B, H, W, _ptr(x), _ptr(target), _ptr(cls), _ptr(loss),
+                                               _ptr(grads), _stream()))
+        return loss
+
+    def adam_step(self, lr):
+        self.ctx._check(lib.twg_unet_adam_step(self.h, float(lr), _stream()))
+
+    def train_step(self, x, target, cls, lr, loss=None):
+        loss = self.loss_grad(x, target, cls, loss)
+        self.adam_step(lr)
+        return loss
+
+    def features(self, cls, ring, goal, H=None, W=None, out=None):
+        nx, ny, pitch = _grid_of(cls)
+        H = H if H is not None else (ny + 7) // 8 * 8
+        W = W if W is not None else (nx + 7) // 8 * 8
+        if out is None:
+            out = torch.empty((H, W, 3), dtype=torch.float32, device=cls.device)
+        if ring is not None and ring.stride(0) != pitch:
+            raise ValueError("ring map must share the class map's pitch")
+        self.ctx._check(lib.twg_unet_features(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(ring), int(goal[0]),
+                                              int(goal[1]), int(H), int(W), _ptr(out), _stream()))
+        return out
+
+    def warm_start(self, cls, ring, goal, psi):
+        nx, ny, pitch = _grid_of(psi)
+        if cls.stride(0) != pitch or (ring is not None and ring.stride(0) != pitch):
+            raise ValueError("class and ring maps must share psi's pitch")
+        self.ctx._check(lib.twg_unet_warm_start(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(ring), int(goal[0]),
+                                                int(goal[1]), _ptr(psi), _stream()))
+        return psi
 
 
 def plan(ctx, cls, psi, psi64, start, tol=1e-6, tol_cert=5e-7, init=INIT_HALF, extra_sweeps=256,
