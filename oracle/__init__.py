@@ -74,6 +74,7 @@ def _load():
         "orc_index_matrix": (None, [i32, i32, p, p, p]),
         "orc_descend": (i32, [i32, i32, p, p, i32, i32, i32, p, p]),
         "orc_goal_reachable": (i32, [i32, i32, p, i32, i32]),
+        "orc_rubber_band": (None, [i32, i32, p, p, p, i32, f64, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -280,3 +281,13 @@ def goal_reachable(cls, start) -> bool:
     cls = _u8(cls)
     ny, nx = cls.shape
     return bool(_load().orc_goal_reachable(nx, ny, _ptr(cls), int(start[0]), int(start[1])))
+
+
+def rubber_band(cls, psi, path, k=1.0, iters=16):
+    """Rubber-band smoothing of a path (Eqs. 4-6, reading in twg_oracle.c);
+    returns the new (n, 2) int32 path [x, y]."""
+    cls, psi = _u8(cls), _f64(psi)
+    ny, nx = cls.shape
+    out = np.ascontiguousarray(np.asarray(path, dtype=np.int32).reshape(-1, 2)).copy()
+    _load().orc_rubber_band(nx, ny, _ptr(cls), _ptr(psi), _ptr(out), int(out.shape[0]), float(k), int(iters))
+    return out

@@ -549,3 +549,74 @@ int32_t orc_goal_reachable(int32_t nx, int32_t ny, const uint8_t *cls, int32_t s
     free(q);
     return found;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Rubber band (Eqs. 4-6, "Rubber Band Model"; Algorithm 1 "Path Planning")  */
+/* ------------------------------------------------------------------------ */
+
+/* The paper leaves the candidate set and the vector form of F open; the
+ * reading taken here:
+ *   - the band acts on an extracted path p_0 .. p_{n-1}; its endpoints (the
+ *     robot and the goal) stay fixed;
+ *   - one iteration updates the interior points of odd index, then those of
+ *     even index, each from the current positions of its two neighbours;
+ *   - candidates for point i are c = p_i + d, d in the order (0,0), E, W, S,
+ *     N, (1,1), (-1,1), (1,-1), (-1,-1): in the grid, walkable, psi(c) > 0,
+ *     and within one cell (Chebyshev) of both neighbours, so the band stays
+ *     8-connected;
+ *   - tension from the neighbours T = k ((p_{i-1} - c) + (p_{i+1} - c));
+ *   - potential force F = -(1 / psi(c) - 1 / psi(p_i)) u, u the unit vector
+ *     of d (F = 0 for d = 0); 1 / psi = 1 / (1 - phi) as in Eq. (6), signed
+ *     so that it resists moves towards obstacles (lower psi);
+ *   - the point moves to the candidate with the smallest |F + T|^2 (Eq. 4),
+ *     the first one in order on a tie (Eq. 5 moves it one cell at most).
+ * Points whose own psi is not positive do not move. */
+static const int rb_dx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+static const int rb_dy[9] = {0, 0, 0, 1, -1, 1, 1, -1, -1};
+
+static int32_t iabs32(int32_t v) { return v < 0 ? -v : v; }
+
+void orc_rubber_band(int32_t nx, int32_t ny, const uint8_t *cls, const double *psi, int32_t *path,
+                     int32_t n, double k, int32_t iters)
+{
+    const double inv_sqrt2 = 0.70710678118654752440;
+    for (int32_t it = 0; it < iters; ++it) {
+        for (int32_t color = 1; color >= 0; --color) {
+            for (int32_t i = 1; i + 1 < n; ++i) {
+                if ((i & 1) != color) continue;
+                const int32_t px = path[2 * i], py = path[2 * i + 1];
+                const int32_t ax = path[2 * i - 2], ay = path[2 * i - 1];
+                const int32_t bx = path[2 * i + 2], by = path[2 * i + 3];
+                const double p0 = psi[(size_t)py * nx + px];
+                if (!(p0 > 0.0)) continue;
+                const double g0 = 1.0 / p0;
+                int32_t best = -1;
+                double bestv = 0.0;
+                for (int d = 0; d < 9; ++d) {
+                    const int32_t cx = px + rb_dx[d], cy = py + rb_dy[d];
+                    if (cx < 0 || cy < 0 || cx >= nx || cy >= ny) continue;
+                    const size_t c = (size_t)cy * nx + cx;
+                    if (!walkable(cls[c]) || !(psi[c] > 0.0)) continue;
+                    if (iabs32(cx - ax) > 1 || iabs32(cy - ay) > 1 || iabs32(cx - bx) > 1 || iabs32(cy - by) > 1)
+                        continue;
+                    const double tx = k * (double)((ax - cx) + (bx - cx));
+                    const double ty = k * (double)((ay - cy) + (by - cy));
+                    double fx = 0.0, fy = 0.0;
+                    if (d > 0) {
+                        const double m = -(1.0 / psi[c] - g0);
+                        const double u = (rb_dx[d] != 0 && rb_dy[d] != 0) ? inv_sqrt2 : 1.0;
+                        fx = m * ((double)rb_dx[d] * u);
+                        fy = m * ((double)rb_dy[d] * u);
+                    }
+                    const double rx = fx + tx, ry = fy + ty;
+                    const double v = rx * rx + ry * ry;
+                    if (best < 0 || v < bestv) { best = d; bestv = v; }
+                }
+                if (best > 0) {
+                    path[2 * i] = px + rb_dx[best];
+                    path[2 * i + 1] = py + rb_dy[best];
+                }
+            }
+        }
+    }
+}

@@ -10,6 +10,10 @@
 //            inside the window (each step strictly raises psi, so the walk
 //            never revisits a cell) and the window is re-centred when the
 //            walk leaves it.
+//   k_rubber one workgroup relaxes a path as a rubber band (Eqs. 4-6): per
+//            iteration the interior points of odd index, then those of even
+//            index, each move to the best of nine candidate cells given the
+//            positions of their two neighbours (see hpf_rubber_band).
 #include "twg_internal.h"
 
 namespace twg {
@@ -117,7 +121,75 @@ __global__ __launch_bounds__(256) void k_walk(const uint8_t *__restrict__ cls,
     }
 }
 
+// Candidate offsets: stay, E, W, S, N, then the diagonals.
+__constant__ int kRbDx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+__constant__ int kRbDy[9] = {0, 0, 0, 1, -1, 1, 1, -1, -1};
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_rubber(const uint8_t *__restrict__ cls, const T *__restrict__ u,
+                                                 int32_t *__restrict__ path, const int32_t *__restrict__ len,
+                                                 int cap, int nx, int ny, int pitch, double k, int iters)
+{
+    const int n = min(*len, cap);
+    const double inv_sqrt2 = 0.70710678118654752440;
+    for (int it = 0; it < iters; ++it) {
+        for (int color = 1; color >= 0; --color) {
+            // points of this colour read only points of the other colour
+            for (int i = 1 + (color ^ 1) + 2 * (int)threadIdx.x; i + 1 < n; i += 2 * (int)blockDim.x) {
+                const int px = path[2 * i], py = path[2 * i + 1];
+                const int ax = path[2 * i - 2], ay = path[2 * i - 1];
+                const int bx = path[2 * i + 2], by = path[2 * i + 3];
+                const double p0 = (double)u[(size_t)py * pitch + px];
+                if (!(p0 > 0.0)) continue;
+                const double g0 = 1.0 / p0;
+                int best = -1;
+                double bestv = 0.0;
+                for (int d = 0; d < 9; ++d) {
+                    const int cx = px + kRbDx[d], cy = py + kRbDy[d];
+                    if (cx < 0 || cy < 0 || cx >= nx || cy >= ny) continue;
+                    const size_t c = (size_t)cy * pitch + cx;
+                    const double pc = (double)u[c];
+                    if (!walkable(cls[c]) || !(pc > 0.0)) continue;
+                    if (abs(cx - ax) > 1 || abs(cy - ay) > 1 || abs(cx - bx) > 1 || abs(cy - by) > 1) continue;
+                    const double tx = k * (double)((ax - cx) + (bx - cx));
+                    const double ty = k * (double)((ay - cy) + (by - cy));
+                    double fx = 0.0, fy = 0.0;
+                    if (d > 0) {
+                        const double m = -(1.0 / pc - g0);
+                        const double w = (kRbDx[d] != 0 && kRbDy[d] != 0) ? inv_sqrt2 : 1.0;
+                        fx = m * ((double)kRbDx[d] * w);
+                        fy = m * ((double)kRbDy[d] * w);
+                    }
+                    const double rx = fx + tx, ry = fy + ty;
+                    const double v = rx * rx + ry * ry;
+                    if (best < 0 || v < bestv) {
+                        best = d;
+                        bestv = v;
+                    }
+                }
+                if (best > 0) {
+                    path[2 * i] = px + kRbDx[best];
+                    path[2 * i + 1] = py + kRbDy[best];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 }  // namespace
+
+int launch_rubber(const uint8_t *cls, const float *psi, const double *psi64, int32_t *path, const int32_t *len,
+                  int cap, int nx, int ny, int pitch, double k, int iters, hipStream_t st)
+{
+    if (psi64)
+        hipLaunchKernelGGL(k_rubber<double>, dim3(1), dim3(1024), 0, st, cls, psi64, path, len, cap, nx, ny, pitch, k,
+                           iters);
+    else
+        hipLaunchKernelGGL(k_rubber<float>, dim3(1), dim3(1024), 0, st, cls, psi, path, len, cap, nx, ny, pitch, k,
+                           iters);
+    return hipGetLastError() == hipSuccess ? TWG_OK : TWG_EDEVICE;
+}
 
 int launch_index(const uint8_t *cls, const float *psi, const double *psi64, uint8_t *idx, int nx,
                  int ny, int pitch, hipStream_t st)

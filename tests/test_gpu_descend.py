@@ -120,3 +120,35 @@ def test_descent_grade_field_reaches_goal_2048(ctx, orc):
     np.testing.assert_array_equal(p_gpu, p_orc)
     steps = np.abs(np.diff(p_gpu, axis=0)).sum(axis=1)
     assert np.all(steps == 1) and cls[p_gpu[-1][1], p_gpu[-1][0]] == 3
+
+
+@pytest.mark.parametrize("name,idx,k", [("static64", 1, 1.0), ("static64", 6, 0.3), ("warped512", 3, 2.0)])
+def test_rubber_band_parity(ctx, orc, name, idx, k):
+    """The GPU rubber band equals the oracle's on the oracle's field and path
+    (bit-exact: same FP64 arithmetic, same candidate order and colours)."""
+    sc = scenarios.scenario(name, idx, side=128 if name == "warped512" else None)
+    cls_o, _ = orc.rasterize(sc)
+    psi, _ = orc.relax(cls_o, tol=1e-11)
+    st, path = orc.descend(cls_o, psi, sc["robot"])
+    if len(path) < 3:
+        pytest.skip("path too short for a band")
+    print(f"rubber band {name}[{idx}] k={k} n={len(path)}", flush=True)
+    want = orc.rubber_band(cls_o, psi, path, k=k, iters=24)
+    cls = torch.as_tensor(cls_o).cuda()
+    cap = len(path) + 7
+    for fp64 in (True, False):
+        field = psi if fp64 else psi.astype(np.float32)
+        dev_path = torch.zeros((cap, 2), dtype=torch.int32, device="cuda")
+        dev_path[:len(path)] = torch.as_tensor(path).cuda()
+        info = torch.tensor([len(path), st], dtype=torch.int32, device="cuda")
+        f = torch.as_tensor(field).cuda()
+        if fp64:
+            ctx.rubber_band(cls, dev_path, info, psi64=f, k=k, iters=24)
+            ref = want
+        else:
+            ctx.rubber_band(cls, dev_path, info, psi=f, k=k, iters=24)
+            ref = orc.rubber_band(cls_o, field.astype(np.float64), path, k=k, iters=24)
+        torch.cuda.synchronize()
+        got = dev_path.cpu().numpy()
+        assert np.array_equal(got[:len(path)], ref), (name, idx, fp64)
+        assert np.all(got[len(path):] == 0)
