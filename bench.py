@@ -57,6 +57,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-grids leg")
     ap.add_argument("--index", type=int, default=1,
                     help="scenario index (seed 5000 + index); index 0's goal is enclosed by a "
                          "predicted disc, so its field is degenerate (no path)")
@@ -168,6 +169,79 @@ def main():
     roofline_alu = {"bound": "alu", "achieved": round(valu_ach / 1e12, 3), "peak": round(valu_peak / 1e12, 3),
                     "unit": "T VALU lane-instr/s", "frac": round(valu_ach / valu_peak, 4)}
 
+    # ---- learned warm start: network field, then the same FP32 relaxation ----
+    learned = None
+    roofline_mfma = None
+    wpath = os.path.join(ROOT, "paper_1903_07441_amd", "weights", "unet_learn256.npz")
+    if os.path.exists(wpath):
+        from paper_1903_07441_amd import learn
+        params, meta = learn.load_weights(wpath)
+        net = twg.UNet(ctx, torch.as_tensor(params))
+        psi_l = torch.empty_like(psi)
+        el = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        runs = []
+        for i in range(args.warmup + args.steps):
+            el[0].record()
+            net.warm_start(cls, ring, sc["goal"], psi_l)
+            el[1].record()
+            st_l = ctx.relax(cls, psi_l, None, tol=1e-6, init=twg.INIT_KEEP)
+            el[2].record()
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                runs.append((el[0].elapsed_time(el[1]), el[0].elapsed_time(el[2]), st_l["sweeps"]))
+        r = np.median(np.array(runs), axis=0)
+        learned = {"ms_to_residual_1e-6": round(float(r[1]), 3), "ms_network": round(float(r[0]), 3),
+                   "sweeps": int(r[2]), "residual": st_l["residual"],
+                   "speedup_vs_plain": round(float(med[1]) / float(r[1]), 3),
+                   "trained_on": meta.get("recipe"), "weights": os.path.relpath(wpath, ROOT)}
+        # forward FLOPs: 2 * 9 * cin * cout per output pixel and layer (pixels
+        # quartered per level), plus the 1x1 head
+        hp, wp = (ny + 7) // 8 * 8, (nx + 7) // 8 * 8
+        P = hp * wp
+        flops = 2.0 * 9 * (3 * 32 * P + 32 * 64 * P / 4 + 64 * 128 * P / 16 + 128 * 128 * P / 64
+                            + 256 * 64 * P / 16 + 128 * 32 * P / 4 + 64 * 32 * P) + 2.0 * 32 * P
+        ach = flops / (float(r[0]) * 1e-3) / 1e12
+        roofline_mfma = {"bound": "mfma", "achieved": round(ach, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": round(ach / 2500.0, 4), "kernel": "network forward (features + 7 convs + head)",
+                         "flops_per_launch": flops}
+        net.close()
+
+    # ---- batched leg: 256 grids of uneven size, one relaxation call ----
+    batch = None
+    if not args.no_batch:
+        scs = scenarios.batch(256, seed=3000)
+        offs, off = [], 0
+        for b in scs:
+            offs.append(off)
+            off += b["nx"] * b["ny"]
+        bcls = torch.empty(off, dtype=torch.uint8, device=dev)
+        bpsi = torch.empty(off, dtype=torch.float32, device=dev)
+        for b, o in zip(scs, offs):
+            n_b = b["nx"] * b["ny"]
+            ctx.rasterize(b["nx"], b["ny"], b["robot"], b["goal"],
+                          torch.as_tensor(b["pos"], dtype=torch.float64, device=dev).contiguous(),
+                          torch.as_tensor(b["vel"], dtype=torch.float64, device=dev).contiguous(),
+                          torch.as_tensor(b["rad"], dtype=torch.float64, device=dev).contiguous(),
+                          W=b["W"], robot_speed=b["vr"], cls=bcls[o:o + n_b].view(b["ny"], b["nx"]),
+                          want_ring=False)
+        descs = [(b["nx"], b["ny"], b["nx"], o) for b, o in zip(scs, offs)]
+        ctx.relax_batched(bcls, bpsi, descs, tol=1e-6)  # warm-up (captures the pass graph)
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            bst = ctx.relax_batched(bcls, bpsi, descs, tol=1e-6)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - tb0) / reps
+        cu = sum(d[0] * d[1] * st_b["sweeps"] for d, st_b in zip(descs, bst))
+        batch = {"grids": len(scs), "cells": off, "fields_per_s": round(len(scs) / tb, 2),
+                 "ms_per_batch": round(tb * 1e3, 3), "cell_updates_per_s": round(cu / tb, 1),
+                 "converged": sum(1 for st_b in bst if st_b["status"] == twg.OK),
+                 "max_residual": max(st_b["residual"] for st_b in bst),
+                 "workload": "256 grids, sides uniform over {64,128,256,512,1024}, 10-200 moving discs "
+                             "(radius 2-5), FP32 red-black SOR to residual 1e-6 with FP64 residuals"}
+        log(f"batch: {batch}")
+
     # ---- CPU baseline: the oracle on a bounded sample ----
     cpu = None
     if not args.no_cpu:
@@ -204,7 +278,9 @@ def main():
                                "rasterise + FP32 SOR to residual 1e-6 + FP64 SOR polish to a certified "
                                "5e-7, continued until the descent resolves + descent",
                    "grid": [nx, ny], "obstacles": int(len(sc["rad"])), "seed": sc["seed"]},
-        "ms_to_residual_1e-6": {"plain": round(float(med[1]), 3), "learned": None},
+        "ms_to_residual_1e-6": {"plain": round(float(med[1]), 3),
+                                "learned": learned["ms_to_residual_1e-6"] if learned else None},
+        "learned": learned,
         "ms_breakdown": {"rasterize": round(float(med[0]), 3), "plain_relax": round(float(med[1]), 3),
                          "fp64_polish_and_descent_grade": round(float(med[2]), 3),
                          "descent": round(float(med[3]), 3)},
@@ -219,6 +295,8 @@ def main():
                    "omega": round(tuning["omega"], 6)},
         "roofline": roofline,
         "roofline_alu": roofline_alu,
+        "roofline_mfma": roofline_mfma,
+        "batched": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -81,6 +81,12 @@ int32_t twg_ctx_destroy(twg_ctx *ctx);
  * string belongs to ctx and is valid until its next call. */
 const char *twg_last_error(const twg_ctx *ctx);
 
+/* enable = 1 (default): runs of 16 relaxation passes are captured once into a
+ * HIP graph (on a context-owned stream) and replayed on the caller's stream;
+ * enable = 0: every pass is launched on its own.  Results are identical.
+ * Errors: TWG_EINVAL for another value. */
+int32_t twg_ctx_set_graphs(twg_ctx *ctx, int32_t enable);
+
 /* ========================================================================= */
 /* Map update: time rings, prediction, marking                               */
 /* ========================================================================= */
@@ -243,8 +249,10 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
  * and remember, for grids of this exact size, the fastest tiling and an SOR
  * factor; later hpf_relax calls on this context with sweeps_per_pass = 0
  * and omega = 0 use them.  Tilings: sweeps per tile load S in
- * {1, 2, 3, 4, 6, 8} x output rows per tile RH in {8, 16, 32, 64, 128}, each
- * timed with HIP events over repeated passes on context scratch.  Factors:
+ * {1, 2, 3, 4, 6, 8} x output rows per tile RH in {8, 16, 32, 64, 128} plus,
+ * for k = 1..4, the smallest height whose tile count (one wave per tile) fits
+ * k rounds of the device's SIMDs; each timed with HIP events over repeated
+ * passes on context scratch.  Factors:
  * omega = 2 / (1 + c sin(pi / (n + 1))), n = max(nx, ny), c in
  * {0.7, 1, 1.4, 2, 2.8, 4}; the one with the smallest residual after a fixed
  * number of sweeps from the half-initialised field wins (obstacles shrink the
@@ -290,6 +298,26 @@ int32_t hpf_index_matrix(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const flo
 int32_t hpf_descend(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi,
                     const double *psi64, const hpf_descend_params *params, int32_t *path_xy,
                     int32_t *info, void *stream);
+
+/* hpf_rubber_band -- rubber-band smoothing of a path (section "Rubber Band
+ * Model", Eqs. 4-6; Algorithm 1 "Path Planning").  The path's endpoints stay
+ * fixed.  Each of `iters` iterations moves the interior points of odd index,
+ * then those of even index, each to the best of the candidates c = p_i + d,
+ * d in the order (0,0), E, W, S, N, (1,1), (-1,1), (1,-1), (-1,-1): in the
+ * grid, FREE or GOAL, psi(c) > 0, and within one cell (Chebyshev) of both
+ * neighbours, so the band stays 8-connected.  The best candidate minimises
+ * |F + T|^2 with tension T = k ((p_{i-1} - c) + (p_{i+1} - c)) and potential
+ * force F = -(1/psi(c) - 1/psi(p_i)) u, u the unit vector of d (F = 0 for
+ * d = 0; 1/psi = 1/(1 - phi) as in Eq. 6, signed to resist moves towards
+ * obstacles); the first candidate wins a tie.  Arithmetic is FP64 on psi64
+ * if it is not NULL, else on psi widened to FP64.  path_xy (device, int32
+ * (x, y) pairs, capacity cap) is updated in place; its length is read from
+ * device memory at len[0] (e.g. hpf_descend's info).  Asynchronous.
+ * Errors: TWG_EINVAL (bad grid, NULL arrays, cap < 1, iters < 0, k < 0 or
+ * not finite). */
+int32_t hpf_rubber_band(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi, const double *psi64,
+                        int32_t *path_xy, const int32_t *len, int32_t cap, double k, int32_t iters,
+                        void *stream);
 
 /* ========================================================================= */
 /* Learned warm start (not in the paper: an initial field for hpf_relax)     */

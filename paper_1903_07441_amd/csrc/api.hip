@@ -51,6 +51,46 @@ using namespace twg;
 
 namespace {
 
+constexpr int kGraphPasses = 16;  // passes per captured graph (even: ping-pong ends where it began)
+constexpr size_t kMaxGraphs = 16;
+
+// Replay `times` copies of the launch sequence that `record` issues on a
+// stream, as one instantiated graph on `st`.  The graph is captured once per
+// key (the launch arguments) on the context's capture stream and cached.
+template <typename F>
+int graph_replay(twg_ctx *ctx, const std::vector<uintptr_t> &key, hipStream_t st, int64_t times, F record)
+{
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : ctx->graphs)
+        if (g.key == key) exec = g.exec;
+    if (!exec) {
+        if (!ctx->cap && hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) {
+            ctx->cap = nullptr;
+            return TWG_EDEVICE;
+        }
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return TWG_EDEVICE;
+        const int rc = record(ctx->cap);
+        const hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+        if (rc || e != hipSuccess || !graph) {
+            if (graph) hipGraphDestroy(graph);
+            return rc ? rc : TWG_EDEVICE;
+        }
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ei != hipSuccess) return TWG_EDEVICE;
+        if (ctx->graphs.size() >= kMaxGraphs) {
+            hipStreamSynchronize(st);
+            hipGraphExecDestroy(ctx->graphs.front().exec);
+            ctx->graphs.erase(ctx->graphs.begin());
+        }
+        ctx->graphs.push_back({key, exec});
+    }
+    for (int64_t t = 0; t < times; ++t)
+        if (hipGraphLaunch(exec, st) != hipSuccess) return TWG_EDEVICE;
+    return TWG_OK;
+}
+
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 double bits_to_double(unsigned long long b)
@@ -124,15 +164,34 @@ struct Runner {
     }
 
     // `sweeps` FP32 sweeps on a <-> b, S per pass (remainder one per pass);
-    // on return *a holds the newest field.
+    // on return *a holds the newest field.  Runs of kGraphPasses full passes
+    // are replayed from a captured graph.
     int sweep32(float **a, float **b, const float *f, float omega, int S, int RH, int64_t sweeps)
     {
         const Geometry geo = stream_geometry(g.nx, g.ny, S, RH);
         const Geometry geo1 = stream_geometry(g.nx, g.ny, 1, RH);
         int64_t done = 0;
+        const int64_t reps = ctx->use_graphs ? sweeps / ((int64_t)S * kGraphPasses) : 0;
+        if (reps > 0) {
+            const std::vector<uintptr_t> key = {1, (uintptr_t)*a, (uintptr_t)*b, (uintptr_t)cls, (uintptr_t)f,
+                                                (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.pitch,
+                                                (uintptr_t)__builtin_bit_cast(uint32_t, omega), (uintptr_t)S,
+                                                (uintptr_t)RH};
+            float *x = *a, *y = *b;
+            int rc = graph_replay(ctx, key, st, reps, [&](hipStream_t cs) {
+                for (int k = 0; k < kGraphPasses; ++k) {
+                    const int e = launch_stream_f32(k % 2 ? y : x, k % 2 ? x : y, cls, f, g.nx, g.ny, g.pitch,
+                                                    omega, geo, ctx->sink, cs);
+                    if (e) return e;
+                }
+                return TWG_OK;
+            });
+            if (rc) return set_err(ctx, rc, "relaxation graph failed");
+            done = reps * S * kGraphPasses;
+        }
         while (done < sweeps) {
             const bool full = sweeps - done >= S;
-            int rc = launch_stream_f32(*a, *b, cls, f, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, st);
+            int rc = launch_stream_f32(*a, *b, cls, f, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, ctx->sink, st);
             if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
             std::swap(*a, *b);
             done += full ? S : 1;
@@ -231,7 +290,7 @@ struct Runner {
             int64_t chunk = std::max<int64_t>((int64_t)std::ceil(want * 1.05) + S, 8 * S);
             chunk = ((std::min(chunk, max_sweeps - done) + S - 1) / S) * S;
             for (int64_t k = 0; k < chunk; k += S) {
-                rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, geo, st);
+                rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, geo, ctx->sink, st);
                 if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
                 std::swap(a, b);
             }
@@ -275,6 +334,7 @@ int32_t twg_ctx_create(twg_ctx **out, int32_t device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
     if (hipMalloc(&ctx->words, kWords * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&ctx->sink, 1024) != hipSuccess ||
         hipHostMalloc(&ctx->host_words, kWords * sizeof(unsigned long long), hipHostMallocDefault) !=
             hipSuccess) {
         twg_ctx_destroy(ctx);
@@ -289,7 +349,10 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
     if (!ctx) return TWG_EINVAL;
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
-    void *bufs[] = {ctx->alt, ctx->pol, ctx->alt64, ctx->pairs, ctx->idxbuf, ctx->batch, ctx->words};
+    for (auto &g : ctx->graphs) hipGraphExecDestroy(g.exec);
+    ctx->graphs.clear();
+    if (ctx->cap) hipStreamDestroy(ctx->cap);
+    void *bufs[] = {ctx->alt, ctx->pol, ctx->alt64, ctx->pairs, ctx->idxbuf, ctx->batch, ctx->words, ctx->sink};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (ctx->host_words) hipHostFree(ctx->host_words);
@@ -299,6 +362,13 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
 }
 
 const char *twg_last_error(const twg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t twg_ctx_set_graphs(twg_ctx *ctx, int32_t enable)
+{
+    if (!ctx || (enable != 0 && enable != 1)) return TWG_EINVAL;
+    ctx->use_graphs = enable;
+    return TWG_OK;
+}
 
 int32_t twg_rasterize(twg_ctx *ctx, twg_grid g, int32_t n_obs, const double *pos, const double *vel,
                       const double *radius, const uint8_t *static_occ, const twg_raster_params *p,
@@ -532,6 +602,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
         return TWG_OK;
     };
     build_lists(active);
+    const int max_tiles0 = (int)tl.size();
     rc = upload_lists();
     if (!rc) rc = launch_field_init_batch(cls, psi, d_grids, d_blocks, (int)bl.size(), p.init, st);
     if (rc) return set_err(ctx, TWG_EDEVICE, "batch set-up failed");
@@ -589,8 +660,27 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
         }
         chunk = std::min(chunk, p.max_sweeps - done);
         const int64_t passes = (chunk + S - 1) / S;
-        for (int64_t q = 0; q < passes; ++q) {
-            rc = launch_stream_batch(cur, nxt, cls, d_grids, d_tiles, d_count, (int)tl.size(), S, st);
+        // whole runs of kGraphPasses passes replay one captured graph, sized
+        // for the first (largest) tile list: the kernel reads the active tile
+        // count from device memory, so retired grids cost an early exit
+        const int64_t reps = ctx->use_graphs ? passes / kGraphPasses : 0;
+        if (reps > 0) {
+            const std::vector<uintptr_t> key = {2, (uintptr_t)cur, (uintptr_t)nxt, (uintptr_t)cls,
+                                                (uintptr_t)d_grids, (uintptr_t)d_tiles, (uintptr_t)d_count,
+                                                (uintptr_t)max_tiles0, (uintptr_t)S};
+            float *x = cur, *y = nxt;
+            rc = graph_replay(ctx, key, st, reps, [&](hipStream_t cs) {
+                for (int k = 0; k < kGraphPasses; ++k) {
+                    const int e = launch_stream_batch(k % 2 ? y : x, k % 2 ? x : y, cls, d_grids, d_tiles, d_count,
+                                                      max_tiles0, S, ctx->sink, cs);
+                    if (e) return e;
+                }
+                return TWG_OK;
+            });
+            if (rc) return set_err(ctx, rc, "batched relaxation graph failed");
+        }
+        for (int64_t q = reps * kGraphPasses; q < passes; ++q) {
+            rc = launch_stream_batch(cur, nxt, cls, d_grids, d_tiles, d_count, (int)tl.size(), S, ctx->sink, st);
             if (rc) return set_err(ctx, rc, "batched relaxation launch failed");
             std::swap(cur, nxt);
         }
@@ -670,17 +760,29 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
     const double cells = (double)g.nx * g.ny;
     // 1. tiling: fastest cell-update rate
     const int Ss[] = {1, 2, 3, 4, 6, 8};
-    const int RHs[] = {8, 16, 32, 64, 128};
     twg_tuning best;
     const float om0 = (float)omega_open(g.nx, g.ny);
-    for (int S : Ss)
+    const int simds = 4 * std::max(1, ctx->num_cu);
+    for (int S : Ss) {
+        // fixed heights, plus for k = 1..4 the smallest even height whose
+        // wave count (one wave per tile) fits k rounds of the chip's SIMDs
+        std::vector<int> RHs = {8, 16, 32, 64, 128};
+        const int strips = (g.nx + (128 - 4 * S) - 1) / (128 - 4 * S);
+        for (int k = 1; k <= 4; ++k) {
+            const int segs = (k * simds) / strips;
+            if (segs < 1) continue;
+            int RH = (g.ny + segs - 1) / segs;
+            RH += RH & 1;
+            if (RH >= 2 && std::find(RHs.begin(), RHs.end(), RH) == RHs.end()) RHs.push_back(RH);
+        }
         for (int RH : RHs) {
             if (RH > 2 * g.ny && RH > 8) continue;
             rc = launch_fill_f32(a, 0.5f, g.nx, g.ny, g.pitch, st);
             if (!rc) rc = launch_field_init(cls, a, g.nx, g.ny, g.pitch, HPF_INIT_KEEP, st);
             if (rc) break;
             float *x = a, *y = b;
-            rc = run.sweep32(&x, &y, nullptr, om0, S, RH, 2 * S);  // warm-up
+            // warm-up: also captures the pass graph the timed run replays
+            rc = run.sweep32(&x, &y, nullptr, om0, S, RH, (int64_t)kGraphPasses * S);
             if (rc) break;
             // passes for about 2 ms at 1e12 cell-updates/s
             int passes = (int)std::min(400.0, std::max(4.0, 2e9 / (cells * S)));
@@ -694,6 +796,8 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
             const double cups = cells * S * passes / (ms * 1e-3);
             if (cups > best.cups) { best.S = S; best.RH = RH; best.cups = cups; }
         }
+        if (rc) break;
+    }
     // 2. SOR factor: smallest residual after a fixed number of sweeps
     if (!rc) {
         const double pi = 3.14159265358979323846;
@@ -795,7 +899,7 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
     const Geometry geo = stream_geometry(g.nx, g.ny, S, RH), geo1 = stream_geometry(g.nx, g.ny, 1, RH);
     for (int64_t done = 0; done < sweeps;) {
         const bool full = sweeps - done >= S;
-        rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, st);
+        rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, ctx->sink, st);
         if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
         std::swap(a, b);
         done += full ? S : 1;
@@ -863,6 +967,21 @@ int32_t hpf_descend(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *p
     if (!rc) rc = launch_walk(cls, idx, g.nx, g.ny, g.pitch, p->start_x, p->start_y, p->cap, path_xy,
                               info, st);
     return rc ? set_err(ctx, rc, "descent launch failed") : TWG_OK;
+}
+
+int32_t hpf_rubber_band(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi, const double *psi64,
+                        int32_t *path_xy, const int32_t *len, int32_t cap, double k, int32_t iters, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!cls || (!psi && !psi64) || !path_xy || !len) return set_err(ctx, TWG_EINVAL, "missing argument");
+    if (cap < 1) return set_err(ctx, TWG_EINVAL, "cap < 1");
+    if (iters < 0 || !(k >= 0.0) || !std::isfinite(k)) return set_err(ctx, TWG_EINVAL, "need iters >= 0 and finite k >= 0");
+    hipSetDevice(ctx->device);
+    rc = launch_rubber(cls, psi, psi64, path_xy, len, cap, g.nx, g.ny, g.pitch, k, iters, as_stream(stream));
+    return rc ? set_err(ctx, rc, "rubber band launch failed") : TWG_OK;
 }
 
 }  // extern "C"

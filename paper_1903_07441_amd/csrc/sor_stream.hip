@@ -13,7 +13,11 @@
 // half-sweep stages; stage k lags the row loader by k + 1 rows, so every
 // stage sees neighbour rows that are exactly one half-sweep older.  Vertical
 // neighbours come from the rolling register window, horizontal ones from the
-// adjacent lane through wave-wide DPP shifts (no LDS traffic).  Each
+// adjacent lane through wave-wide DPP shifts (no LDS traffic).  The row loop
+// has no per-row branches (its trip count is padded to whole windows, halo
+// lanes store into a sink) and is fenced so that each prefetch stays in its
+// row step: the compiler can then keep the prefetch queue in fixed registers
+// and never has to wait for a load in flight before the window comes round.  Each
 // half-sweep invalidates one column at each edge of the strip, so S lanes on
 // each side are halo and 128 - 4S columns are written; the rows of a tile are
 // likewise extended by 2S halo rows above and below.  Reads come from `src`
@@ -75,7 +79,7 @@ template <typename T, int S, bool RHS>
 __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__restrict__ dst,
                                             const uint8_t *__restrict__ cls,
                                             const T *__restrict__ f, int nx, int ny, int pitch,
-                                            T omega, int x0, int ybeg, int yend)
+                                            T omega, int x0, int ybeg, int yend, T *__restrict__ sink)
 {
     constexpr int NW = 2 * S + 2;      // rolling window of rows (even)
     const int lane = threadIdx.x & (kWave - 1);
@@ -113,56 +117,67 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
         fetch(i, i);
     }
 
-    for (int base = 0; base < T_rows; base += NW) {
+    // the trip count is padded to whole windows so that the unrolled body
+    // has no per-row branches: fetches are unconditional (clamped rows) and
+    // rows past the tile are computed but never stored
+    const int T_pad = ((T_rows + NW - 1) / NW) * NW;
+    for (int base = 0; base < T_pad; base += NW) {
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             const int t = base + u;
-            if (t < T_rows) {
-                const int y = r0 + t;  // parity of y == parity of u
-                T v0 = T(0), v1 = T(0), w0 = T(0), w1 = T(0), f0 = T(0), f1 = T(0);
-                if (y >= 0 && y < ny) {  // uniform
-                    v0 = in0 ? qv0[u] : T(0);
-                    v1 = in1 ? qv1[u] : T(0);
-                    w0 = qc0[u] == TWG_CELL_FREE ? om0 : T(0);
-                    w1 = qc1[u] == TWG_CELL_FREE ? om1 : T(0);
-                    if (RHS) {
-                        f0 = in0 ? qf0[u] : T(0);
-                        f1 = in1 ? qf1[u] : T(0);
-                    }
-                }
-                if (t + NW < T_rows) fetch(u, t + NW);
-                if ((u & 1) == 0) {  // even row: red = first column
-                    R[u] = v0; B[u] = v1; wR[u] = w0; wB[u] = w1; fR[u] = f0; fB[u] = f1;
-                } else {
-                    R[u] = v1; B[u] = v0; wR[u] = w1; wB[u] = w0; fR[u] = f1; fB[u] = f0;
-                }
+            const int y = r0 + t;  // parity of y == parity of u
+            const bool rowok = y >= 0 && y < ny;  // uniform
+            const T v0 = rowok && in0 ? qv0[u] : T(0);
+            const T v1 = rowok && in1 ? qv1[u] : T(0);
+            const T w0 = rowok && qc0[u] == TWG_CELL_FREE ? om0 : T(0);
+            const T w1 = rowok && qc1[u] == TWG_CELL_FREE ? om1 : T(0);
+            T f0 = T(0), f1 = T(0);
+            if (RHS) {
+                f0 = rowok && in0 ? qf0[u] : T(0);
+                f1 = rowok && in1 ? qf1[u] : T(0);
+            }
+            // the slot is refilled only after its values are taken, so the
+            // queue keeps fixed registers across iterations
+            __builtin_amdgcn_sched_barrier(0);
+            fetch(u, t + NW);
+            if ((u & 1) == 0) {  // even row: red = first column
+                R[u] = v0; B[u] = v1; wR[u] = w0; wB[u] = w1; fR[u] = f0; fB[u] = f1;
+            } else {
+                R[u] = v1; B[u] = v0; wR[u] = w1; wB[u] = w0; fR[u] = f1; fB[u] = f0;
+            }
 #pragma unroll
-                for (int k = 0; k < 2 * S; ++k) {
-                    const int s = (u - 1 - k + 4 * NW) % NW;  // slot of row y - 1 - k
-                    const int sp = (s + 1) % NW, sm = (s + NW - 1) % NW;
-                    if ((k & 1) == 0) {
-                        // red half-sweep of sweep k/2 at row y - 1 - k
-                        const T b = B[s];
-                        const T ew = (s & 1) == 0 ? b + shr1(b) : shl1(b) + b;
-                        const T sn = B[sp] + B[sm];
-                        R[s] = upd<RHS>(R[s], ew, sn, wR[s], fR[s]);
-                    } else {
-                        const T r = R[s];
-                        const T ew = (s & 1) == 0 ? shl1(r) + r : r + shr1(r);
-                        const T sn = R[sp] + R[sm];
-                        B[s] = upd<RHS>(B[s], ew, sn, wB[s], fB[s]);
-                    }
-                }
-                const int ys = y - 2 * S;  // row finished by this step (uniform test)
-                if (ys >= ybeg && ys < yend) {
-                    const int s = (u - 2 * S + 4 * NW) % NW;
-                    T *pd = dst + ys * pitch;
-                    const T o0 = (s & 1) == 0 ? R[s] : B[s];
-                    const T o1 = (s & 1) == 0 ? B[s] : R[s];
-                    if (writer && in0) pd[xa] = o0;
-                    if (writer && in1) pd[xa + 1] = o1;
+            for (int k = 0; k < 2 * S; ++k) {
+                const int s = (u - 1 - k + 4 * NW) % NW;  // slot of row y - 1 - k
+                const int sp = (s + 1) % NW, sm = (s + NW - 1) % NW;
+                if ((k & 1) == 0) {
+                    // red half-sweep of sweep k/2 at row y - 1 - k
+                    const T b = B[s];
+                    const T ew = (s & 1) == 0 ? b + shr1(b) : shl1(b) + b;
+                    const T sn = B[sp] + B[sm];
+                    R[s] = upd<RHS>(R[s], ew, sn, wR[s], fR[s]);
+                } else {
+                    const T r = R[s];
+                    const T ew = (s & 1) == 0 ? shl1(r) + r : r + shr1(r);
+                    const T sn = R[sp] + R[sm];
+                    B[s] = upd<RHS>(B[s], ew, sn, wB[s], fB[s]);
                 }
             }
+            const int ys = y - 2 * S;  // row finished by this step (uniform test)
+            if (ys >= ybeg && ys < yend) {
+                const int s = (u - 2 * S + 4 * NW) % NW;
+                T *pd = dst + ys * pitch;
+                const T o0 = (s & 1) == 0 ? R[s] : B[s];
+                const T o1 = (s & 1) == 0 ? B[s] : R[s];
+                // halo lanes and columns outside the grid store into the
+                // sink instead of branching around the store
+                T *p0 = writer && in0 ? pd + xa : sink + 2 * lane;
+                T *p1 = writer && in1 ? pd + xa + 1 : sink + 2 * lane + 1;
+                *p0 = o0;
+                *p1 = o1;
+            }
+            // keep this row's prefetch in this row step: without the fence
+            // the scheduler sinks every prefetch of the window to its end
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
@@ -172,7 +187,7 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
                                                     const uint8_t *__restrict__ cls,
                                                     const T *__restrict__ f, int nx, int ny,
                                                     int pitch, T omega, int strips, int RH,
-                                                    int tiles)
+                                                    int tiles, T *__restrict__ sink)
 {
     constexpr int VW = 128 - 4 * S;  // columns written per strip
     // everything that depends only on the tile is wave-uniform: keep it scalar
@@ -182,7 +197,7 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
     const int strip = tile % strips, seg = tile / strips;
     const int ybeg = seg * RH;
     stream_tile<T, S, RHS>(src, dst, cls, f, nx, ny, pitch, omega, strip * VW - 2 * S, ybeg,
-                           min(ybeg + RH, ny));
+                           min(ybeg + RH, ny), sink);
 }
 
 // Batched form: the tiles of many grids in one launch.  Grid g's arrays start
@@ -194,7 +209,8 @@ __global__ __launch_bounds__(256) void k_sor_stream_batch(const float *__restric
                                                           const uint8_t *__restrict__ cls,
                                                           const BatchGrid *__restrict__ grids,
                                                           const BatchTile *__restrict__ tiles,
-                                                          const int *__restrict__ n_tiles)
+                                                          const int *__restrict__ n_tiles,
+                                                          float *__restrict__ sink)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
@@ -202,18 +218,19 @@ __global__ __launch_bounds__(256) void k_sor_stream_batch(const float *__restric
     const BatchTile t = tiles[tile];
     const BatchGrid g = grids[t.grid];
     stream_tile<float, S, false>(src + g.off, dst + g.off, cls + g.off, nullptr, g.nx, g.ny,
-                                 g.pitch, g.omega, t.x0, t.ybeg, t.yend);
+                                 g.pitch, g.omega, t.x0, t.ybeg, t.yend, sink);
 }
 
 template <typename T, bool RHS>
 int launch_stream(const T *src, T *dst, const uint8_t *cls, const T *f, int nx, int ny, int pitch,
-                  T omega, const Geometry &g, hipStream_t st)
+                  T omega, const Geometry &g, void *sink, hipStream_t st)
 {
     const int blocks = (g.tiles + 3) / 4;
 #define TWG_STREAM_CASE(SV)                                                                     \
     case SV:                                                                                    \
         hipLaunchKernelGGL((k_sor_stream<T, SV, RHS>), dim3(blocks), dim3(256), 0, st, src, dst, \
-                           cls, f, nx, ny, pitch, omega, g.strips, g.RH, g.tiles);              \
+                           cls, f, nx, ny, pitch, omega, g.strips, g.RH, g.tiles,               \
+                           static_cast<T *>(sink));                                              \
         break;
     switch (g.S) {
         TWG_STREAM_CASE(1)
@@ -231,7 +248,7 @@ int launch_stream(const T *src, T *dst, const uint8_t *cls, const T *f, int nx, 
 }  // namespace
 
 int launch_stream_batch(const float *src, float *dst, const uint8_t *cls, const BatchGrid *grids,
-                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S,
+                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S, void *sink,
                         hipStream_t st)
 {
     const int blocks = (max_tiles + 3) / 4;
@@ -239,7 +256,7 @@ int launch_stream_batch(const float *src, float *dst, const uint8_t *cls, const 
 #define TWG_BATCH_CASE(SV)                                                                       \
     case SV:                                                                                     \
         hipLaunchKernelGGL(k_sor_stream_batch<SV>, dim3(blocks), dim3(256), 0, st, src, dst, cls, \
-                           grids, tiles, n_tiles);                                               \
+                           grids, tiles, n_tiles, static_cast<float *>(sink));                   \
         break;
     switch (S) {
         TWG_BATCH_CASE(1)
@@ -269,17 +286,17 @@ Geometry stream_geometry(int nx, int ny, int S, int RH)
 }
 
 int launch_stream_f32(const float *src, float *dst, const uint8_t *cls, const float *f, int nx,
-                      int ny, int pitch, float omega, const Geometry &geo, hipStream_t st)
+                      int ny, int pitch, float omega, const Geometry &geo, void *sink, hipStream_t st)
 {
-    return f ? launch_stream<float, true>(src, dst, cls, f, nx, ny, pitch, omega, geo, st)
-             : launch_stream<float, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, st);
+    return f ? launch_stream<float, true>(src, dst, cls, f, nx, ny, pitch, omega, geo, sink, st)
+             : launch_stream<float, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, sink, st);
 }
 
 int launch_stream_f64(const double *src, double *dst, const uint8_t *cls, const double *f, int nx,
-                      int ny, int pitch, double omega, const Geometry &geo, hipStream_t st)
+                      int ny, int pitch, double omega, const Geometry &geo, void *sink, hipStream_t st)
 {
     if (f) return TWG_EUNSUPPORTED;
-    return launch_stream<double, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, st);
+    return launch_stream<double, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, sink, st);
 }
 
 }  // namespace twg

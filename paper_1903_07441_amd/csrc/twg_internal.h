@@ -7,6 +7,7 @@
 #include <map>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "twg.h"
 
@@ -45,8 +46,19 @@ struct twg_ctx {
     size_t batch_host_bytes = 0;
     // small device words: residual maxima (uint64 bit patterns), counters
     unsigned long long *words = nullptr;
+    // 1 KiB that the relaxation kernels' halo lanes store into (never read)
+    void *sink = nullptr;
     // pinned host mirror of `words`
     unsigned long long *host_words = nullptr;
+    // instantiated graphs of relaxation passes, keyed by their launch
+    // arguments, and the stream they are captured on
+    struct Graph {
+        std::vector<uintptr_t> key;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t cap = nullptr;
+    int use_graphs = 1;
 };
 
 namespace twg {
@@ -65,7 +77,7 @@ struct BatchTile {
 };
 
 int launch_stream_batch(const float *src, float *dst, const uint8_t *cls, const BatchGrid *grids,
-                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S,
+                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S, void *sink,
                         hipStream_t st);
 int launch_resid_batch(const uint8_t *cls, const float *u, const BatchGrid *grids,
                        const int2 *blocks, int n_blocks, unsigned long long *out, int n_words,
@@ -95,10 +107,11 @@ int launch_sweep_color_f32(const uint8_t *cls, float *psi, const float *f, int n
 int launch_sweep_color_f64(const uint8_t *cls, double *psi, const double *f, int nx, int ny,
                            int pitch, double omega, int color, hipStream_t st);
 bool stream_depth_supported(int S);
+// sink: 1 KiB of device memory that the halo lanes' stores go to
 int launch_stream_f32(const float *src, float *dst, const uint8_t *cls, const float *f, int nx,
-                      int ny, int pitch, float omega, const Geometry &geo, hipStream_t st);
+                      int ny, int pitch, float omega, const Geometry &geo, void *sink, hipStream_t st);
 int launch_stream_f64(const double *src, double *dst, const uint8_t *cls, const double *f, int nx,
-                      int ny, int pitch, double omega, const Geometry &geo, hipStream_t st);
+                      int ny, int pitch, double omega, const Geometry &geo, void *sink, hipStream_t st);
 int launch_resid_f32(const uint8_t *cls, const float *u, const float *f, int nx, int ny, int pitch,
                      unsigned long long *out, hipStream_t st);
 int launch_resid_f64(const uint8_t *cls, const double *u, const float *f, int nx, int ny, int pitch,
@@ -123,5 +136,7 @@ int launch_index(const uint8_t *cls, const float *psi, const double *psi64, uint
                  int ny, int pitch, hipStream_t st);
 int launch_walk(const uint8_t *cls, const uint8_t *idx, int nx, int ny, int pitch, int sx, int sy,
                 int cap, int32_t *path, int32_t *info, hipStream_t st);
+int launch_rubber(const uint8_t *cls, const float *psi, const double *psi64, int32_t *path, const int32_t *len,
+                  int cap, int nx, int ny, int pitch, double k, int iters, hipStream_t st);
 
 }  // namespace twg

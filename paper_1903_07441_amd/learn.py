@@ -130,58 +130,61 @@ def train(net, data, epochs=4, batch=16, lr=1e-3, lr_min=2e-5, log_every=100):
     return hist, (time.perf_counter() - t0) / max(1, total)
 
 
-def evaluate(ctx, net, data, tol=1e-6, reps=1):
+LEARNED_OMEGAS = (1.0, 1.3, 1.6, 1.8, 1.9, 0.0)  # 0 = the plain path's factor
+
+
+def evaluate(ctx, net, data, tol=1e-6, omegas=LEARNED_OMEGAS):
     """Relax every scenario of `data` to `tol` from the plain initial fields
-    (half and zero) and from the network's field; per-scenario sweeps and
-    times (the learned time includes features and network)."""
+    (half and zero, the plain path's SOR factor) and from the network's field
+    with each SOR factor of `omegas`; per-mode median sweeps and times (the
+    learned time includes features and network).  A warm start's error is
+    mostly short-wavelength, which small factors damp fastest, so the learned
+    path gets its own factor."""
     n, H, W = data["cls"].shape
     dev = data["cls"].device
     psi = torch.empty((H, W), dtype=torch.float32, device=dev)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    out = {"half": [], "zero": [], "learned": [], "net_ms": [], "net_err": []}
+    modes = ["half", "zero"] + [f"learned_w{w:g}" for w in omegas]
+    out = {m: [] for m in modes}
+    net_ms, net_err = [], []
     for k in range(n):
         cls, ring, goal = data["cls"][k], data["ring"][k], data["goals"][k]
         for mode, init in (("half", twg.INIT_HALF), ("zero", twg.INIT_ZERO)):
-            best = None
-            for _ in range(reps):
-                ev0.record()
-                st = ctx.relax(cls, psi, None, tol=tol, init=init)
-                ev1.record()
-                torch.cuda.synchronize()
-                ms = ev0.elapsed_time(ev1)
-                best = ms if best is None else min(best, ms)
-            out[mode].append((st["sweeps"], best, st["residual"]))
-        best = None
-        for _ in range(reps):
             ev0.record()
-            net.warm_start(cls, ring, goal, psi)
+            st = ctx.relax(cls, psi, None, tol=tol, init=init)
             ev1.record()
             torch.cuda.synchronize()
-            net_ms = ev0.elapsed_time(ev1)
-            if "target" in data:
-                free = cls == twg.FREE
-                out["net_err"].append(float((psi - data["target"][k]).abs()[free].max().item()))
+            out[mode].append((st["sweeps"], ev0.elapsed_time(ev1), st["residual"]))
+        ev0.record()
+        net.warm_start(cls, ring, goal, psi)
+        ev1.record()
+        torch.cuda.synchronize()
+        net_ms.append(ev0.elapsed_time(ev1))
+        if "target" in data:
+            free = cls == twg.FREE
+            net_err.append(float((psi - data["target"][k]).abs()[free].max().item()))
+        for w in omegas:
             ev0.record()
             net.warm_start(cls, ring, goal, psi)
-            st = ctx.relax(cls, psi, None, tol=tol, init=twg.INIT_KEEP)
+            st = ctx.relax(cls, psi, None, tol=tol, init=twg.INIT_KEEP, omega=w)
             ev1.record()
             torch.cuda.synchronize()
-            ms = ev0.elapsed_time(ev1)
-            best = ms if best is None else min(best, ms)
-        out["learned"].append((st["sweeps"], best, st["residual"]))
-        out["net_ms"].append(net_ms)
+            out[f"learned_w{w:g}"].append((st["sweeps"], ev0.elapsed_time(ev1), st["residual"]))
     summ = {}
-    for mode in ("half", "zero", "learned"):
+    for mode in modes:
         a = np.array(out[mode])
         summ[mode] = {"median_sweeps": float(np.median(a[:, 0])), "median_ms": float(np.median(a[:, 1])),
                       "max_residual": float(np.max(a[:, 2]))}
-    summ["net_median_ms"] = float(np.median(out["net_ms"]))
-    if out["net_err"]:
-        summ["net_median_max_err"] = float(np.median(out["net_err"]))
-    best_plain = min(summ["half"]["median_sweeps"], summ["zero"]["median_sweeps"])
-    summ["sweep_ratio_plain_over_learned"] = best_plain / max(1.0, summ["learned"]["median_sweeps"])
+    summ["net_median_ms"] = float(np.median(net_ms))
+    if net_err:
+        summ["net_median_max_err"] = float(np.median(net_err))
+    best = min((summ[f"learned_w{w:g}"]["median_ms"], w) for w in omegas)
+    summ["learned_best_omega"] = best[1]
+    summ["learned"] = summ[f"learned_w{best[1]:g}"]
     best_plain_ms = min(summ["half"]["median_ms"], summ["zero"]["median_ms"])
+    best_plain_sw = min(summ["half"]["median_sweeps"], summ["zero"]["median_sweeps"])
     summ["time_ratio_plain_over_learned"] = best_plain_ms / max(1e-9, summ["learned"]["median_ms"])
+    summ["sweep_ratio_plain_over_learned"] = best_plain_sw / max(1.0, summ["learned"]["median_sweeps"])
     return summ
 
 

@@ -63,6 +63,7 @@ def _load():
         "twg_ctx_create": (i32, [P(vp), i32]),
         "twg_ctx_destroy": (i32, [vp]),
         "twg_last_error": (ctypes.c_char_p, [vp]),
+        "twg_ctx_set_graphs": (i32, [vp, i32]),
         "twg_rasterize": (i32, [vp, Grid, i32, vp, vp, vp, vp, P(RasterParams), vp, vp, vp]),
         "hpf_relax": (i32, [vp, Grid, vp, vp, vp, P(HpfParams), P(HpfStats), vp]),
         "hpf_sweeps": (i32, [vp, Grid, vp, vp, vp, f32, i32, i32, i32, vp]),
@@ -72,6 +73,7 @@ def _load():
         "hpf_sweeps64": (i32, [vp, Grid, vp, vp, f64, i32, i32, i32, vp]),
         "hpf_index_matrix": (i32, [vp, Grid, vp, vp, vp, vp, vp]),
         "hpf_descend": (i32, [vp, Grid, vp, vp, vp, P(DescendParams), vp, vp, vp]),
+        "hpf_rubber_band": (i32, [vp, Grid, vp, vp, vp, vp, vp, i32, f64, i32, vp]),
         "twg_unet_num_params": (i32, []),
         "twg_unet_create": (i32, [vp, P(vp)]),
         "twg_unet_destroy": (i32, [vp]),
@@ -91,9 +93,10 @@ def _load():
 
 
 lib = _load()
-EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error", "twg_rasterize",
+EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error", "twg_ctx_set_graphs",
+            "twg_rasterize",
             "hpf_relax", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
-            "hpf_index_matrix", "hpf_descend", "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
+            "hpf_index_matrix", "hpf_descend", "hpf_rubber_band", "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
             "twg_unet_set_params", "twg_unet_get_params", "twg_unet_forward", "twg_unet_loss_grad",
             "twg_unet_adam_step", "twg_unet_features", "twg_unet_warm_start")
 
@@ -149,6 +152,11 @@ class Context:
             msg = lib.twg_last_error(self.h)
             raise TwgError(rc, msg.decode() if msg else "")
         return rc
+
+    def set_graphs(self, enable: bool):
+        """Replay relaxation passes from captured HIP graphs (default) or
+        launch them one by one."""
+        self._check(lib.twg_ctx_set_graphs(self.h, int(bool(enable))))
 
     @staticmethod
     def grid(nx, ny, pitch):
@@ -275,6 +283,23 @@ class Context:
                              ctypes.byref(p), _ptr(path), _ptr(info), _stream())
         self._check(rc)
         return path, info
+
+
+def _rubber(ctx, cls, psi, psi64, path, info, k, iters):
+    t = psi if psi is not None else psi64
+    nx, ny, pitch = _grid_of(t)
+    if path.dtype != torch.int32 or path.dim() != 2 or path.shape[1] != 2 or not path.is_contiguous():
+        raise ValueError("path must be a contiguous int32 [cap, 2] device tensor")
+    if info.dtype != torch.int32 or info.numel() < 1:
+        raise ValueError("info must hold the path length as int32")
+    rc = lib.hpf_rubber_band(ctx.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(psi64), _ptr(path), _ptr(info),
+                             int(path.shape[0]), float(k), int(iters), _stream())
+    ctx._check(rc)
+    return path
+
+
+Context.rubber_band = lambda self, cls, path, info, psi=None, psi64=None, k=1.0, iters=16: _rubber(
+    self, cls, psi, psi64, path, info, k, iters)
 
 
 class UNet:

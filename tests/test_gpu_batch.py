@@ -56,6 +56,28 @@ def test_batch_matches_solo_and_converges(ctx, orc, pad):
         assert np.array_equal(solo.cpu().numpy(), got[k]), k
 
 
+def test_batch_graphs_equal_eager(ctx, orc):
+    """The batched relaxation gives identical fields and statistics with its
+    passes replayed from a captured graph and launched one by one."""
+    sides = [64, 256, 128, 512, 96]
+    classes = [orc.rasterize(scenarios.scenario("batch", seed=3100 + k, side=n))[0] for k, n in enumerate(sides)]
+    flat_c, descs = pack(classes, 0)
+    cls = torch.as_tensor(flat_c).cuda()
+    out = []
+    try:
+        for graphs in (False, True, True):
+            ctx.set_graphs(graphs)
+            psi = torch.zeros(len(flat_c), dtype=torch.float32, device="cuda")
+            st = ctx.relax_batched(cls, psi, descs, tol=1e-6, sweeps_per_pass=2)
+            torch.cuda.synchronize()
+            out.append((psi.cpu().numpy(), [(s["sweeps"], s["residual"], s["status"]) for s in st]))
+    finally:
+        ctx.set_graphs(True)
+    for psi, st in out[1:]:
+        assert np.array_equal(psi, out[0][0])
+        assert st == out[0][1]
+
+
 def test_batch_rejects_bad_arguments(ctx):
     from paper_1903_07441_amd import twg
     cls = torch.zeros(100, dtype=torch.uint8, device="cuda")
