@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-grids leg")
+    ap.add_argument("--loop-steps", type=int, default=20,
+                    help="replanning-loop steps after the first (0 = skip the loop leg)")
     ap.add_argument("--index", type=int, default=1,
                     help="scenario index (seed 5000 + index); index 0's goal is enclosed by a "
                          "predicted disc, so its field is degenerate (no path)")
@@ -206,6 +208,73 @@ def main():
                          "flops_per_launch": flops}
         net.close()
 
+    # ---- replanning loop: the robot advances one cell along its path per
+    # step, obstacles move at constant velocity; each step is warm-started from
+    # the previous step's field (and the network, where the map changed) and
+    # compared with a cold solve of the same map ----
+    loop = None
+    if args.loop_steps > 0:
+        net_l = None
+        if learned is not None:
+            from paper_1903_07441_amd import learn as _learn
+            net_l = twg.UNet(ctx, torch.as_tensor(_learn.load_weights(wpath)[0]))
+        pos0 = np.asarray(sc["pos"], dtype=np.float64)
+        vel0 = np.asarray(sc["vel"], dtype=np.float64)
+        robot = [int(sc["robot"][0]), int(sc["robot"][1])]
+        cls_prev = torch.empty_like(cls)
+        psi_prev = torch.empty_like(psi)
+        cls_k = torch.empty_like(cls)
+        ring_k = torch.empty_like(ring)
+        psi_k = torch.empty_like(psi)
+        psi_c = torch.empty_like(psi)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        warm, cold, warm_sw, cold_sw, reached = [], [], [], [], 0
+        for k in range(args.loop_steps + 1):
+            pk = torch.as_tensor(pos0 + k * vel0, dtype=torch.float64, device=dev).contiguous()
+            e[0].record()
+            ctx.rasterize(nx, ny, robot, sc["goal"], pk, vel, rad, W=sc["W"], robot_speed=sc["vr"],
+                          cls=cls_k, ring=ring_k)
+            if net_l is not None:
+                net_l.warm_start(cls_k, ring_k, sc["goal"], psi_k)
+            else:
+                ctx.init_field(cls_k, psi_k, twg.INIT_HALF)
+            if k > 0:
+                ctx.merge_previous(cls_k, cls_prev, psi_prev, psi_k)
+            st_w = ctx.relax(cls_k, psi_k, None, tol=1e-6, init=twg.INIT_KEEP)
+            ctx.descend(cls_k, psi=psi_k, start=robot, cap=cap, path=path, info=info)
+            e[1].record()
+            # the same map solved cold, for comparison
+            e[2].record()
+            st_c = ctx.relax(cls_k, psi_c, None, tol=1e-6, init=twg.INIT_HALF)
+            e[3].record()
+            torch.cuda.synchronize()
+            n_k, s_k = info.cpu().tolist()
+            if k > 0:
+                warm.append(e[0].elapsed_time(e[1]))
+                cold.append(e[2].elapsed_time(e[3]))
+                warm_sw.append(st_w["sweeps"])
+                cold_sw.append(st_c["sweeps"])
+                reached += int(s_k == twg.OK)
+            if s_k == twg.OK and n_k > 1:
+                robot = [int(v) for v in path[1].cpu().tolist()]
+            cls_prev, cls_k = cls_k, cls_prev
+            psi_prev, psi_k = psi_k, psi_prev
+        w, c = np.array(warm), np.array(cold)
+        loop = {"steps": args.loop_steps,
+                "warm_ms_p50": round(float(np.percentile(w, 50)), 3),
+                "warm_ms_p95": round(float(np.percentile(w, 95)), 3),
+                "warm_ms_max": round(float(w.max()), 3),
+                "cold_relax_ms_p50": round(float(np.percentile(c, 50)), 3),
+                "warm_sweeps_p50": int(np.median(warm_sw)), "cold_sweeps_p50": int(np.median(cold_sw)),
+                "speedup_relax_p50": round(float(np.percentile(c, 50) / np.percentile(w, 50)), 3),
+                "descent_reached_goal": f"{reached}/{args.loop_steps}",
+                "warm_start": ("previous field + network where the map changed" if net_l is not None
+                               else "previous field + 0.5 where the map changed"),
+                "step": "rasterise + warm start + FP32 relax to residual 1e-6 + descent (FP32 field)"}
+        log(f"loop: {loop}")
+        if net_l is not None:
+            net_l.close()
+
     # ---- batched leg: 256 grids of uneven size, one relaxation call ----
     batch = None
     if not args.no_batch:
@@ -297,6 +366,7 @@ def main():
         "roofline_alu": roofline_alu,
         "roofline_mfma": roofline_mfma,
         "batched": batch,
+        "replan_loop": loop,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

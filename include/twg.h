@@ -227,6 +227,20 @@ typedef struct {
 int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, const uint8_t *cls,
                           float *psi, const hpf_params *params, hpf_stats *stats, void *stream);
 
+/* hpf_init_field -- the initial field of hpf_relax without relaxing: OBST
+ * and WALL cells 0, GOAL 1, FIXED unchanged, FREE cells by `init`
+ * (HPF_INIT_*; KEEP leaves them).  Asynchronous.  Errors: TWG_EINVAL. */
+int32_t hpf_init_field(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, int32_t init, void *stream);
+
+/* hpf_merge_previous -- warm start of a replanning step from the previous
+ * step's field: every cell that is FREE in cls and was FREE in cls_prev takes
+ * psi_prev's value; all other cells of psi are left as they are (so a
+ * network warm start, or Dirichlet values, written to psi beforehand remain
+ * where the map changed).  All arrays device, pitch g.pitch.  Asynchronous.
+ * Errors: TWG_EINVAL. */
+int32_t hpf_merge_previous(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const uint8_t *cls_prev,
+                           const float *psi_prev, float *psi, void *stream);
+
 /* hpf_sweeps -- exactly `sweeps` red-black SOR sweeps of the same update as
  * hpf_relax, with an optional FP32 source f (psi + omega (avg4(psi) + f - psi);
  * NULL = 0), no convergence test.  tiled = 0 runs one launch per colour

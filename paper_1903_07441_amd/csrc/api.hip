@@ -984,4 +984,30 @@ int32_t hpf_rubber_band(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const floa
     return rc ? set_err(ctx, rc, "rubber band launch failed") : TWG_OK;
 }
 
+int32_t hpf_merge_previous(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const uint8_t *cls_prev,
+                           const float *psi_prev, float *psi, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!cls || !cls_prev || !psi_prev || !psi) return set_err(ctx, TWG_EINVAL, "missing argument");
+    hipSetDevice(ctx->device);
+    rc = launch_merge_prev(cls, cls_prev, psi_prev, psi, g.nx, g.ny, g.pitch, as_stream(stream));
+    return rc ? set_err(ctx, rc, "merge launch failed") : TWG_OK;
+}
+
+int32_t hpf_init_field(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, int32_t init, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!cls || !psi) return set_err(ctx, TWG_EINVAL, "missing argument");
+    if (init < HPF_INIT_KEEP || init > HPF_INIT_ZERO) return set_err(ctx, TWG_EINVAL, "bad init mode");
+    hipSetDevice(ctx->device);
+    rc = launch_field_init(cls, psi, g.nx, g.ny, g.pitch, init, as_stream(stream));
+    return rc ? set_err(ctx, rc, "init launch failed") : TWG_OK;
+}
+
 }  // extern "C"

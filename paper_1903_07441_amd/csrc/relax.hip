@@ -164,6 +164,19 @@ __global__ void k_copy_batch(const float *__restrict__ s, float *__restrict__ d,
     }
 }
 
+// Warm start from a previous field: FREE cells that were FREE in the
+// previous step take the previous value; every other cell keeps psi.
+__global__ void k_merge_prev(const uint8_t *__restrict__ cls, const uint8_t *__restrict__ cls_prev,
+                             const float *__restrict__ psi_prev, float *__restrict__ psi, int nx, int ny,
+                             int pitch)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= nx || y >= ny) return;
+    const size_t i = (size_t)y * pitch + x;
+    if (cls[i] == TWG_CELL_FREE && cls_prev[i] == TWG_CELL_FREE) psi[i] = psi_prev[i];
+}
+
 // ---- element-wise helpers --------------------------------------------------
 __global__ void k_field_init(const uint8_t *__restrict__ cls, float *psi, int nx, int ny, int pitch,
                              int mode)
@@ -375,6 +388,14 @@ int launch_fill_f32(float *a, float v, int nx, int ny, int pitch, hipStream_t st
 int launch_copy_f32(const float *src, float *dst, int nx, int ny, int pitch, hipStream_t st)
 {
     hipLaunchKernelGGL(k_copy, cell_grid(nx, ny), dim3(256), 0, st, src, dst, nx, ny, pitch);
+    return last_status();
+}
+
+int launch_merge_prev(const uint8_t *cls, const uint8_t *cls_prev, const float *psi_prev, float *psi, int nx,
+                      int ny, int pitch, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_merge_prev, cell_grid(nx, ny), dim3(256), 0, st, cls, cls_prev, psi_prev, psi, nx, ny,
+                       pitch);
     return last_status();
 }
 

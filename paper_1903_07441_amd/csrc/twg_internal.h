@@ -125,6 +125,8 @@ int launch_narrow(const double *u, float *psi, int nx, int ny, int pitch, hipStr
 int launch_fill_f32(float *a, float v, int nx, int ny, int pitch, hipStream_t st);
 int launch_copy_f32(const float *src, float *dst, int nx, int ny, int pitch, hipStream_t st);
 int launch_zero_words(unsigned long long *w, int n, hipStream_t st);
+int launch_merge_prev(const uint8_t *cls, const uint8_t *cls_prev, const float *psi_prev, float *psi, int nx,
+                      int ny, int pitch, hipStream_t st);
 
 // raster.hip
 int launch_rasterize(twg_ctx *ctx, const twg_grid &g, int n_obs, const double *pos,

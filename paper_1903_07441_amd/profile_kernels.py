@@ -1,4 +1,5 @@
-"""Drive the relaxation kernel alone, for profilers.
+"""Drive the relaxation kernel (default) or the network kernels (--net)
+alone, for profilers.
 
 Rasterises a 2048 x 2048 replanning scenario, tunes the tiling, then runs
 `--passes` passes of the streamed SOR kernel, followed by one device copy of
@@ -7,6 +8,10 @@ many bytes) so that hardware byte counters can be calibrated against it.
 
     rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_1903_07441_amd.profile_kernels
     rocprofv3 --pmc FETCH_SIZE -d OUT -- python -m paper_1903_07441_amd.profile_kernels
+
+With --net: `--passes` warm starts (features + forward + head) of the
+network on the rasterised grid, then `--passes` training steps (forward,
+backward, Adam) on a batch of 16 random 256 x 256 inputs.
 """
 from __future__ import annotations
 
@@ -24,6 +29,7 @@ def main(argv=None):
     ap.add_argument("--index", type=int, default=1)
     ap.add_argument("--passes", type=int, default=50)
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--net", action="store_true", help="profile the network kernels instead")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -35,6 +41,29 @@ def main(argv=None):
     rad = torch.as_tensor(sc["rad"], dtype=torch.float64, device=dev).contiguous()
     cls, _ = ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"],
                            robot_speed=sc["vr"], want_ring=False)
+    if args.net:
+        import numpy as np
+        from . import learn
+        net = twg.UNet(ctx, torch.as_tensor(learn.he_init(0)))
+        ring = torch.empty((ny, nx), dtype=torch.uint16, device=dev)
+        ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"], robot_speed=sc["vr"],
+                      cls=cls, ring=ring)
+        psi = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+        for _ in range(args.passes):
+            net.warm_start(cls, ring, sc["goal"], psi)
+        rng = np.random.default_rng(0)
+        B, H = 16, 256
+        x = torch.as_tensor(rng.uniform(0, 1, (B, H, H, 3)), dtype=torch.float32, device=dev)
+        t = torch.as_tensor(rng.uniform(0, 1, (B, H, H)), dtype=torch.float32, device=dev)
+        c = torch.zeros((B, H, H), dtype=torch.uint8, device=dev)
+        for _ in range(args.passes):
+            net.train_step(x, t, c, 1e-4)
+        torch.cuda.synchronize()
+        print(f"profiled {args.passes} warm starts on {nx}x{ny} and {args.passes} training steps "
+              f"(batch {B}, {H}x{H})", flush=True)
+        net.close()
+        ctx.close()
+        return 0
     tune = ctx.autotune(cls)
     psi = torch.full((ny, nx), 0.5, dtype=torch.float32, device=dev)
     ctx.sweeps(cls, psi, tune["omega"], 2 * tune["S"] * args.passes, sweeps_per_pass=tune["S"])

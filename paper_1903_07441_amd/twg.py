@@ -74,6 +74,8 @@ def _load():
         "hpf_index_matrix": (i32, [vp, Grid, vp, vp, vp, vp, vp]),
         "hpf_descend": (i32, [vp, Grid, vp, vp, vp, P(DescendParams), vp, vp, vp]),
         "hpf_rubber_band": (i32, [vp, Grid, vp, vp, vp, vp, vp, i32, f64, i32, vp]),
+        "hpf_merge_previous": (i32, [vp, Grid, vp, vp, vp, vp, vp]),
+        "hpf_init_field": (i32, [vp, Grid, vp, vp, i32, vp]),
         "twg_unet_num_params": (i32, []),
         "twg_unet_create": (i32, [vp, P(vp)]),
         "twg_unet_destroy": (i32, [vp]),
@@ -96,7 +98,8 @@ lib = _load()
 EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error", "twg_ctx_set_graphs",
             "twg_rasterize",
             "hpf_relax", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
-            "hpf_index_matrix", "hpf_descend", "hpf_rubber_band", "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
+            "hpf_index_matrix", "hpf_descend", "hpf_rubber_band", "hpf_merge_previous",
+            "hpf_init_field", "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
             "twg_unet_set_params", "twg_unet_get_params", "twg_unet_forward", "twg_unet_loss_grad",
             "twg_unet_adam_step", "twg_unet_features", "twg_unet_warm_start")
 
@@ -298,6 +301,26 @@ def _rubber(ctx, cls, psi, psi64, path, info, k, iters):
     return path
 
 
+def _merge_previous(ctx, cls, cls_prev, psi_prev, psi):
+    nx, ny, pitch = _grid_of(psi)
+    for t in (cls, cls_prev, psi_prev):
+        if t.stride(0) != pitch:
+            raise ValueError("all maps must share psi's pitch")
+    ctx._check(lib.hpf_merge_previous(ctx.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(cls_prev), _ptr(psi_prev),
+                                      _ptr(psi), _stream()))
+    return psi
+
+
+def _init_field(ctx, cls, psi, init=INIT_HALF):
+    nx, ny, pitch = _grid_of(psi)
+    if cls.stride(0) != pitch:
+        raise ValueError("class map must share psi's pitch")
+    ctx._check(lib.hpf_init_field(ctx.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), int(init), _stream()))
+    return psi
+
+
+Context.merge_previous = _merge_previous
+Context.init_field = _init_field
 Context.rubber_band = lambda self, cls, path, info, psi=None, psi64=None, k=1.0, iters=16: _rubber(
     self, cls, psi, psi64, path, info, k, iters)
 
