@@ -254,8 +254,8 @@ int32_t hpf_sweeps(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, con
  * psi64, the update evaluated unfused in the order of the definition
  * (g = ((E + W) + (S + N)) * 0.25, psi + omega * (g - psi)), so one sweep
  * matches a plain FP64 sweep bit for bit.  tiled = 0: one launch per colour;
- * tiled = 1: sweeps_per_pass (1, 2, 3, 4, 6 or 8; 0 = 4) sweeps per tile
- * load, bit-identical.  Asynchronous.  Errors: TWG_EINVAL. */
+ * tiled = 1: sweeps_per_pass (1, 2, 3, 4, 6 or 8; 0 = the autotuned FP64
+ * tiling of this grid size, else 4) sweeps per tile load, bit-identical.  Asynchronous.  Errors: TWG_EINVAL. */
 int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64, double omega,
                      int32_t sweeps, int32_t tiled, int32_t sweeps_per_pass, void *stream);
 
@@ -271,7 +271,10 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
  * {0.7, 1, 1.4, 2, 2.8, 4}; the one with the smallest residual after a fixed
  * number of sweeps from the half-initialised field wins (obstacles shrink the
  * effective domain, so the best factor is below the open-rectangle one).
- * out (host, optional) receives [S, RH, omega, cell-updates per second].
+ * The FP64 sweeps (polish, hpf_sweeps64 with sweeps_per_pass = 0) get their
+ * own tiling the same way, S in {2, 3, 4, 6, 8}.
+ * out (host, optional, 7 doubles) receives [S, RH, omega, cell-updates per
+ * second, S64, RH64, FP64 cell-updates per second].
  * Blocking.  Errors: TWG_EINVAL, TWG_ENOMEM, TWG_EDEVICE. */
 int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, void *stream);
 

@@ -134,6 +134,36 @@ void tiling_for(twg_ctx *ctx, int nx, int ny, int *S, int *RH, float *omega)
     }
 }
 
+// Tile heights to try for S sweeps per load: a fixed set plus, for k = 1..kmax,
+// the smallest even height whose tile count (one wave per tile) fits k rounds
+// of the device's SIMDs.
+std::vector<int> tile_heights(const twg_ctx *ctx, int nx, int ny, int S, int kmax)
+{
+    std::vector<int> RHs = {8, 16, 32, 64, 128};
+    const int simds = 4 * std::max(1, ctx->num_cu);
+    const int strips = (nx + (128 - 4 * S) - 1) / (128 - 4 * S);
+    for (int k = 1; k <= kmax; ++k) {
+        const int segs = (k * simds) / strips;
+        if (segs < 1) continue;
+        int RH = (ny + segs - 1) / segs;
+        RH += RH & 1;
+        if (RH >= 2 && std::find(RHs.begin(), RHs.end(), RH) == RHs.end()) RHs.push_back(RH);
+    }
+    return RHs;
+}
+
+// FP64 tiling for a grid: the autotuned one, else 4 sweeps per load and 32 rows
+void tiling64_for(twg_ctx *ctx, int nx, int ny, int *S, int *RH)
+{
+    *S = 4;
+    *RH = 32;
+    auto it = ctx->tuned.find({nx, ny});
+    if (it != ctx->tuned.end() && it->second.S64 > 0) {
+        *S = it->second.S64;
+        *RH = it->second.RH64;
+    }
+}
+
 struct Runner {
     twg_ctx *ctx;
     twg_grid g;
@@ -272,7 +302,8 @@ struct Runner {
     {
         int rc = ensure(ctx, &ctx->alt64, &ctx->alt64_bytes, (size_t)g.pitch * g.ny * sizeof(double));
         if (rc) return rc;
-        constexpr int S = 4, RH = 32;
+        int S, RH;
+        tiling64_for(ctx, g.nx, g.ny, &S, &RH);
         const Geometry geo = stream_geometry(g.nx, g.ny, S, RH);
         double *a = field, *b = reinterpret_cast<double *>(ctx->alt64);
         double r;
@@ -762,20 +793,8 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
     const int Ss[] = {1, 2, 3, 4, 6, 8};
     twg_tuning best;
     const float om0 = (float)omega_open(g.nx, g.ny);
-    const int simds = 4 * std::max(1, ctx->num_cu);
     for (int S : Ss) {
-        // fixed heights, plus for k = 1..4 the smallest even height whose
-        // wave count (one wave per tile) fits k rounds of the chip's SIMDs
-        std::vector<int> RHs = {8, 16, 32, 64, 128};
-        const int strips = (g.nx + (128 - 4 * S) - 1) / (128 - 4 * S);
-        for (int k = 1; k <= 4; ++k) {
-            const int segs = (k * simds) / strips;
-            if (segs < 1) continue;
-            int RH = (g.ny + segs - 1) / segs;
-            RH += RH & 1;
-            if (RH >= 2 && std::find(RHs.begin(), RHs.end(), RH) == RHs.end()) RHs.push_back(RH);
-        }
-        for (int RH : RHs) {
+        for (int RH : tile_heights(ctx, g.nx, g.ny, S, 4)) {
             if (RH > 2 * g.ny && RH > 8) continue;
             rc = launch_fill_f32(a, 0.5f, g.nx, g.ny, g.pitch, st);
             if (!rc) rc = launch_field_init(cls, a, g.nx, g.ny, g.pitch, HPF_INIT_KEEP, st);
@@ -798,7 +817,42 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
         }
         if (rc) break;
     }
-    // 2. SOR factor: smallest residual after a fixed number of sweeps
+    // 2. FP64 tiling (the polish sweeps), on a widened copy of the field
+    if (!rc) {
+        rc = ensure(ctx, &ctx->alt64, &ctx->alt64_bytes, n32 * sizeof(double));
+        if (!rc) rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, n32 * sizeof(double));
+        double *a64 = reinterpret_cast<double *>(ctx->pol), *b64 = reinterpret_cast<double *>(ctx->alt64);
+        if (!rc) rc = launch_fill_f32(b, 0.5f, g.nx, g.ny, g.pitch, st);
+        if (!rc) rc = launch_field_init(cls, b, g.nx, g.ny, g.pitch, HPF_INIT_KEEP, st);
+        if (!rc) rc = launch_widen(b, a64, g.nx, g.ny, g.pitch, st);
+        const int Ss64[] = {2, 3, 4, 6, 8};
+        for (int S : Ss64) {
+            if (rc) break;
+            for (int RH : tile_heights(ctx, g.nx, g.ny, S, 3)) {
+                if (RH > 2 * g.ny && RH > 8) continue;
+                const Geometry geo = stream_geometry(g.nx, g.ny, S, RH);
+                int passes = (int)std::min(200.0, std::max(4.0, 1e9 / (cells * S)));
+                passes += passes & 1;
+                double *x = a64, *y = b64;
+                for (int k = 0; k < 2 && !rc; ++k) {  // warm-up
+                    rc = launch_stream_f64(x, y, cls, nullptr, g.nx, g.ny, g.pitch, (double)om0, geo, ctx->sink, st);
+                    std::swap(x, y);
+                }
+                hipEventRecord(e0, st);
+                for (int k = 0; k < passes && !rc; ++k) {
+                    rc = launch_stream_f64(x, y, cls, nullptr, g.nx, g.ny, g.pitch, (double)om0, geo, ctx->sink, st);
+                    std::swap(x, y);
+                }
+                hipEventRecord(e1, st);
+                if (rc || hipEventSynchronize(e1) != hipSuccess) { rc = rc ? rc : TWG_EDEVICE; break; }
+                float ms = 0.0f;
+                hipEventElapsedTime(&ms, e0, e1);
+                const double cups = cells * S * passes / (ms * 1e-3);
+                if (cups > best.cups64) { best.S64 = S; best.RH64 = RH; best.cups64 = cups; }
+            }
+        }
+    }
+    // 3. SOR factor: smallest residual after a fixed number of sweeps
     if (!rc) {
         const double pi = 3.14159265358979323846;
         const int n = std::max(g.nx, g.ny);
@@ -807,7 +861,8 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
         double best_r = INFINITY;
         for (double c : cs) {
             const float om = (float)(2.0 / (1.0 + c * std::sin(pi / (n + 1))));
-            rc = launch_field_init(cls, a, g.nx, g.ny, g.pitch, HPF_INIT_HALF, st);
+            rc = launch_fill_f32(a, 0.5f, g.nx, g.ny, g.pitch, st);
+            if (!rc) rc = launch_field_init(cls, a, g.nx, g.ny, g.pitch, HPF_INIT_HALF, st);
             if (rc) break;
             float *x = a, *y = b;
             rc = run.sweep32(&x, &y, nullptr, om, best.S, best.RH, sweeps);
@@ -826,6 +881,9 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
         out[1] = best.RH;
         out[2] = best.omega;
         out[3] = best.cups;
+        out[4] = best.S64;
+        out[5] = best.RH64;
+        out[6] = best.cups64;
     }
     return TWG_OK;
 }
@@ -889,13 +947,14 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
             }
         return TWG_OK;
     }
-    const int S = sweeps_per_pass ? sweeps_per_pass : 4;
+    int S, RH;
+    tiling64_for(ctx, g.nx, g.ny, &S, &RH);
+    if (sweeps_per_pass) S = sweeps_per_pass;
     if (!stream_depth_supported(S))
         return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
     rc = ensure(ctx, &ctx->alt64, &ctx->alt64_bytes, (size_t)g.pitch * g.ny * sizeof(double));
     if (rc) return rc;
     double *a = psi64, *b = reinterpret_cast<double *>(ctx->alt64);
-    const int RH = 32;
     const Geometry geo = stream_geometry(g.nx, g.ny, S, RH), geo1 = stream_geometry(g.nx, g.ny, 1, RH);
     for (int64_t done = 0; done < sweeps;) {
         const bool full = sweeps - done >= S;

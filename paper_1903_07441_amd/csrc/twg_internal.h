@@ -16,6 +16,9 @@ struct twg_tuning {
     int RH = 0;       // output rows per tile
     float omega = 0;  // 0 = open-rectangle optimum
     double cups = 0;  // measured cell-updates per second
+    int S64 = 0;      // the same for FP64 sweeps (0 = untuned)
+    int RH64 = 0;
+    double cups64 = 0;
 };
 
 struct twg_ctx {

@@ -42,7 +42,8 @@ struct twg_unet {
              *g_e1 = nullptr, *g_e0 = nullptr;
     float *f_c0 = nullptr, *f_c1 = nullptr, *f_c2 = nullptr, *f_p2 = nullptr, *f_p1 = nullptr,
           *f_p0 = nullptr;
-    float *part = nullptr, *bpart = nullptr, *inv_n = nullptr;
+    float *part = nullptr, *bpart = nullptr;
+    unsigned int *counts = nullptr;  // FREE cells per image
     // small device words: [0] ring maximum
     unsigned int *words = nullptr;
 };

@@ -340,15 +340,22 @@ __global__ __launch_bounds__(256) void k_wgrad3(const uint16_t *__restrict__ A, 
     if (ch == 0 && tid < COUT) bpart[(size_t)split * COUT + tid] = bsum;
 }
 
-// out[i] = sum over s < n of part[s * stride + i], in order of s
-__global__ void k_sum_parts(const float *__restrict__ part, float *__restrict__ out, int count, int n,
-                            size_t stride)
+// out[i] = sum over s < n of part[s * stride + i].  A block covers 64
+// consecutive i with 4 lanes each; lane q adds s = q, q + 4, ... in order and
+// the four lane sums are combined in a fixed order, so the result does not
+// depend on scheduling.
+__global__ __launch_bounds__(256) void k_sum_parts(const float *__restrict__ part, float *__restrict__ out,
+                                                   int count, int n, size_t stride)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
+    __shared__ float red[4][64];
+    const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int i = blockIdx.x * 64 + l;
     float s = 0.f;
-    for (int k = 0; k < n; ++k) s += part[(size_t)k * stride + i];
-    out[i] = s;
+    if (i < count)
+        for (int k = q; k < n; k += 4) s += part[(size_t)k * stride + i];
+    red[q][l] = s;
+    __syncthreads();
+    if (q == 0 && i < count) out[i] = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
 }
 
 // ---- head, loss, routing ---------------------------------------------------
@@ -377,7 +384,7 @@ __device__ __forceinline__ float head_value(const uint16_t *__restrict__ d0p, co
 __global__ __launch_bounds__(256) void k_head_loss(const uint16_t *__restrict__ d0, const float *__restrict__ hw,
                                                    const float *__restrict__ hb, const float *__restrict__ target,
                                                    const uint8_t *__restrict__ cls,
-                                                   const float *__restrict__ inv_n, int hw_pixels, int nb,
+                                                   const unsigned int *__restrict__ cnt, int hw_pixels, int nb,
                                                    uint16_t *__restrict__ dd0, float *__restrict__ y_out,
                                                    float *__restrict__ part)
 {
@@ -393,7 +400,8 @@ __global__ __launch_bounds__(256) void k_head_loss(const uint16_t *__restrict__ 
         const float y = head_value(d0 + (size_t)p * 32, hw, hb[0], d);
         if (y_out) y_out[p] = y;
         const float diff = cls[p] == TWG_CELL_FREE ? y - target[p] : 0.f;
-        const float sc = inv_n[b] / (float)nb;
+        const unsigned int nf = cnt[b];
+        const float sc = (1.f / (float)(nf > 1u ? nf : 1u)) / (float)nb;
         lp = diff * diff * sc;
         const float dy = 2.f * diff * sc;
         gb = dy;
@@ -580,16 +588,22 @@ __global__ __launch_bounds__(256) void k_features(const uint8_t *__restrict__ cl
     }
 }
 
-// largest ring number of a grid; *out must be zero beforehand
+// largest ring number of a grid; *out must be zero beforehand.  Grid-stride
+// over rows, wave and block maxima, one atomic per block.
 __global__ __launch_bounds__(256) void k_ring_max(const uint16_t *__restrict__ ring, int nx, int ny, int pitch,
                                                   unsigned int *out)
 {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    __shared__ unsigned int red[4];
     unsigned int r = 0;
-    if (x < nx && y < ny) r = ring[(size_t)y * pitch + x];
+    for (int y = blockIdx.x; y < ny; y += gridDim.x)
+        for (int x = threadIdx.x; x < nx; x += 256) r = max(r, (unsigned int)ring[(size_t)y * pitch + x]);
     for (int o = 32; o > 0; o >>= 1) r = max(r, (unsigned int)__shfl_xor((int)r, o));
-    if ((threadIdx.x & 63) == 0 && r > 0) atomicMax(out, r);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        r = max(max(red[0], red[1]), max(red[2], red[3]));
+        if (r) atomicMax(out, r);
+    }
 }
 
 // ---- parameters ------------------------------------------------------------
@@ -691,33 +705,44 @@ __global__ void k_adam(NetLayout L, float *__restrict__ master, float *__restric
     if (pp.kind == 0) store_copies(L, pp, p, wt, wf, i);
 }
 
-// per-image count of FREE cells -> inv_n[b] = 1 / max(1, count)
-__global__ __launch_bounds__(256) void k_count_free(const uint8_t *__restrict__ cls, int hw_pixels,
-                                                    float *__restrict__ inv_n)
+__global__ void k_zero_u32n(unsigned int *__restrict__ w, int n)
 {
-    __shared__ int red[4];
-    const int b = blockIdx.x;
-    int n = 0;
-    for (int p = threadIdx.x; p < hw_pixels; p += 256) n += cls[(size_t)b * hw_pixels + p] == TWG_CELL_FREE;
-    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = n;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int t = red[0] + red[1] + red[2] + red[3];
-        inv_n[b] = 1.f / (float)(t > 1 ? t : 1);
-    }
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) w[i] = 0u;
 }
 
-__global__ void k_sum_loss(const float *__restrict__ part, int nblk, float *__restrict__ loss,
-                           float *__restrict__ head_grad)
+// per-image count of FREE cells, added into cnt[b] (integer additions are
+// exact in any order); grid (blocks per image, images)
+__global__ __launch_bounds__(256) void k_count_free(const uint8_t *__restrict__ cls, int hw_pixels,
+                                                    unsigned int *__restrict__ cnt)
 {
-    // thread c < 34 adds column c of part in block order
-    const int c = threadIdx.x;
-    if (c >= 34) return;
+    const int b = blockIdx.y;
+    unsigned int n = 0;
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < hw_pixels; p += gridDim.x * 256)
+        n += cls[(size_t)b * hw_pixels + p] == TWG_CELL_FREE;
+    for (int o = 32; o > 0; o >>= 1) n += (unsigned int)__shfl_xor((int)n, o);
+    if ((threadIdx.x & 63) == 0 && n) atomicAdd(cnt + b, n);
+}
+
+// column c < 34 of part[nblk][34] summed by block c: thread t adds rows t,
+// t + 256, ... in order, then a fixed tree over the 256 thread sums.
+__global__ __launch_bounds__(256) void k_sum_loss(const float *__restrict__ part, int nblk, float *__restrict__ loss,
+                                                  float *__restrict__ head_grad)
+{
+    __shared__ float red[256];
+    const int c = blockIdx.x;
     float s = 0.f;
-    for (int k = 0; k < nblk; ++k) s += part[(size_t)k * 34 + c];
-    if (c < 33) head_grad[c] = s;
-    else if (loss) loss[0] = s;
+    for (int k = threadIdx.x; k < nblk; k += 256) s += part[(size_t)k * 34 + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (c < 33) head_grad[c] = red[0];
+        else if (loss) loss[0] = red[0];
+    }
 }
 
 // ---- launch helpers -----------------------------------------------------------
@@ -732,7 +757,7 @@ int conv(const uint16_t *A, const uint16_t *Bs, const uint16_t *wt, const float 
 
 int choose_split(int nchunk, int ntile)
 {
-    int s = std::max(1, 512 / nchunk);
+    int s = std::max(1, 256 / nchunk);
     return std::min(s, ntile);
 }
 
@@ -745,8 +770,8 @@ int wgrad(const uint16_t *A, const uint16_t *Bs, const uint16_t *dout, float *pa
     hipLaunchKernelGGL((k_wgrad3<CIN, COUT, MODE, CA>), dim3(CIN / kCK, ns), dim3(256), 0, st, A, Bs, dout, part,
                        bpart, nb, H, W, ns);
     const int nw = COUT * 9 * CIN;
-    hipLaunchKernelGGL(k_sum_parts, dim3((nw + 255) / 256), dim3(256), 0, st, part, gw, nw, ns, (size_t)nw);
-    hipLaunchKernelGGL(k_sum_parts, dim3((COUT + 255) / 256), dim3(256), 0, st, bpart, gb, COUT, ns, (size_t)COUT);
+    hipLaunchKernelGGL(k_sum_parts, dim3((nw + 63) / 64), dim3(256), 0, st, part, gw, nw, ns, (size_t)nw);
+    hipLaunchKernelGGL(k_sum_parts, dim3((COUT + 63) / 64), dim3(256), 0, st, bpart, gb, COUT, ns, (size_t)COUT);
     return last_status();
 }
 
@@ -828,11 +853,14 @@ int net_backward(twg_unet *n, int nb, int H, int W, const float *target, const u
     const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
     const int hwp = H * W, total = nb * hwp;
     // head and loss
-    hipLaunchKernelGGL(k_count_free, dim3(nb), dim3(256), 0, st, cls, hwp, n->inv_n);
+    unsigned int *cnt = n->counts;
+    hipLaunchKernelGGL(k_zero_u32n, dim3((nb + 255) / 256), dim3(256), 0, st, cnt, nb);
+    hipLaunchKernelGGL(k_count_free, dim3(std::max(1, std::min(64, hwp / 4096)), nb), dim3(256), 0, st, cls, hwp,
+                       cnt);
     const int nblk = (total + 255) / 256;
     hipLaunchKernelGGL(k_head_loss, dim3(nblk), dim3(256), 0, st, n->d0, n->master + L.offw[7],
-                       n->master + L.offb[7], target, cls, n->inv_n, hwp, nb, n->g_d0, nullptr, n->part);
-    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(64), 0, st, n->part, nblk, loss, n->grad + L.offw[7]);
+                       n->master + L.offb[7], target, cls, cnt, hwp, nb, n->g_d0, nullptr, n->part);
+    hipLaunchKernelGGL(k_sum_loss, dim3(34), dim3(256), 0, st, n->part, nblk, loss, n->grad + L.offw[7]);
     int rc = last_status();
     // d0: input cat(up(d1), e0) at H
     if (!rc) rc = wgrad<64, 32, kUpCat, 32>(n->d1, n->e0, n->g_d0, n->part, n->bpart, GW(6), GB(6), nb, H, W, st);
@@ -924,7 +952,7 @@ int net_features(const uint8_t *cls, const uint16_t *ring, int nx, int ny, int p
 
 int net_ring_max(const uint16_t *ring, int nx, int ny, int pitch, unsigned int *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ring_max, dim3((nx + 63) / 64, (ny + 3) / 4), dim3(256), 0, st, ring, nx, ny, pitch, out);
+    hipLaunchKernelGGL(k_ring_max, dim3(std::min(ny, 512)), dim3(256), 0, st, ring, nx, ny, pitch, out);
     return last_status();
 }
 

@@ -87,7 +87,7 @@ int ensure_bwd(twg_unet *n, long long P)
     n->f_p0 = reinterpret_cast<float *>(take());
     n->part = reinterpret_cast<float *>(take());
     n->bpart = reinterpret_cast<float *>(take());
-    n->inv_n = reinterpret_cast<float *>(take());
+    n->counts = reinterpret_cast<unsigned int *>(take());
     n->bwd_pixels = P;
     return TWG_OK;
 }

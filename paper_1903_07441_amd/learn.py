@@ -81,13 +81,14 @@ def make_dataset(ctx, net, first, n, name="learn256", side=None):
                       cls=cls[k], ring=ring[k])
         net.features(cls[k], ring[k], sc["goal"], H=H, W=W, out=x[k])
         goals.append((int(sc["goal"][0]), int(sc["goal"][1])))
-        if (k + 1) % 2048 == 0:
+        if (k + 1) % 512 == 0 or k + 1 == n:
             log(f"  rasterised {k + 1}/{n}")
     return dict(x=x, cls=cls, ring=ring, goals=goals, H=H, W=W, first=first, name=name)
 
 
-def relax_targets(ctx, data, tol=1e-7, chunk=256):
-    """Converged FP32 fields of every scenario (batched relaxation)."""
+def relax_targets(ctx, data, tol=3e-7, chunk=256, max_sweeps=20000):
+    """Converged FP32 fields of every scenario (batched relaxation; the
+    tolerance sits just above FP32's rounding floor next to the goal)."""
     n, H, W = data["cls"].shape
     psi = torch.empty((n, H, W), dtype=torch.float32, device=data["cls"].device)
     cls_flat = data["cls"].view(-1)
@@ -96,10 +97,11 @@ def relax_targets(ctx, data, tol=1e-7, chunk=256):
     for s in range(0, n, chunk):
         e = min(n, s + chunk)
         descs = [(W, H, W, (k - s) * H * W) for k in range(s, e)]
-        st = ctx.relax_batched(cls_flat[s * H * W:e * H * W], psi_flat[s * H * W:e * H * W], descs, tol=tol)
+        st = ctx.relax_batched(cls_flat[s * H * W:e * H * W], psi_flat[s * H * W:e * H * W], descs, tol=tol,
+                               max_sweeps=max_sweeps)
         sweeps += [d["sweeps"] for d in st]
-        if (e // chunk) % 8 == 0 or e == n:
-            log(f"  relaxed {e}/{n} (median sweeps {int(np.median(sweeps))})")
+        log(f"  relaxed {e}/{n} (median sweeps {int(np.median(sweeps))}, "
+            f"{sum(d['status'] == twg.OK for d in st)}/{len(st)} at tol)")
     data["target"] = psi
     return psi
 
@@ -130,31 +132,26 @@ def train(net, data, epochs=4, batch=16, lr=1e-3, lr_min=2e-5, log_every=100):
     return hist, (time.perf_counter() - t0) / max(1, total)
 
 
-LEARNED_OMEGAS = (1.0, 1.3, 1.6, 1.8, 1.9, 0.0)  # 0 = the plain path's factor
+OMEGAS = (1.6, 1.8, 1.9, 1.95, 0.0)  # 0 = the open-rectangle optimum of the grid
 
 
-def evaluate(ctx, net, data, tol=1e-6, omegas=LEARNED_OMEGAS):
+def evaluate(ctx, net, data, tol=1e-6, omegas=OMEGAS):
     """Relax every scenario of `data` to `tol` from the plain initial fields
-    (half and zero, the plain path's SOR factor) and from the network's field
-    with each SOR factor of `omegas`; per-mode median sweeps and times (the
-    learned time includes features and network).  A warm start's error is
-    mostly short-wavelength, which small factors damp fastest, so the learned
-    path gets its own factor."""
+    (half, zero) and from the network's field, each with every SOR factor of
+    `omegas`; per-mode median sweeps and times (the learned time includes
+    features and network).  Both paths are credited with their best factor:
+    obstacles shrink the domain, so the best factor is below the open-grid
+    optimum, and a warm start's error is mostly short-wavelength, which
+    smaller factors damp fastest."""
     n, H, W = data["cls"].shape
     dev = data["cls"].device
     psi = torch.empty((H, W), dtype=torch.float32, device=dev)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    modes = ["half", "zero"] + [f"learned_w{w:g}" for w in omegas]
-    out = {m: [] for m in modes}
+    kinds = ("half", "zero", "learned")
+    out = {(kd, w): [] for kd in kinds for w in omegas}
     net_ms, net_err = [], []
     for k in range(n):
         cls, ring, goal = data["cls"][k], data["ring"][k], data["goals"][k]
-        for mode, init in (("half", twg.INIT_HALF), ("zero", twg.INIT_ZERO)):
-            ev0.record()
-            st = ctx.relax(cls, psi, None, tol=tol, init=init)
-            ev1.record()
-            torch.cuda.synchronize()
-            out[mode].append((st["sweeps"], ev0.elapsed_time(ev1), st["residual"]))
         ev0.record()
         net.warm_start(cls, ring, goal, psi)
         ev1.record()
@@ -164,27 +161,31 @@ def evaluate(ctx, net, data, tol=1e-6, omegas=LEARNED_OMEGAS):
             free = cls == twg.FREE
             net_err.append(float((psi - data["target"][k]).abs()[free].max().item()))
         for w in omegas:
-            ev0.record()
-            net.warm_start(cls, ring, goal, psi)
-            st = ctx.relax(cls, psi, None, tol=tol, init=twg.INIT_KEEP, omega=w)
-            ev1.record()
-            torch.cuda.synchronize()
-            out[f"learned_w{w:g}"].append((st["sweeps"], ev0.elapsed_time(ev1), st["residual"]))
-    summ = {}
-    for mode in modes:
-        a = np.array(out[mode])
-        summ[mode] = {"median_sweeps": float(np.median(a[:, 0])), "median_ms": float(np.median(a[:, 1])),
-                      "max_residual": float(np.max(a[:, 2]))}
+            for kd, init in (("half", twg.INIT_HALF), ("zero", twg.INIT_ZERO), ("learned", twg.INIT_KEEP)):
+                ev0.record()
+                if kd == "learned":
+                    net.warm_start(cls, ring, goal, psi)
+                st = ctx.relax(cls, psi, None, tol=tol, init=init, omega=w)
+                ev1.record()
+                torch.cuda.synchronize()
+                out[(kd, w)].append((st["sweeps"], ev0.elapsed_time(ev1), st["residual"]))
+    summ = {"omegas": list(omegas)}
+    for kd in kinds:
+        rows = {}
+        for w in omegas:
+            a = np.array(out[(kd, w)])
+            rows[f"{w:g}"] = {"median_sweeps": float(np.median(a[:, 0])), "median_ms": float(np.median(a[:, 1])),
+                             "max_residual": float(np.max(a[:, 2]))}
+        best = min(rows, key=lambda r: rows[r]["median_ms"])
+        summ[kd] = {"by_omega": rows, "best_omega": float(best), **rows[best]}
     summ["net_median_ms"] = float(np.median(net_ms))
     if net_err:
         summ["net_median_max_err"] = float(np.median(net_err))
-    best = min((summ[f"learned_w{w:g}"]["median_ms"], w) for w in omegas)
-    summ["learned_best_omega"] = best[1]
-    summ["learned"] = summ[f"learned_w{best[1]:g}"]
-    best_plain_ms = min(summ["half"]["median_ms"], summ["zero"]["median_ms"])
-    best_plain_sw = min(summ["half"]["median_sweeps"], summ["zero"]["median_sweeps"])
-    summ["time_ratio_plain_over_learned"] = best_plain_ms / max(1e-9, summ["learned"]["median_ms"])
-    summ["sweep_ratio_plain_over_learned"] = best_plain_sw / max(1.0, summ["learned"]["median_sweeps"])
+    plain = min((summ["half"], summ["zero"]), key=lambda r: r["median_ms"])
+    summ["plain_best"] = {"init": "half" if plain is summ["half"] else "zero", "omega": plain["best_omega"],
+                          "median_ms": plain["median_ms"], "median_sweeps": plain["median_sweeps"]}
+    summ["time_ratio_plain_over_learned"] = plain["median_ms"] / max(1e-9, summ["learned"]["median_ms"])
+    summ["sweep_ratio_plain_over_learned"] = plain["median_sweeps"] / max(1.0, summ["learned"]["median_sweeps"])
     return summ
 
 

@@ -242,13 +242,14 @@ class Context:
         self._check(rc)
 
     def autotune(self, cls):
-        """Tune tiling and SOR factor for grids of cls's size; returns
-        dict(S, RH, omega, cups)."""
+        """Tune tiling (FP32 and FP64 sweeps) and SOR factor for grids of
+        cls's size; returns dict(S, RH, omega, cups, S64, RH64, cups64)."""
         nx, ny, pitch = _grid_of(cls)
-        out = (ctypes.c_double * 4)()
+        out = (ctypes.c_double * 7)()
         rc = lib.hpf_autotune(self.h, Grid(nx, ny, pitch), _ptr(cls), out, _stream())
         self._check(rc)
-        return dict(S=int(out[0]), RH=int(out[1]), omega=float(out[2]), cups=float(out[3]))
+        return dict(S=int(out[0]), RH=int(out[1]), omega=float(out[2]), cups=float(out[3]), S64=int(out[4]),
+                    RH64=int(out[5]), cups64=float(out[6]))
 
     def residual(self, cls, psi=None, psi64=None, f=None):
         t = psi if psi is not None else psi64
