@@ -28,10 +28,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
-    summary, or None when the summary is for another kernel or the kernel
-    source has changed since the counters were taken."""
+def profiled_traffic(kernel, rows):
+    """HBM bytes per launch of `kernel` at `rows` output rows per tile from
+    the committed rocprofv3 PMC summary, or None when the summary has no such
+    entry or the kernel source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_sor_stream_replan2048.md")
     src = os.path.join(ROOT, "paper_1903_07441_amd", "csrc", "sor_stream.hip")
@@ -40,15 +40,12 @@ def profiled_traffic(kernel):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    kv = {}
     for ln in text:
-        ln = ln.strip()
-        if ":" in ln and ln.split(":", 1)[0] in ("kernel", "source_sha256_16", "traffic_bytes_per_launch"):
-            k, v = ln.split(":", 1)
-            kv[k] = v.strip()
-    if kv.get("kernel") != kernel or kv.get("source_sha256_16") != sha:
-        return None
-    return int(kv["traffic_bytes_per_launch"])
+        f = ln.split()
+        # entry lines: "traffic <kernel> rows_per_tile <RH> source_sha256_16 <sha> bytes_per_launch <B>"
+        if len(f) == 8 and f[0] == "traffic" and f[1] == kernel and f[3] == str(rows) and f[5] == sha:
+            return int(f[7])
+    return None
 
 
 def main():
@@ -160,7 +157,7 @@ def main():
     achieved = alg_bytes / t_launch / 1e9
     kname = f"k_sor_stream<float,{S},false>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(kname),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(kname, tuning["RH"]),
                 "kernel": kname, "launch_us": round(t_launch * 1e6, 2),
                 "algorithmic_bytes_per_launch": alg_bytes}
     # the same launch against the vector-ALU issue rate: 5 VALU instructions

@@ -278,6 +278,14 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
  * Blocking.  Errors: TWG_EINVAL, TWG_ENOMEM, TWG_EDEVICE. */
 int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, void *stream);
 
+/* hpf_set_tiling -- set, for grids of size nx x ny on this context, what
+ * hpf_autotune would remember: FP32 sweeps per tile load S and rows per tile
+ * RH, SOR factor omega (0 = the open-rectangle optimum), FP64 tiling S64 and
+ * RH64 (S64 = 0: the FP64 default).  Host only.  Errors: TWG_EINVAL (S or
+ * S64 not in {1, 2, 3, 4, 6, 8}, RH < 2, omega outside [0, 2)). */
+int32_t hpf_set_tiling(twg_ctx *ctx, int32_t nx, int32_t ny, int32_t S, int32_t RH, float omega, int32_t S64,
+                       int32_t RH64);
+
 /* hpf_residual -- max over FREE cells of |avg4(u) + f - u| in FP64, where u
  * is psi64 if it is not NULL, else psi (FP32 values, FP64 arithmetic); f is
  * an optional FP32 source (NULL = 0).  *out is a host double.  Blocking. */

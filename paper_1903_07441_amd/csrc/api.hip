@@ -1069,4 +1069,24 @@ int32_t hpf_init_field(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi,
     return rc ? set_err(ctx, rc, "init launch failed") : TWG_OK;
 }
 
+int32_t hpf_set_tiling(twg_ctx *ctx, int32_t nx, int32_t ny, int32_t S, int32_t RH, float omega, int32_t S64,
+                       int32_t RH64)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    if (nx < 1 || ny < 1) return set_err(ctx, TWG_EINVAL, "bad grid size");
+    if (!stream_depth_supported(S) || (S64 && !stream_depth_supported(S64)))
+        return set_err(ctx, TWG_EINVAL, "sweeps per pass must be one of 1, 2, 3, 4, 6, 8");
+    if (RH < 2 || (S64 && RH64 < 2)) return set_err(ctx, TWG_EINVAL, "rows per tile must be >= 2");
+    if (!(omega >= 0.0f && omega < 2.0f)) return set_err(ctx, TWG_EINVAL, "omega must be in [0, 2)");
+    twg_tuning t;
+    t.S = S;
+    t.RH = RH;
+    t.omega = omega;
+    t.S64 = S64;
+    t.RH64 = RH64;
+    ctx->tuned[{nx, ny}] = t;
+    return TWG_OK;
+}
+
 }  // extern "C"

@@ -30,6 +30,8 @@ def main(argv=None):
     ap.add_argument("--passes", type=int, default=50)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--net", action="store_true", help="profile the network kernels instead")
+    ap.add_argument("--S", type=int, default=0, help="sweeps per tile load (with --RH: skip the autotuner)")
+    ap.add_argument("--RH", type=int, default=0, help="output rows per tile")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -64,7 +66,11 @@ def main(argv=None):
         net.close()
         ctx.close()
         return 0
-    tune = ctx.autotune(cls)
+    if args.S and args.RH:
+        ctx.set_tiling(nx, ny, args.S, args.RH)
+        tune = {"S": args.S, "RH": args.RH, "omega": 1.99}
+    else:
+        tune = ctx.autotune(cls)
     psi = torch.full((ny, nx), 0.5, dtype=torch.float32, device=dev)
     ctx.sweeps(cls, psi, tune["omega"], 2 * tune["S"] * args.passes, sweeps_per_pass=tune["S"])
     n = args.copy_mib * (1 << 20) // 4

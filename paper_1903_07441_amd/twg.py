@@ -76,6 +76,7 @@ def _load():
         "hpf_rubber_band": (i32, [vp, Grid, vp, vp, vp, vp, vp, i32, f64, i32, vp]),
         "hpf_merge_previous": (i32, [vp, Grid, vp, vp, vp, vp, vp]),
         "hpf_init_field": (i32, [vp, Grid, vp, vp, i32, vp]),
+        "hpf_set_tiling": (i32, [vp, i32, i32, i32, i32, f32, i32, i32]),
         "twg_unet_num_params": (i32, []),
         "twg_unet_create": (i32, [vp, P(vp)]),
         "twg_unet_destroy": (i32, [vp]),
@@ -99,7 +100,7 @@ EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error"
             "twg_rasterize",
             "hpf_relax", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
             "hpf_index_matrix", "hpf_descend", "hpf_rubber_band", "hpf_merge_previous",
-            "hpf_init_field", "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
+            "hpf_init_field", "hpf_set_tiling", "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
             "twg_unet_set_params", "twg_unet_get_params", "twg_unet_forward", "twg_unet_loss_grad",
             "twg_unet_adam_step", "twg_unet_features", "twg_unet_warm_start")
 
@@ -250,6 +251,10 @@ class Context:
         self._check(rc)
         return dict(S=int(out[0]), RH=int(out[1]), omega=float(out[2]), cups=float(out[3]), S64=int(out[4]),
                     RH64=int(out[5]), cups64=float(out[6]))
+
+    def set_tiling(self, nx, ny, S, RH, omega=0.0, S64=0, RH64=0):
+        """Fix the tiling (and SOR factor) used for grids of this size."""
+        self._check(lib.hpf_set_tiling(self.h, int(nx), int(ny), int(S), int(RH), float(omega), int(S64), int(RH64)))
 
     def residual(self, cls, psi=None, psi64=None, f=None):
         t = psi if psi is not None else psi64
