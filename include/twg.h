@@ -97,6 +97,14 @@ typedef struct {
     int32_t ring_width;       /* W >= 1, cells per time ring */
     int32_t border_walls;     /* 1: cells on the grid border are WALL */
     double robot_speed;       /* v_r > 0, cells per step */
+    /* The fields below may be left zero (circular rings, per-cell horizon,
+     * no inflation). */
+    int32_t ring_mode;        /* 0 circular rings; 1 elliptical warp metric (Eqs. 14-15) */
+    int32_t per_object;       /* 0 per-cell horizon; 1 per-object horizon (Algorithm 1) */
+    double heading_x, heading_y; /* robot heading (cos, sin) for ring_mode 1, used as given */
+    double kappa;             /* covariance inflation factor >= 0 (0 = off) */
+    const double *cov;        /* n_obs x 16 doubles (device): row-major 4x4 covariance of the
+                                 state [x, y, vx, vy], or NULL (no inflation) */
 } twg_raster_params;
 
 /* twg_rasterize -- class map of one replanning step (Algorithm 1, "Map
@@ -118,6 +126,20 @@ typedef struct {
  * there.  Class, by precedence: WALL (border, if border_walls), GOAL (the goal
  * cell), OBST (static_occ nonzero, or occupied), FREE.
  *
+ * ring_mode 1 replaces the circles by the paper's elliptical time warps
+ * (Eqs. 14-15): the ellipse through a cell is centred 0.9 r_x ahead of the
+ * robot along the heading with r_x = 4 r_y, i.e. with u = hx dx + hy dy and
+ * v = hy dx - hx dy, r_x = (-1.8 u + sqrt(4 u^2 + 12.16 v^2)) / 0.38, and
+ * j = floor(r_x / W), decided exactly: r_x >= j W when 0.38 j W + 1.8 u <= 0
+ * or 4 u^2 + 12.16 v^2 >= (0.38 j W + 1.8 u)^2 (each operation rounded once).
+ * per_object 1 follows Algorithm 1 literally: obstacle i is predicted once,
+ * to the horizon of the ring of the cell nearest its current centre (round
+ * half to even), and every cell of that disc is marked, whatever its ring.
+ * kappa > 0 with cov grows each disc by min(W, kappa sqrt(lambda_max)),
+ * lambda_max the larger eigenvalue of the predicted position covariance
+ * P_pp + t (P_pv + P_vp) + t^2 P_vv at the disc's horizon t (the paper's
+ * Gaussian marking of the prediction uncertainty, read as a capped radius).
+ *
  *   pos, vel   n_obs x 2 doubles [x, y] (device): position in cells, velocity
  *              in cells per step.  Obstacles with a non-finite predicted
  *              position, or with |256 mu| >= 2^40, are ignored.
@@ -128,8 +150,10 @@ typedef struct {
  *   cls        out uint8 class map (device, pitch g.pitch).
  *   ring       optional out uint16 ring map (device, pitch g.pitch), or NULL.
  * Asynchronous.  Errors: TWG_EINVAL for a bad grid, robot or goal outside the
- * grid, W < 1, non-positive or non-finite speed, n_obs < 0, NULL cls, or
- * n_obs > 0 with NULL pos/vel/radius. */
+ * grid, W < 1, non-positive or non-finite speed, n_obs < 0, NULL cls, n_obs > 0
+ * with NULL pos/vel/radius, ring_mode or per_object not 0/1, a heading that is
+ * not finite or is zero with ring_mode 1, kappa negative or not finite;
+ * TWG_EUNSUPPORTED when more than 65536 rings would touch the grid. */
 int32_t twg_rasterize(twg_ctx *ctx, twg_grid g, int32_t n_obs, const double *pos,
                       const double *vel, const double *radius, const uint8_t *static_occ,
                       const twg_raster_params *params, uint8_t *cls, uint16_t *ring,

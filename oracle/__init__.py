@@ -75,6 +75,12 @@ def _load():
         "orc_descend": (i32, [i32, i32, p, p, i32, i32, i32, p, p]),
         "orc_goal_reachable": (i32, [i32, i32, p, i32, i32]),
         "orc_rubber_band": (None, [i32, i32, p, p, p, i32, f64, i32]),
+        "orc_ring_ellipse": (i32, [i64, i64, f64, f64, i32]),
+        "orc_ring_map_mode": (None, [i32, i32, i32, i32, i32, i32, f64, f64, p]),
+        "orc_pos_cov": (None, [p, f64, p]),
+        "orc_inflated_radius": (f64, [f64, p, f64, f64, i32]),
+        "orc_rasterize_modes": (None, [i32, i32, i32, i32, i32, i32, i32, f64, i32, i32, p, p, p, p,
+                                       i32, f64, f64, i32, f64, p, p, p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -291,3 +297,43 @@ def rubber_band(cls, psi, path, k=1.0, iters=16):
     out = np.ascontiguousarray(np.asarray(path, dtype=np.int32).reshape(-1, 2)).copy()
     _load().orc_rubber_band(nx, ny, _ptr(cls), _ptr(psi), _ptr(out), int(out.shape[0]), float(k), int(iters))
     return out
+
+
+def ring_ellipse(dx, dy, hc, hs, W):
+    """Elliptical warp ring of the cell at offset (dx, dy) from the robot."""
+    return int(_load().orc_ring_ellipse(int(dx), int(dy), float(hc), float(hs), int(W)))
+
+
+def pos_cov(P, t):
+    """[a, b, d] of the 2x2 position covariance after horizon t."""
+    P = _f64(np.asarray(P, dtype=np.float64).reshape(16))
+    out = np.zeros(3)
+    _load().orc_pos_cov(_ptr(P), float(t), _ptr(out))
+    return out
+
+
+def inflated_radius(r, P, t, kappa, W):
+    P = None if P is None else _f64(np.asarray(P, dtype=np.float64).reshape(16))
+    return float(_load().orc_inflated_radius(float(r), _ptr(P) if P is not None else None, float(t),
+                                             float(kappa), int(W)))
+
+
+def rasterize_modes(sc, ring_mode=0, heading=(1.0, 0.0), per_object=False, kappa=0.0, cov=None,
+                    static_occ=None, border_walls=True):
+    """Class and ring maps with the warp metric, horizon rule and covariance
+    inflation chosen (see orc_rasterize_modes)."""
+    nx, ny = int(sc["nx"]), int(sc["ny"])
+    pos = _f64(np.asarray(sc["pos"], dtype=np.float64).reshape(-1, 2))
+    vel = _f64(np.asarray(sc["vel"], dtype=np.float64).reshape(-1, 2))
+    rad = _f64(np.asarray(sc["rad"], dtype=np.float64).reshape(-1))
+    n = rad.shape[0]
+    cv = None if cov is None else _f64(np.asarray(cov, dtype=np.float64).reshape(n, 16))
+    so = None if static_occ is None else _u8(static_occ)
+    cls = np.zeros((ny, nx), np.uint8)
+    ring = np.zeros((ny, nx), np.uint16)
+    _load().orc_rasterize_modes(nx, ny, int(sc["robot"][0]), int(sc["robot"][1]), int(sc["goal"][0]),
+                                int(sc["goal"][1]), int(sc["W"]), float(sc["vr"]), int(bool(border_walls)), n,
+                                _ptr(pos), _ptr(vel), _ptr(rad), _ptr(so) if so is not None else None,
+                                int(ring_mode), float(heading[0]), float(heading[1]), int(bool(per_object)),
+                                float(kappa), _ptr(cv) if cv is not None else None, _ptr(cls), _ptr(ring))
+    return cls, ring

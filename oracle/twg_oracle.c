@@ -86,6 +86,50 @@ void orc_ring_map(int32_t nx, int32_t ny, int32_t xr, int32_t yr, int32_t W,
                 (uint16_t)orc_ring_of((int64_t)x - xr, (int64_t)y - yr, W);
 }
 
+/* Elliptical warp metric (Eqs. 14-15).  The ellipse through a point has its
+ * centre 0.9 r_x ahead of the robot along the heading (hc, hs) and r_x = 4
+ * r_y; with u = hc dx + hs dy and v = hs dx - hc dy relative to the robot,
+ * Eq. (15) becomes r_x^2 = (u - 0.9 r_x)^2 + 16 v^2, whose positive root is
+ *     r_x = (-1.8 u + sqrt(4 u^2 + 12.16 v^2)) / 0.38.
+ * The ring j = floor(r_x / W) is decided without rounding a root: r_x >= j W
+ * exactly when sqrt(4u^2 + 12.16v^2) >= 0.38 j W + 1.8 u, i.e. when the right
+ * side is <= 0 or 4u^2 + 12.16v^2 >= (0.38 j W + 1.8 u)^2.  Every term is one
+ * rounded IEEE operation, and the test is monotone in j. */
+static int ellipse_reaches(double u, double v, int32_t j, int32_t W)
+{
+    const double q = 4.0 * (u * u) + 12.16 * (v * v);
+    const double rhs = 0.38 * ((double)j * (double)W) + 1.8 * u;
+    return rhs <= 0.0 || q >= rhs * rhs;
+}
+
+int32_t orc_ring_ellipse(int64_t dx, int64_t dy, double hc, double hs, int32_t W)
+{
+    const double u = hc * (double)dx + hs * (double)dy;
+    const double v = hs * (double)dx - hc * (double)dy;
+    /* estimate from the rounded root, then settle on the exact test */
+    const double r = (-1.8 * u + sqrt(4.0 * (u * u) + 12.16 * (v * v))) / 0.38;
+    int32_t j = (r > 0.0 && r < 1e9) ? (int32_t)(r / (double)W) : 0;
+    while (j > 0 && !ellipse_reaches(u, v, j, W)) --j;
+    while (ellipse_reaches(u, v, j + 1, W)) ++j;
+    return j;
+}
+
+/* Ring of a cell in either mode: 0 circular (isotropic), 1 elliptical. */
+static int32_t ring_any(int64_t dx, int64_t dy, int32_t W, int32_t mode, double hc, double hs)
+{
+    return mode == 1 ? orc_ring_ellipse(dx, dy, hc, hs, W) : orc_ring_of(dx, dy, W);
+}
+
+void orc_ring_map_mode(int32_t nx, int32_t ny, int32_t xr, int32_t yr, int32_t W, int32_t mode,
+                       double hc, double hs, uint16_t *ring)
+{
+#pragma omp parallel for schedule(static)
+    for (int32_t y = 0; y < ny; ++y)
+        for (int32_t x = 0; x < nx; ++x)
+            ring[(size_t)y * nx + x] =
+                (uint16_t)ring_any((int64_t)x - xr, (int64_t)y - yr, W, mode, hc, hs);
+}
+
 /* Number of rings that touch the grid: one more than the largest ring
  * number, which is reached at one of the four corners. */
 int32_t orc_num_rings(int32_t nx, int32_t ny, int32_t xr, int32_t yr, int32_t W)
@@ -180,6 +224,34 @@ void orc_kalman_update(double x[4], double P[16], const double z[2], const doubl
     memcpy(P, nP, sizeof nP);
 }
 
+/* Position covariance after a horizon t for the constant-velocity model:
+ * the 2x2 position block of A(t) P A(t)^T,
+ *     P_pos(t) = P_pp + t (P_pv + P_vp) + t^2 P_vv,
+ * entries a = [0][0], b = [0][1], d = [1][1] (P row-major 4x4, state
+ * [x, y, vx, vy]); summed as ((P_pp + t (P_pv + P_vp)) + (t t) P_vv). */
+void orc_pos_cov(const double P[16], double t, double out[3])
+{
+    const double tt = t * t;
+    out[0] = (P[0] + t * (P[2] + P[8])) + tt * P[10];
+    out[1] = (P[1] + t * (P[3] + P[9])) + tt * P[11];
+    out[2] = (P[5] + t * (P[7] + P[13])) + tt * P[15];
+}
+
+/* Disc radius with covariance inflation (reading of the paper's Gaussian
+ * marking): r + min(W, kappa sqrt(lambda_max(P_pos(t)))), lambda_max =
+ * (a + d) / 2 + sqrt(((a - d) / 2)^2 + b^2).  kappa = 0 or P = NULL: r. */
+double orc_inflated_radius(double r, const double *P, double t, double kappa, int32_t W)
+{
+    if (!(kappa > 0.0) || !P) return r;
+    double c[3];
+    orc_pos_cov(P, t, c);
+    const double h = (c[0] - c[2]) * 0.5;
+    const double lam = (c[0] + c[2]) * 0.5 + sqrt(h * h + c[1] * c[1]);
+    double g = kappa * sqrt(lam > 0.0 ? lam : 0.0);
+    if (!(g <= (double)W)) g = (double)W; /* also catches NaN */
+    return r + g;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Marking predicted poses on the grid (Algorithm 1, "Map Update")          */
 /* ------------------------------------------------------------------------ */
@@ -248,6 +320,76 @@ void orc_rasterize_allpairs(int32_t nx, int32_t ny, int32_t xr, int32_t yr,
             cls[idx] = c;
         }
     }
+}
+
+/* All modes, all-pairs definition.
+ *   ring_mode   0 circular rings, 1 elliptical warp metric (heading (hc, hs)).
+ *   per_object  0: each cell sees every obstacle at its own ring's horizon;
+ *               1 (Algorithm 1): obstacle i is predicted once, to the horizon
+ *               of the ring of the cell nearest its current centre (round
+ *               half to even), and its disc is marked on every ring.
+ *   kappa, cov  covariance inflation (cov: n_obs x 16 doubles or NULL). */
+void orc_rasterize_modes(int32_t nx, int32_t ny, int32_t xr, int32_t yr, int32_t xg, int32_t yg,
+                         int32_t W, double vr, int32_t border_walls, int32_t n_obs, const double *pos,
+                         const double *vel, const double *rad, const uint8_t *static_occ,
+                         int32_t ring_mode, double hc, double hs, int32_t per_object, double kappa,
+                         const double *cov, uint8_t *cls, uint16_t *ring)
+{
+    /* per-object discs, computed once */
+    int64_t *ocx = (int64_t *)malloc((size_t)(n_obs > 0 ? n_obs : 1) * 3 * sizeof(int64_t));
+    uint8_t *ook = (uint8_t *)calloc((size_t)(n_obs > 0 ? n_obs : 1), 1);
+    if (per_object) {
+        for (int32_t i = 0; i < n_obs; ++i) {
+            if (!radius_ok(rad[i])) continue;
+            const double px = nearbyint(pos[2 * i]), py = nearbyint(pos[2 * i + 1]);
+            if (!(fabs(px) < 1e9) || !(fabs(py) < 1e9)) continue;
+            const int32_t j = ring_any((int64_t)px - xr, (int64_t)py - yr, W, ring_mode, hc, hs);
+            const double t = orc_ring_time(j, W, vr);
+            double mu[2];
+            int64_t cx, cy;
+            orc_predict_mean(&pos[2 * i], &vel[2 * i], t, mu);
+            if (!q8(mu[0], &cx) || !q8(mu[1], &cy)) continue;
+            const double re = orc_inflated_radius(rad[i], cov ? cov + 16 * (size_t)i : NULL, t, kappa, W);
+            ocx[3 * i] = cx;
+            ocx[3 * i + 1] = cy;
+            ocx[3 * i + 2] = (int64_t)nearbyint(256.0 * re);
+            ook[i] = 1;
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int32_t y = 0; y < ny; ++y) {
+        for (int32_t x = 0; x < nx; ++x) {
+            size_t idx = (size_t)y * nx + x;
+            int32_t j = ring_any((int64_t)x - xr, (int64_t)y - yr, W, ring_mode, hc, hs);
+            if (ring) ring[idx] = (uint16_t)j;
+            uint8_t c = base_class(nx, ny, x, y, xg, yg, border_walls);
+            if (c == O_FREE && static_occ && static_occ[idx]) c = O_OBST;
+            if (c == O_FREE) {
+                double t = orc_ring_time(j, W, vr);
+                for (int32_t i = 0; i < n_obs; ++i) {
+                    int64_t cx, cy, R;
+                    if (per_object) {
+                        if (!ook[i]) continue;
+                        cx = ocx[3 * i];
+                        cy = ocx[3 * i + 1];
+                        R = ocx[3 * i + 2];
+                    } else {
+                        double mu[2];
+                        if (!radius_ok(rad[i])) continue;
+                        orc_predict_mean(&pos[2 * i], &vel[2 * i], t, mu);
+                        if (!q8(mu[0], &cx) || !q8(mu[1], &cy)) continue;
+                        const double re =
+                            orc_inflated_radius(rad[i], cov ? cov + 16 * (size_t)i : NULL, t, kappa, W);
+                        R = (int64_t)nearbyint(256.0 * re);
+                    }
+                    if (disc_covers(x, y, cx, cy, R)) { c = O_OBST; break; }
+                }
+            }
+            cls[idx] = c;
+        }
+    }
+    free(ocx);
+    free(ook);
 }
 
 /* Same result, organised per obstacle: for every (obstacle, ring) pair the

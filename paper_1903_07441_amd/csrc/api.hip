@@ -420,6 +420,13 @@ int32_t twg_rasterize(twg_ctx *ctx, twg_grid g, int32_t n_obs, const double *pos
     if (p->ring_width < 1) return set_err(ctx, TWG_EINVAL, "ring_width < 1");
     if (!(p->robot_speed > 0.0) || !std::isfinite(p->robot_speed))
         return set_err(ctx, TWG_EINVAL, "robot_speed must be positive and finite");
+    if ((p->ring_mode != 0 && p->ring_mode != 1) || (p->per_object != 0 && p->per_object != 1))
+        return set_err(ctx, TWG_EINVAL, "ring_mode and per_object must be 0 or 1");
+    if (p->ring_mode == 1 && (!std::isfinite(p->heading_x) || !std::isfinite(p->heading_y) ||
+                              (p->heading_x == 0.0 && p->heading_y == 0.0)))
+        return set_err(ctx, TWG_EINVAL, "ring_mode 1 needs a finite, nonzero heading");
+    if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa))
+        return set_err(ctx, TWG_EINVAL, "kappa must be finite and >= 0");
     hipSetDevice(ctx->device);
     return launch_rasterize(ctx, g, n_obs, pos, vel, radius, static_occ, *p, cls, ring,
                             as_stream(stream));

@@ -27,7 +27,9 @@ class Grid(ctypes.Structure):
 
 class RasterParams(ctypes.Structure):
     _fields_ = [("robot_x", i32), ("robot_y", i32), ("goal_x", i32), ("goal_y", i32),
-                ("ring_width", i32), ("border_walls", i32), ("robot_speed", f64)]
+                ("ring_width", i32), ("border_walls", i32), ("robot_speed", f64),
+                ("ring_mode", i32), ("per_object", i32), ("heading_x", f64), ("heading_y", f64),
+                ("kappa", f64), ("cov", vp)]
 
 
 class HpfParams(ctypes.Structure):
@@ -168,7 +170,8 @@ class Context:
 
     # ---- map update ------------------------------------------------------
     def rasterize(self, nx, ny, robot, goal, pos, vel, rad, W=8, robot_speed=1.0,
-                  border_walls=True, static_occ=None, cls=None, ring=None, want_ring=True):
+                  border_walls=True, static_occ=None, cls=None, ring=None, want_ring=True,
+                  ring_mode=0, heading=(1.0, 0.0), per_object=False, kappa=0.0, cov=None):
         dev = torch.device("cuda", self.device)
         if cls is None:
             cls = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
@@ -184,8 +187,12 @@ class Context:
             raise ValueError("ring map must share the class map's pitch")
         if static_occ is not None and static_occ.stride(0) != pitch:
             raise ValueError("static map must share the class map's pitch")
+        if cov is not None and (cov.dtype != torch.float64 or not cov.is_cuda or not cov.is_contiguous()
+                                or cov.numel() != 16 * n):
+            raise ValueError("cov must be a contiguous float64 device tensor of n_obs x 16")
         p = RasterParams(int(robot[0]), int(robot[1]), int(goal[0]), int(goal[1]), int(W),
-                         int(bool(border_walls)), float(robot_speed))
+                         int(bool(border_walls)), float(robot_speed), int(ring_mode), int(bool(per_object)),
+                         float(heading[0]), float(heading[1]), float(kappa), _ptr(cov))
         rc = lib.twg_rasterize(self.h, Grid(nx, ny, pitch), n, _ptr(pos), _ptr(vel), _ptr(rad),
                                _ptr(static_occ), ctypes.byref(p), _ptr(cls), _ptr(ring), _stream())
         self._check(rc)

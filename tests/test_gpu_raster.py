@@ -93,3 +93,59 @@ def test_raster_rejects_bad_arguments(ctx):
     with pytest.raises(twg.TwgError) as e:
         ctx.rasterize(20, 20, (3, 3), (4, 4), pos, vel, rad, robot_speed=0.0)
     assert e.value.code == twg.EINVAL
+
+
+@pytest.mark.parametrize("name,idx,side,mode,heading,per_object,kappa", [
+    ("warped512", 7, 128, 1, (1.0, 0.0), False, 0.0),
+    ("warped512", 8, 160, 1, (0.0, -1.0), True, 0.0),
+    ("warped512", 9, 200, 1, (0.6, 0.8), False, 1.5),
+    ("warped512", 10, 256, 0, (1.0, 0.0), True, 1.0),
+    ("warped512", 11, 512, 1, (-0.28, 0.96), True, 0.7),
+])
+def test_raster_warp_modes_parity(ctx, orc, name, idx, side, mode, heading, per_object, kappa):
+    """Elliptical warps (Eqs. 14-15), the per-object horizon of Algorithm 1
+    and covariance inflation: class and ring maps bit-exact with the oracle."""
+    sc = scenarios.scenario(name, idx, side=side)
+    rng = np.random.default_rng(idx)
+    n = len(sc["rad"])
+    M = rng.standard_normal((n, 4, 4)) * 0.3
+    cov = np.einsum("nij,nkj->nik", M, M) + 0.25 * np.eye(4)
+    pos, vel, rad = scenario_tensors(sc)
+    covt = torch.as_tensor(cov.reshape(n, 16), dtype=torch.float64).cuda().contiguous()
+    print(f"warp modes {name}[{idx}] side={side} mode={mode} heading={heading} per_object={per_object} "
+          f"kappa={kappa}", flush=True)
+    cls, ring = ctx.rasterize(sc["nx"], sc["ny"], sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"],
+                              robot_speed=sc["vr"], ring_mode=mode, heading=heading, per_object=per_object,
+                              kappa=kappa, cov=covt if kappa > 0 else None)
+    torch.cuda.synchronize()
+    want_c, want_r = orc.rasterize_modes(sc, ring_mode=mode, heading=heading, per_object=per_object,
+                                         kappa=kappa, cov=cov if kappa > 0 else None)
+    assert np.array_equal(ring.cpu().numpy(), want_r)
+    assert np.array_equal(cls.cpu().numpy(), want_c)
+
+
+def test_raster_warp_modes_full_size(ctx, orc):
+    sc = scenarios.scenario("replan2048", 1)
+    pos, vel, rad = scenario_tensors(sc)
+    n = len(sc["rad"])
+    cov = np.tile(0.25 * np.eye(4), (n, 1, 1))
+    covt = torch.as_tensor(cov.reshape(n, 16), dtype=torch.float64).cuda().contiguous()
+    print("warp modes replan2048[1] ellipse + per-object + kappa 1", flush=True)
+    cls, ring = ctx.rasterize(sc["nx"], sc["ny"], sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"],
+                              robot_speed=sc["vr"], ring_mode=1, heading=(0.8, -0.6), per_object=True,
+                              kappa=1.0, cov=covt)
+    torch.cuda.synchronize()
+    want_c, want_r = orc.rasterize_modes(sc, ring_mode=1, heading=(0.8, -0.6), per_object=True, kappa=1.0,
+                                         cov=cov)
+    assert np.array_equal(ring.cpu().numpy(), want_r)
+    assert np.array_equal(cls.cpu().numpy(), want_c)
+
+
+def test_raster_warp_modes_reject_bad_arguments(ctx):
+    from paper_1903_07441_amd import twg
+    sc = scenarios.scenario("static64", 0)
+    pos, vel, rad = scenario_tensors(sc)
+    for kw in (dict(ring_mode=2), dict(ring_mode=1, heading=(0.0, 0.0)), dict(kappa=-1.0),
+               dict(ring_mode=1, heading=(float("nan"), 1.0))):
+        with pytest.raises(twg.TwgError):
+            ctx.rasterize(sc["nx"], sc["ny"], sc["robot"], sc["goal"], pos, vel, rad, **kw)
