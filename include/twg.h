@@ -159,6 +159,26 @@ int32_t twg_rasterize(twg_ctx *ctx, twg_grid g, int32_t n_obs, const double *pos
                       const twg_raster_params *params, uint8_t *cls, uint16_t *ring,
                       void *stream);
 
+/* twg_kalman_step -- one step of the obstacles' Kalman filters (section
+ * "Kalman Filter", Eqs. 9-13), one thread per obstacle, FP64.  State
+ * [x, y, vx, vy] in cells and cells per step, constant-velocity model with
+ * time step dt: time update x <- A x, P <- A P A^T + Q with A = [[I, dt I],
+ * [0, I]] (Eqs. 9-10); then, if z is not NULL, measurement update with
+ * H = [I 0]: K = P H^T (H P H^T + R)^-1, x <- x + K (z - H x),
+ * P <- (I - K H) P (Eqs. 11-13, the 2x2 inverse written out).  Products are
+ * summed in index order, each operation rounded once.
+ *   x    n x 4 doubles (device), in/out.   P  n x 16 (row-major 4x4), in/out
+ *        (the covariance layout twg_raster_params.cov takes).
+ *   z    n x 2 measured positions (device) or NULL (prediction only).
+ *   Q    16 doubles (device) or NULL (no process noise); R 4 doubles (device),
+ *        required with z.
+ *   pos, vel  optional n x 2 outputs (device): the new state's position and
+ *        velocity, the arrays twg_rasterize takes.
+ * Asynchronous.  Errors: TWG_EINVAL (n < 0, NULL x/P with n > 0, z without
+ * R, dt not finite). */
+int32_t twg_kalman_step(twg_ctx *ctx, int32_t n, double *x, double *P, const double *z, double dt,
+                        const double *Q, const double *R, double *pos, double *vel, void *stream);
+
 /* ========================================================================= */
 /* Harmonic potential                                                        */
 /* ========================================================================= */

@@ -1096,4 +1096,18 @@ int32_t hpf_set_tiling(twg_ctx *ctx, int32_t nx, int32_t ny, int32_t S, int32_t 
     return TWG_OK;
 }
 
+int32_t twg_kalman_step(twg_ctx *ctx, int32_t n, double *x, double *P, const double *z, double dt,
+                        const double *Q, const double *R, double *pos, double *vel, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    if (n < 0) return set_err(ctx, TWG_EINVAL, "n < 0");
+    if (n > 0 && (!x || !P)) return set_err(ctx, TWG_EINVAL, "x and P are required");
+    if (z && !R) return set_err(ctx, TWG_EINVAL, "a measurement needs R");
+    if (!std::isfinite(dt)) return set_err(ctx, TWG_EINVAL, "dt must be finite");
+    hipSetDevice(ctx->device);
+    const int rc = launch_kalman(n, x, P, z, dt, Q, R, pos, vel, as_stream(stream));
+    return rc ? set_err(ctx, rc, "Kalman launch failed") : TWG_OK;
+}
+
 }  // extern "C"

@@ -136,6 +136,10 @@ int launch_rasterize(twg_ctx *ctx, const twg_grid &g, int n_obs, const double *p
                      const double *vel, const double *rad, const uint8_t *static_occ,
                      const twg_raster_params &p, uint8_t *cls, uint16_t *ring, hipStream_t st);
 
+// kalman.hip
+int launch_kalman(int n, double *x, double *P, const double *z, double dt, const double *Q, const double *R,
+                  double *pos, double *vel, hipStream_t st);
+
 // descend.hip
 int launch_index(const uint8_t *cls, const float *psi, const double *psi64, uint8_t *idx, int nx,
                  int ny, int pitch, hipStream_t st);

@@ -79,6 +79,7 @@ def _load():
         "hpf_merge_previous": (i32, [vp, Grid, vp, vp, vp, vp, vp]),
         "hpf_init_field": (i32, [vp, Grid, vp, vp, i32, vp]),
         "hpf_set_tiling": (i32, [vp, i32, i32, i32, i32, f32, i32, i32]),
+        "twg_kalman_step": (i32, [vp, i32, vp, vp, vp, f64, vp, vp, vp, vp, vp]),
         "twg_unet_num_params": (i32, []),
         "twg_unet_create": (i32, [vp, P(vp)]),
         "twg_unet_destroy": (i32, [vp]),
@@ -102,7 +103,7 @@ EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error"
             "twg_rasterize",
             "hpf_relax", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
             "hpf_index_matrix", "hpf_descend", "hpf_rubber_band", "hpf_merge_previous",
-            "hpf_init_field", "hpf_set_tiling", "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
+            "hpf_init_field", "hpf_set_tiling", "twg_kalman_step", "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
             "twg_unet_set_params", "twg_unet_get_params", "twg_unet_forward", "twg_unet_loss_grad",
             "twg_unet_adam_step", "twg_unet_features", "twg_unet_warm_start")
 
@@ -197,6 +198,22 @@ class Context:
                                _ptr(static_occ), ctypes.byref(p), _ptr(cls), _ptr(ring), _stream())
         self._check(rc)
         return cls, ring
+
+    def kalman_step(self, x, P, z=None, dt=1.0, Q=None, R=None, pos=None, vel=None):
+        """One Kalman step for every obstacle; x [n, 4] and P [n, 16] float64
+        device tensors are updated in place (z [n, 2] or None; Q [16] and
+        R [4] float64 device tensors or None)."""
+        n = int(x.shape[0])
+        for t, m in ((x, 4), (P, 16)):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n * m:
+                raise ValueError("x and P must be contiguous float64 device tensors [n, 4] and [n, 16]")
+        for t in (z, Q, R, pos, vel):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError("z, Q, R, pos, vel must be contiguous float64 device tensors")
+        rc = lib.twg_kalman_step(self.h, n, _ptr(x), _ptr(P), _ptr(z), float(dt), _ptr(Q), _ptr(R), _ptr(pos),
+                                 _ptr(vel), _stream())
+        self._check(rc)
+        return x, P
 
     # ---- relaxation --------------------------------------------------------
     def relax(self, cls, psi, psi64=None, tol=1e-6, tol_cert=0.0, max_sweeps=0, omega=0.0,
