@@ -368,6 +368,17 @@ int32_t hpf_descend(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *p
                     const double *psi64, const hpf_descend_params *params, int32_t *path_xy,
                     int32_t *info, void *stream);
 
+/* hpf_descent_all -- the steepest descent of hpf_descend from every cell at
+ * once: steps (device int32, row stride steps_pitch >= nx) receives, for each
+ * FREE or GOAL cell, the number of moves its descent takes to reach a GOAL
+ * cell (0 on GOAL cells), and -1 where the descent stops elsewhere (a cell
+ * with no strictly better neighbour) or the cell is not walkable.  Computed
+ * by pointer jumping over the index matrix (ceil(log2(nx ny)) rounds); on a
+ * converged field every FREE cell connected to the goal gets a length
+ * (discrete maximum principle).  Asynchronous.  Errors: TWG_EINVAL. */
+int32_t hpf_descent_all(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi, const double *psi64,
+                        int32_t *steps, int32_t steps_pitch, void *stream);
+
 /* hpf_rubber_band -- rubber-band smoothing of a path (section "Rubber Band
  * Model", Eqs. 4-6; Algorithm 1 "Path Planning").  The path's endpoints stay
  * fixed.  Each of `iters` iterations moves the interior points of odd index,

@@ -383,7 +383,8 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
     for (auto &g : ctx->graphs) hipGraphExecDestroy(g.exec);
     ctx->graphs.clear();
     if (ctx->cap) hipStreamDestroy(ctx->cap);
-    void *bufs[] = {ctx->alt, ctx->pol, ctx->alt64, ctx->pairs, ctx->idxbuf, ctx->batch, ctx->words, ctx->sink};
+    void *bufs[] = {ctx->alt, ctx->pol, ctx->alt64, ctx->pairs, ctx->idxbuf, ctx->batch, ctx->words, ctx->sink,
+                    ctx->jumpbuf};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (ctx->host_words) hipHostFree(ctx->host_words);
@@ -1108,6 +1109,29 @@ int32_t twg_kalman_step(twg_ctx *ctx, int32_t n, double *x, double *P, const dou
     hipSetDevice(ctx->device);
     const int rc = launch_kalman(n, x, P, z, dt, Q, R, pos, vel, as_stream(stream));
     return rc ? set_err(ctx, rc, "Kalman launch failed") : TWG_OK;
+}
+
+int32_t hpf_descent_all(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *psi, const double *psi64,
+                        int32_t *steps, int32_t steps_pitch, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_grid(ctx, g);
+    if (rc) return rc;
+    if (!cls || (!psi && !psi64) || !steps) return set_err(ctx, TWG_EINVAL, "missing argument");
+    if (steps_pitch < g.nx) return set_err(ctx, TWG_EINVAL, "steps_pitch must be >= nx");
+    hipSetDevice(ctx->device);
+    hipStream_t st = as_stream(stream);
+    const size_t cells = (size_t)g.nx * g.ny;
+    rc = ensure(ctx, &ctx->idxbuf, &ctx->idxbuf_bytes, (size_t)g.pitch * g.ny);
+    if (!rc) rc = ensure(ctx, &ctx->jumpbuf, &ctx->jumpbuf_bytes, 4 * cells * sizeof(int));
+    if (rc) return rc;
+    uint8_t *idx = reinterpret_cast<uint8_t *>(ctx->idxbuf);
+    rc = launch_index(cls, psi, psi64, idx, g.nx, g.ny, g.pitch, st);
+    if (!rc)
+        rc = launch_descent_all(cls, idx, g.nx, g.ny, g.pitch, reinterpret_cast<int *>(ctx->jumpbuf), steps,
+                                steps_pitch, st);
+    return rc ? set_err(ctx, rc, "descent launch failed") : TWG_OK;
 }
 
 }  // extern "C"

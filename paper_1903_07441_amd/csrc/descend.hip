@@ -16,6 +16,8 @@
 //            positions of their two neighbours (see hpf_rubber_band).
 #include "twg_internal.h"
 
+#include <utility>
+
 namespace twg {
 
 namespace {
@@ -121,6 +123,59 @@ __global__ __launch_bounds__(256) void k_walk(const uint8_t *__restrict__ cls,
     }
 }
 
+// Descent from every cell by pointer jumping over the index matrix: nxt[c]
+// is the cell one descent step from c (c itself at a GOAL cell or where the
+// index matrix has no move), len[c] the steps taken so far.  Each round
+// doubles the steps covered: nxt'[c] = nxt[nxt[c]], len'[c] = len[c] +
+// len[nxt[c]] (ping-pong buffers, so the rounds are order-free).  Descent
+// strictly raises psi, so the chains have no cycles and ceil(log2(cells))
+// rounds reach their ends.
+__global__ void k_jump_init(const uint8_t *__restrict__ cls, const uint8_t *__restrict__ idx, int nx, int ny,
+                            int pitch, int *__restrict__ nxt, int *__restrict__ len)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= nx || y >= ny) return;
+    const int c = y * nx + x;
+    const size_t i = (size_t)y * pitch + x;
+    const uint8_t k = cls[i];
+    const int d = idx[i];
+    int n = c, l = 0;
+    if (walkable(k) && k != TWG_CELL_GOAL && d < 4) {
+        const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+        n = (y + dy[d]) * nx + (x + dx[d]);
+        l = 1;
+    }
+    nxt[c] = n;
+    len[c] = l;
+}
+
+__global__ void k_jump(int total, const int *__restrict__ na, const int *__restrict__ la, int *__restrict__ nb,
+                       int *__restrict__ lb)
+{
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= total) return;
+    const int n = na[c];
+    nb[c] = na[n];
+    lb[c] = la[c] + la[n];
+}
+
+// steps[c] = descent length to a GOAL cell, or -1 (not walkable, or the
+// descent ends elsewhere)
+__global__ void k_jump_final(const uint8_t *__restrict__ cls, int nx, int ny, int pitch,
+                             const int *__restrict__ nxt, const int *__restrict__ len, int32_t *__restrict__ steps,
+                             int pitch_out)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= nx || y >= ny) return;
+    const int c = y * nx + x;
+    const int e = nxt[c];
+    const bool ok = walkable(cls[(size_t)y * pitch + x]) &&
+                    cls[(size_t)(e / nx) * pitch + (e % nx)] == TWG_CELL_GOAL;
+    steps[(size_t)y * pitch_out + x] = ok ? len[c] : -1;
+}
+
 // Candidate offsets: stay, E, W, S, N, then the diagonals.
 __constant__ int kRbDx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
 __constant__ int kRbDy[9] = {0, 0, 0, 1, -1, 1, 1, -1, -1};
@@ -188,6 +243,24 @@ int launch_rubber(const uint8_t *cls, const float *psi, const double *psi64, int
     else
         hipLaunchKernelGGL(k_rubber<float>, dim3(1), dim3(1024), 0, st, cls, psi, path, len, cap, nx, ny, pitch, k,
                            iters);
+    return hipGetLastError() == hipSuccess ? TWG_OK : TWG_EDEVICE;
+}
+
+int launch_descent_all(const uint8_t *cls, const uint8_t *idx, int nx, int ny, int pitch, int *buf,
+                       int32_t *steps, int pitch_out, hipStream_t st)
+{
+    const int total = nx * ny;
+    int *na = buf, *la = buf + total, *nb = buf + 2 * (size_t)total, *lb = buf + 3 * (size_t)total;
+    const dim3 grid((nx + 63) / 64, (ny + 3) / 4);
+    hipLaunchKernelGGL(k_jump_init, grid, dim3(256), 0, st, cls, idx, nx, ny, pitch, na, la);
+    int rounds = 1;
+    while ((1LL << rounds) < (long long)total) ++rounds;
+    for (int r = 0; r < rounds; ++r) {
+        hipLaunchKernelGGL(k_jump, dim3((total + 255) / 256), dim3(256), 0, st, total, na, la, nb, lb);
+        std::swap(na, nb);
+        std::swap(la, lb);
+    }
+    hipLaunchKernelGGL(k_jump_final, grid, dim3(256), 0, st, cls, nx, ny, pitch, na, la, steps, pitch_out);
     return hipGetLastError() == hipSuccess ? TWG_OK : TWG_EDEVICE;
 }
 

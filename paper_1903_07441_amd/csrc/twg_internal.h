@@ -42,6 +42,9 @@ struct twg_ctx {
     // index matrix of hpf_descend
     void *idxbuf = nullptr;
     size_t idxbuf_bytes = 0;
+    // pointer-jumping buffers of hpf_descent_all (4 int32 per cell)
+    void *jumpbuf = nullptr;
+    size_t jumpbuf_bytes = 0;
     // batched relaxation: descriptors, tile and block lists, per-grid words
     void *batch = nullptr;
     size_t batch_bytes = 0;
@@ -145,6 +148,8 @@ int launch_index(const uint8_t *cls, const float *psi, const double *psi64, uint
                  int ny, int pitch, hipStream_t st);
 int launch_walk(const uint8_t *cls, const uint8_t *idx, int nx, int ny, int pitch, int sx, int sy,
                 int cap, int32_t *path, int32_t *info, hipStream_t st);
+int launch_descent_all(const uint8_t *cls, const uint8_t *idx, int nx, int ny, int pitch, int *buf,
+                       int32_t *steps, int pitch_out, hipStream_t st);
 int launch_rubber(const uint8_t *cls, const float *psi, const double *psi64, int32_t *path, const int32_t *len,
                   int cap, int nx, int ny, int pitch, double k, int iters, hipStream_t st);
 

@@ -80,6 +80,7 @@ def _load():
         "hpf_init_field": (i32, [vp, Grid, vp, vp, i32, vp]),
         "hpf_set_tiling": (i32, [vp, i32, i32, i32, i32, f32, i32, i32]),
         "twg_kalman_step": (i32, [vp, i32, vp, vp, vp, f64, vp, vp, vp, vp, vp]),
+        "hpf_descent_all": (i32, [vp, Grid, vp, vp, vp, vp, i32, vp]),
         "twg_unet_num_params": (i32, []),
         "twg_unet_create": (i32, [vp, P(vp)]),
         "twg_unet_destroy": (i32, [vp]),
@@ -103,7 +104,8 @@ EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error"
             "twg_rasterize",
             "hpf_relax", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
             "hpf_index_matrix", "hpf_descend", "hpf_rubber_band", "hpf_merge_previous",
-            "hpf_init_field", "hpf_set_tiling", "twg_kalman_step", "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
+            "hpf_init_field", "hpf_set_tiling", "twg_kalman_step", "hpf_descent_all",
+            "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
             "twg_unet_set_params", "twg_unet_get_params", "twg_unet_forward", "twg_unet_loss_grad",
             "twg_unet_adam_step", "twg_unet_features", "twg_unet_warm_start")
 
@@ -299,6 +301,20 @@ class Context:
                                   _ptr(idx), _stream())
         self._check(rc)
         return idx
+
+    def descent_all(self, cls, psi=None, psi64=None, steps=None):
+        """Descent length to the goal from every cell (-1: does not reach it);
+        int32 device tensor [ny, nx]."""
+        t = psi if psi is not None else psi64
+        nx, ny, pitch = _grid_of(t)
+        if steps is None:
+            steps = torch.empty((ny, nx), dtype=torch.int32, device=t.device)
+        if steps.dtype != torch.int32 or steps.stride(1) != 1:
+            raise ValueError("steps must be an int32 grid")
+        rc = lib.hpf_descent_all(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(psi64), _ptr(steps),
+                                 int(steps.stride(0)), _stream())
+        self._check(rc)
+        return steps
 
     def descend(self, cls, psi=None, psi64=None, start=(0, 0), cap=None, path=None, info=None):
         """Returns (path tensor [cap, 2] int32, info tensor [2] int32 = [len, status]);

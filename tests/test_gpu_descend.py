@@ -152,3 +152,33 @@ def test_rubber_band_parity(ctx, orc, name, idx, k):
         got = dev_path.cpu().numpy()
         assert np.array_equal(got[:len(path)], ref), (name, idx, fp64)
         assert np.all(got[len(path):] == 0)
+
+
+@pytest.mark.parametrize("name,idx,side,pitch_pad", [("static64", 2, None, 0), ("warped512", 4, 120, 5)])
+def test_descent_from_every_cell(ctx, orc, name, idx, side, pitch_pad):
+    """Pointer-jumping descent from every cell equals the oracle's walk from
+    each cell (length to the goal, or -1), on the oracle's field."""
+    sc = scenarios.scenario(name, idx, side=side)
+    cls_o, _ = orc.rasterize(sc)
+    psi, _ = orc.relax(cls_o, tol=1e-12)
+    ny, nx = cls_o.shape
+    want = np.full((ny, nx), -1, np.int64)
+    for y in range(ny):
+        for x in range(nx):
+            if cls_o[y, x] in (orc.FREE, orc.GOAL):
+                st, p = orc.descend(cls_o, psi, (x, y))
+                if st == orc.OK:
+                    want[y, x] = len(p) - 1
+    pitch = nx + pitch_pad
+    c = torch.zeros((ny, pitch), dtype=torch.uint8, device="cuda")[:, :nx]
+    c.copy_(torch.as_tensor(cls_o))
+    f = torch.zeros((ny, pitch), dtype=torch.float64, device="cuda")[:, :nx]
+    f.copy_(torch.as_tensor(psi))
+    print(f"descent from every cell {name}[{idx}] {nx}x{ny}", flush=True)
+    steps = ctx.descent_all(c, psi64=f)
+    torch.cuda.synchronize()
+    got = steps.cpu().numpy()
+    assert np.array_equal(got, want)
+    # discrete maximum principle: every FREE cell that can reach the goal does
+    reach = (want >= 0) | (cls_o != orc.FREE)
+    assert reach.mean() > 0.5
