@@ -141,6 +141,41 @@ def main():
     cell_updates = cells * plain["sweeps"]
     cups = cell_updates / (med[1] * 1e-3)
 
+    # ---- descent from every cell: what the FP64 polish buys ----
+    steps_all = torch.empty((ny, nx), dtype=torch.int32, device=dev)
+    free_n = int((cls == twg.FREE).sum().item())
+
+    def reach_frac(**field):
+        ctx.descent_all(cls, steps=steps_all, **field)
+        return round(int(((steps_all >= 0) & (cls == twg.FREE)).sum().item()) / max(1, free_n), 6)
+
+    descent_all = {"fp64_polished": reach_frac(psi64=psi64)}
+    ctx.relax(cls, psi, None, tol=1e-6, init=twg.INIT_HALF)
+    descent_all["fp32_residual_1e-6"] = reach_frac(psi=psi)
+    e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e_a.record()
+    ctx.descent_all(cls, psi64=psi64, steps=steps_all)
+    e_b.record()
+    torch.cuda.synchronize()
+    descent_all["ms"] = round(e_a.elapsed_time(e_b), 3)
+    descent_all["what"] = "share of FREE cells whose steepest descent reaches the goal"
+    log(f"descent from every cell: {descent_all}")
+
+    # ---- the paper's own mode: cleared grid, a fixed 100 Gauss-Seidel iterations ----
+    psi_p = torch.empty_like(psi)
+    ctx.init_field(cls, psi_p, twg.INIT_HALF)
+    e_a.record()
+    ctx.sweeps(cls, psi_p, 1.0, 100)
+    e_b.record()
+    torch.cuda.synchronize()
+    paper_mode = {"ms": round(e_a.elapsed_time(e_b), 3), "sweeps": 100, "omega": 1.0,
+                  "residual": ctx.residual(cls, psi=psi_p), "reach_frac": reach_frac(psi=psi_p)}
+    ctx.descend(cls, psi=psi_p, start=sc["robot"], cap=cap, path=path, info=info)
+    pm_n, pm_s = info.cpu().tolist()
+    paper_mode["descent_from_robot"] = {"status": pm_s, "length": pm_n, "reached_goal": pm_s == twg.OK}
+    log(f"paper mode: {paper_mode}")
+    ctx.descend(cls, psi64=psi64, start=sc["robot"], cap=cap, path=path, info=info)  # restore the path
+
     # ---- roofline of the dominant kernel (streamed SOR pass), timed live ----
     S = tuning["S"]
     passes = 200
@@ -226,9 +261,20 @@ def main():
     # only reported)
     route = path[:max(1, n)].cpu().numpy().tolist() if status == twg.OK else [list(sc["robot"])]
 
-    def run_loop(net_l):
+    def run_loop(net_l, sigma):
+        # true obstacles move at constant velocity; each step the filters
+        # (twg_kalman_step) take a position measurement with noise sigma
+        # (R = 0.25 I) and the map is rasterised from their estimates
         pos0 = np.asarray(sc["pos"], dtype=np.float64)
         vel0 = np.asarray(sc["vel"], dtype=np.float64)
+        n_o = len(pos0)
+        meas = np.random.default_rng(sc["seed"] + 77)
+        kx = torch.as_tensor(np.concatenate([pos0, vel0], axis=1), dtype=torch.float64, device=dev).contiguous()
+        kP = torch.as_tensor(np.tile(0.25 * np.eye(4).reshape(16), (n_o, 1)), dtype=torch.float64,
+                             device=dev).contiguous()
+        kR = torch.as_tensor((0.25 * np.eye(2)).reshape(4), dtype=torch.float64, device=dev)
+        est_p = torch.empty((n_o, 2), dtype=torch.float64, device=dev)
+        est_v = torch.empty((n_o, 2), dtype=torch.float64, device=dev)
         robot = [int(sc["robot"][0]), int(sc["robot"][1])]
         cls_prev = torch.empty_like(cls)
         psi_prev = torch.empty_like(psi)
@@ -243,9 +289,15 @@ def main():
         # fastest; the first warm step picks one from a fixed family
         w_warm, w_trials, w_cold, c_trials = None, {}, 0.0, {}
         for k in range(args.loop_steps + 1):
-            pk = torch.as_tensor(pos0 + k * vel0, dtype=torch.float64, device=dev).contiguous()
+            zk = torch.as_tensor(pos0 + k * vel0 + sigma * meas.normal(0.0, 1.0, size=(n_o, 2)),
+                                 dtype=torch.float64, device=dev).contiguous()
             e[0].record()
-            ctx.rasterize(nx, ny, robot, sc["goal"], pk, vel, rad, W=sc["W"], robot_speed=sc["vr"],
+            if k == 0:
+                est_p.copy_(kx[:, :2])
+                est_v.copy_(kx[:, 2:])
+            else:
+                ctx.kalman_step(kx, kP, zk, dt=1.0, R=kR, pos=est_p, vel=est_v)
+            ctx.rasterize(nx, ny, robot, sc["goal"], est_p, est_v, rad, W=sc["W"], robot_speed=sc["vr"],
                           cls=cls_k, ring=ring_k)
             if net_l is not None:
                 net_l.warm_start(cls_k, ring_k, sc["goal"], psi_k)
@@ -308,17 +360,24 @@ def main():
                 "cold_omega": w_cold, "cold_omega_trials_ms": {str(a): round(b * 1e3, 3) for a, b in c_trials.items()},
                 "warm_start": ("previous field + network where the map changed" if net_l is not None
                                else "previous field + 0.5 where the map changed"),
-                "step": "rasterise + warm start + FP32 relax to residual 1e-6 + descent (FP32 field)"}
+                "measurement_sigma": sigma,
+                "step": "Kalman update of all obstacles from noisy positions + rasterise + warm start + "
+                        "FP32 relax to residual 1e-6 + descent (FP32 field)"}
         log(f"loop: {loop}")
         return loop
 
     loop = None
     if args.loop_steps > 0:
-        loop = {"previous_field": run_loop(None)}
+        net_l = None
         if learned is not None:
             from paper_1903_07441_amd import learn as _learn
             net_l = twg.UNet(ctx, torch.as_tensor(_learn.load_weights(wpath)[0]))
-            loop["previous_field_and_network"] = run_loop(net_l)
+        loop = {}
+        for sigma, tag in ((0.0, "exact_measurements"), (0.5, "noisy_measurements")):
+            loop[tag] = {"previous_field": run_loop(None, sigma)}
+            if net_l is not None:
+                loop[tag]["previous_field_and_network"] = run_loop(net_l, sigma)
+        if net_l is not None:
             net_l.close()
 
     # ---- batched leg: 256 grids of uneven size, one relaxation call ----
@@ -413,6 +472,8 @@ def main():
         "roofline_alu": roofline_alu,
         "roofline_mfma": roofline_mfma,
         "batched": batch,
+        "descent_from_every_cell": descent_all,
+        "paper_mode": paper_mode,
         "replan_loop": loop,
         "cpu_baseline": cpu,
     }
