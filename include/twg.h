@@ -197,9 +197,9 @@ typedef struct {
     int32_t init;            /* HPF_INIT_* */
     int32_t polish;          /* 0: FP32 only; 1: FP64 defect correction (FP32 correction
                                 solves); 2: FP64 red-black SOR sweeps */
-    int32_t sweeps_per_pass; /* red-black sweeps per tile load, 1..16; 0 = tuned */
+    int32_t sweeps_per_pass; /* red-black sweeps per tile load (1, 2, 3, 4, 6, 8); 0 = tuned */
     int32_t check_passes;    /* passes between residual checks; 0 = adaptive */
-    int32_t reserved;
+    int32_t rows_per_tile;   /* output rows per tile (even, >= 2); 0 = tuned */
 } hpf_params;
 
 typedef struct {
@@ -262,8 +262,8 @@ typedef struct {
  * above tolerance, and the FP64 residuals of all grids are reduced in one
  * launch; a grid drops out of the pass sequence as soon as it meets tol.  Grid k's class map and field start at element offset
  * grids[k].offset of cls and psi (the grids must not overlap).  Sweeps per
- * tile load come from the autotuned entry of the largest grid (or
- * params->sweeps_per_pass); each grid's SOR factor is params->omega, else its
+ * tile load and rows per tile come from the autotuned entry of the largest
+ * grid (or params->sweeps_per_pass / rows_per_tile); each grid's SOR factor is params->omega, else its
  * size's autotuned factor, else its open-rectangle optimum.  polish must be 0.
  * stats: host array of n entries, or NULL.  Blocking.  Returns TWG_OK when
  * every grid converged, else TWG_NOT_CONVERGED.  Errors: TWG_EINVAL (n < 1,

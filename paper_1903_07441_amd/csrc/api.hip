@@ -174,8 +174,7 @@ struct Runner {
     // FP64 residual of an FP32 field: *out = max |r|, *rel = max |r| / |u|
     int residual32(const float *u, const float *f, double *out, double *rel = nullptr)
     {
-        int rc = launch_zero_words(ctx->words, 2, st);
-        if (!rc) rc = launch_resid_f32(cls, u, f, g.nx, g.ny, g.pitch, ctx->words, st);
+        int rc = launch_resid_f32(cls, u, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st);
         if (!rc) rc = readback(2);
         if (rc) return set_err(ctx, rc, "residual kernel failed");
         *out = bits_to_double(ctx->host_words[0]);
@@ -287,8 +286,7 @@ struct Runner {
     // FP64 residual of an FP64 field
     int residual64(const double *u, double *out)
     {
-        int rc = launch_zero_words(ctx->words, 2, st);
-        if (!rc) rc = launch_resid_f64(cls, u, nullptr, g.nx, g.ny, g.pitch, ctx->words, st);
+        int rc = launch_resid_f64(cls, u, nullptr, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st);
         if (!rc) rc = readback(2);
         if (rc) return set_err(ctx, rc, "residual kernel failed");
         *out = bits_to_double(ctx->host_words[0]);
@@ -366,6 +364,7 @@ int32_t twg_ctx_create(twg_ctx **out, int32_t device)
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
     if (hipMalloc(&ctx->words, kWords * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&ctx->sink, 1024) != hipSuccess ||
+        hipMalloc(&ctx->rpart, 2 * kResidBlocks * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc(&ctx->host_words, kWords * sizeof(unsigned long long), hipHostMallocDefault) !=
             hipSuccess) {
         twg_ctx_destroy(ctx);
@@ -384,7 +383,7 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
     ctx->graphs.clear();
     if (ctx->cap) hipStreamDestroy(ctx->cap);
     void *bufs[] = {ctx->alt, ctx->pol, ctx->alt64, ctx->pairs, ctx->idxbuf, ctx->batch, ctx->words, ctx->sink,
-                    ctx->jumpbuf};
+                    ctx->jumpbuf, ctx->rpart};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (ctx->host_words) hipHostFree(ctx->host_words);
@@ -449,6 +448,8 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
     if (p.polish && !psi64) return set_err(ctx, TWG_EINVAL, "polish needs psi64");
     if (p.sweeps_per_pass && !stream_depth_supported(p.sweeps_per_pass))
         return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
+    if (p.rows_per_tile && (p.rows_per_tile < 2 || (p.rows_per_tile & 1)))
+        return set_err(ctx, TWG_EINVAL, "rows_per_tile must be even and >= 2");
     if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
     hipSetDevice(ctx->device);
     hipStream_t st = as_stream(stream);
@@ -457,6 +458,7 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
     tiling_for(ctx, g.nx, g.ny, &S, &RH, &omega_t);
     const float omega = p.omega > 0.0f ? p.omega : omega_t;
     if (p.sweeps_per_pass) S = p.sweeps_per_pass;
+    if (p.rows_per_tile) RH = p.rows_per_tile;
     const double wb = std::pow((double)std::min(g.nx, g.ny) + 1.0, 2) / 2.0;
 
     Runner run{ctx, g, cls, st};
@@ -503,8 +505,7 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
         // residual the result must reach: tol, and tol_cert / wbound if set
         const double need = p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / wb) : p.tol;
         for (int round = 0; round < 12; ++round) {
-            rc = launch_zero_words(ctx->words, 2, st);
-            if (!rc) rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->words, st);
+            rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st);
             if (!rc) rc = run.readback(1);
             if (rc) return set_err(ctx, rc, "defect kernel failed");
             r64 = bits_to_double(ctx->host_words[0]);
@@ -552,6 +553,8 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
     if (p.polish) return set_err(ctx, TWG_EINVAL, "the batched relaxation has no polish");
     if (p.sweeps_per_pass && !stream_depth_supported(p.sweeps_per_pass))
         return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
+    if (p.rows_per_tile && (p.rows_per_tile < 2 || (p.rows_per_tile & 1)))
+        return set_err(ctx, TWG_EINVAL, "rows_per_tile must be even and >= 2");
     if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
     int big = 0;
     long long total = 0;
@@ -569,6 +572,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
     float om_big;
     tiling_for(ctx, grids[big].nx, grids[big].ny, &S, &RH, &om_big);
     if (p.sweeps_per_pass) S = p.sweeps_per_pass;
+    if (p.rows_per_tile) RH = p.rows_per_tile;
     const int VW = 128 - 4 * S;
 
     // host descriptors, full tile and block lists
@@ -988,10 +992,8 @@ int32_t hpf_residual(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *
     if (!cls || (!psi && !psi64) || !out) return set_err(ctx, TWG_EINVAL, "missing argument");
     hipSetDevice(ctx->device);
     hipStream_t st = as_stream(stream);
-    rc = launch_zero_words(ctx->words, 2, st);
-    if (!rc)
-        rc = psi64 ? launch_resid_f64(cls, psi64, f, g.nx, g.ny, g.pitch, ctx->words, st)
-                   : launch_resid_f32(cls, psi, f, g.nx, g.ny, g.pitch, ctx->words, st);
+    rc = psi64 ? launch_resid_f64(cls, psi64, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st)
+               : launch_resid_f32(cls, psi, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st);
     Runner run{ctx, g, cls, st};
     if (!rc) rc = run.readback(1);
     if (rc) return set_err(ctx, rc, "residual kernel failed");

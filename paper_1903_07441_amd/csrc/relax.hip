@@ -44,15 +44,16 @@ __device__ __forceinline__ double block_max(double v)
     return nanmax(nanmax(part[0], part[1]), nanmax(part[2], part[3]));
 }
 
-// Residual |avg4(u) + f - u| over FREE cells; the max's bit pattern goes to
-// out[0] by atomicMax (non-negative doubles order like their bit patterns; a
-// NaN anywhere yields a NaN pattern, which is larger than +inf).  out[1]
-// receives max |r| / |u| over FREE cells with |u| >= 1e-30.
+// Residual |avg4(u) + f - u| over FREE cells; each block writes the bit
+// pattern of its max to part[2 b] (non-negative doubles order like their bit
+// patterns; a NaN yields a NaN pattern, which is larger than +inf) and of its
+// max |r| / |u| over FREE cells with |u| >= 1e-30 to part[2 b + 1];
+// k_resid_reduce combines the blocks (no same-address atomics).
 template <typename T, bool RHS, bool WRITE_R32>
 __global__ __launch_bounds__(256) void k_resid(const uint8_t *__restrict__ cls,
                                                const T *__restrict__ u, const float *__restrict__ f,
                                                float *__restrict__ r32, int nx, int ny, int pitch,
-                                               unsigned long long *out)
+                                               unsigned long long *__restrict__ part)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     double m = 0.0, mr = 0.0;
@@ -80,8 +81,36 @@ __global__ __launch_bounds__(256) void k_resid(const uint8_t *__restrict__ cls,
     __syncthreads();
     mr = block_max(mr);
     if (threadIdx.x == 0) {
-        atomicMax(out, (unsigned long long)__double_as_longlong(m));
-        atomicMax(out + 1, (unsigned long long)__double_as_longlong(mr));
+        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        part[2 * b] = (unsigned long long)__double_as_longlong(m);
+        part[2 * b + 1] = (unsigned long long)__double_as_longlong(mr);
+    }
+}
+
+// out[0], out[1] = maxima of the n block partials (bit patterns of
+// non-negative doubles, or NaN patterns, which compare larger)
+__global__ __launch_bounds__(256) void k_resid_reduce(const unsigned long long *__restrict__ part, int n,
+                                                      unsigned long long *out)
+{
+    __shared__ unsigned long long red[2][256];
+    unsigned long long a = 0, b = 0;
+    for (int k = threadIdx.x; k < n; k += 256) {
+        a = max(a, part[2 * k]);
+        b = max(b, part[2 * k + 1]);
+    }
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] = max(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+            red[1][threadIdx.x] = max(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = red[0][0];
+        out[1] = red[1][0];
     }
 }
 
@@ -247,11 +276,6 @@ __global__ void k_copy(const float *__restrict__ s, float *__restrict__ d, int n
     d[i] = s[i];
 }
 
-__global__ void k_zero_words(unsigned long long *w, int n)
-{
-    if ((int)threadIdx.x < n) w[threadIdx.x] = 0ull;
-}
-
 dim3 cell_grid(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); }
 
 int last_status()
@@ -321,43 +345,57 @@ int launch_sweep_color_f64(const uint8_t *cls, double *psi, const double *f, int
     return last_status();
 }
 
+// at most kResidBlocks blocks: 64 columns per block across, rows split so
+// that the partial buffer of the context holds every block
 static dim3 resid_grid(int nx, int ny)
 {
+    const int gx = (nx + 63) / 64;
     int gy = (ny + 3) / 4;
     if (gy > 64) gy = 64;
-    return dim3((nx + 63) / 64, gy);
+    const int cap = kResidBlocks / gx;
+    if (gy > cap) gy = cap > 0 ? cap : 1;
+    return dim3(gx, gy);
+}
+
+static int finish_resid(const dim3 &g, const unsigned long long *part, unsigned long long *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_resid_reduce, dim3(1), dim3(256), 0, st, part, (int)(g.x * g.y), out);
+    return last_status();
 }
 
 int launch_resid_f32(const uint8_t *cls, const float *u, const float *f, int nx, int ny, int pitch,
-                     unsigned long long *out, hipStream_t st)
+                     unsigned long long *part, unsigned long long *out, hipStream_t st)
 {
+    const dim3 g = resid_grid(nx, ny);
     if (f)
-        hipLaunchKernelGGL((k_resid<float, true, false>), resid_grid(nx, ny), dim3(256), 0, st, cls, u,
-                           f, nullptr, nx, ny, pitch, out);
+        hipLaunchKernelGGL((k_resid<float, true, false>), g, dim3(256), 0, st, cls, u, f, nullptr, nx, ny, pitch,
+                           part);
     else
-        hipLaunchKernelGGL((k_resid<float, false, false>), resid_grid(nx, ny), dim3(256), 0, st, cls,
-                           u, f, nullptr, nx, ny, pitch, out);
-    return last_status();
+        hipLaunchKernelGGL((k_resid<float, false, false>), g, dim3(256), 0, st, cls, u, f, nullptr, nx, ny,
+                           pitch, part);
+    return finish_resid(g, part, out, st);
 }
 
 int launch_resid_f64(const uint8_t *cls, const double *u, const float *f, int nx, int ny, int pitch,
-                     unsigned long long *out, hipStream_t st)
+                     unsigned long long *part, unsigned long long *out, hipStream_t st)
 {
+    const dim3 g = resid_grid(nx, ny);
     if (f)
-        hipLaunchKernelGGL((k_resid<double, true, false>), resid_grid(nx, ny), dim3(256), 0, st, cls,
-                           u, f, nullptr, nx, ny, pitch, out);
+        hipLaunchKernelGGL((k_resid<double, true, false>), g, dim3(256), 0, st, cls, u, f, nullptr, nx, ny,
+                           pitch, part);
     else
-        hipLaunchKernelGGL((k_resid<double, false, false>), resid_grid(nx, ny), dim3(256), 0, st, cls,
-                           u, f, nullptr, nx, ny, pitch, out);
-    return last_status();
+        hipLaunchKernelGGL((k_resid<double, false, false>), g, dim3(256), 0, st, cls, u, f, nullptr, nx, ny,
+                           pitch, part);
+    return finish_resid(g, part, out, st);
 }
 
 int launch_defect64(const uint8_t *cls, const double *u, float *r32, int nx, int ny, int pitch,
-                    unsigned long long *out, hipStream_t st)
+                    unsigned long long *part, unsigned long long *out, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_resid<double, false, true>), resid_grid(nx, ny), dim3(256), 0, st, cls, u,
-                       nullptr, r32, nx, ny, pitch, out);
-    return last_status();
+    const dim3 g = resid_grid(nx, ny);
+    hipLaunchKernelGGL((k_resid<double, false, true>), g, dim3(256), 0, st, cls, u, nullptr, r32, nx, ny, pitch,
+                       part);
+    return finish_resid(g, part, out, st);
 }
 
 int launch_update64(const uint8_t *cls, double *u, const float *e, float *psi, int nx, int ny,
@@ -396,12 +434,6 @@ int launch_merge_prev(const uint8_t *cls, const uint8_t *cls_prev, const float *
 {
     hipLaunchKernelGGL(k_merge_prev, cell_grid(nx, ny), dim3(256), 0, st, cls, cls_prev, psi_prev, psi, nx, ny,
                        pitch);
-    return last_status();
-}
-
-int launch_zero_words(unsigned long long *w, int n, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, w, n);
     return last_status();
 }
 

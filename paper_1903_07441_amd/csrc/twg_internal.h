@@ -54,6 +54,8 @@ struct twg_ctx {
     unsigned long long *words = nullptr;
     // 1 KiB that the relaxation kernels' halo lanes store into (never read)
     void *sink = nullptr;
+    // per-block partial maxima of the residual kernels (2 kResidBlocks words)
+    unsigned long long *rpart = nullptr;
     // pinned host mirror of `words`
     unsigned long long *host_words = nullptr;
     // instantiated graphs of relaxation passes, keyed by their launch
@@ -118,19 +120,21 @@ int launch_stream_f32(const float *src, float *dst, const uint8_t *cls, const fl
                       int ny, int pitch, float omega, const Geometry &geo, void *sink, hipStream_t st);
 int launch_stream_f64(const double *src, double *dst, const uint8_t *cls, const double *f, int nx,
                       int ny, int pitch, double omega, const Geometry &geo, void *sink, hipStream_t st);
+// residual reductions: part = the context's block partials (2 kResidBlocks
+// words), out = 2 words receiving max |r| and max |r| / |u|
+constexpr int kResidBlocks = 4096;
 int launch_resid_f32(const uint8_t *cls, const float *u, const float *f, int nx, int ny, int pitch,
-                     unsigned long long *out, hipStream_t st);
+                     unsigned long long *part, unsigned long long *out, hipStream_t st);
 int launch_resid_f64(const uint8_t *cls, const double *u, const float *f, int nx, int ny, int pitch,
-                     unsigned long long *out, hipStream_t st);
+                     unsigned long long *part, unsigned long long *out, hipStream_t st);
 int launch_defect64(const uint8_t *cls, const double *u, float *r32, int nx, int ny, int pitch,
-                    unsigned long long *out, hipStream_t st);
+                    unsigned long long *part, unsigned long long *out, hipStream_t st);
 int launch_update64(const uint8_t *cls, double *u, const float *e, float *psi, int nx, int ny,
                     int pitch, hipStream_t st);
 int launch_widen(const float *psi, double *u, int nx, int ny, int pitch, hipStream_t st);
 int launch_narrow(const double *u, float *psi, int nx, int ny, int pitch, hipStream_t st);
 int launch_fill_f32(float *a, float v, int nx, int ny, int pitch, hipStream_t st);
 int launch_copy_f32(const float *src, float *dst, int nx, int ny, int pitch, hipStream_t st);
-int launch_zero_words(unsigned long long *w, int n, hipStream_t st);
 int launch_merge_prev(const uint8_t *cls, const uint8_t *cls_prev, const float *psi_prev, float *psi, int nx,
                       int ny, int pitch, hipStream_t st);
 

@@ -35,7 +35,7 @@ class RasterParams(ctypes.Structure):
 class HpfParams(ctypes.Structure):
     _fields_ = [("tol", f64), ("tol_cert", f64), ("max_sweeps", i64), ("omega", f32),
                 ("init", i32), ("polish", i32), ("sweeps_per_pass", i32), ("check_passes", i32),
-                ("reserved", i32)]
+                ("rows_per_tile", i32)]
 
 
 class HpfStats(ctypes.Structure):
@@ -219,7 +219,7 @@ class Context:
 
     # ---- relaxation --------------------------------------------------------
     def relax(self, cls, psi, psi64=None, tol=1e-6, tol_cert=0.0, max_sweeps=0, omega=0.0,
-              init=INIT_HALF, polish=0, sweeps_per_pass=0, check_passes=0):
+              init=INIT_HALF, polish=0, sweeps_per_pass=0, check_passes=0, rows_per_tile=0):
         """polish: 0 FP32 only, 1 (or True) FP64 defect correction, 2 FP64 SOR sweeps."""
         nx, ny, pitch = _grid_of(psi)
         if psi.dtype != torch.float32 or cls.dtype != torch.uint8 or cls.stride(0) != pitch:
@@ -227,7 +227,7 @@ class Context:
         if psi64 is not None and (psi64.dtype != torch.float64 or psi64.stride(0) != pitch):
             raise ValueError("psi64 must be float64 with the same pitch")
         prm = HpfParams(float(tol), float(tol_cert), int(max_sweeps), float(omega), int(init),
-                        int(polish), int(sweeps_per_pass), int(check_passes), 0)
+                        int(polish), int(sweeps_per_pass), int(check_passes), int(rows_per_tile))
         st = HpfStats()
         rc = lib.hpf_relax(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(psi64),
                            ctypes.byref(prm), ctypes.byref(st), _stream())
@@ -235,7 +235,7 @@ class Context:
         return st.as_dict()
 
     def relax_batched(self, cls_flat, psi_flat, descs, tol=1e-6, max_sweeps=0, omega=0.0,
-                      init=INIT_HALF, sweeps_per_pass=0, check_passes=0):
+                      init=INIT_HALF, sweeps_per_pass=0, check_passes=0, rows_per_tile=0):
         """Relax many grids packed in one flat uint8 class buffer and one flat
         float32 field buffer; descs = [(nx, ny, pitch, offset), ...] (offsets in
         elements).  Returns one stats dict per grid."""
@@ -249,7 +249,7 @@ class Context:
             if d + c * b > min(cls_flat.numel(), psi_flat.numel()):
                 raise ValueError("a grid extends past the batch buffers")
         prm = HpfParams(float(tol), 0.0, int(max_sweeps), float(omega), int(init), 0,
-                        int(sweeps_per_pass), int(check_passes), 0)
+                        int(sweeps_per_pass), int(check_passes), int(rows_per_tile))
         st = (HpfStats * n)()
         rc = lib.hpf_relax_batched(self.h, n, arr, _ptr(cls_flat), _ptr(psi_flat), ctypes.byref(prm),
                                    st, _stream())
