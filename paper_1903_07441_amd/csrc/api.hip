@@ -42,6 +42,7 @@ int check_grid(twg_ctx *ctx, const twg_grid &g)
     if (g.pitch < g.nx) return set_err(ctx, TWG_EINVAL, "pitch must be >= nx");
     if ((long long)g.pitch * g.ny >= (1LL << 31))
         return set_err(ctx, TWG_EINVAL, "pitch * ny must be below 2^31 elements");
+    if (g.pitch > 65536) return set_err(ctx, TWG_EINVAL, "pitch must be <= 65536");
     return TWG_OK;
 }
 
@@ -210,7 +211,7 @@ struct Runner {
             int rc = graph_replay(ctx, key, st, reps, [&](hipStream_t cs) {
                 for (int k = 0; k < kGraphPasses; ++k) {
                     const int e = launch_stream_f32(k % 2 ? y : x, k % 2 ? x : y, cls, f, g.nx, g.ny, g.pitch,
-                                                    omega, geo, ctx->sink, cs);
+                                                    omega, geo, cs);
                     if (e) return e;
                 }
                 return TWG_OK;
@@ -220,7 +221,7 @@ struct Runner {
         }
         while (done < sweeps) {
             const bool full = sweeps - done >= S;
-            int rc = launch_stream_f32(*a, *b, cls, f, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, ctx->sink, st);
+            int rc = launch_stream_f32(*a, *b, cls, f, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, st);
             if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
             std::swap(*a, *b);
             done += full ? S : 1;
@@ -319,7 +320,7 @@ struct Runner {
             int64_t chunk = std::max<int64_t>((int64_t)std::ceil(want * 1.05) + S, 8 * S);
             chunk = ((std::min(chunk, max_sweeps - done) + S - 1) / S) * S;
             for (int64_t k = 0; k < chunk; k += S) {
-                rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, geo, ctx->sink, st);
+                rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, geo, st);
                 if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
                 std::swap(a, b);
             }
@@ -363,7 +364,6 @@ int32_t twg_ctx_create(twg_ctx **out, int32_t device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
     if (hipMalloc(&ctx->words, kWords * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&ctx->sink, 1024) != hipSuccess ||
         hipMalloc(&ctx->rpart, 2 * kResidBlocks * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc(&ctx->host_words, kWords * sizeof(unsigned long long), hipHostMallocDefault) !=
             hipSuccess) {
@@ -382,8 +382,8 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
     for (auto &g : ctx->graphs) hipGraphExecDestroy(g.exec);
     ctx->graphs.clear();
     if (ctx->cap) hipStreamDestroy(ctx->cap);
-    void *bufs[] = {ctx->alt, ctx->pol, ctx->alt64, ctx->pairs, ctx->idxbuf, ctx->batch, ctx->words, ctx->sink,
-                    ctx->jumpbuf, ctx->rpart};
+    void *bufs[] = {ctx->alt, ctx->pol, ctx->alt64, ctx->pairs, ctx->idxbuf, ctx->batch, ctx->words, ctx->jumpbuf,
+                    ctx->rpart};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (ctx->host_words) hipHostFree(ctx->host_words);
@@ -574,6 +574,15 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
     if (p.sweeps_per_pass) S = p.sweeps_per_pass;
     if (p.rows_per_tile) RH = p.rows_per_tile;
     const int VW = 128 - 4 * S;
+    // paired column access when every grid allows it; tiles within the
+    // streamed kernels' addressable span
+    bool pair = (reinterpret_cast<uintptr_t>(psi) & 7) == 0 && (reinterpret_cast<uintptr_t>(cls) & 1) == 0;
+    int max_pitch = 1;
+    for (int k = 0; k < n; ++k) {
+        pair = pair && grids[k].nx % 2 == 0 && grids[k].pitch % 2 == 0 && grids[k].offset % 2 == 0;
+        max_pitch = std::max(max_pitch, grids[k].pitch);
+    }
+    RH = std::min(RH < 2 ? 2 : (RH & ~1), stream_rows_cap(max_pitch, (int)sizeof(float), S));
 
     // host descriptors, full tile and block lists
     std::vector<BatchGrid> bg(n);
@@ -710,12 +719,12 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
         if (reps > 0) {
             const std::vector<uintptr_t> key = {2, (uintptr_t)cur, (uintptr_t)nxt, (uintptr_t)cls,
                                                 (uintptr_t)d_grids, (uintptr_t)d_tiles, (uintptr_t)d_count,
-                                                (uintptr_t)max_tiles0, (uintptr_t)S};
+                                                (uintptr_t)max_tiles0, (uintptr_t)S, (uintptr_t)pair};
             float *x = cur, *y = nxt;
             rc = graph_replay(ctx, key, st, reps, [&](hipStream_t cs) {
                 for (int k = 0; k < kGraphPasses; ++k) {
                     const int e = launch_stream_batch(k % 2 ? y : x, k % 2 ? x : y, cls, d_grids, d_tiles, d_count,
-                                                      max_tiles0, S, ctx->sink, cs);
+                                                      max_tiles0, S, pair, cs);
                     if (e) return e;
                 }
                 return TWG_OK;
@@ -723,7 +732,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
             if (rc) return set_err(ctx, rc, "batched relaxation graph failed");
         }
         for (int64_t q = reps * kGraphPasses; q < passes; ++q) {
-            rc = launch_stream_batch(cur, nxt, cls, d_grids, d_tiles, d_count, (int)tl.size(), S, ctx->sink, st);
+            rc = launch_stream_batch(cur, nxt, cls, d_grids, d_tiles, d_count, (int)tl.size(), S, pair, st);
             if (rc) return set_err(ctx, rc, "batched relaxation launch failed");
             std::swap(cur, nxt);
         }
@@ -847,12 +856,12 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
                 passes += passes & 1;
                 double *x = a64, *y = b64;
                 for (int k = 0; k < 2 && !rc; ++k) {  // warm-up
-                    rc = launch_stream_f64(x, y, cls, nullptr, g.nx, g.ny, g.pitch, (double)om0, geo, ctx->sink, st);
+                    rc = launch_stream_f64(x, y, cls, nullptr, g.nx, g.ny, g.pitch, (double)om0, geo, st);
                     std::swap(x, y);
                 }
                 hipEventRecord(e0, st);
                 for (int k = 0; k < passes && !rc; ++k) {
-                    rc = launch_stream_f64(x, y, cls, nullptr, g.nx, g.ny, g.pitch, (double)om0, geo, ctx->sink, st);
+                    rc = launch_stream_f64(x, y, cls, nullptr, g.nx, g.ny, g.pitch, (double)om0, geo, st);
                     std::swap(x, y);
                 }
                 hipEventRecord(e1, st);
@@ -970,7 +979,7 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
     const Geometry geo = stream_geometry(g.nx, g.ny, S, RH), geo1 = stream_geometry(g.nx, g.ny, 1, RH);
     for (int64_t done = 0; done < sweeps;) {
         const bool full = sweeps - done >= S;
-        rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, ctx->sink, st);
+        rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, st);
         if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
         std::swap(a, b);
         done += full ? S : 1;

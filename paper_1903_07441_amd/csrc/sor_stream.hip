@@ -15,7 +15,7 @@
 // neighbours come from the rolling register window, horizontal ones from the
 // adjacent lane through wave-wide DPP shifts (no LDS traffic).  The row loop
 // has no per-row branches (its trip count is padded to whole windows, halo
-// lanes store into a sink) and is fenced so that each prefetch stays in its
+// lanes store out of range) and is fenced so that each prefetch stays in its
 // row step: the compiler can then keep the prefetch queue in fixed registers
 // and never has to wait for a load in flight before the window comes round.  Each
 // half-sweep invalidates one column at each edge of the strip, so S lanes on
@@ -67,45 +67,147 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// ---- buffer addressing ---------------------------------------------------
+// A tile reads its rows through buffer resources based at its first row and
+// writes through one based at its first output row, so every access is a
+// scalar row offset plus a per-lane column offset.  The hardware checks the
+// sum of the two against the resource's size and turns an access outside it
+// into a zero read or a dropped store; the row loop relies on that instead
+// of clamping: rows above or below the tile read zeros, rows that are not
+// output rows (and halo lanes, whose column offset is kNoStore) are not
+// stored.  A tile spans less than 2^30 bytes, so no offset sum wraps.
+constexpr uint32_t kNoStore = 0x80000000u;
+constexpr int64_t kMaxTileBytes = 1LL << 30;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(float *, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ double bload(double *, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+}
+// the 64- and 128-bit buffer builtins take and return these (GCC-style)
+// vector types; they are only ever bit-cast or subscripted
+typedef uint32_t bv2 __attribute__((__vector_size__(8)));
+typedef uint32_t bv4 __attribute__((__vector_size__(16)));
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bv2, v), r, (int)vo, (int)so, 0);
+}
+
+// two adjacent elements in one access (PAIR tiles: even pitch, even nx and
+// aligned bases, so a pair never straddles a row, the grid's edge or the
+// resource's end)
+template <typename T> struct Pair { T a, b; };
+__device__ __forceinline__ Pair<float> bload2(float *, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    // elements are copied out before the bit cast: clang bit-casts a vector
+    // element lvalue from the vector's first element
+    const bv2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0);
+    const uint32_t a = v[0], b = v[1];
+    return {__builtin_bit_cast(float, a), __builtin_bit_cast(float, b)};
+}
+__device__ __forceinline__ Pair<double> bload2(double *, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    struct D2 { double a, b; };
+    const D2 v = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+    return {v.a, v.b};
+}
+__device__ __forceinline__ void bstore2(float a, float b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    bv2 v;
+    v[0] = __builtin_bit_cast(uint32_t, a);
+    v[1] = __builtin_bit_cast(uint32_t, b);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    struct D2 { double a, b; };
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(bv4, D2{a, b}), r, (int)vo, (int)so, 0);
+}
+
 // ---- streamed temporal-blocked red-black SOR ----------------------------
 // Rows are prefetched one window (NW rows) ahead into a register queue, so a
-// load has NW row-steps of arithmetic to arrive.  Loads use clamped (always
-// in-bounds) addresses; cells outside the grid are zeroed with a fixed-cell
-// factor when they are taken from the queue.
+// load has NW row-steps of arithmetic to arrive.  Cells outside the grid are
+// zeroed with a fixed-cell factor when they are taken from the queue.
 // One wave relaxes one tile: output columns [x0 + 2S, x0 + 128 - 2S) and
 // rows [ybeg, yend) of a grid; x0 and ybeg are even, all tile values are
-// wave-uniform.
-template <typename T, int S, bool RHS>
+// wave-uniform.  PAIR tiles move each lane's two columns in one access (three
+// memory operations per row instead of six), which keeps a whole window of
+// prefetches within the hardware's count of outstanding vector memory
+// operations, so no row step ever waits for the loads of the rows after it.
+template <typename T, int S, bool RHS, bool PAIR>
 __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__restrict__ dst,
                                             const uint8_t *__restrict__ cls,
                                             const T *__restrict__ f, int nx, int ny, int pitch,
-                                            T omega, int x0, int ybeg, int yend, T *__restrict__ sink)
+                                            T omega, int x0, int ybeg, int yend)
 {
     constexpr int NW = 2 * S + 2;      // rolling window of rows (even)
     const int lane = threadIdx.x & (kWave - 1);
     const int r0 = ybeg - 2 * S;                   // first row streamed (even)
     const int T_rows = (yend - ybeg) + 4 * S;
-    // per-lane constants
+    // rows that can reach a stored row: [lo, hi)
+    const int lo = max(r0, 0), hi = min(yend + 2 * S, ny);
+    // read resources end at the last cell of row hi - 1 and the write
+    // resource at the last cell of row yend - 1, so no access reaches past
+    // the caller's last row even when its allocation ends there
+    const uint32_t rowb = (uint32_t)pitch * sizeof(T);
+    const uint32_t cells = (uint32_t)(hi - lo - 1) * (uint32_t)pitch + (uint32_t)nx;
+    const uint32_t outc = (uint32_t)(yend - ybeg - 1) * (uint32_t)pitch + (uint32_t)nx;
+    const size_t base = (size_t)lo * pitch;
+    const __amdgpu_buffer_rsrc_t rs = rsrc(src + base, cells * sizeof(T));
+    const __amdgpu_buffer_rsrc_t rc = rsrc(cls + base, cells);
+    const __amdgpu_buffer_rsrc_t rf = rsrc(RHS ? f + base : src + base, cells * sizeof(T));
+    const __amdgpu_buffer_rsrc_t rd = rsrc(dst + (size_t)ybeg * pitch, outc * sizeof(T));
+    // per-lane constants: columns outside the grid read as zero values (a
+    // negative column is out of range; one past nx is masked) and carry a
+    // zero SOR factor
     const int xa = x0 + 2 * lane;
     const bool in0 = xa >= 0 && xa < nx, in1 = xa + 1 >= 0 && xa + 1 < nx;
-    const int xc0 = min(max(xa, 0), nx - 1), xc1 = min(max(xa + 1, 0), nx - 1);
     const T om0 = in0 ? omega : T(0), om1 = in1 ? omega : T(0);
     const bool writer = lane >= S && lane < kWave - S;
+    const uint32_t xb0 = (uint32_t)xa * sizeof(T), xb1 = (uint32_t)(xa + 1) * sizeof(T);
+    const uint32_t so0 = writer && in0 ? xb0 : kNoStore;
+    const uint32_t so1 = writer && in1 ? xb1 : kNoStore;
+    // row offsets (bytes) of streamed row t: values, classes, and output row
+    // t - 4S; negative ones are far out of range as unsigned sums
+    const int vrow0 = (r0 - lo) * (int)rowb, crow0 = (r0 - lo) * pitch;
+    const int orow0 = (r0 - 2 * S - ybeg) * (int)rowb;
 
     T qv0[NW], qv1[NW], qf0[NW], qf1[NW];
     uint32_t qc0[NW], qc1[NW];
     auto fetch = [&](int slot, int t) {
-        const int yc = min(max(r0 + t, 0), ny - 1);
-        const T *ps = src + yc * pitch;
-        const uint8_t *pc = cls + yc * pitch;
-        qv0[slot] = ps[xc0];
-        qv1[slot] = ps[xc1];
-        qc0[slot] = pc[xc0];
-        qc1[slot] = pc[xc1];
-        if (RHS) {
-            const T *pf = f + yc * pitch;
-            qf0[slot] = pf[xc0];
-            qf1[slot] = pf[xc1];
+        const uint32_t vo = (uint32_t)(vrow0 + t * (int)rowb), co = (uint32_t)(crow0 + t * pitch);
+        if constexpr (PAIR) {
+            const Pair<T> v = bload2((T *)nullptr, rs, xb0, vo);
+            qv0[slot] = v.a;
+            qv1[slot] = v.b;
+            const uint32_t c = __builtin_amdgcn_raw_buffer_load_b16(rc, (int)xa, (int)co, 0);
+            qc0[slot] = c & 0xffu;
+            qc1[slot] = c >> 8;
+            if (RHS) {
+                const Pair<T> w = bload2((T *)nullptr, rf, xb0, vo);
+                qf0[slot] = w.a;
+                qf1[slot] = w.b;
+            }
+        } else {
+            qv0[slot] = bload((T *)nullptr, rs, xb0, vo);
+            qv1[slot] = bload((T *)nullptr, rs, xb1, vo);
+            qc0[slot] = __builtin_amdgcn_raw_buffer_load_b8(rc, xa, (int)co, 0);
+            qc1[slot] = __builtin_amdgcn_raw_buffer_load_b8(rc, xa + 1, (int)co, 0);
+            if (RHS) {
+                qf0[slot] = bload((T *)nullptr, rf, xb0, vo);
+                qf1[slot] = bload((T *)nullptr, rf, xb1, vo);
+            }
         }
     };
 
@@ -126,15 +228,17 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
         for (int u = 0; u < NW; ++u) {
             const int t = base + u;
             const int y = r0 + t;  // parity of y == parity of u
-            const bool rowok = y >= 0 && y < ny;  // uniform
-            const T v0 = rowok && in0 ? qv0[u] : T(0);
-            const T v1 = rowok && in1 ? qv1[u] : T(0);
+            // rows outside the grid read zero values; their classes read as
+            // zero too, so the row test keeps them fixed (uniform)
+            const bool rowok = (uint32_t)y < (uint32_t)ny;
+            const T v0 = in0 ? qv0[u] : T(0);
+            const T v1 = in1 ? qv1[u] : T(0);
             const T w0 = rowok && qc0[u] == TWG_CELL_FREE ? om0 : T(0);
             const T w1 = rowok && qc1[u] == TWG_CELL_FREE ? om1 : T(0);
             T f0 = T(0), f1 = T(0);
             if (RHS) {
-                f0 = rowok && in0 ? qf0[u] : T(0);
-                f1 = rowok && in1 ? qf1[u] : T(0);
+                f0 = in0 ? qf0[u] : T(0);
+                f1 = in1 ? qf1[u] : T(0);
             }
             // the slot is refilled only after its values are taken, so the
             // queue keeps fixed registers across iterations
@@ -162,18 +266,19 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
                     B[s] = upd<RHS>(B[s], ew, sn, wB[s], fB[s]);
                 }
             }
-            const int ys = y - 2 * S;  // row finished by this step (uniform test)
-            if (ys >= ybeg && ys < yend) {
+            // the row finished by this step (row y - 2S) is stored; rows
+            // outside [ybeg, yend) fall outside the write resource
+            {
                 const int s = (u - 2 * S + 4 * NW) % NW;
-                T *pd = dst + ys * pitch;
+                const uint32_t ro = (uint32_t)(orow0 + t * (int)rowb);
                 const T o0 = (s & 1) == 0 ? R[s] : B[s];
                 const T o1 = (s & 1) == 0 ? B[s] : R[s];
-                // halo lanes and columns outside the grid store into the
-                // sink instead of branching around the store
-                T *p0 = writer && in0 ? pd + xa : sink + 2 * lane;
-                T *p1 = writer && in1 ? pd + xa + 1 : sink + 2 * lane + 1;
-                *p0 = o0;
-                *p1 = o1;
+                if constexpr (PAIR) {
+                    bstore2(o0, o1, rd, so0, ro);
+                } else {
+                    bstore(o0, rd, so0, ro);
+                    bstore(o1, rd, so1, ro);
+                }
             }
             // keep this row's prefetch in this row step: without the fence
             // the scheduler sinks every prefetch of the window to its end
@@ -182,12 +287,12 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     }
 }
 
-template <typename T, int S, bool RHS>
+template <typename T, int S, bool RHS, bool PAIR>
 __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T *__restrict__ dst,
                                                     const uint8_t *__restrict__ cls,
                                                     const T *__restrict__ f, int nx, int ny,
                                                     int pitch, T omega, int strips, int RH,
-                                                    int tiles, T *__restrict__ sink)
+                                                    int tiles)
 {
     constexpr int VW = 128 - 4 * S;  // columns written per strip
     // everything that depends only on the tile is wave-uniform: keep it scalar
@@ -196,41 +301,51 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
     if (tile >= tiles) return;  // whole wave
     const int strip = tile % strips, seg = tile / strips;
     const int ybeg = seg * RH;
-    stream_tile<T, S, RHS>(src, dst, cls, f, nx, ny, pitch, omega, strip * VW - 2 * S, ybeg,
-                           min(ybeg + RH, ny), sink);
+    stream_tile<T, S, RHS, PAIR>(src, dst, cls, f, nx, ny, pitch, omega, strip * VW - 2 * S, ybeg,
+                           min(ybeg + RH, ny));
 }
 
 // Batched form: the tiles of many grids in one launch.  Grid g's arrays start
 // at element offset desc.off of the batch base pointers; the tile count is
 // read from device memory so that one captured launch serves any active set.
-template <int S>
+template <int S, bool PAIR>
 __global__ __launch_bounds__(256) void k_sor_stream_batch(const float *__restrict__ src,
                                                           float *__restrict__ dst,
                                                           const uint8_t *__restrict__ cls,
                                                           const BatchGrid *__restrict__ grids,
                                                           const BatchTile *__restrict__ tiles,
-                                                          const int *__restrict__ n_tiles,
-                                                          float *__restrict__ sink)
+                                                          const int *__restrict__ n_tiles)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
     if (tile >= *n_tiles) return;  // whole wave
     const BatchTile t = tiles[tile];
     const BatchGrid g = grids[t.grid];
-    stream_tile<float, S, false>(src + g.off, dst + g.off, cls + g.off, nullptr, g.nx, g.ny,
-                                 g.pitch, g.omega, t.x0, t.ybeg, t.yend, sink);
+    stream_tile<float, S, false, PAIR>(src + g.off, dst + g.off, cls + g.off, nullptr, g.nx, g.ny,
+                                 g.pitch, g.omega, t.x0, t.ybeg, t.yend);
 }
 
-template <typename T, bool RHS>
-int launch_stream(const T *src, T *dst, const uint8_t *cls, const T *f, int nx, int ny, int pitch,
-                  T omega, const Geometry &g, void *sink, hipStream_t st)
+// Pair access needs even pitch and nx (a pair never leaves its row or the
+// grid) and bases aligned to a pair.
+template <typename T>
+bool pairable(const T *src, const T *dst, const uint8_t *cls, const T *f, int nx, int pitch)
 {
+    const auto al = [](const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; };
+    return nx % 2 == 0 && pitch % 2 == 0 && al(src, 2 * sizeof(T)) && al(dst, 2 * sizeof(T)) && al(cls, 2) &&
+           (!f || al(f, 2 * sizeof(T)));
+}
+
+template <typename T, bool RHS, bool PAIR>
+int launch_stream(const T *src, T *dst, const uint8_t *cls, const T *f, int nx, int ny, int pitch,
+                  T omega, const Geometry &geo, hipStream_t st)
+{
+    const int cap = stream_rows_cap(pitch, sizeof(T), geo.S);
+    const Geometry g = geo.RH > cap ? stream_geometry(nx, ny, geo.S, cap) : geo;
     const int blocks = (g.tiles + 3) / 4;
-#define TWG_STREAM_CASE(SV)                                                                     \
-    case SV:                                                                                    \
-        hipLaunchKernelGGL((k_sor_stream<T, SV, RHS>), dim3(blocks), dim3(256), 0, st, src, dst, \
-                           cls, f, nx, ny, pitch, omega, g.strips, g.RH, g.tiles,               \
-                           static_cast<T *>(sink));                                              \
+#define TWG_STREAM_CASE(SV)                                                                           \
+    case SV:                                                                                          \
+        hipLaunchKernelGGL((k_sor_stream<T, SV, RHS, PAIR>), dim3(blocks), dim3(256), 0, st, src, dst, \
+                           cls, f, nx, ny, pitch, omega, g.strips, g.RH, g.tiles);                    \
         break;
     switch (g.S) {
         TWG_STREAM_CASE(1)
@@ -248,15 +363,19 @@ int launch_stream(const T *src, T *dst, const uint8_t *cls, const T *f, int nx, 
 }  // namespace
 
 int launch_stream_batch(const float *src, float *dst, const uint8_t *cls, const BatchGrid *grids,
-                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S, void *sink,
+                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S, bool pair,
                         hipStream_t st)
 {
     const int blocks = (max_tiles + 3) / 4;
     if (blocks == 0) return TWG_OK;
-#define TWG_BATCH_CASE(SV)                                                                       \
-    case SV:                                                                                     \
-        hipLaunchKernelGGL(k_sor_stream_batch<SV>, dim3(blocks), dim3(256), 0, st, src, dst, cls, \
-                           grids, tiles, n_tiles, static_cast<float *>(sink));                   \
+#define TWG_BATCH_CASE(SV)                                                                             \
+    case SV:                                                                                           \
+        if (pair)                                                                                      \
+            hipLaunchKernelGGL((k_sor_stream_batch<SV, true>), dim3(blocks), dim3(256), 0, st, src, dst, \
+                               cls, grids, tiles, n_tiles);                                            \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_sor_stream_batch<SV, false>), dim3(blocks), dim3(256), 0, st, src,     \
+                               dst, cls, grids, tiles, n_tiles);                                       \
         break;
     switch (S) {
         TWG_BATCH_CASE(1)
@@ -269,6 +388,13 @@ int launch_stream_batch(const float *src, float *dst, const uint8_t *cls, const 
     }
 #undef TWG_BATCH_CASE
     return last_status();
+}
+
+int stream_rows_cap(int pitch, int elem_bytes, int S)
+{
+    // a tile's rows (RH + 4S of them) must span less than kMaxTileBytes
+    const long long rows = (kMaxTileBytes - 1) / ((long long)pitch * elem_bytes);
+    return (int)std::max(2LL, (rows - 4 * S - 2) & ~1LL);
 }
 
 bool stream_depth_supported(int S) { return S == 1 || S == 2 || S == 3 || S == 4 || S == 6 || S == 8; }
@@ -286,17 +412,22 @@ Geometry stream_geometry(int nx, int ny, int S, int RH)
 }
 
 int launch_stream_f32(const float *src, float *dst, const uint8_t *cls, const float *f, int nx,
-                      int ny, int pitch, float omega, const Geometry &geo, void *sink, hipStream_t st)
+                      int ny, int pitch, float omega, const Geometry &geo, hipStream_t st)
 {
-    return f ? launch_stream<float, true>(src, dst, cls, f, nx, ny, pitch, omega, geo, sink, st)
-             : launch_stream<float, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, sink, st);
+    if (pairable(src, dst, cls, f, nx, pitch))
+        return f ? launch_stream<float, true, true>(src, dst, cls, f, nx, ny, pitch, omega, geo, st)
+                 : launch_stream<float, false, true>(src, dst, cls, f, nx, ny, pitch, omega, geo, st);
+    return f ? launch_stream<float, true, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, st)
+             : launch_stream<float, false, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, st);
 }
 
 int launch_stream_f64(const double *src, double *dst, const uint8_t *cls, const double *f, int nx,
-                      int ny, int pitch, double omega, const Geometry &geo, void *sink, hipStream_t st)
+                      int ny, int pitch, double omega, const Geometry &geo, hipStream_t st)
 {
     if (f) return TWG_EUNSUPPORTED;
-    return launch_stream<double, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, sink, st);
+    if (pairable(src, dst, cls, f, nx, pitch))
+        return launch_stream<double, false, true>(src, dst, cls, f, nx, ny, pitch, omega, geo, st);
+    return launch_stream<double, false, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, st);
 }
 
 }  // namespace twg

@@ -52,8 +52,6 @@ struct twg_ctx {
     size_t batch_host_bytes = 0;
     // small device words: residual maxima (uint64 bit patterns), counters
     unsigned long long *words = nullptr;
-    // 1 KiB that the relaxation kernels' halo lanes store into (never read)
-    void *sink = nullptr;
     // per-block partial maxima of the residual kernels (2 kResidBlocks words)
     unsigned long long *rpart = nullptr;
     // pinned host mirror of `words`
@@ -84,8 +82,9 @@ struct BatchTile {
     int grid, x0, ybeg, yend;
 };
 
+// pair: every grid has even nx, pitch and offset (PAIR tiles)
 int launch_stream_batch(const float *src, float *dst, const uint8_t *cls, const BatchGrid *grids,
-                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S, void *sink,
+                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S, bool pair,
                         hipStream_t st);
 int launch_resid_batch(const uint8_t *cls, const float *u, const BatchGrid *grids,
                        const int2 *blocks, int n_blocks, unsigned long long *out, int n_words,
@@ -115,11 +114,13 @@ int launch_sweep_color_f32(const uint8_t *cls, float *psi, const float *f, int n
 int launch_sweep_color_f64(const uint8_t *cls, double *psi, const double *f, int nx, int ny,
                            int pitch, double omega, int color, hipStream_t st);
 bool stream_depth_supported(int S);
-// sink: 1 KiB of device memory that the halo lanes' stores go to
+// largest RH whose tiles the streamed kernels can address (RH above it is
+// lowered at launch)
+int stream_rows_cap(int pitch, int elem_bytes, int S);
 int launch_stream_f32(const float *src, float *dst, const uint8_t *cls, const float *f, int nx,
-                      int ny, int pitch, float omega, const Geometry &geo, void *sink, hipStream_t st);
+                      int ny, int pitch, float omega, const Geometry &geo, hipStream_t st);
 int launch_stream_f64(const double *src, double *dst, const uint8_t *cls, const double *f, int nx,
-                      int ny, int pitch, double omega, const Geometry &geo, void *sink, hipStream_t st);
+                      int ny, int pitch, double omega, const Geometry &geo, hipStream_t st);
 // residual reductions: part = the context's block partials (2 kResidBlocks
 // words), out = 2 words receiving max |r| and max |r| / |u|
 constexpr int kResidBlocks = 4096;

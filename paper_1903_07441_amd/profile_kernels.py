@@ -2,7 +2,8 @@
 alone, for profilers.
 
 Rasterises a 2048 x 2048 replanning scenario, tunes the tiling, then runs
-`--passes` passes of the streamed SOR kernel, followed by one device copy of
+`--passes` passes of the streamed SOR kernel (and with --fp64 as many FP64
+passes), followed by one device copy of
 `--copy-mib` MiB (a kernel of known traffic: it reads and writes exactly that
 many bytes) so that hardware byte counters can be calibrated against it.
 
@@ -32,6 +33,7 @@ def main(argv=None):
     ap.add_argument("--net", action="store_true", help="profile the network kernels instead")
     ap.add_argument("--S", type=int, default=0, help="sweeps per tile load (with --RH: skip the autotuner)")
     ap.add_argument("--RH", type=int, default=0, help="output rows per tile")
+    ap.add_argument("--fp64", action="store_true", help="also run the FP64 sweeps (tuned tiling)")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -73,6 +75,10 @@ def main(argv=None):
         tune = ctx.autotune(cls)
     psi = torch.full((ny, nx), 0.5, dtype=torch.float32, device=dev)
     ctx.sweeps(cls, psi, tune["omega"], 2 * tune["S"] * args.passes, sweeps_per_pass=tune["S"])
+    if args.fp64:
+        psi64 = torch.full((ny, nx), 0.5, dtype=torch.float64, device=dev)
+        s64 = int(tune.get("S64") or tune["S"])
+        ctx.sweeps64(cls, psi64, tune["omega"], 2 * s64 * args.passes, sweeps_per_pass=s64)
     n = args.copy_mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
