@@ -18,8 +18,10 @@
  *     owns every buffer it passes; the library never frees caller memory.  The
  *     context owns only its scratch buffers (allocated at first use of a size,
  *     released by twg_ctx_destroy).
- *   - Grids are row-major, x fastest: a[y * pitch + x], pitch >= nx, in
- *     elements of the array's type.  1 <= nx, ny <= 32767.
+ *   - Grids are row-major, x fastest: a[y * pitch + x], nx <= pitch <= 65536,
+ *     in elements of the array's type, and pitch * ny < 2^31.
+ *     1 <= nx, ny <= 32767.  Even nx and pitch (with bases aligned to two
+ *     elements) take the faster paired-column relaxation.
  *   - The potential is stored as psi = 1 - phi, phi being the paper's
  *     potential: the goal holds psi = 1, obstacles and walls psi = 0, free
  *     space starts at psi = 0.5 (phi = 0.5).  The equation is linear, so psi
@@ -64,7 +66,7 @@ typedef struct twg_ctx twg_ctx;
 
 typedef struct {
     int32_t nx, ny; /* cells */
-    int32_t pitch;  /* row stride in elements, >= nx */
+    int32_t pitch;  /* row stride in elements, nx <= pitch <= 65536 */
 } twg_grid;
 
 /* Library version, major * 10000 + minor * 100 + patch. */

@@ -193,25 +193,56 @@ struct Runner {
         return TWG_OK;
     }
 
+    // SOR factor maps for the streamed sweeps, built at most once per call
+    // (the class map is fixed for the duration of a call) and omega
+    float w32_omega = -1.0f;
+    double w64_omega = -1.0;
+    int wmap32(float omega, const float **w)
+    {
+        if (w32_omega != omega) {
+            int rc = ensure(ctx, &ctx->wmap32, &ctx->wmap32_bytes, (size_t)g.pitch * g.ny * sizeof(float));
+            if (rc) return rc;
+            rc = launch_wmap_f32(cls, static_cast<float *>(ctx->wmap32), omega, g.nx, g.ny, g.pitch, st);
+            if (rc) return set_err(ctx, rc, "factor map launch failed");
+            w32_omega = omega;
+        }
+        *w = static_cast<const float *>(ctx->wmap32);
+        return TWG_OK;
+    }
+    int wmap64(double omega, const double **w)
+    {
+        if (w64_omega != omega) {
+            int rc = ensure(ctx, &ctx->wmap64, &ctx->wmap64_bytes, (size_t)g.pitch * g.ny * sizeof(double));
+            if (rc) return rc;
+            rc = launch_wmap_f64(cls, static_cast<double *>(ctx->wmap64), omega, g.nx, g.ny, g.pitch, st);
+            if (rc) return set_err(ctx, rc, "factor map launch failed");
+            w64_omega = omega;
+        }
+        *w = static_cast<const double *>(ctx->wmap64);
+        return TWG_OK;
+    }
+
     // `sweeps` FP32 sweeps on a <-> b, S per pass (remainder one per pass);
     // on return *a holds the newest field.  Runs of kGraphPasses full passes
     // are replayed from a captured graph.
     int sweep32(float **a, float **b, const float *f, float omega, int S, int RH, int64_t sweeps)
     {
+        const float *w = nullptr;
+        if (int rc = wmap32(omega, &w)) return rc;
         const Geometry geo = stream_geometry(g.nx, g.ny, S, RH);
         const Geometry geo1 = stream_geometry(g.nx, g.ny, 1, RH);
         int64_t done = 0;
         const int64_t reps = ctx->use_graphs ? sweeps / ((int64_t)S * kGraphPasses) : 0;
         if (reps > 0) {
-            const std::vector<uintptr_t> key = {1, (uintptr_t)*a, (uintptr_t)*b, (uintptr_t)cls, (uintptr_t)f,
+            const std::vector<uintptr_t> key = {1, (uintptr_t)*a, (uintptr_t)*b, (uintptr_t)w, (uintptr_t)f,
                                                 (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.pitch,
                                                 (uintptr_t)__builtin_bit_cast(uint32_t, omega), (uintptr_t)S,
                                                 (uintptr_t)RH};
             float *x = *a, *y = *b;
             int rc = graph_replay(ctx, key, st, reps, [&](hipStream_t cs) {
                 for (int k = 0; k < kGraphPasses; ++k) {
-                    const int e = launch_stream_f32(k % 2 ? y : x, k % 2 ? x : y, cls, f, g.nx, g.ny, g.pitch,
-                                                    omega, geo, cs);
+                    const int e = launch_stream_f32(k % 2 ? y : x, k % 2 ? x : y, w, f, g.nx, g.ny, g.pitch,
+                                                    geo, cs);
                     if (e) return e;
                 }
                 return TWG_OK;
@@ -221,7 +252,7 @@ struct Runner {
         }
         while (done < sweeps) {
             const bool full = sweeps - done >= S;
-            int rc = launch_stream_f32(*a, *b, cls, f, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, st);
+            int rc = launch_stream_f32(*a, *b, w, f, g.nx, g.ny, g.pitch, full ? geo : geo1, st);
             if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
             std::swap(*a, *b);
             done += full ? S : 1;
@@ -304,6 +335,8 @@ struct Runner {
         int S, RH;
         tiling64_for(ctx, g.nx, g.ny, &S, &RH);
         const Geometry geo = stream_geometry(g.nx, g.ny, S, RH);
+        const double *w = nullptr;
+        if ((rc = wmap64(omega, &w))) return rc;
         double *a = field, *b = reinterpret_cast<double *>(ctx->alt64);
         double r;
         rc = residual64(a, &r);
@@ -320,7 +353,7 @@ struct Runner {
             int64_t chunk = std::max<int64_t>((int64_t)std::ceil(want * 1.05) + S, 8 * S);
             chunk = ((std::min(chunk, max_sweeps - done) + S - 1) / S) * S;
             for (int64_t k = 0; k < chunk; k += S) {
-                rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, geo, st);
+                rc = launch_stream_f64(a, b, w, g.nx, g.ny, g.pitch, geo, st);
                 if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
                 std::swap(a, b);
             }
@@ -382,8 +415,8 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
     for (auto &g : ctx->graphs) hipGraphExecDestroy(g.exec);
     ctx->graphs.clear();
     if (ctx->cap) hipStreamDestroy(ctx->cap);
-    void *bufs[] = {ctx->alt, ctx->pol, ctx->alt64, ctx->pairs, ctx->idxbuf, ctx->batch, ctx->words, ctx->jumpbuf,
-                    ctx->rpart};
+    void *bufs[] = {ctx->alt,   ctx->pol,    ctx->alt64, ctx->wmap32,  ctx->wmap64, ctx->pairs,
+                    ctx->idxbuf, ctx->batch, ctx->words, ctx->jumpbuf, ctx->rpart};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (ctx->host_words) hipHostFree(ctx->host_words);
@@ -576,7 +609,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
     const int VW = 128 - 4 * S;
     // paired column access when every grid allows it; tiles within the
     // streamed kernels' addressable span
-    bool pair = (reinterpret_cast<uintptr_t>(psi) & 7) == 0 && (reinterpret_cast<uintptr_t>(cls) & 1) == 0;
+    bool pair = (reinterpret_cast<uintptr_t>(psi) & 7) == 0;
     int max_pitch = 1;
     for (int k = 0; k < n; ++k) {
         pair = pair && grids[k].nx % 2 == 0 && grids[k].pitch % 2 == 0 && grids[k].offset % 2 == 0;
@@ -657,6 +690,10 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
     const int max_tiles0 = (int)tl.size();
     rc = upload_lists();
     if (!rc) rc = launch_field_init_batch(cls, psi, d_grids, d_blocks, (int)bl.size(), p.init, st);
+    // SOR factor map of every grid (each with its own omega), laid out as psi
+    if (!rc) rc = ensure(ctx, &ctx->wmap32, &ctx->wmap32_bytes, (size_t)total * sizeof(float));
+    float *const wmap = static_cast<float *>(ctx->wmap32);
+    if (!rc) rc = launch_wmap_batch(cls, wmap, d_grids, d_blocks, (int)bl.size(), st);
     if (rc) return set_err(ctx, TWG_EDEVICE, "batch set-up failed");
 
     std::vector<double> r(n), rr(n), rate(n);
@@ -717,13 +754,13 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
         // count from device memory, so retired grids cost an early exit
         const int64_t reps = ctx->use_graphs ? passes / kGraphPasses : 0;
         if (reps > 0) {
-            const std::vector<uintptr_t> key = {2, (uintptr_t)cur, (uintptr_t)nxt, (uintptr_t)cls,
+            const std::vector<uintptr_t> key = {2, (uintptr_t)cur, (uintptr_t)nxt, (uintptr_t)wmap,
                                                 (uintptr_t)d_grids, (uintptr_t)d_tiles, (uintptr_t)d_count,
                                                 (uintptr_t)max_tiles0, (uintptr_t)S, (uintptr_t)pair};
             float *x = cur, *y = nxt;
             rc = graph_replay(ctx, key, st, reps, [&](hipStream_t cs) {
                 for (int k = 0; k < kGraphPasses; ++k) {
-                    const int e = launch_stream_batch(k % 2 ? y : x, k % 2 ? x : y, cls, d_grids, d_tiles, d_count,
+                    const int e = launch_stream_batch(k % 2 ? y : x, k % 2 ? x : y, wmap, d_grids, d_tiles, d_count,
                                                       max_tiles0, S, pair, cs);
                     if (e) return e;
                 }
@@ -732,7 +769,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
             if (rc) return set_err(ctx, rc, "batched relaxation graph failed");
         }
         for (int64_t q = reps * kGraphPasses; q < passes; ++q) {
-            rc = launch_stream_batch(cur, nxt, cls, d_grids, d_tiles, d_count, (int)tl.size(), S, pair, st);
+            rc = launch_stream_batch(cur, nxt, wmap, d_grids, d_tiles, d_count, (int)tl.size(), S, pair, st);
             if (rc) return set_err(ctx, rc, "batched relaxation launch failed");
             std::swap(cur, nxt);
         }
@@ -846,6 +883,8 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
         if (!rc) rc = launch_fill_f32(b, 0.5f, g.nx, g.ny, g.pitch, st);
         if (!rc) rc = launch_field_init(cls, b, g.nx, g.ny, g.pitch, HPF_INIT_KEEP, st);
         if (!rc) rc = launch_widen(b, a64, g.nx, g.ny, g.pitch, st);
+        const double *w64 = nullptr;
+        if (!rc) rc = run.wmap64((double)om0, &w64);
         const int Ss64[] = {2, 3, 4, 6, 8};
         for (int S : Ss64) {
             if (rc) break;
@@ -856,12 +895,12 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
                 passes += passes & 1;
                 double *x = a64, *y = b64;
                 for (int k = 0; k < 2 && !rc; ++k) {  // warm-up
-                    rc = launch_stream_f64(x, y, cls, nullptr, g.nx, g.ny, g.pitch, (double)om0, geo, st);
+                    rc = launch_stream_f64(x, y, w64, g.nx, g.ny, g.pitch, geo, st);
                     std::swap(x, y);
                 }
                 hipEventRecord(e0, st);
                 for (int k = 0; k < passes && !rc; ++k) {
-                    rc = launch_stream_f64(x, y, cls, nullptr, g.nx, g.ny, g.pitch, (double)om0, geo, st);
+                    rc = launch_stream_f64(x, y, w64, g.nx, g.ny, g.pitch, geo, st);
                     std::swap(x, y);
                 }
                 hipEventRecord(e1, st);
@@ -976,10 +1015,13 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
     rc = ensure(ctx, &ctx->alt64, &ctx->alt64_bytes, (size_t)g.pitch * g.ny * sizeof(double));
     if (rc) return rc;
     double *a = psi64, *b = reinterpret_cast<double *>(ctx->alt64);
+    Runner run{ctx, g, cls, st};
+    const double *w = nullptr;
+    if ((rc = run.wmap64(omega, &w))) return rc;
     const Geometry geo = stream_geometry(g.nx, g.ny, S, RH), geo1 = stream_geometry(g.nx, g.ny, 1, RH);
     for (int64_t done = 0; done < sweeps;) {
         const bool full = sweeps - done >= S;
-        rc = launch_stream_f64(a, b, cls, nullptr, g.nx, g.ny, g.pitch, omega, full ? geo : geo1, st);
+        rc = launch_stream_f64(a, b, w, g.nx, g.ny, g.pitch, full ? geo : geo1, st);
         if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
         std::swap(a, b);
         done += full ? S : 1;

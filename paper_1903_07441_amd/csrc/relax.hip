@@ -278,6 +278,30 @@ __global__ void k_copy(const float *__restrict__ s, float *__restrict__ d, int n
 
 dim3 cell_grid(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); }
 
+// SOR factor map of the streamed sweeps: omega on FREE cells, 0 on the others
+template <typename T>
+__global__ void k_wmap(const uint8_t *__restrict__ cls, T *__restrict__ w, T omega, int nx, int ny, int pitch)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= nx || y >= ny) return;
+    const size_t i = (size_t)y * pitch + x;
+    w[i] = cls[i] == TWG_CELL_FREE ? omega : T(0);
+}
+
+__global__ void k_wmap_batch(const uint8_t *__restrict__ cls, float *__restrict__ w,
+                             const BatchGrid *__restrict__ grids, const int2 *__restrict__ blocks)
+{
+    const int2 bk = blocks[blockIdx.x];
+    const BatchGrid g = grids[bk.x];
+    const int x = bk.y * 64 + (threadIdx.x & 63);
+    if (x >= g.nx) return;
+    for (int y = threadIdx.x >> 6; y < g.ny; y += 4) {
+        const size_t i = g.off + (size_t)y * g.pitch + x;
+        w[i] = cls[i] == TWG_CELL_FREE ? g.omega : 0.0f;
+    }
+}
+
 int last_status()
 {
     return hipGetLastError() == hipSuccess ? TWG_OK : TWG_EDEVICE;
@@ -310,6 +334,26 @@ int launch_copy_batch(const float *src, float *dst, const BatchGrid *grids, cons
 {
     if (n_blocks > 0)
         hipLaunchKernelGGL(k_copy_batch, dim3(n_blocks), dim3(256), 0, st, src, dst, grids, blocks);
+    return last_status();
+}
+
+int launch_wmap_f32(const uint8_t *cls, float *wmap, float omega, int nx, int ny, int pitch, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_wmap<float>, cell_grid(nx, ny), dim3(256), 0, st, cls, wmap, omega, nx, ny, pitch);
+    return last_status();
+}
+
+int launch_wmap_f64(const uint8_t *cls, double *wmap, double omega, int nx, int ny, int pitch, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_wmap<double>, cell_grid(nx, ny), dim3(256), 0, st, cls, wmap, omega, nx, ny, pitch);
+    return last_status();
+}
+
+int launch_wmap_batch(const uint8_t *cls, float *wmap, const BatchGrid *grids, const int2 *blocks,
+                      int n_blocks, hipStream_t st)
+{
+    if (n_blocks > 0)
+        hipLaunchKernelGGL(k_wmap_batch, dim3(n_blocks), dim3(256), 0, st, cls, wmap, grids, blocks);
     return last_status();
 }
 

@@ -4,8 +4,9 @@
 //
 // Field layout: row-major, x fastest, pitch in elements; psi = 1 - phi.  Red
 // cells are (x + y) even.  One sweep sets every FREE cell of one colour, then
-// of the other, to psi + omega * (((E + W) + (S + N)) / 4 + f - psi); fixed
-// cells carry a factor 0 instead of omega and are rewritten unchanged.
+// of the other, to psi + w * (((E + W) + (S + N)) / 4 + f - psi), where the
+// factor map w holds omega on FREE cells and 0 on fixed ones (which are thus
+// rewritten unchanged); the map is built once per call from the class map.
 //
 // One wave owns a strip of 128 columns (each lane two adjacent columns, so in
 // every row a lane holds exactly one red and one black cell) and streams it
@@ -147,9 +148,9 @@ __device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc
 // operations, so no row step ever waits for the loads of the rows after it.
 template <typename T, int S, bool RHS, bool PAIR>
 __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__restrict__ dst,
-                                            const uint8_t *__restrict__ cls,
+                                            const T *__restrict__ wmap,
                                             const T *__restrict__ f, int nx, int ny, int pitch,
-                                            T omega, int x0, int ybeg, int yend)
+                                            int x0, int ybeg, int yend)
 {
     constexpr int NW = 2 * S + 2;      // rolling window of rows (even)
     const int lane = threadIdx.x & (kWave - 1);
@@ -165,45 +166,44 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     const uint32_t outc = (uint32_t)(yend - ybeg - 1) * (uint32_t)pitch + (uint32_t)nx;
     const size_t base = (size_t)lo * pitch;
     const __amdgpu_buffer_rsrc_t rs = rsrc(src + base, cells * sizeof(T));
-    const __amdgpu_buffer_rsrc_t rc = rsrc(cls + base, cells);
+    const __amdgpu_buffer_rsrc_t rw = rsrc(wmap + base, cells * sizeof(T));
     const __amdgpu_buffer_rsrc_t rf = rsrc(RHS ? f + base : src + base, cells * sizeof(T));
     const __amdgpu_buffer_rsrc_t rd = rsrc(dst + (size_t)ybeg * pitch, outc * sizeof(T));
-    // per-lane constants: columns outside the grid read as zero values (a
-    // negative column is out of range; one past nx is masked) and carry a
-    // zero SOR factor
+    // per-lane constants: a column outside the grid gets an out-of-range
+    // offset, so its value and factor read as zero; rows outside the grid
+    // are out of range as well.  The row step thus uses the loads as they are.
     const int xa = x0 + 2 * lane;
     const bool in0 = xa >= 0 && xa < nx, in1 = xa + 1 >= 0 && xa + 1 < nx;
-    const T om0 = in0 ? omega : T(0), om1 = in1 ? omega : T(0);
     const bool writer = lane >= S && lane < kWave - S;
-    const uint32_t xb0 = (uint32_t)xa * sizeof(T), xb1 = (uint32_t)(xa + 1) * sizeof(T);
-    const uint32_t so0 = writer && in0 ? xb0 : kNoStore;
-    const uint32_t so1 = writer && in1 ? xb1 : kNoStore;
-    // row offsets (bytes) of streamed row t: values, classes, and output row
-    // t - 4S; negative ones are far out of range as unsigned sums
-    const int vrow0 = (r0 - lo) * (int)rowb, crow0 = (r0 - lo) * pitch;
+    const uint32_t xb0 = in0 ? (uint32_t)xa * sizeof(T) : kNoStore;
+    const uint32_t xb1 = in1 ? (uint32_t)(xa + 1) * sizeof(T) : kNoStore;
+    const uint32_t so0 = writer ? xb0 : kNoStore;
+    const uint32_t so1 = writer ? xb1 : kNoStore;
+    // row offsets (bytes) of streamed row t and of output row t - 4S;
+    // negative ones are far out of range as unsigned sums
+    const int vrow0 = (r0 - lo) * (int)rowb;
     const int orow0 = (r0 - 2 * S - ybeg) * (int)rowb;
 
-    T qv0[NW], qv1[NW], qf0[NW], qf1[NW];
-    uint32_t qc0[NW], qc1[NW];
+    T qv0[NW], qv1[NW], qw0[NW], qw1[NW], qf0[NW], qf1[NW];
     auto fetch = [&](int slot, int t) {
-        const uint32_t vo = (uint32_t)(vrow0 + t * (int)rowb), co = (uint32_t)(crow0 + t * pitch);
+        const uint32_t vo = (uint32_t)(vrow0 + t * (int)rowb);
         if constexpr (PAIR) {
             const Pair<T> v = bload2((T *)nullptr, rs, xb0, vo);
             qv0[slot] = v.a;
             qv1[slot] = v.b;
-            const uint32_t c = __builtin_amdgcn_raw_buffer_load_b16(rc, (int)xa, (int)co, 0);
-            qc0[slot] = c & 0xffu;
-            qc1[slot] = c >> 8;
+            const Pair<T> w = bload2((T *)nullptr, rw, xb0, vo);
+            qw0[slot] = w.a;
+            qw1[slot] = w.b;
             if (RHS) {
-                const Pair<T> w = bload2((T *)nullptr, rf, xb0, vo);
-                qf0[slot] = w.a;
-                qf1[slot] = w.b;
+                const Pair<T> h = bload2((T *)nullptr, rf, xb0, vo);
+                qf0[slot] = h.a;
+                qf1[slot] = h.b;
             }
         } else {
             qv0[slot] = bload((T *)nullptr, rs, xb0, vo);
             qv1[slot] = bload((T *)nullptr, rs, xb1, vo);
-            qc0[slot] = __builtin_amdgcn_raw_buffer_load_b8(rc, xa, (int)co, 0);
-            qc1[slot] = __builtin_amdgcn_raw_buffer_load_b8(rc, xa + 1, (int)co, 0);
+            qw0[slot] = bload((T *)nullptr, rw, xb0, vo);
+            qw1[slot] = bload((T *)nullptr, rw, xb1, vo);
             if (RHS) {
                 qf0[slot] = bload((T *)nullptr, rf, xb0, vo);
                 qf1[slot] = bload((T *)nullptr, rf, xb1, vo);
@@ -212,33 +212,29 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     };
 
     T R[NW], B[NW], wR[NW], wB[NW], fR[NW], fB[NW];
+    // the first window is fetched in slot order, so that slot 0's loads are
+    // the oldest in flight when the loop starts, as on every later pass
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
         R[i] = B[i] = wR[i] = wB[i] = fR[i] = fB[i] = T(0);
         qf0[i] = qf1[i] = T(0);
         fetch(i, i);
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     // the trip count is padded to whole windows so that the unrolled body
-    // has no per-row branches: fetches are unconditional (clamped rows) and
-    // rows past the tile are computed but never stored
+    // has no per-row branches: fetches are unconditional (rows past the grid
+    // read zeros) and rows past the tile are computed but never stored
     const int T_pad = ((T_rows + NW - 1) / NW) * NW;
     for (int base = 0; base < T_pad; base += NW) {
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             const int t = base + u;
-            const int y = r0 + t;  // parity of y == parity of u
-            // rows outside the grid read zero values; their classes read as
-            // zero too, so the row test keeps them fixed (uniform)
-            const bool rowok = (uint32_t)y < (uint32_t)ny;
-            const T v0 = in0 ? qv0[u] : T(0);
-            const T v1 = in1 ? qv1[u] : T(0);
-            const T w0 = rowok && qc0[u] == TWG_CELL_FREE ? om0 : T(0);
-            const T w1 = rowok && qc1[u] == TWG_CELL_FREE ? om1 : T(0);
+            const T v0 = qv0[u], v1 = qv1[u], w0 = qw0[u], w1 = qw1[u];
             T f0 = T(0), f1 = T(0);
             if (RHS) {
-                f0 = in0 ? qf0[u] : T(0);
-                f1 = in1 ? qf1[u] : T(0);
+                f0 = qf0[u];
+                f1 = qf1[u];
             }
             // the slot is refilled only after its values are taken, so the
             // queue keeps fixed registers across iterations
@@ -289,10 +285,9 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
 
 template <typename T, int S, bool RHS, bool PAIR>
 __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T *__restrict__ dst,
-                                                    const uint8_t *__restrict__ cls,
+                                                    const T *__restrict__ wmap,
                                                     const T *__restrict__ f, int nx, int ny,
-                                                    int pitch, T omega, int strips, int RH,
-                                                    int tiles)
+                                                    int pitch, int strips, int RH, int tiles)
 {
     constexpr int VW = 128 - 4 * S;  // columns written per strip
     // everything that depends only on the tile is wave-uniform: keep it scalar
@@ -301,8 +296,8 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
     if (tile >= tiles) return;  // whole wave
     const int strip = tile % strips, seg = tile / strips;
     const int ybeg = seg * RH;
-    stream_tile<T, S, RHS, PAIR>(src, dst, cls, f, nx, ny, pitch, omega, strip * VW - 2 * S, ybeg,
-                           min(ybeg + RH, ny));
+    stream_tile<T, S, RHS, PAIR>(src, dst, wmap, f, nx, ny, pitch, strip * VW - 2 * S, ybeg,
+                                 min(ybeg + RH, ny));
 }
 
 // Batched form: the tiles of many grids in one launch.  Grid g's arrays start
@@ -311,7 +306,7 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
 template <int S, bool PAIR>
 __global__ __launch_bounds__(256) void k_sor_stream_batch(const float *__restrict__ src,
                                                           float *__restrict__ dst,
-                                                          const uint8_t *__restrict__ cls,
+                                                          const float *__restrict__ wmap,
                                                           const BatchGrid *__restrict__ grids,
                                                           const BatchTile *__restrict__ tiles,
                                                           const int *__restrict__ n_tiles)
@@ -321,23 +316,23 @@ __global__ __launch_bounds__(256) void k_sor_stream_batch(const float *__restric
     if (tile >= *n_tiles) return;  // whole wave
     const BatchTile t = tiles[tile];
     const BatchGrid g = grids[t.grid];
-    stream_tile<float, S, false, PAIR>(src + g.off, dst + g.off, cls + g.off, nullptr, g.nx, g.ny,
-                                 g.pitch, g.omega, t.x0, t.ybeg, t.yend);
+    stream_tile<float, S, false, PAIR>(src + g.off, dst + g.off, wmap + g.off, nullptr, g.nx, g.ny,
+                                       g.pitch, t.x0, t.ybeg, t.yend);
 }
 
 // Pair access needs even pitch and nx (a pair never leaves its row or the
 // grid) and bases aligned to a pair.
 template <typename T>
-bool pairable(const T *src, const T *dst, const uint8_t *cls, const T *f, int nx, int pitch)
+bool pairable(const T *src, const T *dst, const T *wmap, const T *f, int nx, int pitch)
 {
     const auto al = [](const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; };
-    return nx % 2 == 0 && pitch % 2 == 0 && al(src, 2 * sizeof(T)) && al(dst, 2 * sizeof(T)) && al(cls, 2) &&
-           (!f || al(f, 2 * sizeof(T)));
+    return nx % 2 == 0 && pitch % 2 == 0 && al(src, 2 * sizeof(T)) && al(dst, 2 * sizeof(T)) &&
+           al(wmap, 2 * sizeof(T)) && (!f || al(f, 2 * sizeof(T)));
 }
 
 template <typename T, bool RHS, bool PAIR>
-int launch_stream(const T *src, T *dst, const uint8_t *cls, const T *f, int nx, int ny, int pitch,
-                  T omega, const Geometry &geo, hipStream_t st)
+int launch_stream(const T *src, T *dst, const T *wmap, const T *f, int nx, int ny, int pitch,
+                  const Geometry &geo, hipStream_t st)
 {
     const int cap = stream_rows_cap(pitch, sizeof(T), geo.S);
     const Geometry g = geo.RH > cap ? stream_geometry(nx, ny, geo.S, cap) : geo;
@@ -345,7 +340,7 @@ int launch_stream(const T *src, T *dst, const uint8_t *cls, const T *f, int nx, 
 #define TWG_STREAM_CASE(SV)                                                                           \
     case SV:                                                                                          \
         hipLaunchKernelGGL((k_sor_stream<T, SV, RHS, PAIR>), dim3(blocks), dim3(256), 0, st, src, dst, \
-                           cls, f, nx, ny, pitch, omega, g.strips, g.RH, g.tiles);                    \
+                           wmap, f, nx, ny, pitch, g.strips, g.RH, g.tiles);                          \
         break;
     switch (g.S) {
         TWG_STREAM_CASE(1)
@@ -362,7 +357,7 @@ int launch_stream(const T *src, T *dst, const uint8_t *cls, const T *f, int nx, 
 
 }  // namespace
 
-int launch_stream_batch(const float *src, float *dst, const uint8_t *cls, const BatchGrid *grids,
+int launch_stream_batch(const float *src, float *dst, const float *wmap, const BatchGrid *grids,
                         const BatchTile *tiles, const int *n_tiles, int max_tiles, int S, bool pair,
                         hipStream_t st)
 {
@@ -372,10 +367,10 @@ int launch_stream_batch(const float *src, float *dst, const uint8_t *cls, const 
     case SV:                                                                                           \
         if (pair)                                                                                      \
             hipLaunchKernelGGL((k_sor_stream_batch<SV, true>), dim3(blocks), dim3(256), 0, st, src, dst, \
-                               cls, grids, tiles, n_tiles);                                            \
+                               wmap, grids, tiles, n_tiles);                                           \
         else                                                                                           \
             hipLaunchKernelGGL((k_sor_stream_batch<SV, false>), dim3(blocks), dim3(256), 0, st, src,     \
-                               dst, cls, grids, tiles, n_tiles);                                       \
+                               dst, wmap, grids, tiles, n_tiles);                                      \
         break;
     switch (S) {
         TWG_BATCH_CASE(1)
@@ -411,23 +406,22 @@ Geometry stream_geometry(int nx, int ny, int S, int RH)
     return g;
 }
 
-int launch_stream_f32(const float *src, float *dst, const uint8_t *cls, const float *f, int nx,
-                      int ny, int pitch, float omega, const Geometry &geo, hipStream_t st)
+int launch_stream_f32(const float *src, float *dst, const float *wmap, const float *f, int nx, int ny,
+                      int pitch, const Geometry &geo, hipStream_t st)
 {
-    if (pairable(src, dst, cls, f, nx, pitch))
-        return f ? launch_stream<float, true, true>(src, dst, cls, f, nx, ny, pitch, omega, geo, st)
-                 : launch_stream<float, false, true>(src, dst, cls, f, nx, ny, pitch, omega, geo, st);
-    return f ? launch_stream<float, true, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, st)
-             : launch_stream<float, false, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, st);
+    if (pairable(src, dst, wmap, f, nx, pitch))
+        return f ? launch_stream<float, true, true>(src, dst, wmap, f, nx, ny, pitch, geo, st)
+                 : launch_stream<float, false, true>(src, dst, wmap, f, nx, ny, pitch, geo, st);
+    return f ? launch_stream<float, true, false>(src, dst, wmap, f, nx, ny, pitch, geo, st)
+             : launch_stream<float, false, false>(src, dst, wmap, f, nx, ny, pitch, geo, st);
 }
 
-int launch_stream_f64(const double *src, double *dst, const uint8_t *cls, const double *f, int nx,
-                      int ny, int pitch, double omega, const Geometry &geo, hipStream_t st)
+int launch_stream_f64(const double *src, double *dst, const double *wmap, int nx, int ny, int pitch,
+                      const Geometry &geo, hipStream_t st)
 {
-    if (f) return TWG_EUNSUPPORTED;
-    if (pairable(src, dst, cls, f, nx, pitch))
-        return launch_stream<double, false, true>(src, dst, cls, f, nx, ny, pitch, omega, geo, st);
-    return launch_stream<double, false, false>(src, dst, cls, f, nx, ny, pitch, omega, geo, st);
+    if (pairable(src, dst, wmap, (const double *)nullptr, nx, pitch))
+        return launch_stream<double, false, true>(src, dst, wmap, nullptr, nx, ny, pitch, geo, st);
+    return launch_stream<double, false, false>(src, dst, wmap, nullptr, nx, ny, pitch, geo, st);
 }
 
 }  // namespace twg
