@@ -16,14 +16,21 @@ __device__ __forceinline__ float upd(float old, float ew, float sn, float w, flo
     return __builtin_fmaf(w, d, old);
 }
 
-// FP64: unfused, in the order of the definition (this file is compiled with
+// FP64: in the order of the definition (this file is compiled with
 // contraction off), so one sweep reproduces a plain FP64 sweep bit for bit.
+// Without a source the quarter is folded into the subtraction: the product
+// (E + W + S + N) / 4 is exact (unless it is subnormal), so the fma rounds
+// once where the plain form rounds once as well.
 template <bool RHS>
 __device__ __forceinline__ double upd(double old, double ew, double sn, double w, double f)
 {
-    double g = (ew + sn) * 0.25;
-    if (RHS) g = g + f;
-    const double d = g - old;
+    double d;
+    if (RHS) {
+        const double g = (ew + sn) * 0.25 + f;
+        d = g - old;
+    } else {
+        d = __builtin_fma(0.25, ew + sn, -old);
+    }
     return old + w * d;
 }
 
