@@ -33,7 +33,9 @@ def main(argv=None):
     ap.add_argument("--net", action="store_true", help="profile the network kernels instead")
     ap.add_argument("--S", type=int, default=0, help="sweeps per tile load (with --RH: skip the autotuner)")
     ap.add_argument("--RH", type=int, default=0, help="output rows per tile")
-    ap.add_argument("--fp64", action="store_true", help="also run the FP64 sweeps (tuned tiling)")
+    ap.add_argument("--fp64", action="store_true", help="also run the FP64 sweeps")
+    ap.add_argument("--S64", type=int, default=0, help="FP64 sweeps per tile load (with --RH64)")
+    ap.add_argument("--RH64", type=int, default=0, help="FP64 output rows per tile")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -69,8 +71,8 @@ def main(argv=None):
         ctx.close()
         return 0
     if args.S and args.RH:
-        ctx.set_tiling(nx, ny, args.S, args.RH)
-        tune = {"S": args.S, "RH": args.RH, "omega": 1.99}
+        ctx.set_tiling(nx, ny, args.S, args.RH, S64=args.S64, RH64=args.RH64)
+        tune = {"S": args.S, "RH": args.RH, "omega": 1.99, "S64": args.S64 or 4}
     else:
         tune = ctx.autotune(cls)
     psi = torch.full((ny, nx), 0.5, dtype=torch.float32, device=dev)
@@ -84,8 +86,9 @@ def main(argv=None):
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    print(f"profiled {2 * args.passes} passes of S={tune['S']} RH={tune['RH']} on {nx}x{ny}; "
-          f"copy of {args.copy_mib} MiB", flush=True)
+    print(f"profiled {2 * args.passes} passes of S={tune['S']} RH={tune['RH']} on {nx}x{ny}"
+          + (f" and as many FP64 passes (S={tune['S64']})" if args.fp64 else "")
+          + f"; copy of {args.copy_mib} MiB", flush=True)
     ctx.close()
     return 0
 
