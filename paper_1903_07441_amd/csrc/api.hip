@@ -196,7 +196,6 @@ struct Runner {
     // SOR factor maps for the streamed sweeps, built at most once per call
     // (the class map is fixed for the duration of a call) and omega
     float w32_omega = -1.0f;
-    double w64_omega = -1.0;
     int wmap32(float omega, const float **w)
     {
         if (w32_omega != omega) {
@@ -209,16 +208,17 @@ struct Runner {
         *w = static_cast<const float *>(ctx->wmap32);
         return TWG_OK;
     }
-    int wmap64(double omega, const double **w)
+    bool have_fmask = false;
+    int fmask(const uint8_t **m)
     {
-        if (w64_omega != omega) {
-            int rc = ensure(ctx, &ctx->wmap64, &ctx->wmap64_bytes, (size_t)g.pitch * g.ny * sizeof(double));
+        if (!have_fmask) {
+            int rc = ensure(ctx, &ctx->fmask, &ctx->fmask_bytes, (size_t)g.pitch * g.ny);
             if (rc) return rc;
-            rc = launch_wmap_f64(cls, static_cast<double *>(ctx->wmap64), omega, g.nx, g.ny, g.pitch, st);
-            if (rc) return set_err(ctx, rc, "factor map launch failed");
-            w64_omega = omega;
+            rc = launch_fmask(cls, static_cast<uint8_t *>(ctx->fmask), g.nx, g.ny, g.pitch, st);
+            if (rc) return set_err(ctx, rc, "free mask launch failed");
+            have_fmask = true;
         }
-        *w = static_cast<const double *>(ctx->wmap64);
+        *m = static_cast<const uint8_t *>(ctx->fmask);
         return TWG_OK;
     }
 
@@ -335,8 +335,8 @@ struct Runner {
         int S, RH;
         tiling64_for(ctx, g.nx, g.ny, &S, &RH);
         const Geometry geo = stream_geometry(g.nx, g.ny, S, RH);
-        const double *w = nullptr;
-        if ((rc = wmap64(omega, &w))) return rc;
+        const uint8_t *m = nullptr;
+        if ((rc = fmask(&m))) return rc;
         double *a = field, *b = reinterpret_cast<double *>(ctx->alt64);
         double r;
         rc = residual64(a, &r);
@@ -353,7 +353,7 @@ struct Runner {
             int64_t chunk = std::max<int64_t>((int64_t)std::ceil(want * 1.05) + S, 8 * S);
             chunk = ((std::min(chunk, max_sweeps - done) + S - 1) / S) * S;
             for (int64_t k = 0; k < chunk; k += S) {
-                rc = launch_stream_f64(a, b, w, g.nx, g.ny, g.pitch, geo, st);
+                rc = launch_stream_f64(a, b, m, omega, g.nx, g.ny, g.pitch, geo, st);
                 if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
                 std::swap(a, b);
             }
@@ -415,7 +415,7 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
     for (auto &g : ctx->graphs) hipGraphExecDestroy(g.exec);
     ctx->graphs.clear();
     if (ctx->cap) hipStreamDestroy(ctx->cap);
-    void *bufs[] = {ctx->alt,   ctx->pol,    ctx->alt64, ctx->wmap32,  ctx->wmap64, ctx->pairs,
+    void *bufs[] = {ctx->alt,   ctx->pol,    ctx->alt64, ctx->wmap32,  ctx->fmask,  ctx->pairs,
                     ctx->idxbuf, ctx->batch, ctx->words, ctx->jumpbuf, ctx->rpart};
     for (void *b : bufs)
         if (b) hipFree(b);
@@ -883,8 +883,8 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
         if (!rc) rc = launch_fill_f32(b, 0.5f, g.nx, g.ny, g.pitch, st);
         if (!rc) rc = launch_field_init(cls, b, g.nx, g.ny, g.pitch, HPF_INIT_KEEP, st);
         if (!rc) rc = launch_widen(b, a64, g.nx, g.ny, g.pitch, st);
-        const double *w64 = nullptr;
-        if (!rc) rc = run.wmap64((double)om0, &w64);
+        const uint8_t *m64 = nullptr;
+        if (!rc) rc = run.fmask(&m64);
         const int Ss64[] = {2, 3, 4, 6, 8};
         for (int S : Ss64) {
             if (rc) break;
@@ -895,12 +895,12 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
                 passes += passes & 1;
                 double *x = a64, *y = b64;
                 for (int k = 0; k < 2 && !rc; ++k) {  // warm-up
-                    rc = launch_stream_f64(x, y, w64, g.nx, g.ny, g.pitch, geo, st);
+                    rc = launch_stream_f64(x, y, m64, (double)om0, g.nx, g.ny, g.pitch, geo, st);
                     std::swap(x, y);
                 }
                 hipEventRecord(e0, st);
                 for (int k = 0; k < passes && !rc; ++k) {
-                    rc = launch_stream_f64(x, y, w64, g.nx, g.ny, g.pitch, geo, st);
+                    rc = launch_stream_f64(x, y, m64, (double)om0, g.nx, g.ny, g.pitch, geo, st);
                     std::swap(x, y);
                 }
                 hipEventRecord(e1, st);
@@ -1016,12 +1016,12 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
     if (rc) return rc;
     double *a = psi64, *b = reinterpret_cast<double *>(ctx->alt64);
     Runner run{ctx, g, cls, st};
-    const double *w = nullptr;
-    if ((rc = run.wmap64(omega, &w))) return rc;
+    const uint8_t *m = nullptr;
+    if ((rc = run.fmask(&m))) return rc;
     const Geometry geo = stream_geometry(g.nx, g.ny, S, RH), geo1 = stream_geometry(g.nx, g.ny, 1, RH);
     for (int64_t done = 0; done < sweeps;) {
         const bool full = sweeps - done >= S;
-        rc = launch_stream_f64(a, b, w, g.nx, g.ny, g.pitch, full ? geo : geo1, st);
+        rc = launch_stream_f64(a, b, m, omega, g.nx, g.ny, g.pitch, full ? geo : geo1, st);
         if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
         std::swap(a, b);
         done += full ? S : 1;

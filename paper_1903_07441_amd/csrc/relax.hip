@@ -278,7 +278,8 @@ __global__ void k_copy(const float *__restrict__ s, float *__restrict__ d, int n
 
 dim3 cell_grid(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); }
 
-// SOR factor map of the streamed sweeps: omega on FREE cells, 0 on the others
+// SOR factor map of the FP32 streamed sweeps (omega on FREE cells, 0 on the
+// others) and free mask of the FP64 ones (1 on FREE cells, 0 on the others)
 template <typename T>
 __global__ void k_wmap(const uint8_t *__restrict__ cls, T *__restrict__ w, T omega, int nx, int ny, int pitch)
 {
@@ -343,9 +344,10 @@ int launch_wmap_f32(const uint8_t *cls, float *wmap, float omega, int nx, int ny
     return last_status();
 }
 
-int launch_wmap_f64(const uint8_t *cls, double *wmap, double omega, int nx, int ny, int pitch, hipStream_t st)
+int launch_fmask(const uint8_t *cls, uint8_t *fmask, int nx, int ny, int pitch, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_wmap<double>, cell_grid(nx, ny), dim3(256), 0, st, cls, wmap, omega, nx, ny, pitch);
+    hipLaunchKernelGGL(k_wmap<uint8_t>, cell_grid(nx, ny), dim3(256), 0, st, cls, fmask, (uint8_t)1, nx, ny,
+                       pitch);
     return last_status();
 }
 

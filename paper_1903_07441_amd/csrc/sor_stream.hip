@@ -4,9 +4,12 @@
 //
 // Field layout: row-major, x fastest, pitch in elements; psi = 1 - phi.  Red
 // cells are (x + y) even.  One sweep sets every FREE cell of one colour, then
-// of the other, to psi + w * (((E + W) + (S + N)) / 4 + f - psi), where the
-// factor map w holds omega on FREE cells and 0 on fixed ones (which are thus
-// rewritten unchanged); the map is built once per call from the class map.
+// of the other, to psi + w * (((E + W) + (S + N)) / 4 + f - psi), where w is
+// omega on FREE cells and 0 on fixed ones (which are thus rewritten
+// unchanged).  The FP32 kernels read w from a factor map; the FP64 kernels,
+// which move twice the bytes per cell and are closer to the HBM bound, read a
+// one-byte free mask and select omega or 0.  Both maps are built once per
+// call from the class map.
 //
 // One wave owns a strip of 128 columns (each lane two adjacent columns, so in
 // every row a lane holds exactly one red and one black cell) and streams it
@@ -148,10 +151,11 @@ __device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc
 // operations, so no row step ever waits for the loads of the rows after it.
 template <typename T, int S, bool RHS, bool PAIR>
 __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__restrict__ dst,
-                                            const T *__restrict__ wmap,
+                                            const void *__restrict__ wsrc, T omega,
                                             const T *__restrict__ f, int nx, int ny, int pitch,
                                             int x0, int ybeg, int yend)
 {
+    constexpr bool MASK = sizeof(T) == 8;  // free mask (FP64) or factor map (FP32)
     constexpr int NW = 2 * S + 2;      // rolling window of rows (even)
     const int lane = threadIdx.x & (kWave - 1);
     const int r0 = ybeg - 2 * S;                   // first row streamed (even)
@@ -166,7 +170,9 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     const uint32_t outc = (uint32_t)(yend - ybeg - 1) * (uint32_t)pitch + (uint32_t)nx;
     const size_t base = (size_t)lo * pitch;
     const __amdgpu_buffer_rsrc_t rs = rsrc(src + base, cells * sizeof(T));
-    const __amdgpu_buffer_rsrc_t rw = rsrc(wmap + base, cells * sizeof(T));
+    const __amdgpu_buffer_rsrc_t rw =
+        MASK ? rsrc(static_cast<const uint8_t *>(wsrc) + base, cells)
+             : rsrc(static_cast<const T *>(wsrc) + base, cells * sizeof(T));
     const __amdgpu_buffer_rsrc_t rf = rsrc(RHS ? f + base : src + base, cells * sizeof(T));
     const __amdgpu_buffer_rsrc_t rd = rsrc(dst + (size_t)ybeg * pitch, outc * sizeof(T));
     // per-lane constants: a column outside the grid gets an out-of-range
@@ -177,23 +183,35 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     const bool writer = lane >= S && lane < kWave - S;
     const uint32_t xb0 = in0 ? (uint32_t)xa * sizeof(T) : kNoStore;
     const uint32_t xb1 = in1 ? (uint32_t)(xa + 1) * sizeof(T) : kNoStore;
+    const uint32_t xm0 = in0 ? (uint32_t)xa : kNoStore, xm1 = in1 ? (uint32_t)(xa + 1) : kNoStore;
     const uint32_t so0 = writer ? xb0 : kNoStore;
     const uint32_t so1 = writer ? xb1 : kNoStore;
     // row offsets (bytes) of streamed row t and of output row t - 4S;
     // negative ones are far out of range as unsigned sums
-    const int vrow0 = (r0 - lo) * (int)rowb;
+    const int vrow0 = (r0 - lo) * (int)rowb, mrow0 = (r0 - lo) * pitch;
     const int orow0 = (r0 - 2 * S - ybeg) * (int)rowb;
 
     T qv0[NW], qv1[NW], qw0[NW], qw1[NW], qf0[NW], qf1[NW];
+    uint32_t qm0[NW], qm1[NW];
     auto fetch = [&](int slot, int t) {
-        const uint32_t vo = (uint32_t)(vrow0 + t * (int)rowb);
+        const uint32_t vo = (uint32_t)(vrow0 + t * (int)rowb), mo = (uint32_t)(mrow0 + t * pitch);
+        if constexpr (MASK) {
+            if constexpr (PAIR) {
+                qm0[slot] = __builtin_amdgcn_raw_buffer_load_b16(rw, (int)xm0, (int)mo, 0);
+            } else {
+                qm0[slot] = __builtin_amdgcn_raw_buffer_load_b8(rw, (int)xm0, (int)mo, 0);
+                qm1[slot] = __builtin_amdgcn_raw_buffer_load_b8(rw, (int)xm1, (int)mo, 0);
+            }
+        }
         if constexpr (PAIR) {
             const Pair<T> v = bload2((T *)nullptr, rs, xb0, vo);
             qv0[slot] = v.a;
             qv1[slot] = v.b;
-            const Pair<T> w = bload2((T *)nullptr, rw, xb0, vo);
-            qw0[slot] = w.a;
-            qw1[slot] = w.b;
+            if constexpr (!MASK) {
+                const Pair<T> w = bload2((T *)nullptr, rw, xb0, vo);
+                qw0[slot] = w.a;
+                qw1[slot] = w.b;
+            }
             if (RHS) {
                 const Pair<T> h = bload2((T *)nullptr, rf, xb0, vo);
                 qf0[slot] = h.a;
@@ -202,8 +220,10 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
         } else {
             qv0[slot] = bload((T *)nullptr, rs, xb0, vo);
             qv1[slot] = bload((T *)nullptr, rs, xb1, vo);
-            qw0[slot] = bload((T *)nullptr, rw, xb0, vo);
-            qw1[slot] = bload((T *)nullptr, rw, xb1, vo);
+            if constexpr (!MASK) {
+                qw0[slot] = bload((T *)nullptr, rw, xb0, vo);
+                qw1[slot] = bload((T *)nullptr, rw, xb1, vo);
+            }
             if (RHS) {
                 qf0[slot] = bload((T *)nullptr, rf, xb0, vo);
                 qf1[slot] = bload((T *)nullptr, rf, xb1, vo);
@@ -230,7 +250,18 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             const int t = base + u;
-            const T v0 = qv0[u], v1 = qv1[u], w0 = qw0[u], w1 = qw1[u];
+            const T v0 = qv0[u], v1 = qv1[u];
+            T w0, w1;
+            if constexpr (!MASK) {
+                w0 = qw0[u];
+                w1 = qw1[u];
+            } else if constexpr (PAIR) {
+                w0 = (qm0[u] & 0xffu) ? omega : T(0);
+                w1 = (qm0[u] >> 8) ? omega : T(0);
+            } else {
+                w0 = qm0[u] ? omega : T(0);
+                w1 = qm1[u] ? omega : T(0);
+            }
             T f0 = T(0), f1 = T(0);
             if (RHS) {
                 f0 = qf0[u];
@@ -285,7 +316,7 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
 
 template <typename T, int S, bool RHS, bool PAIR>
 __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T *__restrict__ dst,
-                                                    const T *__restrict__ wmap,
+                                                    const void *__restrict__ wsrc, T omega,
                                                     const T *__restrict__ f, int nx, int ny,
                                                     int pitch, int strips, int RH, int tiles)
 {
@@ -296,7 +327,7 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
     if (tile >= tiles) return;  // whole wave
     const int strip = tile % strips, seg = tile / strips;
     const int ybeg = seg * RH;
-    stream_tile<T, S, RHS, PAIR>(src, dst, wmap, f, nx, ny, pitch, strip * VW - 2 * S, ybeg,
+    stream_tile<T, S, RHS, PAIR>(src, dst, wsrc, omega, f, nx, ny, pitch, strip * VW - 2 * S, ybeg,
                                  min(ybeg + RH, ny));
 }
 
@@ -316,22 +347,23 @@ __global__ __launch_bounds__(256) void k_sor_stream_batch(const float *__restric
     if (tile >= *n_tiles) return;  // whole wave
     const BatchTile t = tiles[tile];
     const BatchGrid g = grids[t.grid];
-    stream_tile<float, S, false, PAIR>(src + g.off, dst + g.off, wmap + g.off, nullptr, g.nx, g.ny,
+    stream_tile<float, S, false, PAIR>(src + g.off, dst + g.off, wmap + g.off, 0.0f, nullptr, g.nx, g.ny,
                                        g.pitch, t.x0, t.ybeg, t.yend);
 }
 
 // Pair access needs even pitch and nx (a pair never leaves its row or the
 // grid) and bases aligned to a pair.
+// (wsrc holds elements of wbytes bytes: the factor map or the free mask)
 template <typename T>
-bool pairable(const T *src, const T *dst, const T *wmap, const T *f, int nx, int pitch)
+bool pairable(const T *src, const T *dst, const void *wsrc, size_t wbytes, const T *f, int nx, int pitch)
 {
     const auto al = [](const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; };
     return nx % 2 == 0 && pitch % 2 == 0 && al(src, 2 * sizeof(T)) && al(dst, 2 * sizeof(T)) &&
-           al(wmap, 2 * sizeof(T)) && (!f || al(f, 2 * sizeof(T)));
+           al(wsrc, 2 * wbytes) && (!f || al(f, 2 * sizeof(T)));
 }
 
 template <typename T, bool RHS, bool PAIR>
-int launch_stream(const T *src, T *dst, const T *wmap, const T *f, int nx, int ny, int pitch,
+int launch_stream(const T *src, T *dst, const void *wsrc, T omega, const T *f, int nx, int ny, int pitch,
                   const Geometry &geo, hipStream_t st)
 {
     const int cap = stream_rows_cap(pitch, sizeof(T), geo.S);
@@ -340,7 +372,7 @@ int launch_stream(const T *src, T *dst, const T *wmap, const T *f, int nx, int n
 #define TWG_STREAM_CASE(SV)                                                                           \
     case SV:                                                                                          \
         hipLaunchKernelGGL((k_sor_stream<T, SV, RHS, PAIR>), dim3(blocks), dim3(256), 0, st, src, dst, \
-                           wmap, f, nx, ny, pitch, g.strips, g.RH, g.tiles);                          \
+                           wsrc, omega, f, nx, ny, pitch, g.strips, g.RH, g.tiles);                   \
         break;
     switch (g.S) {
         TWG_STREAM_CASE(1)
@@ -409,19 +441,19 @@ Geometry stream_geometry(int nx, int ny, int S, int RH)
 int launch_stream_f32(const float *src, float *dst, const float *wmap, const float *f, int nx, int ny,
                       int pitch, const Geometry &geo, hipStream_t st)
 {
-    if (pairable(src, dst, wmap, f, nx, pitch))
-        return f ? launch_stream<float, true, true>(src, dst, wmap, f, nx, ny, pitch, geo, st)
-                 : launch_stream<float, false, true>(src, dst, wmap, f, nx, ny, pitch, geo, st);
-    return f ? launch_stream<float, true, false>(src, dst, wmap, f, nx, ny, pitch, geo, st)
-             : launch_stream<float, false, false>(src, dst, wmap, f, nx, ny, pitch, geo, st);
+    if (pairable(src, dst, wmap, sizeof(float), f, nx, pitch))
+        return f ? launch_stream<float, true, true>(src, dst, wmap, 0.0f, f, nx, ny, pitch, geo, st)
+                 : launch_stream<float, false, true>(src, dst, wmap, 0.0f, f, nx, ny, pitch, geo, st);
+    return f ? launch_stream<float, true, false>(src, dst, wmap, 0.0f, f, nx, ny, pitch, geo, st)
+             : launch_stream<float, false, false>(src, dst, wmap, 0.0f, f, nx, ny, pitch, geo, st);
 }
 
-int launch_stream_f64(const double *src, double *dst, const double *wmap, int nx, int ny, int pitch,
-                      const Geometry &geo, hipStream_t st)
+int launch_stream_f64(const double *src, double *dst, const uint8_t *fmask, double omega, int nx, int ny,
+                      int pitch, const Geometry &geo, hipStream_t st)
 {
-    if (pairable(src, dst, wmap, (const double *)nullptr, nx, pitch))
-        return launch_stream<double, false, true>(src, dst, wmap, nullptr, nx, ny, pitch, geo, st);
-    return launch_stream<double, false, false>(src, dst, wmap, nullptr, nx, ny, pitch, geo, st);
+    if (pairable(src, dst, fmask, 1, (const double *)nullptr, nx, pitch))
+        return launch_stream<double, false, true>(src, dst, fmask, omega, nullptr, nx, ny, pitch, geo, st);
+    return launch_stream<double, false, false>(src, dst, fmask, omega, nullptr, nx, ny, pitch, geo, st);
 }
 
 }  // namespace twg

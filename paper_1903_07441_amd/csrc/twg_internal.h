@@ -36,12 +36,12 @@ struct twg_ctx {
     // FP64 ping-pong partner (FP64 sweeps)
     void *alt64 = nullptr;
     size_t alt64_bytes = 0;
-    // SOR factor maps of the streamed sweeps (FP32 and FP64), rebuilt by
+    // SOR factor map (FP32 sweeps) and free mask (FP64 sweeps), rebuilt by
     // every call that sweeps
     void *wmap32 = nullptr;
     size_t wmap32_bytes = 0;
-    void *wmap64 = nullptr;
-    size_t wmap64_bytes = 0;
+    void *fmask = nullptr;
+    size_t fmask_bytes = 0;
     // (obstacle, ring) work list of the rasteriser and its counter
     void *pairs = nullptr;
     size_t pairs_bytes = 0;
@@ -123,14 +123,16 @@ bool stream_depth_supported(int S);
 // largest RH whose tiles the streamed kernels can address (RH above it is
 // lowered at launch)
 int stream_rows_cap(int pitch, int elem_bytes, int S);
-// streamed sweeps; wmap: the SOR factor map (omega on FREE cells, 0 on the
-// others) built by launch_wmap_* for the sweeps' omega
+// streamed sweeps.  FP32: wmap is the SOR factor map (omega on FREE cells, 0
+// on the others) built by launch_wmap_f32 for the sweeps' omega.  FP64:
+// fmask is the free mask (1 on FREE cells, 0 on the others) built by
+// launch_fmask.
 int launch_stream_f32(const float *src, float *dst, const float *wmap, const float *f, int nx, int ny,
                       int pitch, const Geometry &geo, hipStream_t st);
-int launch_stream_f64(const double *src, double *dst, const double *wmap, int nx, int ny, int pitch,
-                      const Geometry &geo, hipStream_t st);
+int launch_stream_f64(const double *src, double *dst, const uint8_t *fmask, double omega, int nx, int ny,
+                      int pitch, const Geometry &geo, hipStream_t st);
 int launch_wmap_f32(const uint8_t *cls, float *wmap, float omega, int nx, int ny, int pitch, hipStream_t st);
-int launch_wmap_f64(const uint8_t *cls, double *wmap, double omega, int nx, int ny, int pitch, hipStream_t st);
+int launch_fmask(const uint8_t *cls, uint8_t *fmask, int nx, int ny, int pitch, hipStream_t st);
 // the batch's map, each grid with its own omega, over the batch's column blocks
 int launch_wmap_batch(const uint8_t *cls, float *wmap, const BatchGrid *grids, const int2 *blocks,
                       int n_blocks, hipStream_t st);
