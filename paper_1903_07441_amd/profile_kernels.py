@@ -2,8 +2,8 @@
 alone, for profilers.
 
 Rasterises a 2048 x 2048 replanning scenario, tunes the tiling, then runs
-`--passes` passes of the streamed SOR kernel (and with --fp64 as many FP64
-passes), followed by one device copy of
+`--passes` passes of the streamed SOR kernel (with --rhs as many passes with
+a source term, with --fp64 as many FP64 passes), followed by one device copy of
 `--copy-mib` MiB (a kernel of known traffic: it reads and writes exactly that
 many bytes) so that hardware byte counters can be calibrated against it.
 
@@ -34,6 +34,8 @@ def main(argv=None):
     ap.add_argument("--S", type=int, default=0, help="sweeps per tile load (with --RH: skip the autotuner)")
     ap.add_argument("--RH", type=int, default=0, help="output rows per tile")
     ap.add_argument("--fp64", action="store_true", help="also run the FP64 sweeps")
+    ap.add_argument("--rhs", action="store_true",
+                    help="also run FP32 sweeps with a source term (the defect-correction solves' kernel)")
     ap.add_argument("--S64", type=int, default=0, help="FP64 sweeps per tile load (with --RH64)")
     ap.add_argument("--RH64", type=int, default=0, help="FP64 output rows per tile")
     args = ap.parse_args(argv)
@@ -77,6 +79,9 @@ def main(argv=None):
         tune = ctx.autotune(cls)
     psi = torch.full((ny, nx), 0.5, dtype=torch.float32, device=dev)
     ctx.sweeps(cls, psi, tune["omega"], 2 * tune["S"] * args.passes, sweeps_per_pass=tune["S"])
+    if args.rhs:
+        src = torch.zeros_like(psi)
+        ctx.sweeps(cls, psi, tune["omega"], 2 * tune["S"] * args.passes, sweeps_per_pass=tune["S"], f=src)
     if args.fp64:
         psi64 = torch.full((ny, nx), 0.5, dtype=torch.float64, device=dev)
         s64 = int(tune.get("S64") or tune["S"])
@@ -87,6 +92,7 @@ def main(argv=None):
     b.copy_(a)
     torch.cuda.synchronize()
     print(f"profiled {2 * args.passes} passes of S={tune['S']} RH={tune['RH']} on {nx}x{ny}"
+          + (" and as many with a source term" if args.rhs else "")
           + (f" and as many FP64 passes (S={tune['S64']})" if args.fp64 else "")
           + f"; copy of {args.copy_mib} MiB", flush=True)
     ctx.close()
