@@ -228,7 +228,8 @@ typedef struct {
  * avg4 is the mean of the four neighbours (Eq. 1), with Dirichlet values on
  * every other cell: OBST and WALL 0, GOAL 1, FIXED the input value.  The
  * iteration is red-black SOR (red = (x + y) even first; each FREE cell set to
- * psi + omega (avg4(psi) - psi), summed as ((E + W) + (S + N)) / 4) in FP32,
+ * psi + omega (avg4(psi) - psi), evaluated as fma(omega, fma(1/4,
+ * ((E + W) + N) + S, -psi), psi) with N the row above and S the row below) in FP32,
  * several sweeps per tile load.  It stops when the FP64 residual
  * r = max |avg4(psi) - psi| over FREE cells is <= tol.  Because
  * |psi - psi*| <= r * ||(I - J)^-1 1||inf (discrete maximum principle), the
@@ -297,9 +298,9 @@ int32_t hpf_sweeps(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, con
                    void *stream);
 
 /* hpf_sweeps64 -- exactly `sweeps` red-black SOR sweeps of an FP64 field
- * psi64, the update evaluated unfused in the order of the definition
- * (g = ((E + W) + (S + N)) * 0.25, psi + omega * (g - psi)), so one sweep
- * matches a plain FP64 sweep bit for bit.  tiled = 0: one launch per colour;
+ * psi64, the update evaluated as fma(omega, fma(1/4, ((E + W) + N) + S,
+ * -psi), psi) (N the row above, S the row below, each operation rounded
+ * once), the expression the oracle's FP64 sweep evaluates, bit for bit.  tiled = 0: one launch per colour;
  * tiled = 1: sweeps_per_pass (1, 2, 3, 4, 6 or 8; 0 = the autotuned FP64
  * tiling of this grid size, else 4) sweeps per tile load, bit-identical.  Asynchronous.  Errors: TWG_EINVAL. */
 int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64, double omega,

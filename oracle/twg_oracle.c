@@ -519,7 +519,11 @@ void orc_residual_field(int32_t nx, int32_t ny, const uint8_t *cls, const double
 /* One red-black SOR sweep: red cells ((x + y) even) first, then black, each
  * FREE cell set to psi + omega * (avg4(psi) + f - psi).  With omega = 1 this
  * is Gauss-Seidel in red-black order: the in-place use of already updated
- * neighbours of Eq. (2), with a different visiting order. */
+ * neighbours of Eq. (2), with a different visiting order.  The update is
+ * evaluated as
+ *     d = fma(1/4, ((E + W) + N) + S, f - psi),   psi' = fma(omega, d, psi)
+ * (N the row above, S the row below, f = 0 without a source), one rounding
+ * per operation; the GPU's FP64 sweeps use the same expression. */
 void orc_sor_sweep(int32_t nx, int32_t ny, const uint8_t *cls, double *psi,
                    const double *f, double omega)
 {
@@ -529,9 +533,12 @@ void orc_sor_sweep(int32_t nx, int32_t ny, const uint8_t *cls, double *psi,
             for (int32_t x = (y + color) & 1; x < nx; x += 2) {
                 size_t idx = (size_t)y * nx + x;
                 if (cls[idx] != O_FREE) continue;
-                double g = avg4(psi, nx, ny, x, y);
-                if (f) g = g + f[idx];
-                psi[idx] = psi[idx] + omega * (g - psi[idx]);
+                double e = at(psi, nx, ny, x + 1, y), w = at(psi, nx, ny, x - 1, y);
+                double n = at(psi, nx, ny, x, y - 1), s = at(psi, nx, ny, x, y + 1);
+                double sum = ((e + w) + n) + s;
+                double rest = f ? f[idx] - psi[idx] : -psi[idx];
+                double d = fma(0.25, sum, rest);
+                psi[idx] = fma(omega, d, psi[idx]);
             }
     }
 }

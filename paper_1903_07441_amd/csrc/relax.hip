@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void k_sweep_color(const uint8_t *__restrict__
     const T s = y + 1 < ny ? psi[i + pitch] : T(0);
     const T n = y > 0 ? psi[i - pitch] : T(0);
     const T om = cls[i] == TWG_CELL_FREE ? omega : T(0);
-    psi[i] = upd<RHS>(psi[i], e + w, s + n, om, RHS ? f[i] : T(0));
+    psi[i] = upd<RHS>(psi[i], (e + w) + n, s, om, RHS ? f[i] : T(0));
 }
 
 // ---- residual, FP64 arithmetic ------------------------------------------

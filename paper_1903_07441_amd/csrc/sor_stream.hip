@@ -4,8 +4,8 @@
 //
 // Field layout: row-major, x fastest, pitch in elements; psi = 1 - phi.  Red
 // cells are (x + y) even.  One sweep sets every FREE cell of one colour, then
-// of the other, to psi + w * (((E + W) + (S + N)) / 4 + f - psi), where w is
-// omega on FREE cells and 0 on fixed ones (which are thus rewritten
+// of the other, to psi + w * (avg4 + f - psi), evaluated as in update.h, where
+// w is omega on FREE cells and 0 on fixed ones (which are thus rewritten
 // unchanged).  The FP32 kernels read w from a factor map; the FP64 kernels,
 // which move twice the bytes per cell and are closer to the HBM bound, read a
 // one-byte free mask and select omega or 0.  Both maps are built once per
@@ -276,22 +276,32 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
             } else {
                 R[u] = v1; B[u] = v0; wR[u] = w1; wB[u] = w0; fR[u] = f1; fB[u] = f0;
             }
+            // stage k: half-sweep k of the pass (red for even k) at row
+            // y - 1 - k (slot s).  Its E, W and N (row above, slot sm)
+            // neighbours were finished in earlier row steps, so their sums
+            // are formed first for all stages; S (row below, slot sp) is the
+            // value stage k - 1 produces in this row step and is added last.
+            T ewn[2 * S];
 #pragma unroll
             for (int k = 0; k < 2 * S; ++k) {
-                const int s = (u - 1 - k + 4 * NW) % NW;  // slot of row y - 1 - k
-                const int sp = (s + 1) % NW, sm = (s + NW - 1) % NW;
+                const int s = (u - 1 - k + 4 * NW) % NW;
+                const int sm = (s + NW - 1) % NW;
                 if ((k & 1) == 0) {
-                    // red half-sweep of sweep k/2 at row y - 1 - k
                     const T b = B[s];
-                    const T ew = (s & 1) == 0 ? b + shr1(b) : shl1(b) + b;
-                    const T sn = B[sp] + B[sm];
-                    R[s] = upd<RHS>(R[s], ew, sn, wR[s], fR[s]);
+                    ewn[k] = ((s & 1) == 0 ? b + shr1(b) : shl1(b) + b) + B[sm];
                 } else {
                     const T r = R[s];
-                    const T ew = (s & 1) == 0 ? shl1(r) + r : r + shr1(r);
-                    const T sn = R[sp] + R[sm];
-                    B[s] = upd<RHS>(B[s], ew, sn, wB[s], fB[s]);
+                    ewn[k] = ((s & 1) == 0 ? shl1(r) + r : r + shr1(r)) + R[sm];
                 }
+            }
+#pragma unroll
+            for (int k = 0; k < 2 * S; ++k) {
+                const int s = (u - 1 - k + 4 * NW) % NW;
+                const int sp = (s + 1) % NW;
+                if ((k & 1) == 0)
+                    R[s] = upd<RHS>(R[s], ewn[k], B[sp], wR[s], fR[s]);
+                else
+                    B[s] = upd<RHS>(B[s], ewn[k], R[sp], wB[s], fB[s]);
             }
             // the row finished by this step (row y - 2S) is stored; rows
             // outside [ybeg, yend) fall outside the write resource

@@ -6,33 +6,25 @@
 
 namespace twg {
 
-// FP32: d = avg4 (+ f) - old with the exact quarter folded into one fma,
-// then old + w * d in a second fma.
-template <bool RHS>
-__device__ __forceinline__ float upd(float old, float ew, float sn, float w, float f)
-{
-    const float s = ew + sn;
-    const float d = RHS ? __builtin_fmaf(0.25f, s, f) - old : __builtin_fmaf(0.25f, s, -old);
-    return __builtin_fmaf(w, d, old);
-}
+// The update of a FREE cell with neighbours E, W, N (the row above) and S
+// (the row below):
+//   d    = fma(1/4, ((E + W) + N) + S, f - old)     (f = 0 without a source)
+//   new  = fma(w, d, old)
+// in the element type, each operation rounded once (this file is compiled
+// with contraction off).  S is added last because in the streamed kernels it
+// is the neighbour the previous half-sweep of the same row step has just
+// produced: the order keeps that dependency three operations deep.  The
+// oracle's FP64 sweep evaluates the same expression, so FP64 sweeps match it
+// bit for bit.
+__device__ __forceinline__ float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// FP64: in the order of the definition (this file is compiled with
-// contraction off), so one sweep reproduces a plain FP64 sweep bit for bit.
-// Without a source the quarter is folded into the subtraction: the product
-// (E + W + S + N) / 4 is exact (unless it is subnormal), so the fma rounds
-// once where the plain form rounds once as well.
-template <bool RHS>
-__device__ __forceinline__ double upd(double old, double ew, double sn, double w, double f)
+template <bool RHS, typename T>
+__device__ __forceinline__ T upd(T old, T ewn, T s, T w, T f)
 {
-    double d;
-    if (RHS) {
-        const double g = (ew + sn) * 0.25 + f;
-        d = g - old;
-    } else {
-        d = __builtin_fma(0.25, ew + sn, -old);
-    }
-    return old + w * d;
+    const T sum = ewn + s;
+    const T d = fused(T(0.25), sum, RHS ? f - old : -old);
+    return fused(w, d, old);
 }
-
 
 }  // namespace twg
