@@ -313,15 +313,21 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
  * {1, 2, 3, 4, 6, 8} x output rows per tile RH in {8, 16, 32, 64, 128} plus,
  * for k = 1..4, the smallest height whose tile count (one wave per tile) fits
  * k rounds of the device's SIMDs; each timed with HIP events over repeated
- * passes on context scratch.  Factors:
+ * passes on context scratch.  SOR factors:
  * omega = 2 / (1 + c sin(pi / (n + 1))), n = max(nx, ny), c in
- * {0.7, 1, 1.4, 2, 2.8, 4}; the one with the smallest residual after a fixed
- * number of sweeps from the half-initialised field wins (obstacles shrink the
- * effective domain, so the best factor is below the open-rectangle one).
+ * {1, 1.4, 2, 2.4, 2.8, 3, 3.3, 3.6, 4, 4.5, 5, 6} (obstacles shrink the
+ * effective domain, so the best factor is below the open-rectangle one):
+ * the relaxation's factor by the fewest sweeps from the half-initialised
+ * field to residual 1e-6, the defect-correction solves' factor (polish = 1)
+ * by the fewest correction sweeps in polishing that field to a certified
+ * 1e-7;
+ * each keeps the next factor towards 2 unless that costs over 25 % more
+ * sweeps (below the optimum the count climbs steeply).
  * The FP64 sweeps (polish, hpf_sweeps64 with sweeps_per_pass = 0) get their
  * own tiling the same way, S in {2, 3, 4, 6, 8}.
- * out (host, optional, 7 doubles) receives [S, RH, omega, cell-updates per
- * second, S64, RH64, FP64 cell-updates per second].
+ * out (host, optional, 8 doubles) receives [S, RH, omega, cell-updates per
+ * second, S64, RH64, FP64 cell-updates per second, defect-correction
+ * omega].
  * Blocking.  Errors: TWG_EINVAL, TWG_ENOMEM, TWG_EDEVICE. */
 int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, void *stream);
 

@@ -104,6 +104,14 @@ double bits_to_double(unsigned long long b)
 // Optimal SOR factor of the open rectangle: Jacobi spectral radius of the
 // 5-point average with fixed values outside an nx-by-ny grid, then Young's
 // formula omega = 2 / (1 + sqrt(1 - rho^2)).
+// The autotuner's family of SOR factors for a grid of side n:
+// 2 / (1 + c sin(pi / (n + 1))), c = 1 being the square's optimum.
+float omega_family(int n, double c)
+{
+    const double pi = 3.14159265358979323846;
+    return (float)(2.0 / (1.0 + c * std::sin(pi / (n + 1))));
+}
+
 double omega_open(int nx, int ny)
 {
     const double pi = 3.14159265358979323846;
@@ -273,8 +281,9 @@ struct Runner {
         double r, rr;
         rc = residual32(a, f, &r, &rr);
         if (rc) return rc;
-        int64_t done = 0;
+        int64_t done = 0, last_chunk = 0;
         int stalls = 0;
+        double best = r;
         // per-sweep contraction guess before any measurement
         double rate = std::max((double)omega - 1.0, 0.5);
         *converged = false;
@@ -286,23 +295,33 @@ struct Runner {
             if (check_passes > 0) {
                 chunk = (int64_t)check_passes * S;
             } else {
+                // sweeps the measured rate predicts, at most twice the last
+                // chunk (a rate near 1 near the rounding floor must not turn
+                // into one huge chunk)
                 const double want = std::log(tol / r) / std::log(rate);
-                chunk = (int64_t)std::ceil(want * (checks <= 1 ? 0.8 : 1.05)) + S;
+                chunk = (int64_t)std::min(std::ceil(want * (checks <= 1 ? 0.8 : 1.05)), 1e12) + S;
                 chunk = std::max<int64_t>(chunk, 8 * S);
+                if (last_chunk > 0) chunk = std::min(chunk, std::max<int64_t>(2 * last_chunk, 64 * S));
             }
             chunk = std::min(chunk, max_sweeps - done);
+            last_chunk = chunk;
             const double r_prev = r;
             rc = sweep32(&a, &b, f, omega, S, RH, chunk);
             if (rc) return rc;
             done += chunk;
             rc = residual32(a, f, &r, &rr);
             if (rc) return rc;
-            if (r < r_prev * 0.999) {
-                stalls = 0;
+            if (r < r_prev) {
                 const double q = std::pow(r / r_prev, 1.0 / (double)chunk);
                 if (q > 0.0 && q < 1.0) rate = q;
+            }
+            // stop at the rounding floor: three checks in a row without a
+            // 10 % gain on the best residual so far
+            if (r < 0.9 * best) {
+                best = r;
+                stalls = 0;
             } else if (++stalls >= 3) {
-                break;  // rounding floor or no convergence
+                break;
             }
         }
         if (a != field) {
@@ -325,6 +344,51 @@ struct Runner {
         return TWG_OK;
     }
 
+    // FP64 defect correction of psi64 (widened from psi): r = avg4(psi64) -
+    // psi64 in FP64, solve (I - J) e = r in FP32 from e = 0 (e = 0 on fixed
+    // cells) with factor omega_dc, psi64 += e (psi receives the rounded
+    // field), until the FP64 residual is <= need or 12 rounds.
+    int polish_dc(float *psi, double *psi64, float omega_dc, double need, int S, int RH, int64_t max_sweeps,
+                  int64_t *sweeps_out, int32_t *rounds_out, double *res_out, bool *done)
+    {
+        const size_t n32 = (size_t)g.pitch * g.ny;
+        int rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n32 * sizeof(float));
+        if (rc) return rc;
+        float *r32 = reinterpret_cast<float *>(ctx->pol);
+        float *e = r32 + n32;
+        rc = launch_widen(psi, psi64, g.nx, g.ny, g.pitch, st);
+        if (rc) return set_err(ctx, rc, "widen launch failed");
+        *done = false;
+        *sweeps_out = 0;
+        *rounds_out = 0;
+        double r64 = 0.0;
+        for (int round = 0; round < 12; ++round) {
+            rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st);
+            if (!rc) rc = readback(1);
+            if (rc) return set_err(ctx, rc, "defect kernel failed");
+            r64 = bits_to_double(ctx->host_words[0]);
+            if (std::isnan(r64)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
+            if (r64 <= need) { *done = true; break; }
+            rc = launch_fill_f32(e, 0.0f, g.nx, g.ny, g.pitch, st);
+            if (rc) return set_err(ctx, rc, "fill launch failed");
+            // correction solve: at most four decades per round (the FP32
+            // correction keeps about that much relative accuracy), and no
+            // further than a third of what is still needed
+            const double target = std::max(r64 * 1e-4, need / 3.0);
+            int64_t sw = 0;
+            double re = 0.0;
+            bool cconv = false;
+            rc = solve32(e, r32, omega_dc, S, RH, target, max_sweeps, 0, &sw, &re, &cconv);
+            if (rc) return rc;
+            *sweeps_out += sw;
+            rc = launch_update64(cls, psi64, e, psi, g.nx, g.ny, g.pitch, st);
+            if (rc) return set_err(ctx, rc, "update launch failed");
+            *rounds_out = round + 1;
+        }
+        *res_out = r64;
+        return TWG_OK;
+    }
+
     // FP64 red-black SOR on `field` (ping-pong with ctx->alt64), four sweeps
     // per tile load, until the FP64 residual is <= tol or the budget is spent.
     int solve64(double *field, double omega, double tol, int64_t max_sweeps, int64_t *sweeps_out,
@@ -341,7 +405,7 @@ struct Runner {
         double r;
         rc = residual64(a, &r);
         if (rc) return rc;
-        int64_t done = 0;
+        int64_t done = 0, last_chunk = 0;
         int stalls = 0;
         double rate = std::max(omega - 1.0, 0.5);
         *converged = false;
@@ -350,8 +414,10 @@ struct Runner {
             if (r <= tol) { *converged = true; break; }
             if (done >= max_sweeps) break;
             const double want = std::log(tol / r) / std::log(rate);
-            int64_t chunk = std::max<int64_t>((int64_t)std::ceil(want * 1.05) + S, 8 * S);
+            int64_t chunk = std::max<int64_t>((int64_t)std::min(std::ceil(want * 1.05), 1e12) + S, 8 * S);
+            if (last_chunk > 0) chunk = std::min(chunk, std::max<int64_t>(2 * last_chunk, 64 * S));
             chunk = ((std::min(chunk, max_sweeps - done) + S - 1) / S) * S;
+            last_chunk = chunk;
             for (int64_t k = 0; k < chunk; k += S) {
                 rc = launch_stream_f64(a, b, m, omega, g.nx, g.ny, g.pitch, geo, st);
                 if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
@@ -416,7 +482,7 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
     ctx->graphs.clear();
     if (ctx->cap) hipStreamDestroy(ctx->cap);
     void *bufs[] = {ctx->alt,   ctx->pol,    ctx->alt64, ctx->wmap32,  ctx->fmask,  ctx->pairs,
-                    ctx->idxbuf, ctx->batch, ctx->words, ctx->jumpbuf, ctx->rpart};
+                    ctx->idxbuf, ctx->batch, ctx->words, ctx->jumpbuf, ctx->rpart, ctx->tunebuf};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (ctx->host_words) hipHostFree(ctx->host_words);
@@ -524,43 +590,21 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
         s.status = done ? TWG_OK : TWG_NOT_CONVERGED;
         hipStreamSynchronize(st);
     } else if (p.polish == 1) {
-        // FP64 defect correction: r = avg4(psi64) - psi64 in FP64, solve
-        // (I - J) e = r in FP32 (e = 0 on fixed cells), psi64 += e.
-        const size_t n32 = (size_t)g.pitch * g.ny;
-        rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n32 * sizeof(float));
-        if (rc) return rc;
-        float *r32 = reinterpret_cast<float *>(ctx->pol);
-        float *e = r32 + n32;
-        rc = launch_widen(psi, psi64, g.nx, g.ny, g.pitch, st);
-        if (rc) return set_err(ctx, rc, "widen launch failed");
-        bool done = false;
-        double r64 = 0.0;
+        // SOR factor of the correction solves: the caller's factor if given,
+        // else the autotuned one, else 2 / (1 + 2.8 sin(pi / (n + 1))).
+        float omega_dc = omega_family(std::max(g.nx, g.ny), 2.8);
+        if (p.omega > 0.0f) {
+            omega_dc = p.omega;
+        } else {
+            auto it = ctx->tuned.find({g.nx, g.ny});
+            if (it != ctx->tuned.end() && it->second.omega_dc > 0.0f) omega_dc = it->second.omega_dc;
+        }
         // residual the result must reach: tol, and tol_cert / wbound if set
         const double need = p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / wb) : p.tol;
-        for (int round = 0; round < 12; ++round) {
-            rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st);
-            if (!rc) rc = run.readback(1);
-            if (rc) return set_err(ctx, rc, "defect kernel failed");
-            r64 = bits_to_double(ctx->host_words[0]);
-            if (std::isnan(r64)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
-            if (r64 <= need) { done = true; break; }
-            rc = launch_fill_f32(e, 0.0f, g.nx, g.ny, g.pitch, st);
-            if (rc) return set_err(ctx, rc, "fill launch failed");
-            // correction solve: at most four decades per round (the FP32
-            // correction keeps about that much relative accuracy), and no
-            // further than a third of what is still needed
-            const double target = std::max(r64 * 1e-4, need / 3.0);
-            int64_t sw = 0;
-            double re = 0.0;
-            bool cconv = false;
-            rc = run.solve32(e, r32, omega, S, RH, target, p.max_sweeps, 0, &sw, &re, &cconv);
-            if (rc) return rc;
-            s.polish_sweeps += sw;
-            rc = launch_update64(cls, psi64, e, psi, g.nx, g.ny, g.pitch, st);
-            if (rc) return set_err(ctx, rc, "update launch failed");
-            s.polish_rounds = round + 1;
-        }
-        s.residual = r64;
+        bool done = false;
+        rc = run.polish_dc(psi, psi64, omega_dc, need, S, RH, p.max_sweeps, &s.polish_sweeps, &s.polish_rounds,
+                           &s.residual, &done);
+        if (rc) return rc;
         s.status = done ? TWG_OK : TWG_NOT_CONVERGED;
         hipStreamSynchronize(st);
     }
@@ -609,7 +653,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
     const int VW = 128 - 4 * S;
     // paired column access when every grid allows it; tiles within the
     // streamed kernels' addressable span
-    bool pair = (reinterpret_cast<uintptr_t>(psi) & 7) == 0;
+    bool pair = (reinterpret_cast<uintptr_t>(psi) & 7) == 0;  // the mask is context-owned (aligned)
     int max_pitch = 1;
     for (int k = 0; k < n; ++k) {
         pair = pair && grids[k].nx % 2 == 0 && grids[k].pitch % 2 == 0 && grids[k].offset % 2 == 0;
@@ -690,10 +734,11 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
     const int max_tiles0 = (int)tl.size();
     rc = upload_lists();
     if (!rc) rc = launch_field_init_batch(cls, psi, d_grids, d_blocks, (int)bl.size(), p.init, st);
-    // SOR factor map of every grid (each with its own omega), laid out as psi
-    if (!rc) rc = ensure(ctx, &ctx->wmap32, &ctx->wmap32_bytes, (size_t)total * sizeof(float));
-    float *const wmap = static_cast<float *>(ctx->wmap32);
-    if (!rc) rc = launch_wmap_batch(cls, wmap, d_grids, d_blocks, (int)bl.size(), st);
+    // free mask of every grid, laid out as the class buffer (each grid's
+    // omega comes from its descriptor)
+    if (!rc) rc = ensure(ctx, &ctx->fmask, &ctx->fmask_bytes, (size_t)total);
+    uint8_t *const fmask = static_cast<uint8_t *>(ctx->fmask);
+    if (!rc) rc = launch_fmask_batch(cls, fmask, d_grids, d_blocks, (int)bl.size(), st);
     if (rc) return set_err(ctx, TWG_EDEVICE, "batch set-up failed");
 
     std::vector<double> r(n), rr(n), rate(n);
@@ -754,13 +799,13 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
         // count from device memory, so retired grids cost an early exit
         const int64_t reps = ctx->use_graphs ? passes / kGraphPasses : 0;
         if (reps > 0) {
-            const std::vector<uintptr_t> key = {2, (uintptr_t)cur, (uintptr_t)nxt, (uintptr_t)wmap,
+            const std::vector<uintptr_t> key = {2, (uintptr_t)cur, (uintptr_t)nxt, (uintptr_t)fmask,
                                                 (uintptr_t)d_grids, (uintptr_t)d_tiles, (uintptr_t)d_count,
                                                 (uintptr_t)max_tiles0, (uintptr_t)S, (uintptr_t)pair};
             float *x = cur, *y = nxt;
             rc = graph_replay(ctx, key, st, reps, [&](hipStream_t cs) {
                 for (int k = 0; k < kGraphPasses; ++k) {
-                    const int e = launch_stream_batch(k % 2 ? y : x, k % 2 ? x : y, wmap, d_grids, d_tiles, d_count,
+                    const int e = launch_stream_batch(k % 2 ? y : x, k % 2 ? x : y, fmask, d_grids, d_tiles, d_count,
                                                       max_tiles0, S, pair, cs);
                     if (e) return e;
                 }
@@ -769,7 +814,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
             if (rc) return set_err(ctx, rc, "batched relaxation graph failed");
         }
         for (int64_t q = reps * kGraphPasses; q < passes; ++q) {
-            rc = launch_stream_batch(cur, nxt, wmap, d_grids, d_tiles, d_count, (int)tl.size(), S, pair, st);
+            rc = launch_stream_batch(cur, nxt, fmask, d_grids, d_tiles, d_count, (int)tl.size(), S, pair, st);
             if (rc) return set_err(ctx, rc, "batched relaxation launch failed");
             std::swap(cur, nxt);
         }
@@ -912,24 +957,66 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
             }
         }
     }
-    // 3. SOR factor: smallest residual after a fixed number of sweeps
+    // 3. SOR factors, from the family 2 / (1 + c sin(pi / (n + 1))).  The
+    // relaxation's: fewest sweeps from the paper's initial field (0.5) to
+    // residual 1e-6.  The defect-correction solves': fewest correction sweeps
+    // in the whole polish of that converged field to a certified 1e-7.
+    // Below the optimum the sweep count climbs steeply (above it, gently),
+    // and the optimum moves with the obstacles, so each keeps the next larger
+    // factor of the family (one step towards 2) unless that costs over 25 %
+    // more sweeps.  (The residual after a fixed sweep count does not rank
+    // factors once it reaches the FP32 rounding floor.)
     if (!rc) {
-        const double pi = 3.14159265358979323846;
         const int n = std::max(g.nx, g.ny);
-        const double cs[] = {0.7, 1.0, 1.4, 2.0, 2.8, 4.0};
-        const int64_t sweeps = std::max<int64_t>(64, (int64_t)(1.5 * n));
-        double best_r = INFINITY;
-        for (double c : cs) {
-            const float om = (float)(2.0 / (1.0 + c * std::sin(pi / (n + 1))));
+        const double cs[] = {1.0, 1.4, 2.0, 2.4, 2.8, 3.0, 3.3, 3.6, 4.0, 4.5, 5.0, 6.0};
+        constexpr int NC = sizeof(cs) / sizeof(cs[0]);
+        const int64_t cap = std::max<int64_t>(256, (int64_t)(4.0 * n));
+        auto pick = [&](const int64_t *sw) {
+            int best_i = -1;
+            for (int i = 0; i < NC; ++i)
+                if (sw[i] > 0 && (best_i < 0 || sw[i] < sw[best_i])) best_i = i;
+            if (best_i > 0 && sw[best_i - 1] > 0 && sw[best_i - 1] <= sw[best_i] * 1.25) --best_i;
+            return best_i;
+        };
+        int64_t sw_plain[NC] = {0};
+        for (int i = 0; i < NC && !rc; ++i) {
             rc = launch_fill_f32(a, 0.5f, g.nx, g.ny, g.pitch, st);
             if (!rc) rc = launch_field_init(cls, a, g.nx, g.ny, g.pitch, HPF_INIT_HALF, st);
-            if (rc) break;
-            float *x = a, *y = b;
-            rc = run.sweep32(&x, &y, nullptr, om, best.S, best.RH, sweeps);
-            double r;
-            if (!rc) rc = run.residual32(x, nullptr, &r);
-            if (rc) break;
-            if (r < best_r) { best_r = r; best.omega = om; }
+            int64_t sw = 0;
+            double r = 0.0;
+            bool conv = false;
+            if (!rc) rc = run.solve32(a, nullptr, omega_family(n, cs[i]), best.S, best.RH, 1e-6, cap, 0, &sw, &r,
+                                      &conv);
+            if (!rc && conv) sw_plain[i] = sw;
+        }
+        const int ip = rc ? -1 : pick(sw_plain);
+        if (ip >= 0) best.omega = omega_family(n, cs[ip]);
+        // the whole defect-correction polish of that converged field to a
+        // certified 1e-7, once per factor
+        if (!rc && ip >= 0) {
+            rc = ensure(ctx, &ctx->tunebuf, &ctx->tunebuf_bytes, n32 * sizeof(float));
+            float *fld = static_cast<float *>(ctx->tunebuf);
+            double *f64 = reinterpret_cast<double *>(ctx->alt64);
+            const double wb = std::pow((double)std::min(g.nx, g.ny) + 1.0, 2) / 2.0;
+            int64_t sw_dc[NC] = {0};
+            for (int i = 0; i < NC && !rc; ++i) {
+                int64_t sw = 0;
+                double r = 0.0;
+                bool conv = false;
+                rc = launch_fill_f32(fld, 0.5f, g.nx, g.ny, g.pitch, st);
+                if (!rc) rc = launch_field_init(cls, fld, g.nx, g.ny, g.pitch, HPF_INIT_HALF, st);
+                if (!rc) rc = run.solve32(fld, nullptr, best.omega, best.S, best.RH, 1e-6, cap, 0, &sw, &r, &conv);
+                int64_t swc = 0;
+                int32_t rounds = 0;
+                double r64 = 0.0;
+                bool done = false;
+                if (!rc && conv)
+                    rc = run.polish_dc(fld, f64, omega_family(n, cs[i]), 1e-7 / wb, best.S, best.RH, 3 * cap,
+                                       &swc, &rounds, &r64, &done);
+                if (!rc && done) sw_dc[i] = swc;
+            }
+            const int id = rc ? -1 : pick(sw_dc);
+            if (id >= 0) best.omega_dc = omega_family(n, cs[id]);
         }
     }
     hipEventDestroy(e0);
@@ -944,6 +1031,7 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
         out[4] = best.S64;
         out[5] = best.RH64;
         out[6] = best.cups64;
+        out[7] = best.omega_dc;
     }
     return TWG_OK;
 }

@@ -290,8 +290,8 @@ __global__ void k_wmap(const uint8_t *__restrict__ cls, T *__restrict__ w, T ome
     w[i] = cls[i] == TWG_CELL_FREE ? omega : T(0);
 }
 
-__global__ void k_wmap_batch(const uint8_t *__restrict__ cls, float *__restrict__ w,
-                             const BatchGrid *__restrict__ grids, const int2 *__restrict__ blocks)
+__global__ void k_fmask_batch(const uint8_t *__restrict__ cls, uint8_t *__restrict__ m,
+                              const BatchGrid *__restrict__ grids, const int2 *__restrict__ blocks)
 {
     const int2 bk = blocks[blockIdx.x];
     const BatchGrid g = grids[bk.x];
@@ -299,7 +299,7 @@ __global__ void k_wmap_batch(const uint8_t *__restrict__ cls, float *__restrict_
     if (x >= g.nx) return;
     for (int y = threadIdx.x >> 6; y < g.ny; y += 4) {
         const size_t i = g.off + (size_t)y * g.pitch + x;
-        w[i] = cls[i] == TWG_CELL_FREE ? g.omega : 0.0f;
+        m[i] = cls[i] == TWG_CELL_FREE ? 1 : 0;
     }
 }
 
@@ -351,11 +351,11 @@ int launch_fmask(const uint8_t *cls, uint8_t *fmask, int nx, int ny, int pitch, 
     return last_status();
 }
 
-int launch_wmap_batch(const uint8_t *cls, float *wmap, const BatchGrid *grids, const int2 *blocks,
-                      int n_blocks, hipStream_t st)
+int launch_fmask_batch(const uint8_t *cls, uint8_t *fmask, const BatchGrid *grids, const int2 *blocks,
+                       int n_blocks, hipStream_t st)
 {
     if (n_blocks > 0)
-        hipLaunchKernelGGL(k_wmap_batch, dim3(n_blocks), dim3(256), 0, st, cls, wmap, grids, blocks);
+        hipLaunchKernelGGL(k_fmask_batch, dim3(n_blocks), dim3(256), 0, st, cls, fmask, grids, blocks);
     return last_status();
 }
 

@@ -6,10 +6,11 @@
 // cells are (x + y) even.  One sweep sets every FREE cell of one colour, then
 // of the other, to psi + w * (avg4 + f - psi), evaluated as in update.h, where
 // w is omega on FREE cells and 0 on fixed ones (which are thus rewritten
-// unchanged).  The FP32 kernels read w from a factor map; the FP64 kernels,
-// which move twice the bytes per cell and are closer to the HBM bound, read a
-// one-byte free mask and select omega or 0.  Both maps are built once per
-// call from the class map.
+// unchanged).  The single-grid FP32 kernels read w from a factor map; the
+// FP64 kernels, which move twice the bytes per cell, and the batched kernel,
+// whose grids together outgrow the last-level cache, read a one-byte free
+// mask and select omega or 0.  Both maps are built once per call from the
+// class map.
 //
 // One wave owns a strip of 128 columns (each lane two adjacent columns, so in
 // every row a lane holds exactly one red and one black cell) and streams it
@@ -149,13 +150,13 @@ __device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc
 // memory operations per row instead of six), which keeps a whole window of
 // prefetches within the hardware's count of outstanding vector memory
 // operations, so no row step ever waits for the loads of the rows after it.
-template <typename T, int S, bool RHS, bool PAIR>
+// MASK: wsrc is the one-byte free mask (else the factor map of T).
+template <typename T, int S, bool RHS, bool PAIR, bool MASK>
 __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__restrict__ dst,
                                             const void *__restrict__ wsrc, T omega,
                                             const T *__restrict__ f, int nx, int ny, int pitch,
                                             int x0, int ybeg, int yend)
 {
-    constexpr bool MASK = sizeof(T) == 8;  // free mask (FP64) or factor map (FP32)
     constexpr int NW = 2 * S + 2;      // rolling window of rows (even)
     const int lane = threadIdx.x & (kWave - 1);
     const int r0 = ybeg - 2 * S;                   // first row streamed (even)
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
     if (tile >= tiles) return;  // whole wave
     const int strip = tile % strips, seg = tile / strips;
     const int ybeg = seg * RH;
-    stream_tile<T, S, RHS, PAIR>(src, dst, wsrc, omega, f, nx, ny, pitch, strip * VW - 2 * S, ybeg,
+    stream_tile<T, S, RHS, PAIR, sizeof(T) == 8>(src, dst, wsrc, omega, f, nx, ny, pitch, strip * VW - 2 * S, ybeg,
                                  min(ybeg + RH, ny));
 }
 
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
 template <int S, bool PAIR>
 __global__ __launch_bounds__(256) void k_sor_stream_batch(const float *__restrict__ src,
                                                           float *__restrict__ dst,
-                                                          const float *__restrict__ wmap,
+                                                          const uint8_t *__restrict__ fmask,
                                                           const BatchGrid *__restrict__ grids,
                                                           const BatchTile *__restrict__ tiles,
                                                           const int *__restrict__ n_tiles)
@@ -357,8 +358,8 @@ __global__ __launch_bounds__(256) void k_sor_stream_batch(const float *__restric
     if (tile >= *n_tiles) return;  // whole wave
     const BatchTile t = tiles[tile];
     const BatchGrid g = grids[t.grid];
-    stream_tile<float, S, false, PAIR>(src + g.off, dst + g.off, wmap + g.off, 0.0f, nullptr, g.nx, g.ny,
-                                       g.pitch, t.x0, t.ybeg, t.yend);
+    stream_tile<float, S, false, PAIR, true>(src + g.off, dst + g.off, fmask + g.off, g.omega, nullptr,
+                                             g.nx, g.ny, g.pitch, t.x0, t.ybeg, t.yend);
 }
 
 // Pair access needs even pitch and nx (a pair never leaves its row or the
@@ -399,7 +400,7 @@ int launch_stream(const T *src, T *dst, const void *wsrc, T omega, const T *f, i
 
 }  // namespace
 
-int launch_stream_batch(const float *src, float *dst, const float *wmap, const BatchGrid *grids,
+int launch_stream_batch(const float *src, float *dst, const uint8_t *fmask, const BatchGrid *grids,
                         const BatchTile *tiles, const int *n_tiles, int max_tiles, int S, bool pair,
                         hipStream_t st)
 {
@@ -409,10 +410,10 @@ int launch_stream_batch(const float *src, float *dst, const float *wmap, const B
     case SV:                                                                                           \
         if (pair)                                                                                      \
             hipLaunchKernelGGL((k_sor_stream_batch<SV, true>), dim3(blocks), dim3(256), 0, st, src, dst, \
-                               wmap, grids, tiles, n_tiles);                                           \
+                               fmask, grids, tiles, n_tiles);                                          \
         else                                                                                           \
             hipLaunchKernelGGL((k_sor_stream_batch<SV, false>), dim3(blocks), dim3(256), 0, st, src,     \
-                               dst, wmap, grids, tiles, n_tiles);                                      \
+                               dst, fmask, grids, tiles, n_tiles);                                     \
         break;
     switch (S) {
         TWG_BATCH_CASE(1)

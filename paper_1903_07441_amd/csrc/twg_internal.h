@@ -14,7 +14,8 @@
 struct twg_tuning {
     int S = 0;        // sweeps per tile load
     int RH = 0;       // output rows per tile
-    float omega = 0;  // 0 = open-rectangle optimum
+    float omega = 0;     // 0 = open-rectangle optimum
+    float omega_dc = 0;  // factor of the defect-correction solves (0 = default)
     double cups = 0;  // measured cell-updates per second
     int S64 = 0;      // the same for FP64 sweeps (0 = untuned)
     int RH64 = 0;
@@ -33,6 +34,9 @@ struct twg_ctx {
     // defect-correction buffers: FP32 defect, FP32 correction, its partner
     void *pol = nullptr;
     size_t pol_bytes = 0;
+    // the autotuner's defect and correction while it times correction solves
+    void *tunebuf = nullptr;
+    size_t tunebuf_bytes = 0;
     // FP64 ping-pong partner (FP64 sweeps)
     void *alt64 = nullptr;
     size_t alt64_bytes = 0;
@@ -89,7 +93,7 @@ struct BatchTile {
 };
 
 // pair: every grid has even nx, pitch and offset (PAIR tiles)
-int launch_stream_batch(const float *src, float *dst, const float *wmap, const BatchGrid *grids,
+int launch_stream_batch(const float *src, float *dst, const uint8_t *fmask, const BatchGrid *grids,
                         const BatchTile *tiles, const int *n_tiles, int max_tiles, int S, bool pair,
                         hipStream_t st);
 int launch_resid_batch(const uint8_t *cls, const float *u, const BatchGrid *grids,
@@ -133,9 +137,9 @@ int launch_stream_f64(const double *src, double *dst, const uint8_t *fmask, doub
                       int pitch, const Geometry &geo, hipStream_t st);
 int launch_wmap_f32(const uint8_t *cls, float *wmap, float omega, int nx, int ny, int pitch, hipStream_t st);
 int launch_fmask(const uint8_t *cls, uint8_t *fmask, int nx, int ny, int pitch, hipStream_t st);
-// the batch's map, each grid with its own omega, over the batch's column blocks
-int launch_wmap_batch(const uint8_t *cls, float *wmap, const BatchGrid *grids, const int2 *blocks,
-                      int n_blocks, hipStream_t st);
+// the batch's free mask, over the batch's column blocks
+int launch_fmask_batch(const uint8_t *cls, uint8_t *fmask, const BatchGrid *grids, const int2 *blocks,
+                       int n_blocks, hipStream_t st);
 // residual reductions: part = the context's block partials (2 kResidBlocks
 // words), out = 2 words receiving max |r| and max |r| / |u|
 constexpr int kResidBlocks = 4096;

@@ -269,14 +269,15 @@ class Context:
         self._check(rc)
 
     def autotune(self, cls):
-        """Tune tiling (FP32 and FP64 sweeps) and SOR factor for grids of
-        cls's size; returns dict(S, RH, omega, cups, S64, RH64, cups64)."""
+        """Tune tiling (FP32 and FP64 sweeps) and SOR factors for grids of
+        cls's size; returns dict(S, RH, omega, cups, S64, RH64, cups64,
+        omega_dc)."""
         nx, ny, pitch = _grid_of(cls)
-        out = (ctypes.c_double * 7)()
+        out = (ctypes.c_double * 8)()
         rc = lib.hpf_autotune(self.h, Grid(nx, ny, pitch), _ptr(cls), out, _stream())
         self._check(rc)
         return dict(S=int(out[0]), RH=int(out[1]), omega=float(out[2]), cups=float(out[3]), S64=int(out[4]),
-                    RH64=int(out[5]), cups64=float(out[6]))
+                    RH64=int(out[5]), cups64=float(out[6]), omega_dc=float(out[7]))
 
     def set_tiling(self, nx, ny, S, RH, omega=0.0, S64=0, RH64=0):
         """Fix the tiling (and SOR factor) used for grids of this size."""

@@ -252,3 +252,36 @@ def test_graph_replay_equals_eager(ctx, S):
         ctx.set_graphs(True)
     for a in results:
         assert torch.equal(a, ref)
+
+
+def test_autotune_factors_converge(orc):
+    # the autotuner's tiling and factors, then the tuned relaxation and
+    # defect-correction polish on the same 2048 x 2048 field; certificate
+    # recomputed by the oracle
+    from paper_1903_07441_amd import twg
+    ctx = twg.Context(0)
+    try:
+        sc = scenarios.scenario("replan2048", 1)
+        cls, _ = orc.rasterize(sc)
+        c = to_dev(cls)
+        tune = ctx.autotune(c)
+        print(f"autotune {tune}", flush=True)
+        assert tune["S"] in (1, 2, 3, 4, 6, 8) and tune["S64"] in (2, 3, 4, 6, 8)
+        assert tune["RH"] >= 2 and tune["RH"] % 2 == 0
+        assert 1.9 < tune["omega"] < 2.0 and 1.9 < tune["omega_dc"] < 2.0
+        ny, nx = cls.shape
+        psi = to_dev(np.zeros((ny, nx), np.float32))
+        psi64 = to_dev(np.zeros((ny, nx)), dtype=torch.float64)
+        plain = ctx.relax(c, psi, None, tol=1e-6)
+        pol = ctx.relax(c, psi, psi64, tol=1e-6, init=twg.INIT_KEEP, polish=1, tol_cert=1e-7)
+        torch.cuda.synchronize()
+        print(f"plain {plain['sweeps']} sweeps, polish {pol['polish_sweeps']} correction sweeps "
+              f"in {pol['polish_rounds']} rounds", flush=True)
+        assert plain["status"] == 0 and pol["status"] == 0
+        assert abs(plain["omega"] - tune["omega"]) < 1e-6
+        # the tuned factors keep both solves within a few thousand sweeps
+        assert plain["sweeps"] < 4 * max(nx, ny) and pol["polish_sweeps"] < 4 * max(nx, ny)
+        r = orc.residual(cls, psi64.cpu().numpy())
+        assert r * orc.wbound(nx, ny) <= 1e-7
+    finally:
+        ctx.close()
