@@ -5,8 +5,8 @@
 //            walkable neighbour with the highest psi (lowest phi), first one
 //            on ties; 4 when none is strictly higher than the cell itself.
 //   k_walk   one workgroup follows the index matrix from the start.  The
-//            64 x 64 window of index codes and classes around the current
-//            cell is staged in LDS by all 256 threads; one thread then walks
+//            128 x 128 window of index codes and classes around the current
+//            cell is staged in LDS by all 1024 threads; one thread then walks
 //            inside the window (each step strictly raises psi, so the walk
 //            never revisits a cell) and the window is re-centred when the
 //            walk leaves it.
@@ -54,9 +54,9 @@ __global__ void k_index(const uint8_t *__restrict__ cls, const T *__restrict__ u
     idx[i] = (uint8_t)best;
 }
 
-constexpr int kTile = 64;
+constexpr int kTile = 128;
 
-__global__ __launch_bounds__(256) void k_walk(const uint8_t *__restrict__ cls,
+__global__ __launch_bounds__(1024) void k_walk(const uint8_t *__restrict__ cls,
                                               const uint8_t *__restrict__ idx, int nx, int ny,
                                               int pitch, int sx, int sy, int cap,
                                               int32_t *__restrict__ path, int32_t *__restrict__ info)
@@ -278,7 +278,7 @@ int launch_index(const uint8_t *cls, const float *psi, const double *psi64, uint
 int launch_walk(const uint8_t *cls, const uint8_t *idx, int nx, int ny, int pitch, int sx, int sy,
                 int cap, int32_t *path, int32_t *info, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_walk, dim3(1), dim3(256), 0, st, cls, idx, nx, ny, pitch, sx, sy, cap, path,
+    hipLaunchKernelGGL(k_walk, dim3(1), dim3(1024), 0, st, cls, idx, nx, ny, pitch, sx, sy, cap, path,
                        info);
     return hipGetLastError() == hipSuccess ? TWG_OK : TWG_EDEVICE;
 }
