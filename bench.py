@@ -453,6 +453,17 @@ def main():
                           W=b["W"], robot_speed=b["vr"], cls=bcls[o:o + n_b].view(b["ny"], b["nx"]),
                           want_ring=False)
         descs = [(b["nx"], b["ny"], b["nx"], o) for b, o in zip(scs, offs)]
+        # SOR factors per size class (untimed set-up): the autotuner on the
+        # first grid of each size; the batch takes each grid's factor from it
+        # (untuned sizes would get the open square's factor, far above the
+        # optimum of a grid with obstacles)
+        tuned_sizes = {}
+        for b, o in zip(scs, offs):
+            key = (b["nx"], b["ny"])
+            if key not in tuned_sizes:
+                tb_ = ctx.autotune(bcls[o:o + b["nx"] * b["ny"]].view(b["ny"], b["nx"]))
+                tuned_sizes[key] = round(tb_["omega"], 6)
+        log(f"batch size classes tuned: {tuned_sizes}")
         # tiling of the batch, picked (untimed) from a few candidates: the
         # batch has far more tiles than the chip has SIMDs, so taller tiles
         # (less halo) pay off here, unlike on one grid
@@ -478,6 +489,8 @@ def main():
                  "max_residual": max(st_b["residual"] for st_b in bst),
                  "tiling": {"sweeps_per_pass": S_b, "rows_per_tile": RH_b},
                  "tiling_trials_ms": {f"S{a}_RH{b}": round(v * 1e3, 2) for (a, b), v in b_trials.items()},
+                 "omega_per_size": {f"{a}x{b}": v for (a, b), v in tuned_sizes.items()},
+                 "sweeps_max": max(st_b["sweeps"] for st_b in bst),
                  "workload": "256 grids, sides uniform over {64,128,256,512,1024}, 10-200 moving discs "
                              "(radius 2-5), FP32 red-black SOR to residual 1e-6 with FP64 residuals"}
         log(f"batch: {batch}")
