@@ -202,6 +202,20 @@ def test_relax_not_converged_and_errors(ctx):
     assert e.value.code == twg.EINVAL
 
 
+def test_relax_stops_at_the_fp32_rounding_floor(ctx, orc):
+    # a tolerance FP32 cannot reach: the solve stops once the residual stops
+    # improving, long before its (default, 10^7) sweep budget, and reports it
+    from paper_1903_07441_amd import twg
+    sc = scenarios.scenario("warped512", 2)
+    cls, _ = orc.rasterize(sc)
+    st, psi, _, _ = gpu_relax(ctx, cls, tol=1e-13)
+    print(f"floor stats={st}", flush=True)
+    assert st["status"] == twg.NOT_CONVERGED
+    assert st["sweeps"] < 40 * 512
+    assert 1e-13 < st["residual"] < 1e-5
+    assert abs(orc.residual(cls, psi.astype(np.float64)) - st["residual"]) <= 1e-12
+
+
 @pytest.mark.parametrize("nx,ny,pitch", [(96, 80, 96), (301, 129, 320), (3, 40, 4)])
 @pytest.mark.parametrize("S", [1, 3, 4])
 def test_fp64_sweep_bit_exact_vs_oracle(ctx, orc, nx, ny, pitch, S):
