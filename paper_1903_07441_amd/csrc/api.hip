@@ -303,7 +303,9 @@ struct Runner {
                 chunk = std::max<int64_t>(chunk, 8 * S);
                 if (last_chunk > 0) chunk = std::min(chunk, std::max<int64_t>(2 * last_chunk, 64 * S));
             }
-            chunk = std::min(chunk, max_sweeps - done);
+            // whole passes (a remainder costs a full launch per sweep), unless
+            // the budget ends inside one
+            chunk = std::min(((chunk + S - 1) / S) * S, max_sweeps - done);
             last_chunk = chunk;
             const double r_prev = r;
             rc = sweep32(&a, &b, f, omega, S, RH, chunk);

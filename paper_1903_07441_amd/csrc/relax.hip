@@ -57,23 +57,24 @@ __global__ __launch_bounds__(256) void k_resid(const uint8_t *__restrict__ cls,
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     double m = 0.0, mr = 0.0;
+    // the loads of a cell do not wait on its class (the class only selects
+    // the result), and four rows are in flight per thread
+#pragma unroll 4
     for (int y = blockIdx.y * 4 + (threadIdx.x >> 6); y < ny; y += gridDim.y * 4) {
         if (x >= nx) break;
         const size_t i = (size_t)y * pitch + x;
-        double r = 0.0;
-        if (cls[i] == TWG_CELL_FREE) {
-            const double e = x + 1 < nx ? (double)u[i + 1] : 0.0;
-            const double w = x > 0 ? (double)u[i - 1] : 0.0;
-            const double s = y + 1 < ny ? (double)u[i + pitch] : 0.0;
-            const double n = y > 0 ? (double)u[i - pitch] : 0.0;
-            double g = ((e + w) + (s + n)) * 0.25;
-            if (RHS) g = g + (double)f[i];
-            const double c = (double)u[i];
-            r = g - c;
-            const float ac = fabsf((float)c);
-            // diagnostic ratio: single-precision division is enough
-            if (ac >= 1e-30f) mr = nanmax(mr, (double)(fabsf((float)r) / ac));
-        }
+        const bool free_cell = cls[i] == TWG_CELL_FREE;
+        const double e = x + 1 < nx ? (double)u[i + 1] : 0.0;
+        const double w = x > 0 ? (double)u[i - 1] : 0.0;
+        const double s = y + 1 < ny ? (double)u[i + pitch] : 0.0;
+        const double n = y > 0 ? (double)u[i - pitch] : 0.0;
+        double g = ((e + w) + (s + n)) * 0.25;
+        if (RHS) g = g + (double)f[i];
+        const double c = (double)u[i];
+        const double r = free_cell ? g - c : 0.0;
+        const float ac = fabsf((float)c);
+        // diagnostic ratio: single-precision division is enough
+        if (free_cell && ac >= 1e-30f) mr = nanmax(mr, (double)(fabsf((float)r) / ac));
         if (WRITE_R32) r32[i] = (float)r;
         m = nanmax(m, fabs(r));
     }
@@ -397,7 +398,7 @@ static dim3 resid_grid(int nx, int ny)
 {
     const int gx = (nx + 63) / 64;
     int gy = (ny + 3) / 4;
-    if (gy > 64) gy = 64;
+    if (gy > 128) gy = 128;
     const int cap = kResidBlocks / gx;
     if (gy > cap) gy = cap > 0 ? cap : 1;
     return dim3(gx, gy);
