@@ -55,9 +55,10 @@ def test_tiled_equals_untiled(ctx, nx, ny, pitch, S):
 
 
 @pytest.mark.parametrize("S", [1, 4, 8])
-def test_tiled_equals_untiled_with_source(ctx, S):
+@pytest.mark.parametrize("nx", [257, 256])  # odd: per-column access; even: paired columns
+def test_tiled_equals_untiled_with_source(ctx, S, nx):
     rng = np.random.default_rng(S)
-    nx, ny = 257, 190
+    ny = 190
     cls = random_classes(rng, nx, ny)
     f = (rng.normal(size=(ny, nx)) * 1e-3).astype(np.float32)
     c, fd = to_dev(cls), to_dev(f)
