@@ -546,8 +546,10 @@ def main():
         "hbm_frac_algorithmic": round(cups * BYTES_PER_CELL_UPDATE / (HBM_PEAK_GBS * 1e9), 4),
         "descent": {"status": status, "length": n, "reached_goal": status == 0},
         "tuning": {"sweeps_per_pass": tuning["S"], "rows_per_tile": tuning["RH"],
-                   "omega": round(tuning["omega"], 6), "fp64_sweeps_per_pass": tuning["S64"],
-                   "fp64_rows_per_tile": tuning["RH64"]},
+                   "omega": round(tuning["omega"], 6), "omega_dc": round(tuning["omega_dc"], 6),
+                   "dc_start_phase": {"omega": round(tuning["lead_dc_omega"], 6),
+                                      "sweeps": tuning["lead_dc_sweeps"]},
+                   "fp64_sweeps_per_pass": tuning["S64"], "fp64_rows_per_tile": tuning["RH64"]},
         "roofline": roofline,
         "roofline_other": roofline_other,
         "roofline_alu": roofline_alu,

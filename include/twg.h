@@ -195,7 +195,8 @@ typedef struct {
     double tol_cert;         /* > 0: with polish, also require the certified error
                                 bound residual * wbound <= tol_cert */
     int64_t max_sweeps;      /* cap on FP32 sweeps of the field (0 = 10^7) */
-    float omega;             /* SOR factor in (0, 2); 0 = the open-rectangle optimum */
+    float omega;             /* SOR factor in (0, 2); 0 = the autotuned factors of this grid
+                                size (hpf_autotune), else the open-rectangle optimum */
     int32_t init;            /* HPF_INIT_* */
     int32_t polish;          /* 0: FP32 only; 1: FP64 defect correction (FP32 correction
                                 solves); 2: FP64 red-black SOR sweeps */
@@ -242,7 +243,9 @@ typedef struct {
  * the goal.  Either polish gives one; on 2048 x 2048 fields, defect
  * correction to tol_cert = 1e-7 is faster than FP64 sweeps to 5e-7.  The
  * correction solves use the autotuned defect-correction factor (or omega if
- * given).
+ * given).  With omega = 0 on an autotuned size, each correction solve may
+ * open with a start phase: a few passes at a smaller tuned factor (counted
+ * in polish_sweeps).
  *
  *   cls    uint8 class map (device, pitch g.pitch).
  *   psi    in/out FP32 field (device, pitch g.pitch): FIXED cells must hold their
@@ -325,19 +328,24 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
  * by the fewest correction sweeps in polishing that field to a certified
  * 1e-7;
  * each keeps the next factor towards 2 unless that costs over 25 % more
- * sweeps (below the optimum the count climbs steeply).
+ * sweeps (below the optimum the count climbs steeply).  Start phase: each
+ * correction solve may open with sweeps at a smaller factor (c in
+ * {12, 16, 24}, for about n / 40 or n / 20 sweeps), which damps the rough
+ * start of its error (the correction starts from zero) faster; one is kept
+ * when it saves over 5 % of the correction sweeps of a whole polish.
  * The FP64 sweeps (polish, hpf_sweeps64 with sweeps_per_pass = 0) get their
  * own tiling the same way, S in {2, 3, 4, 6, 8}.
- * out (host, optional, 8 doubles) receives [S, RH, omega, cell-updates per
+ * out (host, optional, 10 doubles) receives [S, RH, omega, cell-updates per
  * second, S64, RH64, FP64 cell-updates per second, defect-correction
- * omega].
+ * omega, correction start-phase omega, correction start-phase sweeps]
+ * (sweeps 0: no start phase).
  * Blocking.  Errors: TWG_EINVAL, TWG_ENOMEM, TWG_EDEVICE. */
 int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, void *stream);
 
 /* hpf_set_tiling -- set, for grids of size nx x ny on this context, what
  * hpf_autotune would remember: FP32 sweeps per tile load S and rows per tile
  * RH, SOR factor omega (0 = the open-rectangle optimum), FP64 tiling S64 and
- * RH64 (S64 = 0: the FP64 default).  Host only.  Errors: TWG_EINVAL (S or
+ * RH64 (S64 = 0: the FP64 default), and no start phase.  Host only.  Errors: TWG_EINVAL (S or
  * S64 not in {1, 2, 3, 4, 6, 8}, RH < 2, omega outside [0, 2)). */
 int32_t hpf_set_tiling(twg_ctx *ctx, int32_t nx, int32_t ny, int32_t S, int32_t RH, float omega, int32_t S64,
                        int32_t RH64);

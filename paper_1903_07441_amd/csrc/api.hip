@@ -53,6 +53,10 @@ using namespace twg;
 namespace {
 
 constexpr int kGraphPasses = 16;  // passes per captured graph (even: ping-pong ends where it began)
+// A solve counts as stalled (at its rounding floor) after three checks
+// without a 10 % gain on its best residual that together span at least this
+// many sweeps; at a useful SOR factor a 10 % gain takes tens of sweeps.
+constexpr int64_t kStallSweeps = 256;
 constexpr size_t kMaxGraphs = 16;
 
 // Replay `times` copies of the launch sequence that `record` issues on a
@@ -202,18 +206,23 @@ struct Runner {
     }
 
     // SOR factor maps for the streamed sweeps, built at most once per call
-    // (the class map is fixed for the duration of a call) and omega
-    float w32_omega = -1.0f;
+    // (the class map is fixed for the duration of a call) and omega; two
+    // slots, so that a start phase and the main factor alternate freely
+    float w32_omega[2] = {-1.0f, -1.0f};
+    int w32_next = 0;
     int wmap32(float omega, const float **w)
     {
-        if (w32_omega != omega) {
-            int rc = ensure(ctx, &ctx->wmap32, &ctx->wmap32_bytes, (size_t)g.pitch * g.ny * sizeof(float));
+        int k = w32_omega[0] == omega ? 0 : w32_omega[1] == omega ? 1 : -1;
+        if (k < 0) {
+            k = w32_next;
+            w32_next ^= 1;
+            int rc = ensure(ctx, &ctx->wmap32[k], &ctx->wmap32_bytes[k], (size_t)g.pitch * g.ny * sizeof(float));
             if (rc) return rc;
-            rc = launch_wmap_f32(cls, static_cast<float *>(ctx->wmap32), omega, g.nx, g.ny, g.pitch, st);
+            rc = launch_wmap_f32(cls, static_cast<float *>(ctx->wmap32[k]), omega, g.nx, g.ny, g.pitch, st);
             if (rc) return set_err(ctx, rc, "factor map launch failed");
-            w32_omega = omega;
+            w32_omega[k] = omega;
         }
-        *w = static_cast<const float *>(ctx->wmap32);
+        *w = static_cast<const float *>(ctx->wmap32[k]);
         return TWG_OK;
     }
     bool have_fmask = false;
@@ -269,10 +278,11 @@ struct Runner {
     }
 
     // FP32 red-black SOR on `field` (ping-pong with ctx->alt) until the FP64
-    // residual is <= tol, the sweep budget is spent, or progress stalls.
+    // residual is <= tol, the sweep budget is spent, or progress stalls; the
+    // first lead.sweeps sweeps (whole passes) use factor lead.omega.
     int solve32(float *field, const float *f, float omega, int S, int RH, double tol,
                 int64_t max_sweeps, int check_passes, int64_t *sweeps_out, double *res_out,
-                bool *converged, double *rel_out = nullptr)
+                bool *converged, double *rel_out = nullptr, StartPhase lead = {})
     {
         const size_t bytes = (size_t)g.pitch * g.ny * sizeof(float);
         int rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, bytes);
@@ -281,7 +291,13 @@ struct Runner {
         double r, rr;
         rc = residual32(a, f, &r, &rr);
         if (rc) return rc;
-        int64_t done = 0, last_chunk = 0;
+        int64_t done = 0, last_chunk = 0, since = 0;
+        if (lead.sweeps > 0 && r > tol && !std::isnan(r) && max_sweeps > 0) {
+            done = std::min(((lead.sweeps + S - 1) / S) * S, max_sweeps);
+            rc = sweep32(&a, &b, f, lead.omega, S, RH, done);
+            if (!rc) rc = residual32(a, f, &r, &rr);
+            if (rc) return rc;
+        }
         int stalls = 0;
         double best = r;
         // per-sweep contraction guess before any measurement
@@ -317,13 +333,17 @@ struct Runner {
                 const double q = std::pow(r / r_prev, 1.0 / (double)chunk);
                 if (q > 0.0 && q < 1.0) rate = q;
             }
-            // stop at the rounding floor: three checks in a row without a
-            // 10 % gain on the best residual so far
+            // stop at the rounding floor: three checks in a row, spanning at
+            // least kStallSweeps sweeps, without a 10 % gain on the best
+            // residual so far (the max-norm residual is not monotone, so a
+            // few closely spaced checks can miss real progress)
             if (r < 0.9 * best) {
                 best = r;
                 stalls = 0;
-            } else if (++stalls >= 3) {
-                break;
+                since = 0;
+            } else {
+                since += chunk;
+                if (++stalls >= 3 && since >= kStallSweeps) break;
             }
         }
         if (a != field) {
@@ -351,7 +371,7 @@ struct Runner {
     // cells) with factor omega_dc, psi64 += e (psi receives the rounded
     // field), until the FP64 residual is <= need or 12 rounds.
     int polish_dc(float *psi, double *psi64, float omega_dc, double need, int S, int RH, int64_t max_sweeps,
-                  int64_t *sweeps_out, int32_t *rounds_out, double *res_out, bool *done)
+                  int64_t *sweeps_out, int32_t *rounds_out, double *res_out, bool *done, StartPhase lead = {})
     {
         const size_t n32 = (size_t)g.pitch * g.ny;
         int rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n32 * sizeof(float));
@@ -380,7 +400,7 @@ struct Runner {
             int64_t sw = 0;
             double re = 0.0;
             bool cconv = false;
-            rc = solve32(e, r32, omega_dc, S, RH, target, max_sweeps, 0, &sw, &re, &cconv);
+            rc = solve32(e, r32, omega_dc, S, RH, target, max_sweeps, 0, &sw, &re, &cconv, nullptr, lead);
             if (rc) return rc;
             *sweeps_out += sw;
             rc = launch_update64(cls, psi64, e, psi, g.nx, g.ny, g.pitch, st);
@@ -451,7 +471,7 @@ struct Runner {
 
 extern "C" {
 
-int32_t twg_version(void) { return 100; }
+int32_t twg_version(void) { return 101; }
 
 int32_t twg_ctx_create(twg_ctx **out, int32_t device)
 {
@@ -483,7 +503,7 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
     for (auto &g : ctx->graphs) hipGraphExecDestroy(g.exec);
     ctx->graphs.clear();
     if (ctx->cap) hipStreamDestroy(ctx->cap);
-    void *bufs[] = {ctx->alt,   ctx->pol,    ctx->alt64, ctx->wmap32,  ctx->fmask,  ctx->pairs,
+    void *bufs[] = {ctx->alt,   ctx->pol,    ctx->alt64, ctx->wmap32[0], ctx->wmap32[1], ctx->fmask,  ctx->pairs,
                     ctx->idxbuf, ctx->batch, ctx->words, ctx->jumpbuf, ctx->rpart, ctx->tunebuf};
     for (void *b : bufs)
         if (b) hipFree(b);
@@ -568,6 +588,14 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
     s.omega = omega;
     s.wbound = wb;
 
+    // the correction solves' start phase comes with the autotuned factors: a
+    // caller's factor runs alone
+    StartPhase lead_dc;
+    if (p.omega == 0.0f) {
+        auto it = ctx->tuned.find({g.nx, g.ny});
+        if (it != ctx->tuned.end()) lead_dc = it->second.lead_dc;
+    }
+
     rc = launch_field_init(cls, psi, g.nx, g.ny, g.pitch, p.init, st);
     if (rc) return set_err(ctx, rc, "init launch failed");
     bool conv = false;
@@ -605,7 +633,7 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
         const double need = p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / wb) : p.tol;
         bool done = false;
         rc = run.polish_dc(psi, psi64, omega_dc, need, S, RH, p.max_sweeps, &s.polish_sweeps, &s.polish_rounds,
-                           &s.residual, &done);
+                           &s.residual, &done, lead_dc);
         if (rc) return rc;
         s.status = done ? TWG_OK : TWG_NOT_CONVERGED;
         hipStreamSynchronize(st);
@@ -744,7 +772,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
     if (rc) return set_err(ctx, TWG_EDEVICE, "batch set-up failed");
 
     std::vector<double> r(n), rr(n), rate(n);
-    std::vector<int64_t> sw(n, 0);
+    std::vector<int64_t> sw(n, 0), since(n, 0);
     std::vector<int> stalls(n, 0);
     std::vector<char> conv(n, 0), parity(n, 0);
     for (int k = 0; k < n; ++k) rate[k] = std::max((double)bg[k].omega - 1.0, 0.5);
@@ -767,6 +795,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
         r[k] = bits_to_double(ctx->batch_host[2 * k]);
         rr[k] = bits_to_double(ctx->batch_host[2 * k + 1]);
     }
+    std::vector<double> best(r);
     while (true) {
         // retire converged, stalled or non-finite grids
         bool changed = false;
@@ -776,7 +805,7 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
             if (std::isnan(r[k]) || std::isnan(rr[k]))
                 return set_err(ctx, TWG_EINVAL, "non-finite value in grid " + std::to_string(k));
             const bool ok = r[k] <= p.tol;
-            if (ok || stalls[k] >= 3 || done >= p.max_sweeps) {
+            if (ok || (stalls[k] >= 3 && since[k] >= kStallSweeps) || done >= p.max_sweeps) {
                 active[k] = 0;
                 conv[k] = ok;
                 parity[k] = cur != psi;
@@ -828,13 +857,19 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
             sw[k] = done;
             const double rn = bits_to_double(ctx->batch_host[2 * k]);
             const double rrn = bits_to_double(ctx->batch_host[2 * k + 1]);
-            bool progress = false;
-            if (rn < r[k] * 0.999) {
-                progress = true;
+            if (rn < r[k]) {
                 const double q = std::pow(rn / r[k], 1.0 / (double)(passes * S));
                 if (q > 0.0 && q < 1.0) rate[k] = q;
             }
-            stalls[k] = progress ? 0 : stalls[k] + 1;
+            // the single-grid solve's stall rule, on the best residual
+            if (rn < 0.9 * best[k]) {
+                best[k] = rn;
+                stalls[k] = 0;
+                since[k] = 0;
+            } else {
+                ++stalls[k];
+                since[k] += passes * S;
+            }
             r[k] = rn;
             rr[k] = rrn;
         }
@@ -1019,6 +1054,44 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
             }
             const int id = rc ? -1 : pick(sw_dc);
             if (id >= 0) best.omega_dc = omega_family(n, cs[id]);
+            // start phase of the correction solves: candidates c' in
+            // {12, 16, 24} for about n / 40 or n / 20 sweeps, kept when the
+            // correction sweeps of a whole polish drop by over 5 %.  (The
+            // relaxation itself gets none: a start phase there reaches the
+            // residual sooner but leaves more smooth error, which costs the
+            // polish more than it saves.)
+            const double c_lead[] = {12.0, 16.0, 24.0};
+            const int64_t k_lead[] = {std::max<int64_t>(n / 40, 2 * best.S), std::max<int64_t>(n / 20, 4 * best.S)};
+            auto dc_sweeps = [&](StartPhase lp, int64_t *out_sw) {
+                int64_t sw = 0, swc = 0;
+                double r = 0.0, r64 = 0.0;
+                bool conv = false, done = false;
+                int32_t rounds = 0;
+                *out_sw = 0;
+                int e = launch_fill_f32(fld, 0.5f, g.nx, g.ny, g.pitch, st);
+                if (!e) e = launch_field_init(cls, fld, g.nx, g.ny, g.pitch, HPF_INIT_HALF, st);
+                if (!e) e = run.solve32(fld, nullptr, best.omega, best.S, best.RH, 1e-6, cap, 0, &sw, &r, &conv);
+                if (!e && conv)
+                    e = run.polish_dc(fld, f64, best.omega_dc, 1e-7 / wb, best.S, best.RH, 3 * cap, &swc, &rounds,
+                                      &r64, &done, lp);
+                if (!e && done) *out_sw = swc;
+                return e;
+            };
+            if (!rc && id >= 0) {
+                const int64_t base = sw_dc[id];
+                int64_t best_sw = base > 0 ? (int64_t)(0.95 * (double)base) : 0;
+                for (double c1 : c_lead)
+                    for (int64_t k : k_lead) {
+                        if (rc) break;
+                        const StartPhase lp{omega_family(n, c1), k};
+                        int64_t sw = 0;
+                        rc = dc_sweeps(lp, &sw);
+                        if (!rc && sw > 0 && best_sw > 0 && sw < best_sw) {
+                            best_sw = sw;
+                            best.lead_dc = lp;
+                        }
+                    }
+            }
         }
     }
     hipEventDestroy(e0);
@@ -1034,6 +1107,8 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
         out[5] = best.RH64;
         out[6] = best.cups64;
         out[7] = best.omega_dc;
+        out[8] = best.lead_dc.omega;
+        out[9] = (double)best.lead_dc.sweeps;
     }
     return TWG_OK;
 }

@@ -11,11 +11,20 @@
 
 #include "twg.h"
 
+// Start phase of an FP32 solve: its first `sweeps` sweeps use the smaller
+// factor `omega`, which damps the rough error of the initial field faster
+// than the asymptotically best factor does (sweeps = 0: none).
+struct StartPhase {
+    float omega = 0.0f;
+    int64_t sweeps = 0;
+};
+
 struct twg_tuning {
     int S = 0;        // sweeps per tile load
     int RH = 0;       // output rows per tile
     float omega = 0;     // 0 = open-rectangle optimum
     float omega_dc = 0;  // factor of the defect-correction solves (0 = default)
+    StartPhase lead_dc;  // start phase of each correction solve
     double cups = 0;  // measured cell-updates per second
     int S64 = 0;      // the same for FP64 sweeps (0 = untuned)
     int RH64 = 0;
@@ -42,8 +51,8 @@ struct twg_ctx {
     size_t alt64_bytes = 0;
     // SOR factor map (FP32 sweeps) and free mask (FP64 sweeps), rebuilt by
     // every call that sweeps
-    void *wmap32 = nullptr;
-    size_t wmap32_bytes = 0;
+    void *wmap32[2] = {nullptr, nullptr};  // two factors (a start phase and the main one)
+    size_t wmap32_bytes[2] = {0, 0};
     void *fmask = nullptr;
     size_t fmask_bytes = 0;
     // (obstacle, ring) work list of the rasteriser and its counter

@@ -269,15 +269,17 @@ class Context:
         self._check(rc)
 
     def autotune(self, cls):
-        """Tune tiling (FP32 and FP64 sweeps) and SOR factors for grids of
-        cls's size; returns dict(S, RH, omega, cups, S64, RH64, cups64,
-        omega_dc)."""
+        """Tune tiling (FP32 and FP64 sweeps), SOR factors and the correction
+        solves' start phase for grids of cls's size; returns dict(S, RH,
+        omega, cups, S64, RH64, cups64, omega_dc, lead_dc_omega,
+        lead_dc_sweeps)."""
         nx, ny, pitch = _grid_of(cls)
-        out = (ctypes.c_double * 8)()
+        out = (ctypes.c_double * 10)()
         rc = lib.hpf_autotune(self.h, Grid(nx, ny, pitch), _ptr(cls), out, _stream())
         self._check(rc)
         return dict(S=int(out[0]), RH=int(out[1]), omega=float(out[2]), cups=float(out[3]), S64=int(out[4]),
-                    RH64=int(out[5]), cups64=float(out[6]), omega_dc=float(out[7]))
+                    RH64=int(out[5]), cups64=float(out[6]), omega_dc=float(out[7]), lead_dc_omega=float(out[8]),
+                    lead_dc_sweeps=int(out[9]))
 
     def set_tiling(self, nx, ny, S, RH, omega=0.0, S64=0, RH64=0):
         """Fix the tiling (and SOR factor) used for grids of this size."""

@@ -217,6 +217,24 @@ def test_relax_stops_at_the_fp32_rounding_floor(ctx, orc):
     assert abs(orc.residual(cls, psi.astype(np.float64)) - st["residual"]) <= 1e-12
 
 
+def test_relax_checked_every_pass_stops_at_the_first_converged_pass(ctx, orc):
+    # a residual check after every pass: the solve runs to the first pass
+    # whose residual meets the tolerance.  Not earlier (the max-norm residual
+    # is not monotone from check to check, which must not read as a stall)
+    # and not later (one pass fewer is still above it).
+    from paper_1903_07441_amd import twg
+    sc = scenarios.scenario("warped512", 2)
+    cls, _ = orc.rasterize(sc)
+    S = 4
+    st, psi, _, _ = gpu_relax(ctx, cls, tol=1e-6, check_passes=1, sweeps_per_pass=S)
+    print(f"checked every pass: stats={st}", flush=True)
+    assert st["status"] == twg.OK and st["residual"] <= 1e-6
+    assert st["sweeps"] % S == 0 and st["checks"] >= st["sweeps"] // S
+    assert abs(orc.residual(cls, psi.astype(np.float64)) - st["residual"]) <= 1e-12
+    st2, _, _, _ = gpu_relax(ctx, cls, tol=1e-6, check_passes=1, sweeps_per_pass=S, max_sweeps=st["sweeps"] - S)
+    assert st2["status"] == twg.NOT_CONVERGED and st2["residual"] > 1e-6
+
+
 @pytest.mark.parametrize("nx,ny,pitch", [(96, 80, 96), (301, 129, 320), (3, 40, 4)])
 @pytest.mark.parametrize("S", [1, 3, 4])
 def test_fp64_sweep_bit_exact_vs_oracle(ctx, orc, nx, ny, pitch, S):
@@ -285,6 +303,12 @@ def test_autotune_factors_converge(orc):
         assert tune["RH"] >= 2 and tune["RH"] % 2 == 0
         assert 1.9 < tune["omega"] < 2.0 and 1.9 < tune["omega_dc"] < 2.0
         ny, nx = cls.shape
+        # the correction solves' start phase, when kept, uses a smaller
+        # factor for at most about n / 20 sweeps
+        k = tune["lead_dc_sweeps"]
+        assert k >= 0
+        if k:
+            assert 1.0 < tune["lead_dc_omega"] < tune["omega_dc"] and k <= max(nx, ny) // 20 + 4 * tune["S"]
         psi = to_dev(np.zeros((ny, nx), np.float32))
         psi64 = to_dev(np.zeros((ny, nx)), dtype=torch.float64)
         plain = ctx.relax(c, psi, None, tol=1e-6)
