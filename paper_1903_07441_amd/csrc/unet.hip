@@ -56,12 +56,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 int last_status() { return hipGetLastError() == hipSuccess ? TWG_OK : TWG_EDEVICE; }
 
 // ---- bf16 helpers -------------------------------------------------------
+// round to nearest even; NaN stays a quiet NaN.  Both results are formed
+// and one selected, so the conversion never branches.
 __device__ __forceinline__ uint32_t f2bf(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return ((u >> 16) | 0x40u) & 0xffffu;  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t qnan = ((u >> 16) | 0x40u) & 0xffffu;
+    return (u & 0x7fffffffu) > 0x7f800000u ? qnan : rounded;
 }
 __device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
@@ -84,7 +86,14 @@ __device__ __forceinline__ uint4 pack8(const float *f)
     return make_uint4(pack2(f[0], f[1]), pack2(f[2], f[3]), pack2(f[4], f[5]), pack2(f[6], f[7]));
 }
 
-constexpr int kPlain = 0, kPool = 1, kUpCat = 2;
+constexpr int kPlain = 0, kPool = 1, kUpCat = 2, kIn4 = 3;
+
+constexpr int kTS = 16;       // output tile side
+constexpr int kHS = 18;       // halo side
+constexpr int kCK = 32;       // input channels per chunk
+constexpr int kPS = kCK + 8;  // LDS pixel stride (bf16), padded against bank conflicts
+constexpr int kNV = kHS * kHS * (kCK / 8);
+constexpr int kVPT = (kNV + 255) / 256;
 
 // 8 channels [c, c + 8) of the conv input at pixel (yy, xx) of image b, at
 // the conv's own resolution H x W (in bounds).
@@ -92,11 +101,17 @@ constexpr int kPlain = 0, kPool = 1, kUpCat = 2;
 //   kPool:  A is [B][2H][2W][CIN]; the 2x2 mean, rounded to bf16.
 //   kUpCat: channels < CA from A = [B][H/2][W/2][CA] (nearest), the rest
 //           from Bs = [B][H][W][CIN - CA].
+//   kIn4:   A is the network input [B][H][W][4] (3 channels and a zero);
+//           channels from 4 on read as zero.
 template <int MODE, int CIN, int CA>
 __device__ __forceinline__ uint4 gather8(const uint16_t *__restrict__ A, const uint16_t *__restrict__ Bs,
                                          int b, int yy, int xx, int c, int H, int W)
 {
-    if (MODE == kPlain) {
+    if (MODE == kIn4) {
+        if (c != 0) return make_uint4(0, 0, 0, 0);
+        const uint2 v = *reinterpret_cast<const uint2 *>(A + (((size_t)b * H + yy) * W + xx) * 4);
+        return make_uint4(v.x, v.y, 0, 0);
+    } else if (MODE == kPlain) {
         return *reinterpret_cast<const uint4 *>(A + (((size_t)b * H + yy) * W + xx) * CIN + c);
     } else if (MODE == kPool) {
         const size_t W2 = 2 * (size_t)W;
@@ -113,19 +128,76 @@ __device__ __forceinline__ uint4 gather8(const uint16_t *__restrict__ A, const u
         for (int i = 0; i < 8; ++i) s1[i] = (s0[i] + (a[i] + t[i])) * 0.25f;
         return pack8(s1);
     } else {
-        if (c < CA)
-            return *reinterpret_cast<const uint4 *>(
-                A + (((size_t)b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * CA + c);
-        return *reinterpret_cast<const uint4 *>(Bs + (((size_t)b * H + yy) * W + xx) * (CIN - CA) + (c - CA));
+        // one load from whichever tensor holds channel c (no branch: the
+        // channel group differs between lanes)
+        const uint16_t *p = c < CA ? A + (((size_t)b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * CA + c
+                                   : Bs + (((size_t)b * H + yy) * W + xx) * (CIN - CA) + (c - CA);
+        return *reinterpret_cast<const uint4 *>(p);
     }
 }
 
-constexpr int kTS = 16;       // output tile side
-constexpr int kHS = 18;       // halo side
-constexpr int kCK = 32;       // input channels per chunk
-constexpr int kPS = kCK + 8;  // LDS pixel stride (bf16), padded against bank conflicts
-constexpr int kNV = kHS * kHS * (kCK / 8);
-constexpr int kVPT = (kNV + 255) / 256;
+// Halo element v (pixel v / 4 of the 18 x 18 halo of the tile at (x0, y0),
+// channel group v % 4) of input chunk ch.  The load is unconditional: an
+// element outside the halo or the image reads a clamped in-bounds pixel and
+// is replaced by zero, so a wave issues all its halo loads back to back
+// instead of waiting for each one inside a divergent branch.
+template <int MODE, int CIN, int CA>
+__device__ __forceinline__ uint4 halo8(const uint16_t *__restrict__ A, const uint16_t *__restrict__ Bs, int b,
+                                       int v, int x0, int y0, int ch, int H, int W)
+{
+    const int vc = v < kNV ? v : 0;
+    const int hp = vc >> 2, cg = vc & 3;
+    const int hy = hp / kHS, hx = hp - hy * kHS;
+    const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+    const bool in = v < kNV && yy >= 0 && yy < H && xx >= 0 && xx < W;
+    const uint4 val = gather8<MODE, CIN, CA>(A, Bs, b, min(max(yy, 0), H - 1), min(max(xx, 0), W - 1),
+                                             ch * kCK + cg * 8, H, W);
+    return in ? val : make_uint4(0, 0, 0, 0);
+}
+
+
+// ---- bf16 output tile ----------------------------------------------------
+// A lane's accumulators hold 4 consecutive output channels of one pixel,
+// 8 bytes, every 2 COUT bytes apart, so storing them directly writes every
+// output line in pieces.  Instead each wave puts its 4 rows x 16 pixels of
+// bf16(relu(acc + bias)) into LDS (a slice of at most 64 channels at a time)
+// and writes them back as 16-byte runs of consecutive channels.  stg must
+// hold 4 x 64 x (min(COB, 64) + 8) bf16; all threads of the workgroup call
+// this together (it synchronises).
+template <int COUT, int COB>
+__device__ __forceinline__ void store_tile(const f32x4 (&acc)[4][COB / 16], const float *__restrict__ bias,
+                                           uint16_t *__restrict__ out, uint16_t *stg_all, int b, int co0, int x0,
+                                           int y0, int H, int W)
+{
+    constexpr int CS = COB < 64 ? COB : 64, NS = COB / CS, RTS = CS / 16, PSO = CS + 8;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    uint16_t *stg = stg_all + wave * 64 * PSO;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int q = 0; q < RTS; ++q) {
+                const int rt = sl * RTS + q, o = co0 + rt * 16 + g * 4;
+                const f32x4 v = acc[ct][rt];
+                const float r0 = fmaxf(v[0] + bias[o], 0.f), r1 = fmaxf(v[1] + bias[o + 1], 0.f);
+                const float r2 = fmaxf(v[2] + bias[o + 2], 0.f), r3 = fmaxf(v[3] + bias[o + 3], 0.f);
+                *reinterpret_cast<uint2 *>(&stg[(ct * 16 + j) * PSO + q * 16 + g * 4]) =
+                    make_uint2(pack2(r0, r1), pack2(r2, r3));
+            }
+        __syncthreads();
+#pragma unroll
+        for (int q = lane; q < 64 * (CS / 8); q += 64) {
+            const int p = q / (CS / 8), c8 = q - p * (CS / 8);
+            const int y = y0 + wave * 4 + (p >> 4), x = x0 + (p & 15);
+            const uint4 v = *reinterpret_cast<const uint4 *>(&stg[p * PSO + c8 * 8]);
+            if (y < H && x < W)
+                *reinterpret_cast<uint4 *>(out + (((size_t)b * H + y) * W + x) * COUT + co0 + sl * CS + c8 * 8) = v;
+        }
+        __syncthreads();
+    }
+}
 
 // ---- forward conv (and input gradient with OUT_F32) ----------------------
 // grid (ceil(W/16), ceil(H/16), B * max(1, COUT / 128)), 256 threads (a
@@ -149,18 +221,7 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ A, c
     uint4 st[kVPT];
     auto fetch = [&](int ch) {
 #pragma unroll
-        for (int r = 0; r < kVPT; ++r) {
-            const int v = tid + 256 * r;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (v < kNV) {
-                const int hp = v >> 2, cg = v & 3;
-                const int hy = hp / kHS, hx = hp - hy * kHS;
-                const int yy = y0 + hy - 1, xx = x0 + hx - 1;
-                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    val = gather8<MODE, CIN, CA>(A, Bs, b, yy, xx, ch * kCK + cg * 8, H, W);
-            }
-            st[r] = val;
-        }
+        for (int r = 0; r < kVPT; ++r) st[r] = halo8<MODE, CIN, CA>(A, Bs, b, tid + 256 * r, x0, y0, ch, H, W);
     };
     auto commit = [&](int buf) {
 #pragma unroll
@@ -212,26 +273,110 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ A, c
         __syncthreads();
     }
 
-    const int x = x0 + j;
+    if (OUT_F32) {
+        const int x = x0 + j;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const int y = y0 + wave * 4 + ct;
-        if (y >= H || x >= W) continue;
-        const size_t pix = ((size_t)b * H + y) * W + x;
+        for (int ct = 0; ct < 4; ++ct) {
+            const int y = y0 + wave * 4 + ct;
+            if (y >= H || x >= W) continue;
+            const size_t pix = ((size_t)b * H + y) * W + x;
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int o = co0 + rt * 16 + g * 4;
-            const f32x4 v = acc[ct][rt];
-            if (OUT_F32) {
+            for (int rt = 0; rt < RT; ++rt) {
+                const int o = co0 + rt * 16 + g * 4;
+                const f32x4 v = acc[ct][rt];
                 *reinterpret_cast<float4 *>(static_cast<float *>(out) + pix * COUT + o) =
                     make_float4(v[0], v[1], v[2], v[3]);
-            } else {
-                const float r0 = fmaxf(v[0] + bias[o], 0.f), r1 = fmaxf(v[1] + bias[o + 1], 0.f);
-                const float r2 = fmaxf(v[2] + bias[o + 2], 0.f), r3 = fmaxf(v[3] + bias[o + 3], 0.f);
-                *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(out) + pix * COUT + o) =
-                    make_uint2(pack2(r0, r1), pack2(r2, r3));
             }
         }
+    } else {
+        // the halo buffers are free after the loop's last barrier
+        store_tile<COUT, COB>(acc, bias, static_cast<uint16_t *>(out), &lds[0][0], b, co0, x0, y0, H, W);
+    }
+}
+
+// ---- first layer ---------------------------------------------------------
+// The input has 3 real channels, so one K = 32 slice of the implicit GEMM
+// covers all nine taps (k = 3 tap + c; k >= 27 is zero) and a 16-pixel row
+// of 16 output channels takes one MFMA instead of nine.  x4 is
+// [B][H][W][4] bf16 (channel 3 zero); the weights keep the layers' internal
+// layout [32][9][32] (input channels padded to 32, only 0..2 used).  256
+// threads; a workgroup builds its weight fragments once and then loops over
+// 16 x 16 pixel tiles (t = blockIdx.x, + gridDim.x, ... < B tx ty), four
+// rows per wave: every workgroup reading the same few weight lines for
+// every tile would queue on the cache channels that hold them.
+// out = bf16(relu(acc + bias)), [B][H][W][32].
+__global__ __launch_bounds__(256) void k_conv3_in(const uint16_t *__restrict__ x4, const uint16_t *__restrict__ wt,
+                                                  const float *__restrict__ bias, uint16_t *__restrict__ out, int nb,
+                                                  int H, int W)
+{
+    constexpr int COUT = 32, RT = 2, ZERO = kHS * kHS * 4;  // lds[ZERO..ZERO + 3] stay zero
+    __shared__ __align__(16) uint16_t lds[kHS * kHS * 4 + 4];
+    __shared__ __align__(16) uint16_t stg[4 * 64 * (COUT + 8)];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    const int tx = (W + kTS - 1) / kTS, ty = (H + kTS - 1) / kTS, ntile = nb * tx * ty;
+    // this lane's k = 8 g + i: A element (output channel rt * 16 + j) and the
+    // LDS offset of its B element from the pixel's own halo position.  Every
+    // load is unconditional (k >= 27 reads a valid element and is zeroed, or
+    // reads the zero slot), so no load waits inside a divergent branch.
+    uint32_t a[RT][4];
+    int off[8];
+    bool live[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = 8 * g + i, tap = k / 3, c = k - 3 * tap;
+        live[i] = k < 27;
+        off[i] = live[i] ? ((tap / 3) * kHS + (tap % 3)) * 4 + c : 0;
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            uint32_t w2[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int k = 8 * g + 2 * h + e, tap = live[2 * h + e] ? k / 3 : 0, c = live[2 * h + e] ? k - 3 * tap : 0;
+                const uint32_t w = wt[((size_t)(rt * 16 + j) * 9 + tap) * 32 + c];
+                w2[e] = live[2 * h + e] ? w : 0u;
+            }
+            a[rt][h] = w2[0] | (w2[1] << 16);
+        }
+    if (tid == 0) *reinterpret_cast<uint2 *>(&lds[ZERO]) = make_uint2(0, 0);
+
+    for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+        const int b = t / (tx * ty), r = t - b * (tx * ty);
+        const int x0 = (r % tx) * kTS, y0 = (r / tx) * kTS;
+        for (int v = tid; v < kHS * kHS; v += 256) {
+            const int hy = v / kHS, hx = v - hy * kHS;
+            const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+            const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+            const uint2 ld = *reinterpret_cast<const uint2 *>(
+                x4 + (((size_t)b * H + min(max(yy, 0), H - 1)) * W + min(max(xx, 0), W - 1)) * 4);
+            *reinterpret_cast<uint2 *>(&lds[v * 4]) = in ? ld : make_uint2(0, 0);
+        }
+        __syncthreads();
+
+        f32x4 acc[4][RT];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const int base = ((wave * 4 + ct) * kHS + j) * 4;
+            uint32_t bw[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const uint32_t lo = lds[live[2 * h] ? base + off[2 * h] : ZERO];
+                const uint32_t hi = lds[live[2 * h + 1] ? base + off[2 * h + 1] : ZERO];
+                bw[h] = lo | (hi << 16);
+            }
+            const uint4 bv = make_uint4(bw[0], bw[1], bw[2], bw[3]);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    as_bf8(make_uint4(a[rt][0], a[rt][1], a[rt][2], a[rt][3])), as_bf8(bv),
+                    f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        }
+        // store_tile synchronises before and after its LDS round trip, so
+        // the halo is free for the next tile when it returns
+        store_tile<COUT, COUT>(acc, bias, out, stg, b, 0, x0, y0, H, W);
     }
 }
 
@@ -271,9 +416,9 @@ __global__ __launch_bounds__(256) void k_wgrad3(const uint16_t *__restrict__ A, 
         for (int v = tid; v < 256 * (COUT / 8); v += 256) {
             const int p = v & 255, cg = v >> 8;
             const int y = y0 + (p >> 4), x = x0 + (p & 15);
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (y < H && x < W)
-                val = *reinterpret_cast<const uint4 *>(dout + (((size_t)b * H + y) * W + x) * COUT + cg * 8);
+            const uint4 ld = *reinterpret_cast<const uint4 *>(
+                dout + (((size_t)b * H + min(y, H - 1)) * W + min(x, W - 1)) * COUT + cg * 8);
+            const uint4 val = y < H && x < W ? ld : make_uint4(0, 0, 0, 0);
             const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -286,10 +431,7 @@ __global__ __launch_bounds__(256) void k_wgrad3(const uint16_t *__restrict__ A, 
         for (int v = tid; v < kNV; v += 256) {
             const int hp = v >> 2, cg = v & 3;
             const int hy = hp / kHS, hx = hp - hy * kHS;
-            const int yy = y0 + hy - 1, xx = x0 + hx - 1;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                val = gather8<MODE, CIN, CA>(A, Bs, b, yy, xx, ch * kCK + cg * 8, H, W);
+            const uint4 val = halo8<MODE, CIN, CA>(A, Bs, b, v, x0, y0, ch, H, W);
             const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
@@ -541,21 +683,19 @@ __global__ __launch_bounds__(256) void k_route_pool(const float *__restrict__ ds
 }
 
 // ---- input packing and features ------------------------------------------
-// x [P][3] FP32 -> xp [P][32] bf16 (channels 3..31 zero)
+// x [P][3] FP32 -> xp [P][4] bf16 (channel 3 zero)
 __global__ __launch_bounds__(256) void k_pack_input(const float *__restrict__ x, uint16_t *__restrict__ xp,
                                                     long long total)
 {
     const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
     if (p >= total) return;
-    uint4 *o = reinterpret_cast<uint4 *>(xp + (size_t)p * 32);
-    o[0] = make_uint4(pack2(x[3 * p], x[3 * p + 1]), pack2(x[3 * p + 2], 0.f), 0u, 0u);
-    o[1] = o[2] = o[3] = make_uint4(0, 0, 0, 0);
+    *reinterpret_cast<uint2 *>(xp + (size_t)p * 4) = make_uint2(pack2(x[3 * p], x[3 * p + 1]), pack2(x[3 * p + 2], 0.f));
 }
 
 // Network input channels of a grid on an Hp x Wp frame (frame cells outside
 // the grid read as walls): occupancy (1 on OBST and WALL), Euclidean goal
 // distance / (max(nx, ny) sqrt 2), ring / max ring (0 without a ring map).
-// Writes FP32 [Hp][Wp][3] to xf and/or bf16 [Hp][Wp][32] to xp.
+// Writes FP32 [Hp][Wp][3] to xf and/or bf16 [Hp][Wp][4] (channel 3 zero) to xp.
 __global__ __launch_bounds__(256) void k_features(const uint8_t *__restrict__ cls, const uint16_t *__restrict__ ring,
                                                   int nx, int ny, int pitch, int Hp, int Wp, int gx, int gy,
                                                   float inv_diag, const unsigned int *__restrict__ jmax,
@@ -581,11 +721,7 @@ __global__ __launch_bounds__(256) void k_features(const uint8_t *__restrict__ cl
         xf[3 * p + 1] = gd;
         xf[3 * p + 2] = rt;
     }
-    if (xp) {
-        uint4 *o = reinterpret_cast<uint4 *>(xp + p * 32);
-        o[0] = make_uint4(pack2(occ, gd), pack2(rt, 0.f), 0u, 0u);
-        o[1] = o[2] = o[3] = make_uint4(0, 0, 0, 0);
-    }
+    if (xp) *reinterpret_cast<uint2 *>(xp + p * 4) = make_uint2(pack2(occ, gd), pack2(rt, 0.f));
 }
 
 // largest ring number of a grid; *out must be zero beforehand.  Grid-stride
@@ -832,7 +968,12 @@ int net_forward(twg_unet *n, int nb, int H, int W, hipStream_t st)
     auto W_ = [&](int l) { return wt + L.offw[l]; };
     auto B_ = [&](int l) { return mb + L.offb[l]; };
     const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
-    int rc = conv<32, 32, kPlain, 0, false>(n->xp, nullptr, W_(0), B_(0), n->e0, nb, H, W, st);
+    {
+        const long long ntile = (long long)nb * ((W + kTS - 1) / kTS) * ((H + kTS - 1) / kTS);
+        const int grid = (int)std::max<long long>(1, std::min<long long>(ntile, 2048));
+        hipLaunchKernelGGL(k_conv3_in, dim3(grid), dim3(256), 0, st, n->xp, W_(0), B_(0), n->e0, nb, H, W);
+    }
+    int rc = last_status();
     if (!rc) rc = conv<32, 64, kPool, 0, false>(n->e0, nullptr, W_(1), B_(1), n->e1, nb, H1, W1, st);
     if (!rc) rc = conv<64, 128, kPool, 0, false>(n->e1, nullptr, W_(2), B_(2), n->e2, nb, H2, W2, st);
     if (!rc) rc = conv<128, 128, kPool, 0, false>(n->e2, nullptr, W_(3), B_(3), n->e3, nb, H3, W3, st);
@@ -887,7 +1028,7 @@ int net_backward(twg_unet *n, int nb, int H, int W, const float *target, const u
     if (!rc) rc = conv<64, 32, kPlain, 0, true>(n->g_e1, nullptr, F_(1), nullptr, n->f_p0, nb, H1, W1, st);
     if (!rc) rc = route_pool<32, 32, 64>(n->f_c0, n->f_p0, n->e0, n->g_e0, nb, H, W, st);
     // e0: input x (padded to 32 channels)
-    if (!rc) rc = wgrad<32, 32, kPlain, 0>(n->xp, nullptr, n->g_e0, n->part, n->bpart, GW(0), GB(0), nb, H, W, st);
+    if (!rc) rc = wgrad<32, 32, kIn4, 0>(n->xp, nullptr, n->g_e0, n->part, n->bpart, GW(0), GB(0), nb, H, W, st);
     return rc;
 }
 

@@ -25,16 +25,16 @@ int ensure_fwd(twg_unet *n, long long P)
         n->fblock = nullptr;
         n->fwd_pixels = 0;
     }
-    const size_t s32 = al((size_t)P * 32 * 2), s1 = al((size_t)P / 4 * 2), s2 = al((size_t)P / 16 * 2),
-                 s3 = al((size_t)P / 64 * 2);
-    const size_t bytes = 3 * s32 + 64 * s1 + 32 * s1 + 128 * s2 + 64 * s2 + 128 * s3;
+    const size_t s32 = al((size_t)P * 32 * 2), s4 = al((size_t)P * 4 * 2), s1 = al((size_t)P / 4 * 2),
+                 s2 = al((size_t)P / 16 * 2), s3 = al((size_t)P / 64 * 2);
+    const size_t bytes = s4 + 2 * s32 + 64 * s1 + 32 * s1 + 128 * s2 + 64 * s2 + 128 * s3;
     if (hipMalloc(&n->fblock, bytes) != hipSuccess) {
         n->fblock = nullptr;
         return set_err(n->ctx, TWG_ENOMEM, "network activation allocation failed");
     }
     char *p = static_cast<char *>(n->fblock);
     auto take = [&](size_t b) { uint16_t *r = reinterpret_cast<uint16_t *>(p); p += b; return r; };
-    n->xp = take(s32);
+    n->xp = take(s4);
     n->e0 = take(s32);
     n->d0 = take(s32);
     n->e1 = take(64 * s1);
