@@ -1248,7 +1248,7 @@ int32_t hpf_descend(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *p
     rc = ensure(ctx, &ctx->idxbuf, &ctx->idxbuf_bytes, (size_t)g.pitch * g.ny);
     if (rc) return rc;
     uint8_t *idx = reinterpret_cast<uint8_t *>(ctx->idxbuf);
-    rc = launch_index(cls, psi, psi64, idx, g.nx, g.ny, g.pitch, st);
+    rc = launch_index(cls, psi, psi64, idx, g.nx, g.ny, g.pitch, st, true);
     if (!rc) rc = launch_walk(cls, idx, g.nx, g.ny, g.pitch, p->start_x, p->start_y, p->cap, path_xy,
                               info, st);
     return rc ? set_err(ctx, rc, "descent launch failed") : TWG_OK;

@@ -4,12 +4,9 @@
 //   k_index  one thread per cell: direction (E 0, W 1, S 2, N 3) of the
 //            walkable neighbour with the highest psi (lowest phi), first one
 //            on ties; 4 when none is strictly higher than the cell itself.
-//   k_walk   one workgroup follows the index matrix from the start.  The
-//            128 x 128 window of index codes and classes around the current
-//            cell is staged in LDS by all 1024 threads; one thread then walks
-//            inside the window (each step strictly raises psi, so the walk
-//            never revisits a cell) and the window is re-centred when the
-//            walk leaves it.
+//   k_walk   one workgroup follows the index matrix from the start, reading
+//            walk codes (the index code, 5 on GOAL cells) from a 256 x 256
+//            LDS window around the current cell (see k_walk).
 //   k_rubber one workgroup relaxes a path as a rubber band (Eqs. 4-6): per
 //            iteration the interior points of odd index, then those of even
 //            index, each move to the best of nine candidate cells given the
@@ -27,7 +24,10 @@ __device__ __forceinline__ bool walkable(uint8_t c)
     return c == TWG_CELL_FREE || c == TWG_CELL_GOAL;
 }
 
-template <typename T>
+// WALK: the walk's code instead of the index matrix: 5 on GOAL cells, else
+// the index code (so the walk reads one byte per step).
+constexpr uint8_t kGoalCode = 5;
+template <typename T, bool WALK>
 __global__ void k_index(const uint8_t *__restrict__ cls, const T *__restrict__ u,
                         uint8_t *__restrict__ idx, int nx, int ny, int pitch)
 {
@@ -51,18 +51,23 @@ __global__ void k_index(const uint8_t *__restrict__ cls, const T *__restrict__ u
         }
     }
     if (best != 4 && !(bv > u[i])) best = 4;
-    idx[i] = (uint8_t)best;
+    idx[i] = WALK && cls[i] == TWG_CELL_GOAL ? kGoalCode : (uint8_t)best;
 }
 
-constexpr int kTile = 128;
+constexpr int kTile = 256;
 
+// code: the walk codes of k_index<T, true> (direction, 4 = no move, 5 =
+// goal).  The 256 x 256 window of codes around the current cell is staged in
+// LDS by all 1024 threads (unconditional loads: cells outside the grid read
+// a clamped cell and become 4); one thread then walks inside the window,
+// one LDS byte per step (each step strictly raises psi, so the walk never
+// revisits a cell), and the window is re-centred when the walk leaves it.
 __global__ __launch_bounds__(1024) void k_walk(const uint8_t *__restrict__ cls,
-                                              const uint8_t *__restrict__ idx, int nx, int ny,
+                                              const uint8_t *__restrict__ code, int nx, int ny,
                                               int pitch, int sx, int sy, int cap,
                                               int32_t *__restrict__ path, int32_t *__restrict__ info)
 {
-    __shared__ uint8_t tidx[kTile * kTile];
-    __shared__ uint8_t tcls[kTile * kTile];
+    __shared__ __align__(16) uint8_t tcode[kTile * kTile];
     __shared__ int state[4];  // x, y, length, status (-1 = walking)
     if (threadIdx.x == 0) {
         const uint8_t c = cls[(size_t)sy * pitch + sx];
@@ -79,36 +84,101 @@ __global__ __launch_bounds__(1024) void k_walk(const uint8_t *__restrict__ cls,
         }
     }
     __syncthreads();
-    const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
     while (state[3] < 0) {
-        const int tx0 = state[0] - kTile / 2, ty0 = state[1] - kTile / 2;
-        for (int k = threadIdx.x; k < kTile * kTile; k += blockDim.x) {
-            const int x = tx0 + (k & (kTile - 1)), y = ty0 + k / kTile;
-            uint8_t d = 4, c = TWG_CELL_WALL;
-            if (x >= 0 && y >= 0 && x < nx && y < ny) {
-                const size_t i = (size_t)y * pitch + x;
-                d = idx[i];
-                c = cls[i];
+        // window origin on a multiple of 16 columns, so that with pitch a
+        // multiple of 16 (else 4) every 16-cell (4-cell) group is one
+        // aligned 128-bit (32-bit) load; all of a thread's loads are issued
+        // before its first LDS store, so a restage costs one memory latency,
+        // not one per load
+        const int tx0 = (state[0] - kTile / 2) & ~15, ty0 = state[1] - kTile / 2;
+        if ((pitch & 15) == 0) {
+            constexpr int PER = kTile * kTile / 16 / 1024;
+            uint4 v[PER];
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                const int q = threadIdx.x + r * 1024;  // 16-cell group
+                const int x = tx0 + 16 * (q & (kTile / 16 - 1)), y = ty0 + q / (kTile / 16);
+                const int xc = min(max(x, 0), pitch - 16), yc = min(max(y, 0), ny - 1);
+                const uint4 w = *reinterpret_cast<const uint4 *>(code + (size_t)yc * pitch + xc);
+                const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+                uint32_t o[4];
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    o[h] = 0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int xe = x + 4 * h + e;
+                        const bool in = xe >= 0 && xe < nx && y >= 0 && y < ny && x == xc;
+                        o[h] |= (in ? (wv[h] >> (8 * e)) & 0xffu : 4u) << (8 * e);
+                    }
+                }
+                v[r] = make_uint4(o[0], o[1], o[2], o[3]);
             }
-            tidx[k] = d;
-            tcls[k] = c;
+#pragma unroll
+            for (int r = 0; r < PER; ++r) reinterpret_cast<uint4 *>(tcode)[threadIdx.x + r * 1024] = v[r];
+        } else if ((pitch & 3) == 0) {
+            constexpr int PER = kTile * kTile / 4 / 1024;
+            uint32_t v[PER];
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                const int q = threadIdx.x + r * 1024;  // 4-cell group
+                const int x = tx0 + 4 * (q & (kTile / 4 - 1)), y = ty0 + q / (kTile / 4);
+                const int xc = min(max(x, 0), pitch - 4), yc = min(max(y, 0), ny - 1);
+                const uint32_t w = *reinterpret_cast<const uint32_t *>(code + (size_t)yc * pitch + xc);
+                uint32_t o = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const bool in = x + e >= 0 && x + e < nx && y >= 0 && y < ny && x == xc;
+                    o |= (in ? (w >> (8 * e)) & 0xffu : 4u) << (8 * e);
+                }
+                v[r] = o;
+            }
+#pragma unroll
+            for (int r = 0; r < PER; ++r) reinterpret_cast<uint32_t *>(tcode)[threadIdx.x + r * 1024] = v[r];
+        } else {
+            constexpr int PER = kTile * kTile / 1024;
+            uint8_t v[PER];
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                const int k = threadIdx.x + r * 1024;
+                const int x = tx0 + (k & (kTile - 1)), y = ty0 + k / kTile;
+                const bool in = x >= 0 && y >= 0 && x < nx && y < ny;
+                const uint8_t d = code[(size_t)min(max(y, 0), ny - 1) * pitch + min(max(x, 0), nx - 1)];
+                v[r] = in ? d : (uint8_t)4;
+            }
+#pragma unroll
+            for (int r = 0; r < PER; ++r) tcode[threadIdx.x + r * 1024] = v[r];
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             int x = state[0], y = state[1], n = state[2], st = -1;
+            // one window test and one exit test per step; the rare exits
+            // (goal, no move, full buffer) are sorted out after the loop
+            int d = 0;
             for (;;) {
-                const int lx = x - tx0, ly = y - ty0;
-                if (lx < 0 || ly < 0 || lx >= kTile || ly >= kTile) break;
-                const int k = ly * kTile + lx;
-                if (tcls[k] == TWG_CELL_GOAL) { st = TWG_OK; break; }
-                const int d = tidx[k];
-                if (d == 4) { st = TWG_NO_PATH; break; }
-                x += dx[d];
-                y += dy[d];
-                if (n >= cap) { st = TWG_PATH_TRUNCATED; break; }
+                const unsigned lx = (unsigned)(x - tx0), ly = (unsigned)(y - ty0);
+                if ((lx | ly) >= (unsigned)kTile) break;
+                d = tcode[ly * kTile + lx];
+                if (d >= 4 || n >= cap) break;
+                // E, W, S, N by arithmetic: a table indexed by d would be a
+                // scalar memory load, and its latency, on every step
+                x += d < 2 ? 1 - 2 * d : 0;
+                y += d < 2 ? 0 : 5 - 2 * d;
                 path[2 * n] = x;
                 path[2 * n + 1] = y;
                 ++n;
+            }
+            const unsigned lx = (unsigned)(x - tx0), ly = (unsigned)(y - ty0);
+            if ((lx | ly) < (unsigned)kTile) {
+                if (d == kGoalCode) {
+                    st = TWG_OK;
+                } else if (d == 4) {
+                    st = TWG_NO_PATH;
+                } else {  // n == cap: the step that did not fit is taken, not stored
+                    x += d < 2 ? 1 - 2 * d : 0;
+                    y += d < 2 ? 0 : 5 - 2 * d;
+                    st = TWG_PATH_TRUNCATED;
+                }
             }
             state[0] = x;
             state[1] = y;
@@ -265,20 +335,27 @@ int launch_descent_all(const uint8_t *cls, const uint8_t *idx, int nx, int ny, i
 }
 
 int launch_index(const uint8_t *cls, const float *psi, const double *psi64, uint8_t *idx, int nx,
-                 int ny, int pitch, hipStream_t st)
+                 int ny, int pitch, hipStream_t st, bool walk)
 {
     const dim3 grid((nx + 63) / 64, (ny + 3) / 4);
-    if (psi64)
-        hipLaunchKernelGGL(k_index<double>, grid, dim3(256), 0, st, cls, psi64, idx, nx, ny, pitch);
-    else
-        hipLaunchKernelGGL(k_index<float>, grid, dim3(256), 0, st, cls, psi, idx, nx, ny, pitch);
+    if (psi64) {
+        if (walk)
+            hipLaunchKernelGGL((k_index<double, true>), grid, dim3(256), 0, st, cls, psi64, idx, nx, ny, pitch);
+        else
+            hipLaunchKernelGGL((k_index<double, false>), grid, dim3(256), 0, st, cls, psi64, idx, nx, ny, pitch);
+    } else {
+        if (walk)
+            hipLaunchKernelGGL((k_index<float, true>), grid, dim3(256), 0, st, cls, psi, idx, nx, ny, pitch);
+        else
+            hipLaunchKernelGGL((k_index<float, false>), grid, dim3(256), 0, st, cls, psi, idx, nx, ny, pitch);
+    }
     return hipGetLastError() == hipSuccess ? TWG_OK : TWG_EDEVICE;
 }
 
-int launch_walk(const uint8_t *cls, const uint8_t *idx, int nx, int ny, int pitch, int sx, int sy,
+int launch_walk(const uint8_t *cls, const uint8_t *code, int nx, int ny, int pitch, int sx, int sy,
                 int cap, int32_t *path, int32_t *info, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_walk, dim3(1), dim3(1024), 0, st, cls, idx, nx, ny, pitch, sx, sy, cap, path,
+    hipLaunchKernelGGL(k_walk, dim3(1), dim3(1024), 0, st, cls, code, nx, ny, pitch, sx, sy, cap, path,
                        info);
     return hipGetLastError() == hipSuccess ? TWG_OK : TWG_EDEVICE;
 }

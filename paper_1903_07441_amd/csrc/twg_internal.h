@@ -176,10 +176,11 @@ int launch_rasterize(twg_ctx *ctx, const twg_grid &g, int n_obs, const double *p
 int launch_kalman(int n, double *x, double *P, const double *z, double dt, const double *Q, const double *R,
                   double *pos, double *vel, hipStream_t st);
 
-// descend.hip
+// descend.hip.  walk: write the walk's codes (5 on GOAL cells, else the
+// index code) instead of the index matrix; launch_walk reads those.
 int launch_index(const uint8_t *cls, const float *psi, const double *psi64, uint8_t *idx, int nx,
-                 int ny, int pitch, hipStream_t st);
-int launch_walk(const uint8_t *cls, const uint8_t *idx, int nx, int ny, int pitch, int sx, int sy,
+                 int ny, int pitch, hipStream_t st, bool walk = false);
+int launch_walk(const uint8_t *cls, const uint8_t *code, int nx, int ny, int pitch, int sx, int sy,
                 int cap, int32_t *path, int32_t *info, hipStream_t st);
 int launch_descent_all(const uint8_t *cls, const uint8_t *idx, int nx, int ny, int pitch, int *buf,
                        int32_t *steps, int pitch_out, hipStream_t st);

@@ -39,11 +39,17 @@ def test_index_and_path_parity(ctx, orc, name, idx):
             assert s_gpu == 0 and cls[p_gpu[-1][1], p_gpu[-1][0]] == 3
 
 
-def test_descent_2048_reaches_goal(ctx, orc):
+@pytest.mark.parametrize("pitch_pad", [0, 4, 3])
+def test_descent_2048_reaches_goal(ctx, orc, pitch_pad):
+    # a path of thousands of cells: the walk re-stages its window many times,
+    # with 128-bit staging loads (pitch a multiple of 16), 32-bit ones
+    # (multiple of 4) or byte loads
     sc = scenarios.scenario("replan2048", 0)
     cls, _ = orc.rasterize(sc)
-    st, psi, psi64, c = gpu_relax(ctx, cls, tol=1e-6, polish=True, tol_cert=5e-7)
-    t = to_dev(psi64, dtype=torch.float64)
+    st, psi, psi64, _ = gpu_relax(ctx, cls, tol=1e-6, polish=True, tol_cert=5e-7)
+    pitch = cls.shape[1] + pitch_pad
+    c = to_dev(cls, pitch)
+    t = to_dev(psi64, pitch, dtype=torch.float64)
     s_gpu, p_gpu = gpu_descend(ctx, c, t, sc["robot"], use64=True)
     s_orc, p_orc = orc.descend(cls, psi64, sc["robot"])
     assert s_gpu == s_orc
