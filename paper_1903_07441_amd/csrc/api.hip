@@ -800,6 +800,8 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
         // retire converged, stalled or non-finite grids
         bool changed = false;
         int64_t chunk = INT64_MAX;
+        // (predicted sweeps to converge, cells) of every active grid
+        std::vector<std::pair<int64_t, double>> pred;
         for (int k = 0; k < n; ++k) {
             if (!active[k]) continue;
             if (std::isnan(r[k]) || std::isnan(rr[k]))
@@ -813,11 +815,31 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
                 continue;
             }
             const double want = std::log(p.tol / r[k]) / std::log(rate[k]);
-            int64_t c = (int64_t)std::ceil(want * (checks <= 1 ? 0.8 : 1.05));
+            int64_t c = (int64_t)std::min(std::ceil(want * (checks <= 1 ? 0.8 : 1.05)), 1e12);
             if (p.check_passes > 0) c = (int64_t)p.check_passes * S;
-            chunk = std::min(chunk, std::max<int64_t>(c, 8 * S));
+            c = std::max<int64_t>(c, 8 * S);
+            chunk = std::min(chunk, c);
+            pred.push_back({c, (double)bg[k].nx * (double)bg[k].ny});
         }
         if (chunk == INT64_MAX) break;  // nothing active
+        // A check stops the whole batch (residuals, read-back, new tile
+        // lists), so the next one is not placed at the first predicted
+        // convergence but at the latest predicted one whose overshoot, the
+        // sweeps that grids predicted to converge earlier run in vain, stays
+        // within 5 % of the chunk's useful cell-updates: small grids are
+        // cheap to sweep on, the batch-wide stop is not.
+        if (p.check_passes <= 0) {
+            std::sort(pred.begin(), pred.end());
+            for (const auto &cand : pred) {
+                const int64_t c = cand.first;
+                double waste = 0.0, useful = 0.0;
+                for (const auto &q : pred) {
+                    waste += q.second * (double)std::max<int64_t>(0, c - q.first);
+                    useful += q.second * (double)std::min(c, q.first);
+                }
+                if (waste <= 0.05 * useful) chunk = std::max(chunk, c);
+            }
+        }
         if (changed) {
             build_lists(active);
             rc = upload_lists();
