@@ -279,18 +279,24 @@ struct Runner {
 
     // FP32 red-black SOR on `field` (ping-pong with ctx->alt) until the FP64
     // residual is <= tol, the sweep budget is spent, or progress stalls; the
-    // first lead.sweeps sweeps (whole passes) use factor lead.omega.
+    // first lead.sweeps sweeps (whole passes) use factor lead.omega.  r0 >= 0
+    // is the caller's residual of the starting field (no check is spent on
+    // it); *rate_io, when in (0, 1), is a measured per-sweep contraction to
+    // start from, and receives the one this solve measured.
     int solve32(float *field, const float *f, float omega, int S, int RH, double tol,
                 int64_t max_sweeps, int check_passes, int64_t *sweeps_out, double *res_out,
-                bool *converged, double *rel_out = nullptr, StartPhase lead = {})
+                bool *converged, double *rel_out = nullptr, StartPhase lead = {}, double r0 = -1.0,
+                double *rate_io = nullptr)
     {
         const size_t bytes = (size_t)g.pitch * g.ny * sizeof(float);
         int rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, bytes);
         if (rc) return rc;
         float *a = field, *b = reinterpret_cast<float *>(ctx->alt);
-        double r, rr;
-        rc = residual32(a, f, &r, &rr);
-        if (rc) return rc;
+        double r = r0, rr = 0.0;
+        if (r0 < 0.0) {
+            rc = residual32(a, f, &r, &rr);
+            if (rc) return rc;
+        }
         int64_t done = 0, last_chunk = 0, since = 0;
         if (lead.sweeps > 0 && r > tol && !std::isnan(r) && max_sweeps > 0) {
             done = std::min(((lead.sweeps + S - 1) / S) * S, max_sweeps);
@@ -300,8 +306,9 @@ struct Runner {
         }
         int stalls = 0;
         double best = r;
-        // per-sweep contraction guess before any measurement
+        // per-sweep contraction: the caller's measurement, else a guess
         double rate = std::max((double)omega - 1.0, 0.5);
+        if (rate_io && *rate_io > 0.0 && *rate_io < 1.0) rate = *rate_io;
         *converged = false;
         while (true) {
             if (std::isnan(r)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
@@ -350,6 +357,7 @@ struct Runner {
             rc = launch_copy_f32(a, field, g.nx, g.ny, g.pitch, st);
             if (rc) return set_err(ctx, rc, "copy launch failed");
         }
+        if (rate_io) *rate_io = rate;
         *sweeps_out = done;
         *res_out = r;
         if (rel_out) *rel_out = rr;
@@ -383,7 +391,7 @@ struct Runner {
         *done = false;
         *sweeps_out = 0;
         *rounds_out = 0;
-        double r64 = 0.0;
+        double r64 = 0.0, rate_dc = 0.0;
         for (int round = 0; round < 12; ++round) {
             rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st);
             if (!rc) rc = readback(1);
@@ -400,7 +408,11 @@ struct Runner {
             int64_t sw = 0;
             double re = 0.0;
             bool cconv = false;
-            rc = solve32(e, r32, omega_dc, S, RH, target, max_sweeps, 0, &sw, &re, &cconv, nullptr, lead);
+            // the correction starts at e = 0, whose residual is the defect
+            // itself (no check needed), and each round starts from the
+            // contraction the previous one measured
+            rc = solve32(e, r32, omega_dc, S, RH, target, max_sweeps, 0, &sw, &re, &cconv, nullptr, lead, r64,
+                         &rate_dc);
             if (rc) return rc;
             *sweeps_out += sw;
             rc = launch_update64(cls, psi64, e, psi, g.nx, g.ny, g.pitch, st);
