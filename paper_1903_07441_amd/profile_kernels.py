@@ -13,6 +13,10 @@ many bytes) so that hardware byte counters can be calibrated against it.
 With --net: `--passes` warm starts (features + forward + head) of the
 network on the rasterised grid, then `--passes` training steps (forward,
 backward, Adam) on a batch of 16 random 256 x 256 inputs.
+
+With --step: after autotuning, `--passes` whole replanning steps as bench.py
+times them (rasterise, FP32 relaxation to residual 1e-6, FP64 defect
+correction to a certified 1e-7, descent from the robot).
 """
 from __future__ import annotations
 
@@ -31,6 +35,7 @@ def main(argv=None):
     ap.add_argument("--passes", type=int, default=50)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--net", action="store_true", help="profile the network kernels instead")
+    ap.add_argument("--step", action="store_true", help="profile whole replanning steps instead")
     ap.add_argument("--S", type=int, default=0, help="sweeps per tile load (with --RH: skip the autotuner)")
     ap.add_argument("--RH", type=int, default=0, help="output rows per tile")
     ap.add_argument("--fp64", action="store_true", help="also run the FP64 sweeps")
@@ -70,6 +75,24 @@ def main(argv=None):
         print(f"profiled {args.passes} warm starts on {nx}x{ny} and {args.passes} training steps "
               f"(batch {B}, {H}x{H})", flush=True)
         net.close()
+        ctx.close()
+        return 0
+    if args.step:
+        ctx.autotune(cls)
+        ring = torch.empty((ny, nx), dtype=torch.uint16, device=dev)
+        psi = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+        psi64 = torch.empty((ny, nx), dtype=torch.float64, device=dev)
+        cap = nx * ny
+        path = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        info = torch.empty(2, dtype=torch.int32, device=dev)
+        for _ in range(args.passes):
+            ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"], robot_speed=sc["vr"],
+                          cls=cls, ring=ring)
+            ctx.relax(cls, psi, None, tol=1e-6, init=twg.INIT_HALF)
+            ctx.relax(cls, psi, psi64, tol=1e-6, init=twg.INIT_KEEP, polish=1, tol_cert=1e-7)
+            ctx.descend(cls, psi64=psi64, start=sc["robot"], cap=cap, path=path, info=info)
+        torch.cuda.synchronize()
+        print(f"profiled {args.passes} replanning steps on {nx}x{ny}; last descent {info.tolist()}", flush=True)
         ctx.close()
         return 0
     if args.S and args.RH:
