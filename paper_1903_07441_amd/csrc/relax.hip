@@ -398,7 +398,7 @@ static dim3 resid_grid(int nx, int ny)
 {
     const int gx = (nx + 63) / 64;
     int gy = (ny + 3) / 4;
-    if (gy > 128) gy = 128;
+    if (gy > 64) gy = 64;
     const int cap = kResidBlocks / gx;
     if (gy > cap) gy = cap > 0 ? cap : 1;
     return dim3(gx, gy);
