@@ -187,23 +187,22 @@ struct Runner {
     // FP64 residual of an FP32 field: *out = max |r|, *rel = max |r| / |u|
     int residual32(const float *u, const float *f, double *out, double *rel = nullptr)
     {
-        int rc = launch_resid_f32(cls, u, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st);
-        if (!rc) rc = readback(2);
+        int rc = launch_resid_f32(cls, u, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, st);
+        if (!rc) rc = wait_words();
         if (rc) return set_err(ctx, rc, "residual kernel failed");
         *out = bits_to_double(ctx->host_words[0]);
         if (rel) *rel = bits_to_double(ctx->host_words[1]);
         return TWG_OK;
     }
 
-    int readback(int n)
+    // results a kernel wrote to ctx->host_words_dev
+    int wait_words()
     {
-        if (hipMemcpyAsync(ctx->host_words, ctx->words, n * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, st) != hipSuccess)
-            return TWG_EDEVICE;
         if (hipStreamSynchronize(st) != hipSuccess) return TWG_EDEVICE;
         ++checks;
         return TWG_OK;
     }
+
 
     // SOR factor maps for the streamed sweeps, built at most once per call
     // (the class map is fixed for the duration of a call) and omega; two
@@ -367,8 +366,8 @@ struct Runner {
     // FP64 residual of an FP64 field
     int residual64(const double *u, double *out)
     {
-        int rc = launch_resid_f64(cls, u, nullptr, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st);
-        if (!rc) rc = readback(2);
+        int rc = launch_resid_f64(cls, u, nullptr, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, st);
+        if (!rc) rc = wait_words();
         if (rc) return set_err(ctx, rc, "residual kernel failed");
         *out = bits_to_double(ctx->host_words[0]);
         return TWG_OK;
@@ -393,8 +392,8 @@ struct Runner {
         *rounds_out = 0;
         double r64 = 0.0, rate_dc = 0.0;
         for (int round = 0; round < 12; ++round) {
-            rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st);
-            if (!rc) rc = readback(1);
+            rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, st);
+            if (!rc) rc = wait_words();
             if (rc) return set_err(ctx, rc, "defect kernel failed");
             r64 = bits_to_double(ctx->host_words[0]);
             if (std::isnan(r64)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
@@ -502,6 +501,11 @@ int32_t twg_ctx_create(twg_ctx **out, int32_t device)
             hipSuccess) {
         twg_ctx_destroy(ctx);
         return TWG_ENOMEM;
+    }
+    if (hipHostGetDevicePointer(reinterpret_cast<void **>(&ctx->host_words_dev), ctx->host_words, 0) !=
+        hipSuccess) {
+        twg_ctx_destroy(ctx);
+        return TWG_EDEVICE;
     }
     *out = ctx;
     return TWG_OK;
@@ -1242,10 +1246,10 @@ int32_t hpf_residual(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *
     if (!cls || (!psi && !psi64) || !out) return set_err(ctx, TWG_EINVAL, "missing argument");
     hipSetDevice(ctx->device);
     hipStream_t st = as_stream(stream);
-    rc = psi64 ? launch_resid_f64(cls, psi64, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st)
-               : launch_resid_f32(cls, psi, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->words, st);
+    rc = psi64 ? launch_resid_f64(cls, psi64, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, st)
+               : launch_resid_f32(cls, psi, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, st);
     Runner run{ctx, g, cls, st};
-    if (!rc) rc = run.readback(1);
+    if (!rc) rc = run.wait_words();
     if (rc) return set_err(ctx, rc, "residual kernel failed");
     *out = bits_to_double(ctx->host_words[0]);
     return TWG_OK;

@@ -69,12 +69,17 @@ struct twg_ctx {
     size_t batch_bytes = 0;
     unsigned long long *batch_host = nullptr;  // pinned mirror of the per-grid words
     size_t batch_host_bytes = 0;
-    // small device words: residual maxima (uint64 bit patterns), counters
+    // small device words: counters of the rasteriser
     unsigned long long *words = nullptr;
     // per-block partial maxima of the residual kernels (2 kResidBlocks words)
     unsigned long long *rpart = nullptr;
-    // pinned host mirror of `words`
+    // pinned host words: residual maxima (uint64 bit patterns) of the last
+    // check
     unsigned long long *host_words = nullptr;
+    // the same pinned words as the device addresses them: the residual
+    // reductions write their results there directly, so a check needs no
+    // copy, only a wait for the stream
+    unsigned long long *host_words_dev = nullptr;
     // instantiated graphs of relaxation passes, keyed by their launch
     // arguments, and the stream they are captured on
     struct Graph {
