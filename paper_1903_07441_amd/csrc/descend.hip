@@ -35,22 +35,29 @@ __global__ void k_index(const uint8_t *__restrict__ cls, const T *__restrict__ u
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= nx || y >= ny) return;
     const size_t i = (size_t)y * pitch + x;
-    const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+    // every neighbour's class and value are loaded (clamped to the grid)
+    // before any is compared, so no load waits inside a divergent branch
+    const int xs[4] = {min(x + 1, nx - 1), max(x - 1, 0), x, x};
+    const int ys[4] = {y, y, min(y + 1, ny - 1), max(y - 1, 0)};
+    const bool inside[4] = {x + 1 < nx, x > 0, y + 1 < ny, y > 0};
+    uint8_t c[4];
+    T v[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const size_t k = (size_t)ys[d] * pitch + xs[d];
+        c[d] = cls[k];
+        v[d] = u[k];
+    }
+    const T self = u[i];
     int best = 4;
     T bv = T(0);
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        const int xx = x + dx[d], yy = y + dy[d];
-        if (xx < 0 || yy < 0 || xx >= nx || yy >= ny) continue;
-        const size_t k = (size_t)yy * pitch + xx;
-        if (!walkable(cls[k])) continue;
-        const T v = u[k];
-        if (best == 4 || v > bv) {
-            best = d;
-            bv = v;
-        }
+        const bool ok = inside[d] && walkable(c[d]) && (best == 4 || v[d] > bv);
+        best = ok ? d : best;
+        bv = ok ? v[d] : bv;
     }
-    if (best != 4 && !(bv > u[i])) best = 4;
+    if (best != 4 && !(bv > self)) best = 4;
     idx[i] = WALK && cls[i] == TWG_CELL_GOAL ? kGoalCode : (uint8_t)best;
 }
 
