@@ -57,26 +57,33 @@ __global__ __launch_bounds__(256) void k_resid(const uint8_t *__restrict__ cls,
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     double m = 0.0, mr = 0.0;
-    // the loads of a cell do not wait on its class (the class only selects
-    // the result), and four rows are in flight per thread
+    // every load of a cell is unconditional (neighbours clamped to the grid,
+    // then zeroed outside it; the class only selects the result), so none
+    // waits inside a divergent branch, and four rows are in flight per thread
+    if (x < nx) {
+        const int xe = min(x + 1, nx - 1), xw = max(x - 1, 0);
 #pragma unroll 4
-    for (int y = blockIdx.y * 4 + (threadIdx.x >> 6); y < ny; y += gridDim.y * 4) {
-        if (x >= nx) break;
-        const size_t i = (size_t)y * pitch + x;
-        const bool free_cell = cls[i] == TWG_CELL_FREE;
-        const double e = x + 1 < nx ? (double)u[i + 1] : 0.0;
-        const double w = x > 0 ? (double)u[i - 1] : 0.0;
-        const double s = y + 1 < ny ? (double)u[i + pitch] : 0.0;
-        const double n = y > 0 ? (double)u[i - pitch] : 0.0;
-        double g = ((e + w) + (s + n)) * 0.25;
-        if (RHS) g = g + (double)f[i];
-        const double c = (double)u[i];
-        const double r = free_cell ? g - c : 0.0;
-        const float ac = fabsf((float)c);
-        // diagnostic ratio: single-precision division is enough
-        if (free_cell && ac >= 1e-30f) mr = nanmax(mr, (double)(fabsf((float)r) / ac));
-        if (WRITE_R32) r32[i] = (float)r;
-        m = nanmax(m, fabs(r));
+        for (int y = blockIdx.y * 4 + (threadIdx.x >> 6); y < ny; y += gridDim.y * 4) {
+            const size_t row = (size_t)y * pitch, i = row + x;
+            const bool free_cell = cls[i] == TWG_CELL_FREE;
+            const double ue = (double)u[row + xe], uw = (double)u[row + xw];
+            const double us = (double)u[(size_t)min(y + 1, ny - 1) * pitch + x];
+            const double un = (double)u[(size_t)max(y - 1, 0) * pitch + x];
+            const double c = (double)u[i];
+            const double e = x + 1 < nx ? ue : 0.0;
+            const double w = x > 0 ? uw : 0.0;
+            const double s = y + 1 < ny ? us : 0.0;
+            const double n = y > 0 ? un : 0.0;
+            double g = ((e + w) + (s + n)) * 0.25;
+            if (RHS) g = g + (double)f[i];
+            const double r = free_cell ? g - c : 0.0;
+            const float ac = fabsf((float)c);
+            // diagnostic ratio: single-precision division is enough
+            const float q = fabsf((float)r) / ac;
+            mr = nanmax(mr, free_cell && ac >= 1e-30f ? (double)q : 0.0);
+            if (WRITE_R32) r32[i] = (float)r;
+            m = nanmax(m, fabs(r));
+        }
     }
     m = block_max(m);
     __syncthreads();
