@@ -137,18 +137,25 @@ __global__ __launch_bounds__(256) void k_resid_batch(const uint8_t *__restrict__
     const int x = bk.y * 64 + (threadIdx.x & 63);
     double m = 0.0, mr = 0.0;
     if (x < g.nx) {
+        // unconditional loads, as in k_resid
+        const int xe = min(x + 1, g.nx - 1), xw = max(x - 1, 0);
+#pragma unroll 4
         for (int y = threadIdx.x >> 6; y < g.ny; y += 4) {
-            const size_t i = (size_t)y * g.pitch + x;
-            if (c[i] != TWG_CELL_FREE) continue;
-            const double e = x + 1 < g.nx ? (double)v[i + 1] : 0.0;
-            const double w = x > 0 ? (double)v[i - 1] : 0.0;
-            const double s = y + 1 < g.ny ? (double)v[i + g.pitch] : 0.0;
-            const double n = y > 0 ? (double)v[i - g.pitch] : 0.0;
+            const size_t row = (size_t)y * g.pitch, i = row + x;
+            const bool free_cell = c[i] == TWG_CELL_FREE;
+            const double ue = (double)v[row + xe], uw = (double)v[row + xw];
+            const double us = (double)v[(size_t)min(y + 1, g.ny - 1) * g.pitch + x];
+            const double un = (double)v[(size_t)max(y - 1, 0) * g.pitch + x];
             const double cc = (double)v[i];
-            const double r = ((e + w) + (s + n)) * 0.25 - cc;
+            const double e = x + 1 < g.nx ? ue : 0.0;
+            const double w = x > 0 ? uw : 0.0;
+            const double s = y + 1 < g.ny ? us : 0.0;
+            const double n = y > 0 ? un : 0.0;
+            const double r = free_cell ? ((e + w) + (s + n)) * 0.25 - cc : 0.0;
             m = nanmax(m, fabs(r));
             const float ac = fabsf((float)cc);
-            if (ac >= 1e-30f) mr = nanmax(mr, (double)(fabsf((float)r) / ac));
+            const float q = fabsf((float)r) / ac;
+            mr = nanmax(mr, free_cell && ac >= 1e-30f ? (double)q : 0.0);
         }
     }
     m = block_max(m);
