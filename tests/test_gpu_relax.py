@@ -324,3 +324,34 @@ def test_autotune_factors_converge(orc):
         assert r * orc.wbound(nx, ny) <= 1e-7
     finally:
         ctx.close()
+
+
+def test_correction_start_phase_keeps_the_certified_field(orc):
+    # the correction solves' start phase (tuned) changes only how the polish
+    # gets there: with and without it (a caller's factor turns it off) the
+    # polish reaches the certificate, both fields lie within their certified
+    # bounds of each other, and the oracle's residual confirms each bound
+    from paper_1903_07441_amd import twg
+    ctx = twg.Context(0)
+    try:
+        sc = scenarios.scenario("warped512", 3)
+        cls, _ = orc.rasterize(sc)
+        c = to_dev(cls)
+        tune = ctx.autotune(c)
+        ny, nx = cls.shape
+        out = []
+        for omega in (0.0, tune["omega_dc"]):
+            psi = to_dev(np.zeros((ny, nx), np.float32))
+            psi64 = to_dev(np.zeros((ny, nx)), dtype=torch.float64)
+            ctx.relax(c, psi, None, tol=1e-6)
+            st = ctx.relax(c, psi, psi64, tol=1e-6, init=twg.INIT_KEEP, polish=1, tol_cert=1e-7, omega=omega)
+            torch.cuda.synchronize()
+            print(f"omega={omega}: lead {tune['lead_dc_omega']:.5f}/{tune['lead_dc_sweeps']} stats={st}", flush=True)
+            assert st["status"] == twg.OK and st["cert_bound"] <= 1e-7
+            f64 = psi64.cpu().numpy()
+            assert orc.residual(cls, f64) * orc.wbound(nx, ny) <= 1e-7
+            out.append((f64, st["cert_bound"]))
+        (a, ca), (b, cb) = out
+        assert np.max(np.abs(a - b)) <= ca + cb
+    finally:
+        ctx.close()
