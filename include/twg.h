@@ -269,7 +269,11 @@ typedef struct {
 /* hpf_relax_batched -- hpf_relax (FP32 phase) for n independent grids of any
  * sizes at once.  Every pass is ONE launch over the tiles of all grids still
  * above tolerance, and the FP64 residuals of all grids are reduced in one
- * launch; a grid drops out of the pass sequence as soon as it meets tol.  Grid k's class map and field start at element offset
+ * launch; a grid drops out of the pass sequence at the first residual check
+ * where it meets tol.  With params->check_passes = 0 the checks are placed at
+ * the latest predicted convergence whose overshoot (sweeps of grids predicted
+ * to converge earlier) stays within 5 % of the useful work, so a grid may sweep
+ * past its tolerance; its stats count those sweeps.  Grid k's class map and field start at element offset
  * grids[k].offset of cls and psi (the grids must not overlap).  Sweeps per
  * tile load and rows per tile come from the autotuned entry of the largest
  * grid (or params->sweeps_per_pass / rows_per_tile); each grid's SOR factor is params->omega, else its
