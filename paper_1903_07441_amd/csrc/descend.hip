@@ -5,8 +5,9 @@
 //            walkable neighbour with the highest psi (lowest phi), first one
 //            on ties; 4 when none is strictly higher than the cell itself.
 //   k_walk   one workgroup follows the index matrix from the start, reading
-//            walk codes (the index code, 5 on GOAL cells) from a 256 x 256
-//            LDS window around the current cell (see k_walk).
+//            the walk codes (the index code, 5 on GOAL cells), turned into
+//            in-window moves, from a 256 x 256 LDS window around the current
+//            cell (see k_walk).
 //   k_rubber one workgroup relaxes a path as a rubber band (Eqs. 4-6): per
 //            iteration the interior points of odd index, then those of even
 //            index, each move to the best of nine candidate cells given the
@@ -63,18 +64,35 @@ __global__ void k_index(const uint8_t *__restrict__ cls, const T *__restrict__ u
 
 constexpr int kTile = 256;
 
+// Four walk codes (one per byte) to four 16-bit moves: the byte offset of the
+// neighbour inside the 256-cell-wide LDS window (E +2, W -2, S +512, N -512),
+// 0 for the codes 4 (no move) and 5 (goal).  v_perm_b32 looks the low and the
+// high bytes up in two 4-byte tables (selectors 4 to 7 pick the zero word),
+// then interleaves them.
+__device__ __forceinline__ uint2 walk_moves(uint32_t codes)
+{
+    const uint32_t lo = __builtin_amdgcn_perm(0u, 0x0000fe02u, codes);
+    const uint32_t hi = __builtin_amdgcn_perm(0u, 0xfe02ff00u, codes);
+    return make_uint2(__builtin_amdgcn_perm(hi, lo, 0x05010400u), __builtin_amdgcn_perm(hi, lo, 0x07030602u));
+}
+
 // code: the walk codes of k_index<T, true> (direction, 4 = no move, 5 =
-// goal).  The 256 x 256 window of codes around the current cell is staged in
-// LDS by all 1024 threads (unconditional loads: cells outside the grid read
-// a clamped cell and become 4); one thread then walks inside the window,
-// one LDS byte per step (each step strictly raises psi, so the walk never
-// revisits a cell), and the window is re-centred when the walk leaves it.
+// goal).  The 256 x 256 window around the current cell is staged in LDS by
+// all 1024 threads as 16-bit moves (unconditional loads: cells outside the
+// grid read a clamped cell and become 4), with the window's border ring set
+// to 0 so that no move leaves it.  The first wave then walks with every lane
+// in step: per step one broadcast LDS read, a zero test and an add (each
+// step strictly raises psi, so the walk never revisits a cell); lane k keeps
+// the k-th cell of the current group of 64, stored in one coalesced write per
+// group.  A 0 move ends the group: its cell's code, read from memory, tells
+// the goal, a cell with no move, and the window's edge apart (at the edge the
+// step is taken and the window is re-centred on the new cell).
 __global__ __launch_bounds__(1024) void k_walk(const uint8_t *__restrict__ cls,
                                               const uint8_t *__restrict__ code, int nx, int ny,
                                               int pitch, int sx, int sy, int cap,
                                               int32_t *__restrict__ path, int32_t *__restrict__ info)
 {
-    __shared__ __align__(16) uint8_t tcode[kTile * kTile];
+    __shared__ __align__(16) uint16_t tmove[kTile * kTile];
     __shared__ int state[4];  // x, y, length, status (-1 = walking)
     if (threadIdx.x == 0) {
         const uint8_t c = cls[(size_t)sy * pitch + sx];
@@ -122,7 +140,13 @@ __global__ __launch_bounds__(1024) void k_walk(const uint8_t *__restrict__ cls,
                 v[r] = make_uint4(o[0], o[1], o[2], o[3]);
             }
 #pragma unroll
-            for (int r = 0; r < PER; ++r) reinterpret_cast<uint4 *>(tcode)[threadIdx.x + r * 1024] = v[r];
+            for (int r = 0; r < PER; ++r) {
+                const uint2 m0 = walk_moves(v[r].x), m1 = walk_moves(v[r].y);
+                const uint2 m2 = walk_moves(v[r].z), m3 = walk_moves(v[r].w);
+                uint4 *dst = reinterpret_cast<uint4 *>(tmove) + 2 * (threadIdx.x + r * 1024);
+                dst[0] = make_uint4(m0.x, m0.y, m1.x, m1.y);
+                dst[1] = make_uint4(m2.x, m2.y, m3.x, m3.y);
+            }
         } else if ((pitch & 3) == 0) {
             constexpr int PER = kTile * kTile / 4 / 1024;
             uint32_t v[PER];
@@ -141,56 +165,84 @@ __global__ __launch_bounds__(1024) void k_walk(const uint8_t *__restrict__ cls,
                 v[r] = o;
             }
 #pragma unroll
-            for (int r = 0; r < PER; ++r) reinterpret_cast<uint32_t *>(tcode)[threadIdx.x + r * 1024] = v[r];
+            for (int r = 0; r < PER; ++r)
+                reinterpret_cast<uint2 *>(tmove)[threadIdx.x + r * 1024] = walk_moves(v[r]);
         } else {
             constexpr int PER = kTile * kTile / 1024;
-            uint8_t v[PER];
+            uint32_t v[PER];
 #pragma unroll
             for (int r = 0; r < PER; ++r) {
                 const int k = threadIdx.x + r * 1024;
                 const int x = tx0 + (k & (kTile - 1)), y = ty0 + k / kTile;
                 const bool in = x >= 0 && y >= 0 && x < nx && y < ny;
                 const uint8_t d = code[(size_t)min(max(y, 0), ny - 1) * pitch + min(max(x, 0), nx - 1)];
-                v[r] = in ? d : (uint8_t)4;
+                v[r] = in ? d : 4u;
             }
 #pragma unroll
-            for (int r = 0; r < PER; ++r) tcode[threadIdx.x + r * 1024] = v[r];
+            for (int r = 0; r < PER; ++r) tmove[threadIdx.x + r * 1024] = (uint16_t)walk_moves(v[r]).x;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int x = state[0], y = state[1], n = state[2], st = -1;
-            // one window test and one exit test per step; the rare exits
-            // (goal, no move, full buffer) are sorted out after the loop
-            int d = 0;
+        {
+            // border ring: rows 0 and 255, columns 0 and 255 (1020 cells)
+            const int t = threadIdx.x, side = t >> 8, i = t & (kTile - 1);
+            const int cell = side == 0 ? i : side == 1 ? (kTile - 1) * kTile + i : side == 2 ? i * kTile
+                                                                                               : i * kTile + kTile - 1;
+            tmove[cell] = 0;
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            const int wx0 = __builtin_amdgcn_readfirstlane(tx0), wy0 = __builtin_amdgcn_readfirstlane(ty0);
+            int n = __builtin_amdgcn_readfirstlane(state[2]);
+            // byte offset of the current cell in the window
+            int a = 2 * ((__builtin_amdgcn_readfirstlane(state[1]) - wy0) * kTile +
+                         (__builtin_amdgcn_readfirstlane(state[0]) - wx0));
+            const char *moves = reinterpret_cast<const char *>(tmove);
             for (;;) {
-                const unsigned lx = (unsigned)(x - tx0), ly = (unsigned)(y - ty0);
-                if ((lx | ly) >= (unsigned)kTile) break;
-                d = tcode[ly * kTile + lx];
-                if (d >= 4 || n >= cap) break;
-                // E, W, S, N by arithmetic: a table indexed by d would be a
-                // scalar memory load, and its latency, on every step
+                const int lim = min(64, cap - n);
+                int k = 0, rec = 0;
+                int m = *reinterpret_cast<const int16_t *>(moves + a);
+                while (m != 0 && k < lim) {
+                    a += m;
+                    rec = lane == k ? a : rec;
+                    ++k;
+                    m = *reinterpret_cast<const int16_t *>(moves + a);
+                }
+                if (lane < k) {
+                    path[2 * (n + lane)] = wx0 + ((rec >> 1) & (kTile - 1));
+                    path[2 * (n + lane) + 1] = wy0 + (rec >> 9);
+                }
+                n += k;
+                if (k < 64) break;
+            }
+            int x = wx0 + ((a >> 1) & (kTile - 1)), y = wy0 + (a >> 9);
+            const int d = code[(size_t)min(max(y, 0), ny - 1) * pitch + min(max(x, 0), nx - 1)];
+            int st = -1;
+            if (d == kGoalCode) {
+                st = TWG_OK;
+            } else if (d >= 4) {
+                st = TWG_NO_PATH;
+            } else {
+                // the buffer is full (the step that did not fit is taken, not
+                // stored), or the step leaves the window: take it here
                 x += d < 2 ? 1 - 2 * d : 0;
                 y += d < 2 ? 0 : 5 - 2 * d;
-                path[2 * n] = x;
-                path[2 * n + 1] = y;
-                ++n;
-            }
-            const unsigned lx = (unsigned)(x - tx0), ly = (unsigned)(y - ty0);
-            if ((lx | ly) < (unsigned)kTile) {
-                if (d == kGoalCode) {
-                    st = TWG_OK;
-                } else if (d == 4) {
-                    st = TWG_NO_PATH;
-                } else {  // n == cap: the step that did not fit is taken, not stored
-                    x += d < 2 ? 1 - 2 * d : 0;
-                    y += d < 2 ? 0 : 5 - 2 * d;
+                if (n >= cap) {
                     st = TWG_PATH_TRUNCATED;
+                } else {
+                    if (lane == 0) {
+                        path[2 * n] = x;
+                        path[2 * n + 1] = y;
+                    }
+                    ++n;
                 }
             }
-            state[0] = x;
-            state[1] = y;
-            state[2] = n;
-            state[3] = st;
+            if (lane == 0) {
+                state[0] = x;
+                state[1] = y;
+                state[2] = n;
+                state[3] = st;
+            }
         }
         __syncthreads();
     }

@@ -56,6 +56,13 @@ def test_descent_2048_reaches_goal(ctx, orc, pitch_pad):
     np.testing.assert_array_equal(p_gpu, p_orc)
     print(f"2048 descent status={s_gpu} length={len(p_gpu)} reachable={orc.goal_reachable(cls, sc['robot'])}",
           flush=True)
+    # buffers that fill on either side of the walk's 64-cell store groups, or
+    # exactly at the goal: a truncated path is the full path's prefix
+    n = len(p_gpu)
+    for cap in (63, 64, 65, 128, n - 1, n):
+        s_cap, p_cap = gpu_descend(ctx, c, t, sc["robot"], cap=cap, use64=True)
+        np.testing.assert_array_equal(p_cap, p_gpu[:cap])
+        assert s_cap == (s_gpu if cap >= n else 5)
 
 
 def test_descent_outcomes(ctx, orc):
