@@ -213,7 +213,7 @@ def main():
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def per_launch(fn, passes):
-        fn(4)  # warm-up (captures the replayed graphs)
+        fn(passes)  # warm-up: as many passes, so the replayed graphs are captured before the timing
         e0.record()
         fn(passes)
         e1.record()

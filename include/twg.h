@@ -83,7 +83,7 @@ int32_t twg_ctx_destroy(twg_ctx *ctx);
  * string belongs to ctx and is valid until its next call. */
 const char *twg_last_error(const twg_ctx *ctx);
 
-/* enable = 1 (default): runs of 16 relaxation passes are captured once into a
+/* enable = 1 (default): runs of 64 relaxation passes are captured once into a
  * HIP graph (on a context-owned stream) and replayed on the caller's stream;
  * enable = 0: every pass is launched on its own.  Results are identical.
  * Errors: TWG_EINVAL for another value. */

@@ -52,7 +52,11 @@ using namespace twg;
 
 namespace {
 
-constexpr int kGraphPasses = 16;  // passes per captured graph (even: ping-pong ends where it began)
+// passes per captured graph (even: the ping-pong ends where it began).  The
+// GPU idles about 8 us between two graph launches but not between two plain
+// kernel launches, so the graphs are long enough to make that idle time small
+// (under 1 % of 64 passes at 2048 x 2048).
+constexpr int kGraphPasses = 64;
 // A solve counts as stalled (at its rounding floor) after three checks
 // without a 10 % gain on its best residual that together span at least this
 // many sweeps; at a useful SOR factor a 10 % gain takes tens of sweeps.

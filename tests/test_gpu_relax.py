@@ -257,14 +257,14 @@ def test_fp64_sweep_bit_exact_vs_oracle(ctx, orc, nx, ny, pitch, S):
 
 @pytest.mark.parametrize("S", [2, 4, 8])
 def test_graph_replay_equals_eager(ctx, S):
-    """Runs of 16 passes replayed from a captured graph give the bits of one
+    """Runs of 64 passes replayed from a captured graph give the bits of one
     launch per colour; the cached graph is replayed again after eager work."""
     rng = np.random.default_rng(100 + S)
     nx, ny, pitch = 300, 211, 320
     cls = random_classes(rng, nx, ny, walls=True, fixed=0.02)
     psi0 = rng.uniform(size=(ny, nx)).astype(np.float32)
     c = to_dev(cls, pitch)
-    sweeps = 3 * 16 * S + 5
+    sweeps = 3 * 64 * S + 5
     print(f"graph-vs-eager S={S} sweeps={sweeps}", flush=True)
     ref = to_dev(psi0, pitch)
     ctx.sweeps(c, ref, 1.9, sweeps, tiled=False)
