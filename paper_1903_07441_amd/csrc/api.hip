@@ -2,6 +2,7 @@
 // convergence control of the relaxation.  The arithmetic runs in the kernels
 // of raster.hip, relax.hip and descend.hip.
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -191,7 +192,7 @@ struct Runner {
     // FP64 residual of an FP32 field: *out = max |r|, *rel = max |r| / |u|
     int residual32(const float *u, const float *f, double *out, double *rel = nullptr)
     {
-        int rc = launch_resid_f32(cls, u, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, st);
+        int rc = launch_resid_f32(cls, u, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, ++ctx->word_seq, st);
         if (!rc) rc = wait_words();
         if (rc) return set_err(ctx, rc, "residual kernel failed");
         *out = bits_to_double(ctx->host_words[0]);
@@ -199,10 +200,22 @@ struct Runner {
         return TWG_OK;
     }
 
-    // results a kernel wrote to ctx->host_words_dev
+    // results the last residual reduction wrote to ctx->host_words_dev: poll
+    // its sequence number in the pinned word 2 (the host sees it a few
+    // microseconds before a stream synchronisation would return), asking the
+    // stream every 1024 polls whether it failed, or finished without writing
+    // the word (then the check fails)
     int wait_words()
     {
-        if (hipStreamSynchronize(st) != hipSuccess) return TWG_EDEVICE;
+        const volatile unsigned long long *w = ctx->host_words;
+        const unsigned long long seq = ctx->word_seq;
+        for (unsigned k = 1; w[2] != seq; ++k) {
+            if (k % 1024) continue;
+            const hipError_t e = hipStreamQuery(st);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess || w[2] != seq) return TWG_EDEVICE;
+        }
+        std::atomic_thread_fence(std::memory_order_acquire);
         ++checks;
         return TWG_OK;
     }
@@ -370,7 +383,7 @@ struct Runner {
     // FP64 residual of an FP64 field
     int residual64(const double *u, double *out)
     {
-        int rc = launch_resid_f64(cls, u, nullptr, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, st);
+        int rc = launch_resid_f64(cls, u, nullptr, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, ++ctx->word_seq, st);
         if (!rc) rc = wait_words();
         if (rc) return set_err(ctx, rc, "residual kernel failed");
         *out = bits_to_double(ctx->host_words[0]);
@@ -396,7 +409,7 @@ struct Runner {
         *rounds_out = 0;
         double r64 = 0.0, rate_dc = 0.0;
         for (int round = 0; round < 12; ++round) {
-            rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, st);
+            rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, ++ctx->word_seq, st);
             if (!rc) rc = wait_words();
             if (rc) return set_err(ctx, rc, "defect kernel failed");
             r64 = bits_to_double(ctx->host_words[0]);
@@ -506,6 +519,7 @@ int32_t twg_ctx_create(twg_ctx **out, int32_t device)
         twg_ctx_destroy(ctx);
         return TWG_ENOMEM;
     }
+    std::memset(ctx->host_words, 0, kWords * sizeof(unsigned long long));
     if (hipHostGetDevicePointer(reinterpret_cast<void **>(&ctx->host_words_dev), ctx->host_words, 0) !=
         hipSuccess) {
         twg_ctx_destroy(ctx);
@@ -1250,8 +1264,8 @@ int32_t hpf_residual(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const float *
     if (!cls || (!psi && !psi64) || !out) return set_err(ctx, TWG_EINVAL, "missing argument");
     hipSetDevice(ctx->device);
     hipStream_t st = as_stream(stream);
-    rc = psi64 ? launch_resid_f64(cls, psi64, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, st)
-               : launch_resid_f32(cls, psi, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, st);
+    rc = psi64 ? launch_resid_f64(cls, psi64, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, ++ctx->word_seq, st)
+               : launch_resid_f32(cls, psi, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, ++ctx->word_seq, st);
     Runner run{ctx, g, cls, st};
     if (!rc) rc = run.wait_words();
     if (rc) return set_err(ctx, rc, "residual kernel failed");

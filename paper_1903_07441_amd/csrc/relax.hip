@@ -96,9 +96,10 @@ __global__ __launch_bounds__(256) void k_resid(const uint8_t *__restrict__ cls,
 }
 
 // out[0], out[1] = maxima of the n block partials (bit patterns of
-// non-negative doubles, or NaN patterns, which compare larger)
+// non-negative doubles, or NaN patterns, which compare larger); then, after
+// a system-scope fence, out[2] = seq
 __global__ __launch_bounds__(256) void k_resid_reduce(const unsigned long long *__restrict__ part, int n,
-                                                      unsigned long long *out)
+                                                      unsigned long long *out, unsigned long long seq)
 {
     __shared__ unsigned long long red[2][256];
     unsigned long long a = 0, b = 0;
@@ -119,6 +120,8 @@ __global__ __launch_bounds__(256) void k_resid_reduce(const unsigned long long *
     if (threadIdx.x == 0) {
         out[0] = red[0][0];
         out[1] = red[1][0];
+        __threadfence_system();
+        out[2] = seq;
     }
 }
 
@@ -418,14 +421,15 @@ static dim3 resid_grid(int nx, int ny)
     return dim3(gx, gy);
 }
 
-static int finish_resid(const dim3 &g, const unsigned long long *part, unsigned long long *out, hipStream_t st)
+static int finish_resid(const dim3 &g, const unsigned long long *part, unsigned long long *out,
+                        unsigned long long seq, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_resid_reduce, dim3(1), dim3(256), 0, st, part, (int)(g.x * g.y), out);
+    hipLaunchKernelGGL(k_resid_reduce, dim3(1), dim3(256), 0, st, part, (int)(g.x * g.y), out, seq);
     return last_status();
 }
 
 int launch_resid_f32(const uint8_t *cls, const float *u, const float *f, int nx, int ny, int pitch,
-                     unsigned long long *part, unsigned long long *out, hipStream_t st)
+                     unsigned long long *part, unsigned long long *out, unsigned long long seq, hipStream_t st)
 {
     const dim3 g = resid_grid(nx, ny);
     if (f)
@@ -434,11 +438,11 @@ int launch_resid_f32(const uint8_t *cls, const float *u, const float *f, int nx,
     else
         hipLaunchKernelGGL((k_resid<float, false, false>), g, dim3(256), 0, st, cls, u, f, nullptr, nx, ny,
                            pitch, part);
-    return finish_resid(g, part, out, st);
+    return finish_resid(g, part, out, seq, st);
 }
 
 int launch_resid_f64(const uint8_t *cls, const double *u, const float *f, int nx, int ny, int pitch,
-                     unsigned long long *part, unsigned long long *out, hipStream_t st)
+                     unsigned long long *part, unsigned long long *out, unsigned long long seq, hipStream_t st)
 {
     const dim3 g = resid_grid(nx, ny);
     if (f)
@@ -447,16 +451,16 @@ int launch_resid_f64(const uint8_t *cls, const double *u, const float *f, int nx
     else
         hipLaunchKernelGGL((k_resid<double, false, false>), g, dim3(256), 0, st, cls, u, f, nullptr, nx, ny,
                            pitch, part);
-    return finish_resid(g, part, out, st);
+    return finish_resid(g, part, out, seq, st);
 }
 
 int launch_defect64(const uint8_t *cls, const double *u, float *r32, int nx, int ny, int pitch,
-                    unsigned long long *part, unsigned long long *out, hipStream_t st)
+                    unsigned long long *part, unsigned long long *out, unsigned long long seq, hipStream_t st)
 {
     const dim3 g = resid_grid(nx, ny);
     hipLaunchKernelGGL((k_resid<double, false, true>), g, dim3(256), 0, st, cls, u, nullptr, r32, nx, ny, pitch,
                        part);
-    return finish_resid(g, part, out, st);
+    return finish_resid(g, part, out, seq, st);
 }
 
 int launch_update64(const uint8_t *cls, double *u, const float *e, float *psi, int nx, int ny,

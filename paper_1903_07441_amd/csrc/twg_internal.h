@@ -74,12 +74,15 @@ struct twg_ctx {
     // per-block partial maxima of the residual kernels (2 kResidBlocks words)
     unsigned long long *rpart = nullptr;
     // pinned host words: residual maxima (uint64 bit patterns) of the last
-    // check
+    // check in words 0 and 1, and in word 2 the sequence number of the
+    // reduction that wrote them
     unsigned long long *host_words = nullptr;
     // the same pinned words as the device addresses them: the residual
     // reductions write their results there directly, so a check needs no
-    // copy, only a wait for the stream
+    // copy, only a wait for word 2 to show the last sequence number
     unsigned long long *host_words_dev = nullptr;
+    // sequence number of the last residual reduction launched
+    unsigned long long word_seq = 0;
     // instantiated graphs of relaxation passes, keyed by their launch
     // arguments, and the stream they are captured on
     struct Graph {
@@ -155,14 +158,16 @@ int launch_fmask(const uint8_t *cls, uint8_t *fmask, int nx, int ny, int pitch, 
 int launch_fmask_batch(const uint8_t *cls, uint8_t *fmask, const BatchGrid *grids, const int2 *blocks,
                        int n_blocks, hipStream_t st);
 // residual reductions: part = the context's block partials (2 kResidBlocks
-// words), out = 2 words receiving max |r| and max |r| / |u|
+// words), out = 3 words receiving max |r| and max |r| / |u|, then seq (after
+// a system-scope fence, so a host that sees seq in out[2] reads final
+// maxima)
 constexpr int kResidBlocks = 4096;
 int launch_resid_f32(const uint8_t *cls, const float *u, const float *f, int nx, int ny, int pitch,
-                     unsigned long long *part, unsigned long long *out, hipStream_t st);
+                     unsigned long long *part, unsigned long long *out, unsigned long long seq, hipStream_t st);
 int launch_resid_f64(const uint8_t *cls, const double *u, const float *f, int nx, int ny, int pitch,
-                     unsigned long long *part, unsigned long long *out, hipStream_t st);
+                     unsigned long long *part, unsigned long long *out, unsigned long long seq, hipStream_t st);
 int launch_defect64(const uint8_t *cls, const double *u, float *r32, int nx, int ny, int pitch,
-                    unsigned long long *part, unsigned long long *out, hipStream_t st);
+                    unsigned long long *part, unsigned long long *out, unsigned long long seq, hipStream_t st);
 int launch_update64(const uint8_t *cls, double *u, const float *e, float *psi, int nx, int ny,
                     int pitch, hipStream_t st);
 int launch_widen(const float *psi, double *u, int nx, int ny, int pitch, hipStream_t st);
