@@ -394,25 +394,35 @@ struct Runner {
     // psi64 in FP64, solve (I - J) e = r in FP32 from e = 0 (e = 0 on fixed
     // cells) with factor omega_dc, psi64 += e (psi receives the rounded
     // field), until the FP64 residual is <= need or 12 rounds.
+    // r_first >= 0: start_dc has widened psi and computed its defect, whose
+    // FP64 residual is r_first, and psi has not changed since
     int polish_dc(float *psi, double *psi64, float omega_dc, double need, int S, int RH, int64_t max_sweeps,
-                  int64_t *sweeps_out, int32_t *rounds_out, double *res_out, bool *done, StartPhase lead = {})
+                  int64_t *sweeps_out, int32_t *rounds_out, double *res_out, bool *done, StartPhase lead = {},
+                  double r_first = -1.0)
     {
         const size_t n32 = (size_t)g.pitch * g.ny;
         int rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n32 * sizeof(float));
         if (rc) return rc;
         float *r32 = reinterpret_cast<float *>(ctx->pol);
         float *e = r32 + n32;
-        rc = launch_widen(psi, psi64, g.nx, g.ny, g.pitch, st);
-        if (rc) return set_err(ctx, rc, "widen launch failed");
+        if (r_first < 0.0) {
+            rc = launch_widen(psi, psi64, g.nx, g.ny, g.pitch, st);
+            if (rc) return set_err(ctx, rc, "widen launch failed");
+        }
         *done = false;
         *sweeps_out = 0;
         *rounds_out = 0;
         double r64 = 0.0, rate_dc = 0.0;
         for (int round = 0; round < 12; ++round) {
-            rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, ++ctx->word_seq, st);
-            if (!rc) rc = wait_words();
-            if (rc) return set_err(ctx, rc, "defect kernel failed");
-            r64 = bits_to_double(ctx->host_words[0]);
+            if (round == 0 && r_first >= 0.0) {
+                r64 = r_first;
+            } else {
+                rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev,
+                                     ++ctx->word_seq, st);
+                if (!rc) rc = wait_words();
+                if (rc) return set_err(ctx, rc, "defect kernel failed");
+                r64 = bits_to_double(ctx->host_words[0]);
+            }
             if (std::isnan(r64)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
             if (r64 <= need) { *done = true; break; }
             rc = launch_fill_f32(e, 0.0f, g.nx, g.ny, g.pitch, st);
@@ -436,6 +446,27 @@ struct Runner {
             *rounds_out = round + 1;
         }
         *res_out = r64;
+        return TWG_OK;
+    }
+
+    // The polish's first step on its own: psi64 = psi widened, its FP64
+    // defect into the polish's buffer, *r = its max |r| and *rel = max |r| /
+    // |u|.  The widened field holds psi's values exactly and the FP32 and
+    // FP64 residual kernels evaluate the same FP64 expression, so these are
+    // also psi's residuals.
+    int start_dc(const float *psi, double *psi64, double *r, double *rel)
+    {
+        const size_t n32 = (size_t)g.pitch * g.ny;
+        int rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n32 * sizeof(float));
+        if (rc) return rc;
+        rc = launch_widen(psi, psi64, g.nx, g.ny, g.pitch, st);
+        if (!rc)
+            rc = launch_defect64(cls, psi64, reinterpret_cast<float *>(ctx->pol), g.nx, g.ny, g.pitch, ctx->rpart,
+                                 ctx->host_words_dev, ++ctx->word_seq, st);
+        if (!rc) rc = wait_words();
+        if (rc) return set_err(ctx, rc, "defect kernel failed");
+        *r = bits_to_double(ctx->host_words[0]);
+        *rel = bits_to_double(ctx->host_words[1]);
         return TWG_OK;
     }
 
@@ -632,10 +663,22 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
 
     rc = launch_field_init(cls, psi, g.nx, g.ny, g.pitch, p.init, st);
     if (rc) return set_err(ctx, rc, "init launch failed");
+    // a kept field that the defect correction follows: the correction's
+    // first FP64 defect also gives the FP32 stage its starting residual, so
+    // a field already at tol costs one check, not two
+    double r_first = -1.0, rel_first = 0.0;
+    if (p.polish == 1 && p.init == HPF_INIT_KEEP) {
+        rc = run.start_dc(psi, psi64, &r_first, &rel_first);
+        if (rc) return rc;
+    }
     bool conv = false;
     rc = run.solve32(psi, nullptr, omega, S, RH, p.tol, p.max_sweeps, p.check_passes, &s.sweeps,
-                     &s.residual32, &conv, &s.residual_rel);
+                     &s.residual32, &conv, &s.residual_rel, {}, r_first);
     if (rc) return rc;
+    // the FP32 stage swept nothing: the correction starts from the defect
+    // already computed
+    const bool dc_ready = r_first >= 0.0 && s.sweeps == 0;
+    if (dc_ready) s.residual_rel = rel_first;
     s.residual = s.residual32;
     s.status = conv ? TWG_OK : TWG_NOT_CONVERGED;
 
@@ -667,7 +710,7 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
         const double need = p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / wb) : p.tol;
         bool done = false;
         rc = run.polish_dc(psi, psi64, omega_dc, need, S, RH, p.max_sweeps, &s.polish_sweeps, &s.polish_rounds,
-                           &s.residual, &done, lead_dc);
+                           &s.residual, &done, lead_dc, dc_ready ? r_first : -1.0);
         if (rc) return rc;
         s.status = done ? TWG_OK : TWG_NOT_CONVERGED;
         hipStreamSynchronize(st);

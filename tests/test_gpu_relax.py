@@ -148,6 +148,31 @@ def test_relax_fp32_only_reaches_tolerance(ctx, orc):
     assert r <= 1e-6 and abs(r - st["residual"]) <= 1e-12
 
 
+def test_kept_field_polish_starts_from_its_fp64_defect(ctx, orc):
+    """A kept field already at tol, then the defect correction: the FP32
+    stage sweeps nothing and reports the residual the FP32 residual kernel
+    gives for that field, bit for bit (the correction's first FP64 defect
+    is the same number), and the correction still certifies the result."""
+    from paper_1903_07441_amd import twg
+    sc = scenarios.scenario("warped512", 0)
+    cls, _ = orc.rasterize(sc)
+    ny, nx = cls.shape
+    c = to_dev(cls)
+    psi = to_dev(np.zeros((ny, nx), np.float32))
+    psi64 = to_dev(np.zeros((ny, nx)), dtype=torch.float64)
+    ctx.relax(c, psi, None, tol=1e-6)
+    r32 = ctx.residual(c, psi=psi)
+    kept = psi.cpu().numpy()
+    st = ctx.relax(c, psi, psi64, tol=1e-6, init=twg.INIT_KEEP, polish=1, tol_cert=5e-7)
+    torch.cuda.synchronize()
+    print(f"kept-field polish stats={st}", flush=True)
+    assert st["sweeps"] == 0 and st["residual32"] == r32 and st["residual_rel"] > 0
+    # the same residual recomputed by the oracle from the kept FP32 field
+    assert abs(orc.residual(cls, kept.astype(np.float64)) - r32) <= 1e-12 * r32
+    assert st["status"] == 0 and st["polish_sweeps"] > 0
+    assert orc.residual(cls, psi64.cpu().numpy()) * orc.wbound(nx, ny) <= 5e-7
+
+
 def test_relax_full_size_2048_certified(ctx, orc):
     # 2048 x 2048 time-warped field: the certificate |psi - psi*| <= r * wbound
     # (maximum principle, any size) with r recomputed in FP64 by the oracle
