@@ -185,9 +185,11 @@ int32_t twg_kalman_step(twg_ctx *ctx, int32_t n, double *x, double *P, const dou
 /* Harmonic potential                                                        */
 /* ========================================================================= */
 
-#define HPF_INIT_KEEP 0 /* free cells keep the values in psi */
-#define HPF_INIT_HALF 1 /* free cells start at phi = psi = 0.5 (the paper's choice) */
-#define HPF_INIT_ZERO 2 /* free cells start at psi = 0 (phi = 1) */
+#define HPF_INIT_KEEP 0   /* free cells keep the values in psi */
+#define HPF_INIT_HALF 1   /* free cells start at phi = psi = 0.5 (the paper's choice) */
+#define HPF_INIT_ZERO 2   /* free cells start at psi = 0 (phi = 1) */
+#define HPF_INIT_LINEAR 3 /* free cells start on the ramp psi = 1 - d / (max(nx, ny) sqrt 2), d the
+                             Euclidean distance to the goal cell (goal_x, goal_y), in FP64 rounded once */
 
 typedef struct {
     double tol;              /* stop when max over FREE cells of |avg4(psi) - psi|,
@@ -203,6 +205,7 @@ typedef struct {
     int32_t sweeps_per_pass; /* red-black sweeps per tile load (1, 2, 3, 4, 6, 8); 0 = tuned */
     int32_t check_passes;    /* passes between residual checks; 0 = adaptive */
     int32_t rows_per_tile;   /* output rows per tile (even, >= 2); 0 = tuned */
+    int32_t goal_x, goal_y;  /* goal cell of HPF_INIT_LINEAR (else unused) */
 } hpf_params;
 
 typedef struct {
@@ -215,7 +218,7 @@ typedef struct {
     float omega;           /* SOR factor used */
     int32_t status;        /* TWG_OK or TWG_NOT_CONVERGED */
     int32_t polish_rounds; /* defect-correction rounds */
-    int32_t checks;        /* residual read-backs */
+    int32_t checks;        /* residual evaluations (fused checks and defects) */
     double residual_rel;   /* max |r| / |psi| over FREE cells with |psi| >= 1e-30 (FP32 phase);
                               far from the goal this stays large in FP32, whose rounding
                               noise there exceeds the field itself */
@@ -247,18 +250,48 @@ typedef struct {
  * open with a start phase: a few passes at a smaller tuned factor (counted
  * in polish_sweeps).
  *
+ * Convergence is decided on the device (polish 0 and 1): the passes that
+ * check measure the residual of their input field as they stream it, and the
+ * last workgroup of each launch applies the stop rules (tolerance, sweep
+ * budget, a stall at the FP32 rounding floor) and picks the next check from
+ * the measured contraction; a solve that ends at a check returns the field
+ * that check measured.  The sweep budget counts whole passes (max_sweeps is
+ * rounded up to a multiple of the sweeps per pass).  The host only keeps
+ * enough launches queued (it reads the device's decisions from pinned
+ * memory and never waits for a residual).  polish = 2 runs the FP64 sweeps
+ * with host-side checks.
+ *
  *   cls    uint8 class map (device, pitch g.pitch).
  *   psi    in/out FP32 field (device, pitch g.pitch): FIXED cells must hold their
  *          values; with HPF_INIT_KEEP the FREE cells hold the initial field.
- *   psi64  FP64 field (device, pitch g.pitch) written when polish = 1; may be
+ *   psi64  FP64 field (device, pitch g.pitch) written when polish != 0; may be
  *          NULL when polish = 0.
  *   stats  host pointer or NULL.
- * Blocking: returns after the field is final (it reads residuals back).
+ * Blocking: returns when the field is final.  Not for two streams at once on
+ * one context (the control block and scratch belong to the context).
  * Returns TWG_OK or TWG_NOT_CONVERGED; errors TWG_EINVAL (bad grid, NULL
  * arrays, tol <= 0, omega outside [0, 2), polish without psi64, bad
- * sweeps_per_pass), TWG_ENOMEM, TWG_EDEVICE. */
+ * sweeps_per_pass, HPF_INIT_LINEAR with the goal outside the grid, a
+ * non-finite value in the field), TWG_ENOMEM, TWG_EDEVICE. */
 int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, double *psi64,
                   const hpf_params *params, hpf_stats *stats, void *stream);
+
+/* hpf_relax_async -- hpf_relax (polish 0 or 1) with nothing done on the
+ * host after the arguments are checked: field initialisation, then exactly
+ * `slots` launches of the device-driven relaxation and one final launch, all
+ * enqueued on `stream`, which a caller may capture into a graph.  Each
+ * launch does one step the device decides (a pass of S sweeps, a defect, an
+ * update); launches after the end return at once, and the final one ends a
+ * solve still running (status TWG_NOT_CONVERGED, with the latest field).  A
+ * solve of P FP32 passes and R polish rounds of C_r correction passes takes
+ * P + 1 + sum_r (C_r + 2) + 1 slots.  stats is a DEVICE hpf_stats written
+ * when the solve ends (status TWG_OK, TWG_NOT_CONVERGED or TWG_EINVAL for a
+ * non-finite value); it is valid once the stream has passed the launches.
+ * Scratch is allocated at the first call of a grid size: make that call
+ * outside capture.  Returns TWG_OK when enqueued; errors as hpf_relax, and
+ * TWG_EINVAL for slots < 1 or NULL stats, TWG_EUNSUPPORTED for polish = 2. */
+int32_t hpf_relax_async(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, double *psi64,
+                        const hpf_params *params, int32_t slots, hpf_stats *stats, void *stream);
 
 typedef struct {
     int32_t nx, ny, pitch; /* as twg_grid */
@@ -286,8 +319,10 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
 
 /* hpf_init_field -- the initial field of hpf_relax without relaxing: OBST
  * and WALL cells 0, GOAL 1, FIXED unchanged, FREE cells by `init`
- * (HPF_INIT_*; KEEP leaves them).  Asynchronous.  Errors: TWG_EINVAL. */
-int32_t hpf_init_field(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, int32_t init, void *stream);
+ * (HPF_INIT_*; KEEP leaves them; LINEAR uses the goal cell (goal_x, goal_y),
+ * ignored otherwise).  Asynchronous.  Errors: TWG_EINVAL. */
+int32_t hpf_init_field(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, int32_t init, int32_t goal_x,
+                       int32_t goal_y, void *stream);
 
 /* hpf_merge_previous -- warm start of a replanning step from the previous
  * step's field: every cell that is FREE in cls and was FREE in cls_prev takes

@@ -62,7 +62,7 @@ def _load():
                                           p, p, p, p, p, p]),
         "orc_rasterize_perobs": (None, [i32, i32, i32, i32, i32, i32, i32, f64, i32, i32,
                                         p, p, p, p, p, p]),
-        "orc_field_init": (None, [i32, i32, p, p, i32]),
+        "orc_field_init": (None, [i32, i32, p, p, i32, i32, i32]),
         "orc_residual": (f64, [i32, i32, p, p, p]),
         "orc_residual_field": (None, [i32, i32, p, p, p, p]),
         "orc_sor_sweep": (None, [i32, i32, p, p, p, f64]),
@@ -174,14 +174,15 @@ def rasterize(sc, method="perobs", static_occ=None, border_walls=True):
 # Field
 # --------------------------------------------------------------------------
 
-INIT_KEEP, INIT_HALF, INIT_ZERO = 0, 1, 2
+INIT_KEEP, INIT_HALF, INIT_ZERO, INIT_LINEAR = 0, 1, 2, 3
 
 
-def field_init(cls, psi=None, mode=INIT_HALF):
+def field_init(cls, psi=None, mode=INIT_HALF, goal=(0, 0)):
+    """Initial field (goal: the goal cell (x, y) of INIT_LINEAR)."""
     cls = _u8(cls)
     ny, nx = cls.shape
     out = np.zeros((ny, nx)) if psi is None else _f64(psi).copy()
-    _load().orc_field_init(nx, ny, _ptr(cls), _ptr(out), int(mode))
+    _load().orc_field_init(nx, ny, _ptr(cls), _ptr(out), int(mode), int(goal[0]), int(goal[1]))
     return out
 
 
@@ -240,14 +241,14 @@ def omega_open(nx, ny) -> float:
 
 
 def relax(cls, psi=None, init=INIT_HALF, omega=None, tol=1e-9, tol_cert=0.0,
-          max_sweeps=10_000_000, check_every=10, f=None):
+          max_sweeps=10_000_000, check_every=10, f=None, goal=(0, 0)):
     """Red-black SOR in FP64 until ||r||inf <= tol and r * wbound <= tol_cert.
 
     Returns (psi, info) with info = dict(status, sweeps, residual, bound).
     """
     cls = _u8(cls)
     ny, nx = cls.shape
-    out = field_init(cls, psi, init)
+    out = field_init(cls, psi, init, goal)
     if omega is None:
         omega = omega_open(nx, ny)
     fa = None if f is None else _f64(f)

@@ -464,21 +464,31 @@ static inline double avg4(const double *a, int32_t nx, int32_t ny, int32_t x, in
 
 /* Dirichlet values: goal phi = 0 (psi = 1), obstacle and wall phi = 1
  * (psi = 0), FIXED cells keep the caller's value.  Free cells: mode 0 keeps
- * the input, 1 sets phi = 0.5 (the paper's initial value), 2 sets psi = 0. */
-void orc_field_init(int32_t nx, int32_t ny, const uint8_t *cls, double *psi, int32_t mode)
+ * the input, 1 sets phi = 0.5 (the paper's initial value), 2 sets psi = 0,
+ * 3 a linear ramp in the distance to the goal cell (gx, gy): psi = 1 - d /
+ * (max(nx, ny) sqrt 2), d = sqrt(dx^2 + dy^2) (a starting field that falls
+ * from the goal's value; max(nx, ny) sqrt 2 bounds any distance on the grid). */
+void orc_field_init(int32_t nx, int32_t ny, const uint8_t *cls, double *psi, int32_t mode,
+                    int32_t gx, int32_t gy)
 {
-    size_t n = (size_t)nx * ny;
-    for (size_t i = 0; i < n; ++i) {
-        switch (cls[i]) {
-        case O_OBST: case O_WALL: psi[i] = 0.0; break;
-        case O_GOAL: psi[i] = 1.0; break;
-        case O_FREE:
-            if (mode == 1) psi[i] = 0.5;
-            else if (mode == 2) psi[i] = 0.0;
-            break;
-        default: break;
+    const double span = (double)(nx > ny ? nx : ny) * sqrt(2.0);
+    for (int32_t y = 0; y < ny; ++y)
+        for (int32_t x = 0; x < nx; ++x) {
+            size_t i = (size_t)y * nx + x;
+            switch (cls[i]) {
+            case O_OBST: case O_WALL: psi[i] = 0.0; break;
+            case O_GOAL: psi[i] = 1.0; break;
+            case O_FREE:
+                if (mode == 1) psi[i] = 0.5;
+                else if (mode == 2) psi[i] = 0.0;
+                else if (mode == 3) {
+                    double dx = (double)(x - gx), dy = (double)(y - gy);
+                    psi[i] = 1.0 - sqrt(dx * dx + dy * dy) / span;
+                }
+                break;
+            default: break;
+            }
         }
-    }
 }
 
 /* Residual of the discrete Laplace equation (the change one step of Eq. 1

@@ -77,7 +77,8 @@ def conv(x, w, b):
     for dy in range(k):
         for dx in range(k):
             patch = xp[:, dy:dy + H, dx:dx + W].reshape(C, H * W)
-            out += (w[:, :, dy, dx] @ patch).reshape(O, H, W)
+            # a contiguous tap matrix lets NumPy hand the product to BLAS
+            out += (np.ascontiguousarray(w[:, :, dy, dx]) @ patch).reshape(O, H, W)
     return out
 
 
@@ -95,7 +96,8 @@ def conv_backward(x, w, dout):
         for dx in range(k):
             patch = xp[:, dy:dy + H, dx:dx + W].reshape(C, H * W)
             dw[:, :, dy, dx] = g @ patch.T
-            dxp[:, dy:dy + H, dx:dx + W] += (w[:, :, dy, dx].T @ g).reshape(C, H, W)
+            wt = np.ascontiguousarray(w[:, :, dy, dx].T)
+            dxp[:, dy:dy + H, dx:dx + W] += (wt @ g).reshape(C, H, W)
     db = dout.sum(axis=(1, 2))
     return dxp[:, r:r + H, r:r + W], dw, db
 
@@ -146,33 +148,37 @@ def forward(p, x, bf16_acts=False):
     return y, c
 
 
-def backward(p, c, dy):
+def backward(p, c, dy, bf16_grads=False):
     """Gradients of a scalar loss with d loss / d y = dy, for every parameter
-    and for the input x."""
+    and for the input x.  With ``bf16_grads`` the gradient with respect to
+    each layer's pre-activation (after the ReLU mask) is rounded to bfloat16,
+    the storage precision of the GPU's backward pass; the parameter and
+    input gradients themselves stay FP64."""
+    q = bf16_round if bf16_grads else (lambda a: a)
     g = {}
     dd0, g["head.w"], g["head.b"] = conv_backward(c["d0"], p["head.w"], dy[None])
-    dd0 = dd0 * (c["d0"] > 0)
+    dd0 = q(dd0 * (c["d0"] > 0))
     dc0, g["d0.w"], g["d0.b"] = conv_backward(c["c0"], p["d0.w"], dd0)
     n1 = c["d1"].shape[0]
     dd1 = up_backward(dc0[:n1])
     de0 = dc0[n1:].copy()
-    dd1 = dd1 * (c["d1"] > 0)
+    dd1 = q(dd1 * (c["d1"] > 0))
     dc1, g["d1.w"], g["d1.b"] = conv_backward(c["c1"], p["d1.w"], dd1)
     n2 = c["d2"].shape[0]
     dd2 = up_backward(dc1[:n2])
     de1 = dc1[n2:].copy()
-    dd2 = dd2 * (c["d2"] > 0)
+    dd2 = q(dd2 * (c["d2"] > 0))
     dc2, g["d2.w"], g["d2.b"] = conv_backward(c["c2"], p["d2.w"], dd2)
     n3 = c["e3"].shape[0]
     de3 = up_backward(dc2[:n3])
     de2 = dc2[n3:].copy()
-    de3 = de3 * (c["e3"] > 0)
+    de3 = q(de3 * (c["e3"] > 0))
     dp2, g["e3.w"], g["e3.b"] = conv_backward(c["p2"], p["e3.w"], de3)
-    de2 = (de2 + pool_backward(dp2)) * (c["e2"] > 0)
+    de2 = q((de2 + pool_backward(dp2)) * (c["e2"] > 0))
     dp1, g["e2.w"], g["e2.b"] = conv_backward(c["p1"], p["e2.w"], de2)
-    de1 = (de1 + pool_backward(dp1)) * (c["e1"] > 0)
+    de1 = q((de1 + pool_backward(dp1)) * (c["e1"] > 0))
     dp0, g["e1.w"], g["e1.b"] = conv_backward(c["p0"], p["e1.w"], de1)
-    de0 = (de0 + pool_backward(dp0)) * (c["e0"] > 0)
+    de0 = q((de0 + pool_backward(dp0)) * (c["e0"] > 0))
     dx, g["e0.w"], g["e0.b"] = conv_backward(c["x"], p["e0.w"], de0)
     g["x"] = dx
     return g
@@ -185,8 +191,9 @@ def masked_mse(y, target, mask):
     return float((diff * diff).sum() / n), 2.0 * diff / n
 
 
-def loss_and_grads(p, xs, targets, masks, bf16_acts=False):
-    """Batch loss (mean of per-sample losses) and summed parameter gradients."""
+def loss_and_grads(p, xs, targets, masks, bf16_acts=False, bf16_grads=False):
+    """Batch loss (mean of per-sample losses) and summed parameter gradients
+    (``bf16_acts``, ``bf16_grads``: see ``forward`` and ``backward``)."""
     total = 0.0
     grads = {k: np.zeros_like(v) for k, v in p.items()}
     B = len(xs)
@@ -194,7 +201,7 @@ def loss_and_grads(p, xs, targets, masks, bf16_acts=False):
         y, c = forward(p, x, bf16_acts)
         l, dy = masked_mse(y, t, m)
         total += l / B
-        g = backward(p, c, dy / B)
+        g = backward(p, c, dy / B, bf16_grads)
         for k in grads:
             grads[k] += g[k]
     return total, grads

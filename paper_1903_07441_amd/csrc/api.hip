@@ -189,17 +189,6 @@ struct Runner {
     hipStream_t st;
     int checks = 0;
 
-    // FP64 residual of an FP32 field: *out = max |r|, *rel = max |r| / |u|
-    int residual32(const float *u, const float *f, double *out, double *rel = nullptr)
-    {
-        int rc = launch_resid_f32(cls, u, f, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, ++ctx->word_seq, st);
-        if (!rc) rc = wait_words();
-        if (rc) return set_err(ctx, rc, "residual kernel failed");
-        *out = bits_to_double(ctx->host_words[0]);
-        if (rel) *rel = bits_to_double(ctx->host_words[1]);
-        return TWG_OK;
-    }
-
     // results the last residual reduction wrote to ctx->host_words_dev: poll
     // its sequence number in the pinned word 2 (the host sees it a few
     // microseconds before a stream synchronisation would return), asking the
@@ -221,26 +210,6 @@ struct Runner {
     }
 
 
-    // SOR factor maps for the streamed sweeps, built at most once per call
-    // (the class map is fixed for the duration of a call) and omega; two
-    // slots, so that a start phase and the main factor alternate freely
-    float w32_omega[2] = {-1.0f, -1.0f};
-    int w32_next = 0;
-    int wmap32(float omega, const float **w)
-    {
-        int k = w32_omega[0] == omega ? 0 : w32_omega[1] == omega ? 1 : -1;
-        if (k < 0) {
-            k = w32_next;
-            w32_next ^= 1;
-            int rc = ensure(ctx, &ctx->wmap32[k], &ctx->wmap32_bytes[k], (size_t)g.pitch * g.ny * sizeof(float));
-            if (rc) return rc;
-            rc = launch_wmap_f32(cls, static_cast<float *>(ctx->wmap32[k]), omega, g.nx, g.ny, g.pitch, st);
-            if (rc) return set_err(ctx, rc, "factor map launch failed");
-            w32_omega[k] = omega;
-        }
-        *w = static_cast<const float *>(ctx->wmap32[k]);
-        return TWG_OK;
-    }
     bool have_fmask = false;
     int fmask(const uint8_t **m)
     {
@@ -260,21 +229,21 @@ struct Runner {
     // are replayed from a captured graph.
     int sweep32(float **a, float **b, const float *f, float omega, int S, int RH, int64_t sweeps)
     {
-        const float *w = nullptr;
-        if (int rc = wmap32(omega, &w)) return rc;
+        const uint8_t *m = nullptr;
+        if (int rc = fmask(&m)) return rc;
         const Geometry geo = stream_geometry(g.nx, g.ny, S, RH);
         const Geometry geo1 = stream_geometry(g.nx, g.ny, 1, RH);
         int64_t done = 0;
         const int64_t reps = ctx->use_graphs ? sweeps / ((int64_t)S * kGraphPasses) : 0;
         if (reps > 0) {
-            const std::vector<uintptr_t> key = {1, (uintptr_t)*a, (uintptr_t)*b, (uintptr_t)w, (uintptr_t)f,
+            const std::vector<uintptr_t> key = {1, (uintptr_t)*a, (uintptr_t)*b, (uintptr_t)m, (uintptr_t)f,
                                                 (uintptr_t)g.nx, (uintptr_t)g.ny, (uintptr_t)g.pitch,
                                                 (uintptr_t)__builtin_bit_cast(uint32_t, omega), (uintptr_t)S,
                                                 (uintptr_t)RH};
             float *x = *a, *y = *b;
             int rc = graph_replay(ctx, key, st, reps, [&](hipStream_t cs) {
                 for (int k = 0; k < kGraphPasses; ++k) {
-                    const int e = launch_stream_f32(k % 2 ? y : x, k % 2 ? x : y, w, f, g.nx, g.ny, g.pitch,
+                    const int e = launch_stream_f32(k % 2 ? y : x, k % 2 ? x : y, m, omega, f, g.nx, g.ny, g.pitch,
                                                     geo, cs);
                     if (e) return e;
                 }
@@ -285,7 +254,7 @@ struct Runner {
         }
         while (done < sweeps) {
             const bool full = sweeps - done >= S;
-            int rc = launch_stream_f32(*a, *b, w, f, g.nx, g.ny, g.pitch, full ? geo : geo1, st);
+            int rc = launch_stream_f32(*a, *b, m, omega, f, g.nx, g.ny, g.pitch, full ? geo : geo1, st);
             if (rc) return set_err(ctx, rc, "relaxation kernel launch failed");
             std::swap(*a, *b);
             done += full ? S : 1;
@@ -293,180 +262,14 @@ struct Runner {
         return TWG_OK;
     }
 
-    // FP32 red-black SOR on `field` (ping-pong with ctx->alt) until the FP64
-    // residual is <= tol, the sweep budget is spent, or progress stalls; the
-    // first lead.sweeps sweeps (whole passes) use factor lead.omega.  r0 >= 0
-    // is the caller's residual of the starting field (no check is spent on
-    // it); *rate_io, when in (0, 1), is a measured per-sweep contraction to
-    // start from, and receives the one this solve measured.
-    int solve32(float *field, const float *f, float omega, int S, int RH, double tol,
-                int64_t max_sweeps, int check_passes, int64_t *sweeps_out, double *res_out,
-                bool *converged, double *rel_out = nullptr, StartPhase lead = {}, double r0 = -1.0,
-                double *rate_io = nullptr)
-    {
-        const size_t bytes = (size_t)g.pitch * g.ny * sizeof(float);
-        int rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, bytes);
-        if (rc) return rc;
-        float *a = field, *b = reinterpret_cast<float *>(ctx->alt);
-        double r = r0, rr = 0.0;
-        if (r0 < 0.0) {
-            rc = residual32(a, f, &r, &rr);
-            if (rc) return rc;
-        }
-        int64_t done = 0, last_chunk = 0, since = 0;
-        if (lead.sweeps > 0 && r > tol && !std::isnan(r) && max_sweeps > 0) {
-            done = std::min(((lead.sweeps + S - 1) / S) * S, max_sweeps);
-            rc = sweep32(&a, &b, f, lead.omega, S, RH, done);
-            if (!rc) rc = residual32(a, f, &r, &rr);
-            if (rc) return rc;
-        }
-        int stalls = 0;
-        double best = r;
-        // per-sweep contraction: the caller's measurement, else a guess
-        double rate = std::max((double)omega - 1.0, 0.5);
-        if (rate_io && *rate_io > 0.0 && *rate_io < 1.0) rate = *rate_io;
-        *converged = false;
-        while (true) {
-            if (std::isnan(r)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
-            if (r <= tol) { *converged = true; break; }
-            if (done >= max_sweeps) break;
-            int64_t chunk;
-            if (check_passes > 0) {
-                chunk = (int64_t)check_passes * S;
-            } else {
-                // sweeps the measured rate predicts, at most twice the last
-                // chunk (a rate near 1 near the rounding floor must not turn
-                // into one huge chunk)
-                const double want = std::log(tol / r) / std::log(rate);
-                chunk = (int64_t)std::min(std::ceil(want * (checks <= 1 ? 0.8 : 1.05)), 1e12) + S;
-                chunk = std::max<int64_t>(chunk, 8 * S);
-                if (last_chunk > 0) chunk = std::min(chunk, std::max<int64_t>(2 * last_chunk, 64 * S));
-            }
-            // whole passes (a remainder costs a full launch per sweep), unless
-            // the budget ends inside one
-            chunk = std::min(((chunk + S - 1) / S) * S, max_sweeps - done);
-            last_chunk = chunk;
-            const double r_prev = r;
-            rc = sweep32(&a, &b, f, omega, S, RH, chunk);
-            if (rc) return rc;
-            done += chunk;
-            rc = residual32(a, f, &r, &rr);
-            if (rc) return rc;
-            if (r < r_prev) {
-                const double q = std::pow(r / r_prev, 1.0 / (double)chunk);
-                if (q > 0.0 && q < 1.0) rate = q;
-            }
-            // stop at the rounding floor: three checks in a row, spanning at
-            // least kStallSweeps sweeps, without a 10 % gain on the best
-            // residual so far (the max-norm residual is not monotone, so a
-            // few closely spaced checks can miss real progress)
-            if (r < 0.9 * best) {
-                best = r;
-                stalls = 0;
-                since = 0;
-            } else {
-                since += chunk;
-                if (++stalls >= 3 && since >= kStallSweeps) break;
-            }
-        }
-        if (a != field) {
-            rc = launch_copy_f32(a, field, g.nx, g.ny, g.pitch, st);
-            if (rc) return set_err(ctx, rc, "copy launch failed");
-        }
-        if (rate_io) *rate_io = rate;
-        *sweeps_out = done;
-        *res_out = r;
-        if (rel_out) *rel_out = rr;
-        return TWG_OK;
-    }
-
     // FP64 residual of an FP64 field
     int residual64(const double *u, double *out)
     {
-        int rc = launch_resid_f64(cls, u, nullptr, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev, ++ctx->word_seq, st);
+        int rc = launch_resid_f64(cls, u, nullptr, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev,
+                                  ++ctx->word_seq, st);
         if (!rc) rc = wait_words();
         if (rc) return set_err(ctx, rc, "residual kernel failed");
         *out = bits_to_double(ctx->host_words[0]);
-        return TWG_OK;
-    }
-
-    // FP64 defect correction of psi64 (widened from psi): r = avg4(psi64) -
-    // psi64 in FP64, solve (I - J) e = r in FP32 from e = 0 (e = 0 on fixed
-    // cells) with factor omega_dc, psi64 += e (psi receives the rounded
-    // field), until the FP64 residual is <= need or 12 rounds.
-    // r_first >= 0: start_dc has widened psi and computed its defect, whose
-    // FP64 residual is r_first, and psi has not changed since
-    int polish_dc(float *psi, double *psi64, float omega_dc, double need, int S, int RH, int64_t max_sweeps,
-                  int64_t *sweeps_out, int32_t *rounds_out, double *res_out, bool *done, StartPhase lead = {},
-                  double r_first = -1.0)
-    {
-        const size_t n32 = (size_t)g.pitch * g.ny;
-        int rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n32 * sizeof(float));
-        if (rc) return rc;
-        float *r32 = reinterpret_cast<float *>(ctx->pol);
-        float *e = r32 + n32;
-        if (r_first < 0.0) {
-            rc = launch_widen(psi, psi64, g.nx, g.ny, g.pitch, st);
-            if (rc) return set_err(ctx, rc, "widen launch failed");
-        }
-        *done = false;
-        *sweeps_out = 0;
-        *rounds_out = 0;
-        double r64 = 0.0, rate_dc = 0.0;
-        for (int round = 0; round < 12; ++round) {
-            if (round == 0 && r_first >= 0.0) {
-                r64 = r_first;
-            } else {
-                rc = launch_defect64(cls, psi64, r32, g.nx, g.ny, g.pitch, ctx->rpart, ctx->host_words_dev,
-                                     ++ctx->word_seq, st);
-                if (!rc) rc = wait_words();
-                if (rc) return set_err(ctx, rc, "defect kernel failed");
-                r64 = bits_to_double(ctx->host_words[0]);
-            }
-            if (std::isnan(r64)) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
-            if (r64 <= need) { *done = true; break; }
-            rc = launch_fill_f32(e, 0.0f, g.nx, g.ny, g.pitch, st);
-            if (rc) return set_err(ctx, rc, "fill launch failed");
-            // correction solve: at most four decades per round (the FP32
-            // correction keeps about that much relative accuracy), and no
-            // further than a third of what is still needed
-            const double target = std::max(r64 * 1e-4, need / 3.0);
-            int64_t sw = 0;
-            double re = 0.0;
-            bool cconv = false;
-            // the correction starts at e = 0, whose residual is the defect
-            // itself (no check needed), and each round starts from the
-            // contraction the previous one measured
-            rc = solve32(e, r32, omega_dc, S, RH, target, max_sweeps, 0, &sw, &re, &cconv, nullptr, lead, r64,
-                         &rate_dc);
-            if (rc) return rc;
-            *sweeps_out += sw;
-            rc = launch_update64(cls, psi64, e, psi, g.nx, g.ny, g.pitch, st);
-            if (rc) return set_err(ctx, rc, "update launch failed");
-            *rounds_out = round + 1;
-        }
-        *res_out = r64;
-        return TWG_OK;
-    }
-
-    // The polish's first step on its own: psi64 = psi widened, its FP64
-    // defect into the polish's buffer, *r = its max |r| and *rel = max |r| /
-    // |u|.  The widened field holds psi's values exactly and the FP32 and
-    // FP64 residual kernels evaluate the same FP64 expression, so these are
-    // also psi's residuals.
-    int start_dc(const float *psi, double *psi64, double *r, double *rel)
-    {
-        const size_t n32 = (size_t)g.pitch * g.ny;
-        int rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n32 * sizeof(float));
-        if (rc) return rc;
-        rc = launch_widen(psi, psi64, g.nx, g.ny, g.pitch, st);
-        if (!rc)
-            rc = launch_defect64(cls, psi64, reinterpret_cast<float *>(ctx->pol), g.nx, g.ny, g.pitch, ctx->rpart,
-                                 ctx->host_words_dev, ++ctx->word_seq, st);
-        if (!rc) rc = wait_words();
-        if (rc) return set_err(ctx, rc, "defect kernel failed");
-        *r = bits_to_double(ctx->host_words[0]);
-        *rel = bits_to_double(ctx->host_words[1]);
         return TWG_OK;
     }
 
@@ -526,11 +329,159 @@ struct Runner {
     }
 };
 
+// What a relaxation call runs with: tiling, SOR factors and the correction
+// solves' start phase.
+struct RelaxPlan {
+    int S = 4, RH = 32;
+    float omega = 1.0f, omega_dc = 1.0f;
+    StartPhase lead;
+};
+
+// The plan of hpf_relax for grid g and params p: the autotuned tiling and
+// factors of this size if the context has them, else the fixed table, the
+// open-rectangle optimum and the correction default 2 / (1 + 2.8 sin(pi /
+// (n + 1))); a caller's omega (which also runs the correction solves, with
+// no start phase) and tiling override them.
+RelaxPlan plan_for(twg_ctx *ctx, const twg_grid &g, const hpf_params &p)
+{
+    RelaxPlan pl;
+    float omega_t;
+    tiling_for(ctx, g.nx, g.ny, &pl.S, &pl.RH, &omega_t);
+    pl.omega = p.omega > 0.0f ? p.omega : omega_t;
+    pl.omega_dc = omega_family(std::max(g.nx, g.ny), 2.8);
+    if (p.omega > 0.0f) {
+        pl.omega_dc = p.omega;
+    } else {
+        auto it = ctx->tuned.find({g.nx, g.ny});
+        if (it != ctx->tuned.end()) {
+            if (it->second.omega_dc > 0.0f) pl.omega_dc = it->second.omega_dc;
+            pl.lead = it->second.lead_dc;
+        }
+    }
+    if (p.sweeps_per_pass) pl.S = p.sweeps_per_pass;
+    if (p.rows_per_tile) pl.RH = p.rows_per_tile;
+    return pl;
+}
+
+// Defect-correction rounds a polish may take.
+constexpr int kMaxRounds = 12;
+// Slots a blocking solve keeps queued beyond the device's next decision.
+constexpr int64_t kSlotMargin = 3;
+
+// The device-driven solve of hpf_relax (polish 0 or 1): field init, free
+// mask, the control block's begin kernel, then slots of k_relax_slot.
+// slots > 0: exactly that many slots and a final one, all asynchronous;
+// the stats land in stats_dev.  slots == 0: the host keeps slots queued just
+// beyond the next decision the device publishes (it never waits for a
+// residual), stops when the device reports the solve done, then waits for
+// the stream and copies the stats to *stats_host.
+int relax_device(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float *psi, double *psi64,
+                 const hpf_params &p, const RelaxPlan &pl, int64_t slots, hpf_stats *stats_dev,
+                 hpf_stats *stats_host, hipStream_t st)
+{
+    const size_t n = (size_t)g.pitch * g.ny;
+    int rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, n * sizeof(float));
+    if (!rc && p.polish) rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n * sizeof(float));
+    if (!rc) rc = ensure(ctx, &ctx->fmask, &ctx->fmask_bytes, n);
+    if (!rc) rc = ensure(ctx, &ctx->ctl, &ctx->ctl_bytes, relax_ctl_bytes() + 256);
+    if (rc) return rc;
+    char *ctl = static_cast<char *>(ctx->ctl);
+    hpf_stats *dstats = stats_dev ? stats_dev : reinterpret_cast<hpf_stats *>(ctl + relax_ctl_bytes());
+    const int cap = stream_rows_cap(g.pitch, (int)sizeof(float), pl.S);
+    const Geometry geo = stream_geometry(g.nx, g.ny, pl.S, std::min(pl.RH, cap));
+    const double wb = std::pow((double)std::min(g.nx, g.ny) + 1.0, 2) / 2.0;
+
+    rc = launch_field_init(cls, psi, g.nx, g.ny, g.pitch, p.init, p.goal_x, p.goal_y, st);
+    if (!rc) rc = launch_fmask(cls, static_cast<uint8_t *>(ctx->fmask), g.nx, g.ny, g.pitch, st);
+    if (rc) return set_err(ctx, rc, "relaxation set-up launch failed");
+    RelaxConfig cfg;
+    cfg.tol = p.tol;
+    cfg.need = p.polish ? (p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / wb) : p.tol) : 0.0;
+    cfg.wbound = wb;
+    cfg.max_sweeps = p.max_sweeps;
+    cfg.omega = pl.omega;
+    cfg.omega_dc = pl.omega_dc;
+    cfg.omega_lead = pl.lead.omega;
+    cfg.lead_passes = pl.lead.sweeps > 0 ? (int32_t)((pl.lead.sweeps + pl.S - 1) / pl.S) : 0;
+    cfg.S = pl.S;
+    cfg.polish = p.polish ? 1 : 0;
+    cfg.check_passes = p.check_passes;
+    cfg.max_rounds = kMaxRounds;
+    rc = launch_relax_begin(ctl, cfg, st);
+    if (rc) return set_err(ctx, rc, "relaxation begin launch failed");
+
+    SlotArgs a;
+    a.mask = static_cast<const uint8_t *>(ctx->fmask);
+    a.psi = psi;
+    a.alt = static_cast<float *>(ctx->alt);
+    a.r32 = p.polish ? static_cast<float *>(ctx->pol) : nullptr;
+    a.e = p.polish ? a.r32 + n : nullptr;
+    a.psi64 = p.polish ? psi64 : nullptr;
+    a.ctl = ctl;
+    a.stats = dstats;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.pitch = g.pitch;
+    a.strips = geo.strips;
+    a.RH = geo.RH;
+    a.tiles = geo.tiles;
+    const auto al8 = [](const void *q) { return (reinterpret_cast<uintptr_t>(q) & 7) == 0; };
+    a.pair = g.nx % 2 == 0 && g.pitch % 2 == 0 && al8(psi) && al8(a.alt) && (!p.polish || (al8(a.r32) && al8(a.e)));
+    a.final_slot = 0;
+
+    if (slots > 0) {
+        a.mirror = nullptr;
+        for (int64_t k = 0; k < slots; ++k)
+            if ((rc = launch_relax_slot(a, pl.S, st))) return set_err(ctx, rc, "relaxation slot launch failed");
+        a.final_slot = 1;
+        rc = launch_relax_slot(a, pl.S, st);
+        return rc ? set_err(ctx, rc, "relaxation slot launch failed") : TWG_OK;
+    }
+
+    // blocking: keep the slots up to the next published decision (plus a
+    // margin) queued.  The device publishes, at every decision, the slot of
+    // the next one; bit 63 marks the end.
+    volatile unsigned long long *word = ctx->host_words + kMirrorWord;
+    *word = 0ull;
+    std::atomic_thread_fence(std::memory_order_seq_cst);
+    a.mirror = ctx->host_words_dev + kMirrorWord;
+    int64_t queued = 0, target = 1 + kSlotMargin;
+    unsigned long long seen = 0;
+    int idle = 0;
+    for (unsigned polls = 0;;) {
+        const unsigned long long w = *word;
+        if (w >> 63) break;
+        if (w != seen) {
+            seen = w;
+            idle = 0;
+            target = std::max<int64_t>(target, (int64_t)(w & 0xffffffffull) + kSlotMargin);
+        }
+        if (queued < target) {
+            if ((rc = launch_relax_slot(a, pl.S, st))) return set_err(ctx, rc, "relaxation slot launch failed");
+            ++queued;
+            continue;
+        }
+        if (++polls % 1024) continue;
+        const hipError_t e = hipStreamQuery(st);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return set_err(ctx, TWG_EDEVICE, "relaxation stream failed");
+        // the stream ran dry: every slot has run and its decisions are
+        // visible, so the word must show a decision past the queue
+        if (*word == seen && ++idle > 2)
+            return set_err(ctx, TWG_EDEVICE, "relaxation control made no progress");
+        target = queued + kSlotMargin;
+    }
+    if (hipMemcpyAsync(stats_host, dstats, sizeof(hpf_stats), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return set_err(ctx, TWG_EDEVICE, "relaxation stats read-back failed");
+    return TWG_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int32_t twg_version(void) { return 101; }
+int32_t twg_version(void) { return 200; }
 
 int32_t twg_ctx_create(twg_ctx **out, int32_t device)
 {
@@ -568,8 +519,8 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
     for (auto &g : ctx->graphs) hipGraphExecDestroy(g.exec);
     ctx->graphs.clear();
     if (ctx->cap) hipStreamDestroy(ctx->cap);
-    void *bufs[] = {ctx->alt,   ctx->pol,    ctx->alt64, ctx->wmap32[0], ctx->wmap32[1], ctx->fmask,  ctx->pairs,
-                    ctx->idxbuf, ctx->batch, ctx->words, ctx->jumpbuf, ctx->rpart, ctx->tunebuf};
+    void *bufs[] = {ctx->alt,   ctx->pol,   ctx->alt64,  ctx->fmask, ctx->pairs,   ctx->idxbuf,
+                    ctx->batch, ctx->words, ctx->jumpbuf, ctx->rpart, ctx->tunebuf, ctx->ctl};
     for (void *b : bufs)
         if (b) hipFree(b);
     if (ctx->host_words) hipHostFree(ctx->host_words);
@@ -618,109 +569,95 @@ int32_t twg_rasterize(twg_ctx *ctx, twg_grid g, int32_t n_obs, const double *pos
                             as_stream(stream));
 }
 
-int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, double *psi64,
-                  const hpf_params *params, hpf_stats *stats, void *stream)
+namespace {
+
+// argument checks shared by hpf_relax and hpf_relax_async
+int check_relax_args(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, const float *psi, const double *psi64,
+                     const hpf_params *params)
 {
-    if (!ctx) return TWG_EINVAL;
-    ctx->err.clear();
     int rc = check_grid(ctx, g);
     if (rc) return rc;
     if (!cls || !psi || !params) return set_err(ctx, TWG_EINVAL, "cls, psi and params are required");
-    hpf_params p = *params;
+    const hpf_params &p = *params;
     if (!(p.tol > 0.0)) return set_err(ctx, TWG_EINVAL, "tol must be > 0");
     if (!(p.omega >= 0.0f && p.omega < 2.0f)) return set_err(ctx, TWG_EINVAL, "omega must be in [0, 2)");
-    if (p.init < HPF_INIT_KEEP || p.init > HPF_INIT_ZERO) return set_err(ctx, TWG_EINVAL, "bad init mode");
+    if (p.init < HPF_INIT_KEEP || p.init > HPF_INIT_LINEAR) return set_err(ctx, TWG_EINVAL, "bad init mode");
+    if (p.init == HPF_INIT_LINEAR && (p.goal_x < 0 || p.goal_y < 0 || p.goal_x >= g.nx || p.goal_y >= g.ny))
+        return set_err(ctx, TWG_EINVAL, "HPF_INIT_LINEAR needs a goal inside the grid");
     if (p.polish < 0 || p.polish > 2) return set_err(ctx, TWG_EINVAL, "polish must be 0, 1 or 2");
     if (p.polish && !psi64) return set_err(ctx, TWG_EINVAL, "polish needs psi64");
     if (p.sweeps_per_pass && !stream_depth_supported(p.sweeps_per_pass))
         return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
     if (p.rows_per_tile && (p.rows_per_tile < 2 || (p.rows_per_tile & 1)))
         return set_err(ctx, TWG_EINVAL, "rows_per_tile must be even and >= 2");
+    if (p.check_passes < 0) return set_err(ctx, TWG_EINVAL, "check_passes must be >= 0");
+    return TWG_OK;
+}
+
+}  // namespace
+
+int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, double *psi64,
+                  const hpf_params *params, hpf_stats *stats, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_relax_args(ctx, g, cls, psi, psi64, params);
+    if (rc) return rc;
+    hpf_params p = *params;
     if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
     hipSetDevice(ctx->device);
     hipStream_t st = as_stream(stream);
-    int S, RH;
-    float omega_t;
-    tiling_for(ctx, g.nx, g.ny, &S, &RH, &omega_t);
-    const float omega = p.omega > 0.0f ? p.omega : omega_t;
-    if (p.sweeps_per_pass) S = p.sweeps_per_pass;
-    if (p.rows_per_tile) RH = p.rows_per_tile;
-    const double wb = std::pow((double)std::min(g.nx, g.ny) + 1.0, 2) / 2.0;
-
-    Runner run{ctx, g, cls, st};
+    const RelaxPlan pl = plan_for(ctx, g, p);
     hpf_stats s;
     std::memset(&s, 0, sizeof s);
-    s.omega = omega;
-    s.wbound = wb;
-
-    // the correction solves' start phase comes with the autotuned factors: a
-    // caller's factor runs alone
-    StartPhase lead_dc;
-    if (p.omega == 0.0f) {
-        auto it = ctx->tuned.find({g.nx, g.ny});
-        if (it != ctx->tuned.end()) lead_dc = it->second.lead_dc;
-    }
-
-    rc = launch_field_init(cls, psi, g.nx, g.ny, g.pitch, p.init, st);
-    if (rc) return set_err(ctx, rc, "init launch failed");
-    // a kept field that the defect correction follows: the correction's
-    // first FP64 defect also gives the FP32 stage its starting residual, so
-    // a field already at tol costs one check, not two
-    double r_first = -1.0, rel_first = 0.0;
-    if (p.polish == 1 && p.init == HPF_INIT_KEEP) {
-        rc = run.start_dc(psi, psi64, &r_first, &rel_first);
-        if (rc) return rc;
-    }
-    bool conv = false;
-    rc = run.solve32(psi, nullptr, omega, S, RH, p.tol, p.max_sweeps, p.check_passes, &s.sweeps,
-                     &s.residual32, &conv, &s.residual_rel, {}, r_first);
-    if (rc) return rc;
-    // the FP32 stage swept nothing: the correction starts from the defect
-    // already computed
-    const bool dc_ready = r_first >= 0.0 && s.sweeps == 0;
-    if (dc_ready) s.residual_rel = rel_first;
-    s.residual = s.residual32;
-    s.status = conv ? TWG_OK : TWG_NOT_CONVERGED;
-
     if (p.polish == 2) {
-        // FP64 SOR sweeps from the FP32 field
-        const double need = p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / wb) : p.tol;
+        // FP32 solve on the device, then FP64 SOR sweeps driven from the host
+        hpf_params p0 = p;
+        p0.polish = 0;
+        rc = relax_device(ctx, g, cls, psi, nullptr, p0, pl, 0, nullptr, &s, st);
+        if (rc) return rc;
+        if (s.status == TWG_EINVAL) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
+        const double need = p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / s.wbound) : p.tol;
         rc = launch_widen(psi, psi64, g.nx, g.ny, g.pitch, st);
         if (rc) return set_err(ctx, rc, "widen launch failed");
+        Runner run{ctx, g, cls, st};
         bool done = false;
         double r64 = 0.0;
-        rc = run.solve64(psi64, (double)omega, need, p.max_sweeps, &s.polish_sweeps, &r64, &done);
+        rc = run.solve64(psi64, (double)pl.omega, need, p.max_sweeps, &s.polish_sweeps, &r64, &done);
         if (rc) return rc;
         rc = launch_narrow(psi64, psi, g.nx, g.ny, g.pitch, st);
         if (rc) return set_err(ctx, rc, "narrow launch failed");
+        if (hipStreamSynchronize(st) != hipSuccess) return set_err(ctx, TWG_EDEVICE, "stream failed");
         s.residual = r64;
+        s.cert_bound = r64 * s.wbound;
         s.status = done ? TWG_OK : TWG_NOT_CONVERGED;
-        hipStreamSynchronize(st);
-    } else if (p.polish == 1) {
-        // SOR factor of the correction solves: the caller's factor if given,
-        // else the autotuned one, else 2 / (1 + 2.8 sin(pi / (n + 1))).
-        float omega_dc = omega_family(std::max(g.nx, g.ny), 2.8);
-        if (p.omega > 0.0f) {
-            omega_dc = p.omega;
-        } else {
-            auto it = ctx->tuned.find({g.nx, g.ny});
-            if (it != ctx->tuned.end() && it->second.omega_dc > 0.0f) omega_dc = it->second.omega_dc;
-        }
-        // residual the result must reach: tol, and tol_cert / wbound if set
-        const double need = p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / wb) : p.tol;
-        bool done = false;
-        rc = run.polish_dc(psi, psi64, omega_dc, need, S, RH, p.max_sweeps, &s.polish_sweeps, &s.polish_rounds,
-                           &s.residual, &done, lead_dc, dc_ready ? r_first : -1.0);
+        s.checks += run.checks;
+    } else {
+        rc = relax_device(ctx, g, cls, psi, psi64, p, pl, 0, nullptr, &s, st);
         if (rc) return rc;
-        s.status = done ? TWG_OK : TWG_NOT_CONVERGED;
-        hipStreamSynchronize(st);
     }
-    s.cert_bound = s.residual * wb;
-    s.checks = run.checks;
     if (stats) *stats = s;
+    if (s.status == TWG_EINVAL) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
     if (s.status == TWG_NOT_CONVERGED)
         set_err(ctx, TWG_NOT_CONVERGED, "relaxation stopped before reaching the tolerance");
     return s.status;
+}
+
+int32_t hpf_relax_async(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, double *psi64,
+                        const hpf_params *params, int32_t slots, hpf_stats *stats, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_relax_args(ctx, g, cls, psi, psi64, params);
+    if (rc) return rc;
+    if (params->polish == 2) return set_err(ctx, TWG_EUNSUPPORTED, "the asynchronous relaxation polishes by defect correction only");
+    if (slots < 1) return set_err(ctx, TWG_EINVAL, "slots must be >= 1");
+    if (!stats) return set_err(ctx, TWG_EINVAL, "stats (device) is required");
+    hpf_params p = *params;
+    if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
+    hipSetDevice(ctx->device);
+    const RelaxPlan pl = plan_for(ctx, g, p);
+    return relax_device(ctx, g, cls, psi, psi64, p, pl, slots, stats, nullptr, as_stream(stream));
 }
 
 int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, const uint8_t *cls,
@@ -1036,7 +973,7 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
         for (int RH : tile_heights(ctx, g.nx, g.ny, S, 4)) {
             if (RH > 2 * g.ny && RH > 8) continue;
             rc = launch_fill_f32(a, 0.5f, g.nx, g.ny, g.pitch, st);
-            if (!rc) rc = launch_field_init(cls, a, g.nx, g.ny, g.pitch, HPF_INIT_KEEP, st);
+            if (!rc) rc = launch_field_init(cls, a, g.nx, g.ny, g.pitch, HPF_INIT_KEEP, 0, 0, st);
             if (rc) break;
             float *x = a, *y = b;
             // warm-up: also captures the pass graph the timed run replays
@@ -1062,7 +999,7 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
         if (!rc) rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, n32 * sizeof(double));
         double *a64 = reinterpret_cast<double *>(ctx->pol), *b64 = reinterpret_cast<double *>(ctx->alt64);
         if (!rc) rc = launch_fill_f32(b, 0.5f, g.nx, g.ny, g.pitch, st);
-        if (!rc) rc = launch_field_init(cls, b, g.nx, g.ny, g.pitch, HPF_INIT_KEEP, st);
+        if (!rc) rc = launch_field_init(cls, b, g.nx, g.ny, g.pitch, HPF_INIT_KEEP, 0, 0, st);
         if (!rc) rc = launch_widen(b, a64, g.nx, g.ny, g.pitch, st);
         const uint8_t *m64 = nullptr;
         if (!rc) rc = run.fmask(&m64);
@@ -1114,42 +1051,45 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
             if (best_i > 0 && sw[best_i - 1] > 0 && sw[best_i - 1] <= sw[best_i] * 1.25) --best_i;
             return best_i;
         };
+        // one device-driven solve from the half-initialised field: the FP32
+        // stage (and with polish the defect correction to a certified 1e-7)
+        // under a trial plan; returns its stats
+        rc = ensure(ctx, &ctx->tunebuf, &ctx->tunebuf_bytes, n32 * sizeof(float));
+        if (!rc) rc = ensure(ctx, &ctx->alt64, &ctx->alt64_bytes, n32 * sizeof(double));
+        float *fld = static_cast<float *>(ctx->tunebuf);
+        double *f64 = reinterpret_cast<double *>(ctx->alt64);
+        auto trial = [&](float om, float om_dc, StartPhase lp, bool polish, hpf_stats *s) {
+            hpf_params tp;
+            std::memset(&tp, 0, sizeof tp);
+            tp.tol = 1e-6;
+            tp.tol_cert = polish ? 1e-7 : 0.0;
+            tp.max_sweeps = polish ? 3 * cap : cap;
+            tp.init = HPF_INIT_HALF;
+            tp.polish = polish ? 1 : 0;
+            RelaxPlan pl;
+            pl.S = best.S;
+            pl.RH = best.RH;
+            pl.omega = om;
+            pl.omega_dc = om_dc;
+            pl.lead = lp;
+            return relax_device(ctx, g, cls, fld, f64, tp, pl, 0, nullptr, s, st);
+        };
         int64_t sw_plain[NC] = {0};
         for (int i = 0; i < NC && !rc; ++i) {
-            rc = launch_fill_f32(a, 0.5f, g.nx, g.ny, g.pitch, st);
-            if (!rc) rc = launch_field_init(cls, a, g.nx, g.ny, g.pitch, HPF_INIT_HALF, st);
-            int64_t sw = 0;
-            double r = 0.0;
-            bool conv = false;
-            if (!rc) rc = run.solve32(a, nullptr, omega_family(n, cs[i]), best.S, best.RH, 1e-6, cap, 0, &sw, &r,
-                                      &conv);
-            if (!rc && conv) sw_plain[i] = sw;
+            hpf_stats s;
+            rc = trial(omega_family(n, cs[i]), 1.0f, {}, false, &s);
+            if (!rc && s.status == TWG_OK) sw_plain[i] = s.sweeps;
         }
         const int ip = rc ? -1 : pick(sw_plain);
         if (ip >= 0) best.omega = omega_family(n, cs[ip]);
         // the whole defect-correction polish of that converged field to a
         // certified 1e-7, once per factor
         if (!rc && ip >= 0) {
-            rc = ensure(ctx, &ctx->tunebuf, &ctx->tunebuf_bytes, n32 * sizeof(float));
-            float *fld = static_cast<float *>(ctx->tunebuf);
-            double *f64 = reinterpret_cast<double *>(ctx->alt64);
-            const double wb = std::pow((double)std::min(g.nx, g.ny) + 1.0, 2) / 2.0;
             int64_t sw_dc[NC] = {0};
             for (int i = 0; i < NC && !rc; ++i) {
-                int64_t sw = 0;
-                double r = 0.0;
-                bool conv = false;
-                rc = launch_fill_f32(fld, 0.5f, g.nx, g.ny, g.pitch, st);
-                if (!rc) rc = launch_field_init(cls, fld, g.nx, g.ny, g.pitch, HPF_INIT_HALF, st);
-                if (!rc) rc = run.solve32(fld, nullptr, best.omega, best.S, best.RH, 1e-6, cap, 0, &sw, &r, &conv);
-                int64_t swc = 0;
-                int32_t rounds = 0;
-                double r64 = 0.0;
-                bool done = false;
-                if (!rc && conv)
-                    rc = run.polish_dc(fld, f64, omega_family(n, cs[i]), 1e-7 / wb, best.S, best.RH, 3 * cap,
-                                       &swc, &rounds, &r64, &done);
-                if (!rc && done) sw_dc[i] = swc;
+                hpf_stats s;
+                rc = trial(best.omega, omega_family(n, cs[i]), {}, true, &s);
+                if (!rc && s.status == TWG_OK && s.residual32 <= 1e-6) sw_dc[i] = s.polish_sweeps;
             }
             const int id = rc ? -1 : pick(sw_dc);
             if (id >= 0) best.omega_dc = omega_family(n, cs[id]);
@@ -1161,21 +1101,6 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
             // polish more than it saves.)
             const double c_lead[] = {12.0, 16.0, 24.0};
             const int64_t k_lead[] = {std::max<int64_t>(n / 40, 2 * best.S), std::max<int64_t>(n / 20, 4 * best.S)};
-            auto dc_sweeps = [&](StartPhase lp, int64_t *out_sw) {
-                int64_t sw = 0, swc = 0;
-                double r = 0.0, r64 = 0.0;
-                bool conv = false, done = false;
-                int32_t rounds = 0;
-                *out_sw = 0;
-                int e = launch_fill_f32(fld, 0.5f, g.nx, g.ny, g.pitch, st);
-                if (!e) e = launch_field_init(cls, fld, g.nx, g.ny, g.pitch, HPF_INIT_HALF, st);
-                if (!e) e = run.solve32(fld, nullptr, best.omega, best.S, best.RH, 1e-6, cap, 0, &sw, &r, &conv);
-                if (!e && conv)
-                    e = run.polish_dc(fld, f64, best.omega_dc, 1e-7 / wb, best.S, best.RH, 3 * cap, &swc, &rounds,
-                                      &r64, &done, lp);
-                if (!e && done) *out_sw = swc;
-                return e;
-            };
             if (!rc && id >= 0) {
                 const int64_t base = sw_dc[id];
                 int64_t best_sw = base > 0 ? (int64_t)(0.95 * (double)base) : 0;
@@ -1183,9 +1108,10 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
                     for (int64_t k : k_lead) {
                         if (rc) break;
                         const StartPhase lp{omega_family(n, c1), k};
-                        int64_t sw = 0;
-                        rc = dc_sweeps(lp, &sw);
-                        if (!rc && sw > 0 && best_sw > 0 && sw < best_sw) {
+                        hpf_stats s;
+                        rc = trial(best.omega, best.omega_dc, lp, true, &s);
+                        const int64_t sw = (!rc && s.status == TWG_OK && s.residual32 <= 1e-6) ? s.polish_sweeps : 0;
+                        if (sw > 0 && best_sw > 0 && sw < best_sw) {
                             best_sw = sw;
                             best.lead_dc = lp;
                         }
@@ -1381,16 +1307,19 @@ int32_t hpf_merge_previous(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const u
     return rc ? set_err(ctx, rc, "merge launch failed") : TWG_OK;
 }
 
-int32_t hpf_init_field(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, int32_t init, void *stream)
+int32_t hpf_init_field(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, int32_t init, int32_t goal_x,
+                       int32_t goal_y, void *stream)
 {
     if (!ctx) return TWG_EINVAL;
     ctx->err.clear();
     int rc = check_grid(ctx, g);
     if (rc) return rc;
     if (!cls || !psi) return set_err(ctx, TWG_EINVAL, "missing argument");
-    if (init < HPF_INIT_KEEP || init > HPF_INIT_ZERO) return set_err(ctx, TWG_EINVAL, "bad init mode");
+    if (init < HPF_INIT_KEEP || init > HPF_INIT_LINEAR) return set_err(ctx, TWG_EINVAL, "bad init mode");
+    if (init == HPF_INIT_LINEAR && (goal_x < 0 || goal_y < 0 || goal_x >= g.nx || goal_y >= g.ny))
+        return set_err(ctx, TWG_EINVAL, "HPF_INIT_LINEAR needs a goal inside the grid");
     hipSetDevice(ctx->device);
-    rc = launch_field_init(cls, psi, g.nx, g.ny, g.pitch, init, as_stream(stream));
+    rc = launch_field_init(cls, psi, g.nx, g.ny, g.pitch, init, goal_x, goal_y, as_stream(stream));
     return rc ? set_err(ctx, rc, "init launch failed") : TWG_OK;
 }
 

@@ -225,8 +225,12 @@ __global__ void k_merge_prev(const uint8_t *__restrict__ cls, const uint8_t *__r
 }
 
 // ---- element-wise helpers --------------------------------------------------
+// Field initialisation: OBST and WALL 0, GOAL 1, FIXED unchanged; FREE cells
+// by mode: HALF 0.5, ZERO 0, LINEAR the ramp 1 - d / (max(nx, ny) sqrt 2)
+// of the Euclidean distance d to the goal cell (gx, gy), evaluated in FP64
+// and rounded once; KEEP leaves them.
 __global__ void k_field_init(const uint8_t *__restrict__ cls, float *psi, int nx, int ny, int pitch,
-                             int mode)
+                             int mode, int gx, int gy)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -237,8 +241,15 @@ __global__ void k_field_init(const uint8_t *__restrict__ cls, float *psi, int nx
     case TWG_CELL_WALL: psi[i] = 0.0f; break;
     case TWG_CELL_GOAL: psi[i] = 1.0f; break;
     case TWG_CELL_FREE:
-        if (mode == HPF_INIT_HALF) psi[i] = 0.5f;
-        else if (mode == HPF_INIT_ZERO) psi[i] = 0.0f;
+        if (mode == HPF_INIT_HALF) {
+            psi[i] = 0.5f;
+        } else if (mode == HPF_INIT_ZERO) {
+            psi[i] = 0.0f;
+        } else if (mode == HPF_INIT_LINEAR) {
+            const double dx = (double)(x - gx), dy = (double)(y - gy);
+            const double d = sqrt(dx * dx + dy * dy);
+            psi[i] = (float)(1.0 - d / ((double)max(nx, ny) * sqrt(2.0)));
+        }
         break;
     default: break;
     }
@@ -296,8 +307,7 @@ __global__ void k_copy(const float *__restrict__ s, float *__restrict__ d, int n
 
 dim3 cell_grid(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); }
 
-// SOR factor map of the FP32 streamed sweeps (omega on FREE cells, 0 on the
-// others) and free mask of the FP64 ones (1 on FREE cells, 0 on the others)
+// free mask of the streamed sweeps: 1 on FREE cells, 0 on the others
 template <typename T>
 __global__ void k_wmap(const uint8_t *__restrict__ cls, T *__restrict__ w, T omega, int nx, int ny, int pitch)
 {
@@ -356,12 +366,6 @@ int launch_copy_batch(const float *src, float *dst, const BatchGrid *grids, cons
     return last_status();
 }
 
-int launch_wmap_f32(const uint8_t *cls, float *wmap, float omega, int nx, int ny, int pitch, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_wmap<float>, cell_grid(nx, ny), dim3(256), 0, st, cls, wmap, omega, nx, ny, pitch);
-    return last_status();
-}
-
 int launch_fmask(const uint8_t *cls, uint8_t *fmask, int nx, int ny, int pitch, hipStream_t st)
 {
     hipLaunchKernelGGL(k_wmap<uint8_t>, cell_grid(nx, ny), dim3(256), 0, st, cls, fmask, (uint8_t)1, nx, ny,
@@ -377,11 +381,10 @@ int launch_fmask_batch(const uint8_t *cls, uint8_t *fmask, const BatchGrid *grid
     return last_status();
 }
 
-int launch_field_init(const uint8_t *cls, float *psi, int nx, int ny, int pitch, int mode,
+int launch_field_init(const uint8_t *cls, float *psi, int nx, int ny, int pitch, int mode, int gx, int gy,
                       hipStream_t st)
 {
-    hipLaunchKernelGGL(k_field_init, cell_grid(nx, ny), dim3(256), 0, st, cls, psi, nx, ny, pitch,
-                       mode);
+    hipLaunchKernelGGL(k_field_init, cell_grid(nx, ny), dim3(256), 0, st, cls, psi, nx, ny, pitch, mode, gx, gy);
     return last_status();
 }
 

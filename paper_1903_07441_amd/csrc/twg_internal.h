@@ -49,10 +49,7 @@ struct twg_ctx {
     // FP64 ping-pong partner (FP64 sweeps)
     void *alt64 = nullptr;
     size_t alt64_bytes = 0;
-    // SOR factor map (FP32 sweeps) and free mask (FP64 sweeps), rebuilt by
-    // every call that sweeps
-    void *wmap32[2] = {nullptr, nullptr};  // two factors (a start phase and the main one)
-    size_t wmap32_bytes[2] = {0, 0};
+    // free mask of the streamed sweeps, rebuilt by every call that sweeps
     void *fmask = nullptr;
     size_t fmask_bytes = 0;
     // (obstacle, ring) work list of the rasteriser and its counter
@@ -83,6 +80,9 @@ struct twg_ctx {
     unsigned long long *host_words_dev = nullptr;
     // sequence number of the last residual reduction launched
     unsigned long long word_seq = 0;
+    // control block of the device-driven relaxation and its device stats
+    void *ctl = nullptr;
+    size_t ctl_bytes = 0;
     // instantiated graphs of relaxation passes, keyed by their launch
     // arguments, and the stream they are captured on
     struct Graph {
@@ -97,6 +97,8 @@ struct twg_ctx {
 namespace twg {
 
 constexpr int kWords = 64;
+// host word the device-driven relaxation publishes its decisions to
+constexpr int kMirrorWord = 8;
 
 // one grid of a batch: arrays start at element offset `off` of the batch base
 struct BatchGrid {
@@ -134,7 +136,8 @@ struct Geometry {
     int tiles;
 };
 Geometry stream_geometry(int nx, int ny, int S, int RH);
-int launch_field_init(const uint8_t *cls, float *psi, int nx, int ny, int pitch, int mode,
+// HPF_INIT_* on psi; HPF_INIT_LINEAR uses the goal cell (gx, gy)
+int launch_field_init(const uint8_t *cls, float *psi, int nx, int ny, int pitch, int mode, int gx, int gy,
                       hipStream_t st);
 int launch_sweep_color_f32(const uint8_t *cls, float *psi, const float *f, int nx, int ny, int pitch,
                            float omega, int color, hipStream_t st);
@@ -144,15 +147,12 @@ bool stream_depth_supported(int S);
 // largest RH whose tiles the streamed kernels can address (RH above it is
 // lowered at launch)
 int stream_rows_cap(int pitch, int elem_bytes, int S);
-// streamed sweeps.  FP32: wmap is the SOR factor map (omega on FREE cells, 0
-// on the others) built by launch_wmap_f32 for the sweeps' omega.  FP64:
-// fmask is the free mask (1 on FREE cells, 0 on the others) built by
-// launch_fmask.
-int launch_stream_f32(const float *src, float *dst, const float *wmap, const float *f, int nx, int ny,
-                      int pitch, const Geometry &geo, hipStream_t st);
+// streamed sweeps: fmask is the free mask (1 on FREE cells, 0 on the others)
+// built by launch_fmask; w = omega on FREE cells, 0 elsewhere
+int launch_stream_f32(const float *src, float *dst, const uint8_t *fmask, float omega, const float *f, int nx,
+                      int ny, int pitch, const Geometry &geo, hipStream_t st);
 int launch_stream_f64(const double *src, double *dst, const uint8_t *fmask, double omega, int nx, int ny,
                       int pitch, const Geometry &geo, hipStream_t st);
-int launch_wmap_f32(const uint8_t *cls, float *wmap, float omega, int nx, int ny, int pitch, hipStream_t st);
 int launch_fmask(const uint8_t *cls, uint8_t *fmask, int nx, int ny, int pitch, hipStream_t st);
 // the batch's free mask, over the batch's column blocks
 int launch_fmask_batch(const uint8_t *cls, uint8_t *fmask, const BatchGrid *grids, const int2 *blocks,
@@ -176,6 +176,41 @@ int launch_fill_f32(float *a, float v, int nx, int ny, int pitch, hipStream_t st
 int launch_copy_f32(const float *src, float *dst, int nx, int ny, int pitch, hipStream_t st);
 int launch_merge_prev(const uint8_t *cls, const uint8_t *cls_prev, const float *psi_prev, float *psi, int nx,
                       int ny, int pitch, hipStream_t st);
+
+// solve.hip: the device-driven relaxation.  One RelaxConfig per call, given
+// to the begin kernel; SlotArgs are the arguments of every slot launch.
+struct RelaxConfig {
+    double tol;          // FP32-stage tolerance on the FP64 residual
+    double need;         // residual the polish must reach (0 without polish)
+    double wbound;       // maximum-principle bound on ||(I - J)^-1 1||inf
+    int64_t max_sweeps;  // sweeps per solve (the FP32 solve, and each correction solve)
+    float omega;         // SOR factor of the FP32 solve
+    float omega_dc;      // SOR factor of the correction solves
+    float omega_lead;    // factor of the correction solves' start phase
+    int32_t lead_passes; // passes of that start phase (0: none)
+    int32_t S;           // sweeps per pass
+    int32_t polish;      // 1: FP64 defect correction after the FP32 solve
+    int32_t check_passes;  // > 0: check every this many passes
+    int32_t max_rounds;  // defect-correction rounds at most
+};
+struct SlotArgs {
+    const uint8_t *mask;  // free mask (1 on FREE cells), the grid's layout
+    float *psi;           // caller's FP32 field
+    float *alt;           // its ping-pong partner (and the correction's)
+    float *e;             // correction
+    float *r32;           // FP32 defect
+    double *psi64;        // caller's FP64 field (polish) or null
+    void *ctl;            // device control block (relax_ctl_bytes())
+    hpf_stats *stats;     // device stats, written when the solve ends
+    unsigned long long *mirror;  // host-mapped decision word, or null
+    int nx, ny, pitch;
+    int strips, RH, tiles;  // SOR tiling (S sweeps per pass)
+    int pair;             // paired-column access
+    int final_slot;       // 1: finish what is left (the solve is then NOT_CONVERGED)
+};
+size_t relax_ctl_bytes();
+int launch_relax_begin(void *ctl, const RelaxConfig &cfg, hipStream_t st);
+int launch_relax_slot(const SlotArgs &a, int S, hipStream_t st);
 
 // raster.hip
 int launch_rasterize(twg_ctx *ctx, const twg_grid &g, int n_obs, const double *pos,

@@ -18,7 +18,9 @@ Units: cells for lengths, steps for time.  Scenario recipes:
 Obstacle centres are uniform over the grid; the robot start and the goal are
 uniform over the interior (one cell inside the border).  Discs whose current
 position would cover the start are redrawn, so that the robot does not start
-inside an obstacle; nothing else is conditioned on.
+inside an obstacle.  ``reachable`` redraws the goal, from a stream of its
+own, until a caller-supplied test (which rasterises the map) finds it
+4-connected to the start; the number of redraws is recorded.
 """
 from __future__ import annotations
 
@@ -67,9 +69,25 @@ def _draw(rng, nx, ny, n_obs, rad_spec, vel_sigma, W=8, vr=1.0):
                 pos=pos, vel=vel, rad=rad, cov=cov)
 
 
-def scenario(name: str, index: int = 0, seed: int | None = None, side: int | None = None):
+def _goal_draw(seed, k, nx, ny, robot):
+    """The k-th redrawn goal (k >= 1) of a scenario: uniform over the
+    interior, never the robot cell, from a stream keyed by the scenario
+    seed alone (so redraws never change the obstacles)."""
+    rng = np.random.default_rng([int(seed), 0x60A1])
+    goal = None
+    for _ in range(k):
+        for _ in range(64):
+            goal = np.array([_cell(rng, nx), _cell(rng, ny)], dtype=np.int32)
+            if goal[0] != robot[0] or goal[1] != robot[1]:
+                break
+    return goal
+
+
+def scenario(name: str, index: int = 0, seed: int | None = None, side: int | None = None,
+             goal_draw: int = 0):
     """One scenario dict: nx, ny, robot[2], goal[2], W, vr, pos[n,2],
-    vel[n,2], rad[n], cov[n,4,4], seed, name."""
+    vel[n,2], rad[n], cov[n,4,4], seed, name, goal_draw.  goal_draw = k > 0
+    replaces the goal by the k-th redraw."""
     if seed is None:
         seed = SEED_BASE[name] + index
     rng = np.random.default_rng(seed)
@@ -83,14 +101,33 @@ def scenario(name: str, index: int = 0, seed: int | None = None, side: int | Non
         lo, hi = rec["n_obs"]
         n_obs = lo if lo == hi else int(rng.integers(lo, hi + 1))
         sc = _draw(rng, n, n, n_obs, rec["rad"], rec["vel_sigma"])
+    if goal_draw:
+        sc["goal"] = _goal_draw(seed, goal_draw, sc["nx"], sc["ny"], sc["robot"])
     sc["seed"] = int(seed)
     sc["name"] = name
+    sc["goal_draw"] = int(goal_draw)
     return sc
 
 
-def batch(n_grids: int = 256, seed: int = 3000):
-    """The uneven batch: grid k uses seed + k."""
-    return [scenario("batch", seed=seed + k) for k in range(n_grids)]
+def reachable(name: str, index: int = 0, is_reachable=None, seed: int | None = None,
+              side: int | None = None, max_draws: int = 256):
+    """The scenario with its goal redrawn until ``is_reachable(sc)`` holds
+    (the caller rasterises the map and tests 4-connectivity of start and
+    goal); sc["goal_draw"] counts the redraws.  Raises RuntimeError after
+    max_draws."""
+    for k in range(max_draws + 1):
+        sc = scenario(name, index, seed=seed, side=side, goal_draw=k)
+        if is_reachable(sc):
+            return sc
+    raise RuntimeError(f"no reachable goal in {max_draws} draws for {name}[{index}]")
+
+
+def batch(n_grids: int = 256, seed: int = 3000, is_reachable=None):
+    """The uneven batch: grid k uses seed + k; with is_reachable, each goal
+    is redrawn until reachable (see ``reachable``)."""
+    if is_reachable is None:
+        return [scenario("batch", seed=seed + k) for k in range(n_grids)]
+    return [reachable("batch", seed=seed + k, is_reachable=is_reachable) for k in range(n_grids)]
 
 
 def custom(nx, ny, n_obs, rad=(2.0, 5.0), vel_sigma=0.5, seed=0, W=8, vr=1.0):

@@ -16,7 +16,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtwg.so"
 OK, NOT_CONVERGED, NO_PATH, START_BLOCKED, NET_FALLBACK, PATH_TRUNCATED = 0, 1, 2, 3, 4, 5
 EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4
 FREE, OBST, WALL, GOAL, FIXED = 0, 1, 2, 3, 4
-INIT_KEEP, INIT_HALF, INIT_ZERO = 0, 1, 2
+INIT_KEEP, INIT_HALF, INIT_ZERO, INIT_LINEAR = 0, 1, 2, 3
 
 i32, i64, f32, f64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_void_p
 
@@ -35,7 +35,7 @@ class RasterParams(ctypes.Structure):
 class HpfParams(ctypes.Structure):
     _fields_ = [("tol", f64), ("tol_cert", f64), ("max_sweeps", i64), ("omega", f32),
                 ("init", i32), ("polish", i32), ("sweeps_per_pass", i32), ("check_passes", i32),
-                ("rows_per_tile", i32)]
+                ("rows_per_tile", i32), ("goal_x", i32), ("goal_y", i32)]
 
 
 class HpfStats(ctypes.Structure):
@@ -45,6 +45,16 @@ class HpfStats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+STATS_BYTES = ctypes.sizeof(HpfStats)
+
+
+def stats_from_device(t):
+    """hpf_stats dict from a device tensor written by relax_async (copies to the host, which
+    waits for the stream)."""
+    raw = bytes(t[:STATS_BYTES].cpu().numpy().tobytes())
+    return HpfStats.from_buffer_copy(raw).as_dict()
 
 
 class GridDesc(ctypes.Structure):
@@ -68,6 +78,7 @@ def _load():
         "twg_ctx_set_graphs": (i32, [vp, i32]),
         "twg_rasterize": (i32, [vp, Grid, i32, vp, vp, vp, vp, P(RasterParams), vp, vp, vp]),
         "hpf_relax": (i32, [vp, Grid, vp, vp, vp, P(HpfParams), P(HpfStats), vp]),
+        "hpf_relax_async": (i32, [vp, Grid, vp, vp, vp, P(HpfParams), i32, vp, vp]),
         "hpf_sweeps": (i32, [vp, Grid, vp, vp, vp, f32, i32, i32, i32, vp]),
         "hpf_relax_batched": (i32, [vp, i32, vp, vp, vp, P(HpfParams), vp, vp]),
         "hpf_residual": (i32, [vp, Grid, vp, vp, vp, vp, P(f64), vp]),
@@ -77,7 +88,7 @@ def _load():
         "hpf_descend": (i32, [vp, Grid, vp, vp, vp, P(DescendParams), vp, vp, vp]),
         "hpf_rubber_band": (i32, [vp, Grid, vp, vp, vp, vp, vp, i32, f64, i32, vp]),
         "hpf_merge_previous": (i32, [vp, Grid, vp, vp, vp, vp, vp]),
-        "hpf_init_field": (i32, [vp, Grid, vp, vp, i32, vp]),
+        "hpf_init_field": (i32, [vp, Grid, vp, vp, i32, i32, i32, vp]),
         "hpf_set_tiling": (i32, [vp, i32, i32, i32, i32, f32, i32, i32]),
         "twg_kalman_step": (i32, [vp, i32, vp, vp, vp, f64, vp, vp, vp, vp, vp]),
         "hpf_descent_all": (i32, [vp, Grid, vp, vp, vp, vp, i32, vp]),
@@ -102,7 +113,7 @@ def _load():
 lib = _load()
 EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error", "twg_ctx_set_graphs",
             "twg_rasterize",
-            "hpf_relax", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
+            "hpf_relax", "hpf_relax_async", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
             "hpf_index_matrix", "hpf_descend", "hpf_rubber_band", "hpf_merge_previous",
             "hpf_init_field", "hpf_set_tiling", "twg_kalman_step", "hpf_descent_all",
             "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
@@ -218,21 +229,48 @@ class Context:
         return x, P
 
     # ---- relaxation --------------------------------------------------------
-    def relax(self, cls, psi, psi64=None, tol=1e-6, tol_cert=0.0, max_sweeps=0, omega=0.0,
-              init=INIT_HALF, polish=0, sweeps_per_pass=0, check_passes=0, rows_per_tile=0):
-        """polish: 0 FP32 only, 1 (or True) FP64 defect correction, 2 FP64 SOR sweeps."""
+    @staticmethod
+    def _relax_params(cls, psi, psi64, tol, tol_cert, max_sweeps, omega, init, polish, sweeps_per_pass,
+                      check_passes, rows_per_tile, goal):
         nx, ny, pitch = _grid_of(psi)
         if psi.dtype != torch.float32 or cls.dtype != torch.uint8 or cls.stride(0) != pitch:
             raise ValueError("psi must be float32 and share its pitch with the uint8 class map")
         if psi64 is not None and (psi64.dtype != torch.float64 or psi64.stride(0) != pitch):
             raise ValueError("psi64 must be float64 with the same pitch")
+        gx, gy = (int(goal[0]), int(goal[1])) if goal is not None else (-1, -1)
         prm = HpfParams(float(tol), float(tol_cert), int(max_sweeps), float(omega), int(init),
-                        int(polish), int(sweeps_per_pass), int(check_passes), int(rows_per_tile))
+                        int(polish), int(sweeps_per_pass), int(check_passes), int(rows_per_tile), gx, gy)
+        return Grid(nx, ny, pitch), prm
+
+    def relax(self, cls, psi, psi64=None, tol=1e-6, tol_cert=0.0, max_sweeps=0, omega=0.0,
+              init=INIT_HALF, polish=0, sweeps_per_pass=0, check_passes=0, rows_per_tile=0, goal=None):
+        """polish: 0 FP32 only, 1 (or True) FP64 defect correction, 2 FP64 SOR
+        sweeps.  goal (x, y): the goal cell of INIT_LINEAR."""
+        g, prm = self._relax_params(cls, psi, psi64, tol, tol_cert, max_sweeps, omega, init, polish,
+                                    sweeps_per_pass, check_passes, rows_per_tile, goal)
         st = HpfStats()
-        rc = lib.hpf_relax(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), _ptr(psi64),
-                           ctypes.byref(prm), ctypes.byref(st), _stream())
+        rc = lib.hpf_relax(self.h, g, _ptr(cls), _ptr(psi), _ptr(psi64), ctypes.byref(prm), ctypes.byref(st),
+                           _stream())
         self._check(rc, allow=(OK, NOT_CONVERGED))
         return st.as_dict()
+
+    def relax_async(self, cls, psi, psi64=None, slots=1024, stats=None, tol=1e-6, tol_cert=0.0, max_sweeps=0,
+                    omega=0.0, init=INIT_HALF, polish=0, sweeps_per_pass=0, check_passes=0, rows_per_tile=0,
+                    goal=None):
+        """Enqueue the device-driven relaxation (slots launches and a final
+        one) on the current stream and return at once; stats is a device
+        uint8 tensor of STATS_BYTES bytes that receives the hpf_stats (read it
+        with stats_from_device after the stream has passed)."""
+        g, prm = self._relax_params(cls, psi, psi64, tol, tol_cert, max_sweeps, omega, init, polish,
+                                    sweeps_per_pass, check_passes, rows_per_tile, goal)
+        if stats is None:
+            stats = torch.zeros(STATS_BYTES, dtype=torch.uint8, device=psi.device)
+        if stats.dtype != torch.uint8 or stats.numel() < STATS_BYTES or not stats.is_cuda:
+            raise ValueError(f"stats must be a device uint8 tensor of at least {STATS_BYTES} bytes")
+        rc = lib.hpf_relax_async(self.h, g, _ptr(cls), _ptr(psi), _ptr(psi64), ctypes.byref(prm), int(slots),
+                                 _ptr(stats), _stream())
+        self._check(rc)
+        return stats
 
     def relax_batched(self, cls_flat, psi_flat, descs, tol=1e-6, max_sweeps=0, omega=0.0,
                       init=INIT_HALF, sweeps_per_pass=0, check_passes=0, rows_per_tile=0):
@@ -249,7 +287,7 @@ class Context:
             if d + c * b > min(cls_flat.numel(), psi_flat.numel()):
                 raise ValueError("a grid extends past the batch buffers")
         prm = HpfParams(float(tol), 0.0, int(max_sweeps), float(omega), int(init), 0,
-                        int(sweeps_per_pass), int(check_passes), int(rows_per_tile))
+                        int(sweeps_per_pass), int(check_passes), int(rows_per_tile), -1, -1)
         st = (HpfStats * n)()
         rc = lib.hpf_relax_batched(self.h, n, arr, _ptr(cls_flat), _ptr(psi_flat), ctypes.byref(prm),
                                    st, _stream())
@@ -360,11 +398,13 @@ def _merge_previous(ctx, cls, cls_prev, psi_prev, psi):
     return psi
 
 
-def _init_field(ctx, cls, psi, init=INIT_HALF):
+def _init_field(ctx, cls, psi, init=INIT_HALF, goal=None):
     nx, ny, pitch = _grid_of(psi)
     if cls.stride(0) != pitch:
         raise ValueError("class map must share psi's pitch")
-    ctx._check(lib.hpf_init_field(ctx.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), int(init), _stream()))
+    gx, gy = (int(goal[0]), int(goal[1])) if goal is not None else (-1, -1)
+    ctx._check(lib.hpf_init_field(ctx.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), int(init), gx, gy,
+                                  _stream()))
     return psi
 
 

@@ -38,3 +38,12 @@ def scenario_tensors(sc, device="cuda"):
     vel = torch.as_tensor(sc["vel"], dtype=torch.float64).reshape(-1, 2).contiguous().to(device)
     rad = torch.as_tensor(sc["rad"], dtype=torch.float64).contiguous().to(device)
     return pos, vel, rad
+
+
+def reachable_scenario(name, index=0, **kw):
+    """The scenario with its goal redrawn until the oracle's class map
+    connects it to the start (4-neighbour flood fill)."""
+    import oracle
+    from paper_1903_07441_amd import scenarios
+    return scenarios.reachable(
+        name, index, is_reachable=lambda sc: oracle.goal_reachable(oracle.rasterize(sc)[0], sc["robot"]), **kw)

@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 import torch
 
+from conftest import reachable_scenario
 from paper_1903_07441_amd import scenarios
 from test_gpu_relax import gpu_relax, random_classes, to_dev
 
@@ -41,10 +42,10 @@ def test_index_and_path_parity(ctx, orc, name, idx):
 
 @pytest.mark.parametrize("pitch_pad", [0, 4, 3])
 def test_descent_2048_reaches_goal(ctx, orc, pitch_pad):
-    # a path of thousands of cells: the walk re-stages its window many times,
-    # with 128-bit staging loads (pitch a multiple of 16), 32-bit ones
-    # (multiple of 4) or byte loads
-    sc = scenarios.scenario("replan2048", 0)
+    # a path of thousands of cells to a reachable goal: the walk re-stages
+    # its window many times, with 128-bit staging loads (pitch a multiple of
+    # 16), 32-bit ones (multiple of 4) or byte loads
+    sc = reachable_scenario("replan2048", 0)
     cls, _ = orc.rasterize(sc)
     st, psi, psi64, _ = gpu_relax(ctx, cls, tol=1e-6, polish=True, tol_cert=5e-7)
     pitch = cls.shape[1] + pitch_pad
@@ -54,8 +55,8 @@ def test_descent_2048_reaches_goal(ctx, orc, pitch_pad):
     s_orc, p_orc = orc.descend(cls, psi64, sc["robot"])
     assert s_gpu == s_orc
     np.testing.assert_array_equal(p_gpu, p_orc)
-    print(f"2048 descent status={s_gpu} length={len(p_gpu)} reachable={orc.goal_reachable(cls, sc['robot'])}",
-          flush=True)
+    print(f"2048 descent status={s_gpu} length={len(p_gpu)}", flush=True)
+    assert s_gpu == 0 and len(p_gpu) > 500
     # buffers that fill on either side of the walk's 64-cell store groups, or
     # exactly at the goal: a truncated path is the full path's prefix
     n = len(p_gpu)

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from conftest import scenario_tensors
+from conftest import reachable_scenario, scenario_tensors
 from paper_1903_07441_amd import scenarios
 
 pytestmark = pytest.mark.gpu
@@ -150,9 +150,10 @@ def test_relax_fp32_only_reaches_tolerance(ctx, orc):
 
 def test_kept_field_polish_starts_from_its_fp64_defect(ctx, orc):
     """A kept field already at tol, then the defect correction: the FP32
-    stage sweeps nothing and reports the residual the FP32 residual kernel
-    gives for that field, bit for bit (the correction's first FP64 defect
-    is the same number), and the correction still certifies the result."""
+    stage sweeps nothing and reports the residual the standalone FP32
+    residual kernel gives for that field, bit for bit (the first pass's
+    fused check evaluates the same FP64 expression), and the correction
+    still certifies the result."""
     from paper_1903_07441_amd import twg
     sc = scenarios.scenario("warped512", 0)
     cls, _ = orc.rasterize(sc)
@@ -174,19 +175,41 @@ def test_kept_field_polish_starts_from_its_fp64_defect(ctx, orc):
 
 
 def test_relax_full_size_2048_certified(ctx, orc):
-    # 2048 x 2048 time-warped field: the certificate |psi - psi*| <= r * wbound
-    # (maximum principle, any size) with r recomputed in FP64 by the oracle
-    sc = scenarios.scenario("replan2048", 0)
+    # 2048 x 2048 time-warped field with a goal reachable from the start: the
+    # certificate |psi - psi*| <= r * wbound (maximum principle, any size)
+    # with r recomputed in FP64 by the oracle, and a field that is not
+    # trivially zero
+    sc = reachable_scenario("replan2048", 0)
     cls, _ = orc.rasterize(sc)
     st, psi, psi64, c = gpu_relax(ctx, cls, tol=1e-6, polish=True, tol_cert=5e-7)
-    print(f"replan2048 stats={st}", flush=True)
+    print(f"replan2048 goal draw {sc['goal_draw']} stats={st}", flush=True)
     assert st["status"] == 0
     r = orc.residual(cls, psi64)
     bound = r * orc.wbound(2048, 2048)
     print(f"replan2048 oracle residual={r:.3e} certified error bound={bound:.3e}", flush=True)
     assert bound <= 1e-6
+    # the goal's component carries a nonzero potential: the robot's cell
+    # lies well above the bound
+    rx, ry = sc["robot"]
+    assert psi64[ry, rx] > 100 * bound
     # the FP32 copy of the field is within FP32 rounding of the FP64 one
     assert np.max(np.abs(psi - psi64)) <= 6e-8
+
+
+def test_relax_2048_enclosed_goal_is_zero_field(ctx, orc):
+    # the unredrawn goal of replan2048[0] is enclosed by a predicted disc:
+    # no FREE cell sees the goal's value, every other Dirichlet value is 0,
+    # so the exact field is psi = 0 and the result lies within its own
+    # certified bound of it
+    sc = scenarios.scenario("replan2048", 0)
+    cls, _ = orc.rasterize(sc)
+    assert not orc.goal_reachable(cls, sc["robot"])
+    st, psi, psi64, c = gpu_relax(ctx, cls, tol=1e-6, polish=True, tol_cert=5e-7)
+    assert st["status"] == 0
+    gx, gy = sc["goal"]
+    nb = [cls[gy + dy, gx + dx] for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1))]
+    assert all(v != 0 for v in nb)
+    assert np.max(np.abs(psi64[cls == 0])) <= st["cert_bound"] <= 5e-7
 
 
 def test_relax_closed_form_linear(ctx):

@@ -1,12 +1,13 @@
 """GPU parity of the learned warm start's network (twg_unet_* through the C
 ABI) against the FP64 reference in oracle/unet.py.
 
-Both sides use the same bf16-representable weights and inputs and round every
-stored activation to bf16; the GPU accumulates in FP32 and also stores the
-backward pass's activation gradients in bf16, so values are compared with a
-relative tolerance (2e-2 of the largest magnitude for outputs, 5e-2 in norm
-for gradients: a handful of 2^-9 roundings, plus ReLU decisions that an FP32
-pre-activation can take differently from an FP64 one).
+Both sides use the same bf16-representable weights and inputs, round every
+stored activation to bf16, and (for gradients) store every layer's
+activation gradient in bf16 too; the GPU accumulates in FP32.  Values are
+compared with a relative tolerance: 2e-2 of the largest magnitude for
+outputs, 1e-2 in norm for gradients (FP32 accumulation, plus the few ReLU
+decisions and bf16 roundings that an FP32 value takes differently from an
+FP64 one).
 """
 import numpy as np
 import pytest
@@ -85,12 +86,11 @@ def test_forward_matches_oracle(ctx, B, H, W):
     net.close()
 
 
-def test_gradients_match_oracle(ctx):
+def _grad_parity(ctx, B, H, W, seed, rel_tol, cos_tol):
     import torch
-    B, H, W = 2, 32, 32
-    p = bf16_params(3)
-    x = inputs(4, B, H, W)
-    rng = np.random.default_rng(5)
+    p = bf16_params(seed)
+    x = inputs(seed + 1, B, H, W)
+    rng = np.random.default_rng(seed + 2)
     target = rng.uniform(0, 1, size=(B, H, W))
     cls = np.where(rng.uniform(size=(B, H, W)) < 0.7, 0, 1).astype(np.uint8)
     net = gpu_net(ctx, p)
@@ -99,10 +99,14 @@ def test_gradients_match_oracle(ctx):
                          torch.as_tensor(target, dtype=torch.float32).cuda(),
                          torch.as_tensor(cls).cuda(), grads=grads)
     torch.cuda.synchronize()
+    # the oracle stores activations and activation gradients in bf16 as the
+    # GPU does; only the FP32 accumulation (and ReLU decisions an FP32
+    # pre-activation takes differently) separate the two
     want_loss, want = ou.loss_and_grads(p, [x[b].transpose(2, 0, 1) for b in range(B)], list(target),
-                                        [cls[b] == 0 for b in range(B)], bf16_acts=True)
-    assert abs(float(loss.item()) - want_loss) <= 1e-2 * want_loss
+                                        [cls[b] == 0 for b in range(B)], bf16_acts=True, bf16_grads=True)
+    assert abs(float(loss.item()) - want_loss) <= 1e-3 * want_loss
     g = unflat(grads.cpu().numpy().astype(np.float64))
+    worst = 0.0
     for n, *_ in ou.LAYERS:
         for part in (".w", ".b"):
             a, b = g[n + part], want[n + part]
@@ -110,8 +114,46 @@ def test_gradients_match_oracle(ctx):
             assert nb > 0, n + part
             rel = np.linalg.norm(a - b) / nb
             cos = float(np.sum(a * b) / (np.linalg.norm(a) * nb))
-            assert rel <= 5e-2 and cos >= 0.998, (n + part, rel, cos)
+            worst = max(worst, rel)
+            print(f"B={B} {H}x{W} {n + part}: rel {rel:.2e} cos {cos:.7f}", flush=True)
+            assert rel <= rel_tol and cos >= cos_tol, (n + part, rel, cos)
     net.close()
+    return worst
+
+
+def test_gradients_match_oracle(ctx):
+    # P13: GPU gradients within ~1e-2 of the FP64 reference on the same bf16
+    # operands (FP32 accumulation)
+    _grad_parity(ctx, 2, 32, 32, 3, 1e-2, 0.9999)
+
+
+def _splits_summing_several_tiles(B, H, W):
+    """Layers whose weight-gradient kernel sums more than one 16 x 16 pixel
+    tile per split of the pixel reduction: the kernel splits the reduction of
+    a layer with CIN input channels into max(1, 256 / (CIN / 32)) parts (at
+    most one per tile) over B * ceil(h / 16) * ceil(w / 16) tiles at the
+    layer's resolution h x w."""
+    layers = {"e0": (32, 1), "e1": (32, 2), "e2": (64, 4), "e3": (128, 8),
+              "d2": (256, 4), "d1": (128, 2), "d0": (64, 1)}
+    out = set()
+    for name, (cin, down) in layers.items():
+        h, w = H // down, W // down
+        ntile = B * ((h + 15) // 16) * ((w + 15) // 16)
+        if ntile > max(1, 256 // (cin // 32)):
+            out.add(name)
+    return out
+
+
+def test_gradients_match_oracle_multi_tile_splits(ctx):
+    # the training batch (16 x 256 x 256) makes every split of the weight
+    # gradient's pixel reduction sum several tiles in layers e0, e1, e2, d2,
+    # d1 and d0; this batch does the same, so the accumulation over tiles
+    # within a split is compared with the oracle too
+    train = _splits_summing_several_tiles(16, 256, 256)
+    here = _splits_summing_several_tiles(9, 256, 256)
+    print(f"multi-tile splits: training {sorted(train)}, test {sorted(here)}", flush=True)
+    assert train <= here and len(train) == 6
+    _grad_parity(ctx, 9, 256, 256, 21, 1e-2, 0.9999)
 
 
 def test_gradients_deterministic(ctx):

@@ -305,3 +305,114 @@ def test_outside_grid_counts_as_fixed_zero(orc):
     padded[1:6, 1:6] = cls
     psi2, _ = orc.relax(padded, tol=1e-15)
     assert np.max(np.abs(psi - psi2[1:6, 1:6])) < 1e-13
+
+
+def _plain_red_black_sweep(cls, psi, omega, f=None, order=(0, 1)):
+    """One red-black SOR sweep written from Eqs. (1)-(2) as plainly as NumPy
+    allows: red cells ((x + y) even) first, then black, each FREE cell set to
+    psi + omega * (mean of its four neighbours + f - psi), neighbours outside
+    the grid counting as psi = 0.  Whole-array arithmetic, NumPy's own
+    evaluation order, no fused operations."""
+    ny, nx = cls.shape
+    psi = psi.copy()
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    for colour in order:
+        p = np.pad(psi, 1)
+        avg = (p[1:-1, 2:] + p[1:-1, :-2] + p[2:, 1:-1] + p[:-2, 1:-1]) / 4.0
+        if f is not None:
+            avg = avg + f
+        new = psi + omega * (avg - psi)
+        sel = (cls == 0) & (((xx + yy) % 2) == colour)
+        psi[sel] = new[sel]
+    return psi
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.5, 1.95])
+@pytest.mark.parametrize("with_source", [False, True])
+def test_sor_sweep_equals_plain_update_within_rounding(orc, omega, with_source):
+    # R2: the oracle's sweep evaluates the update as
+    # fma(omega, fma(1/4, ((E+W)+N)+S, f - psi), psi); the paper fixes the
+    # update (Eqs. 1-2), not its evaluation order.  Against the plain form,
+    # one sweep may differ only by rounding: on values in [0, 1] a handful of
+    # unit roundoffs per half-sweep, growing at most linearly over sweeps
+    # (the sweep is non-expansive in the max norm for omega <= 2 on these
+    # fields' scale).  A wrong colour order, a dropped neighbour, a wrong
+    # factor or a wrong sign differs by orders of magnitude more.
+    rng = np.random.default_rng(int(omega * 100) + with_source)
+    ny, nx = 37, 52
+    cls = np.where(rng.uniform(size=(ny, nx)) < 0.15, 1, 0).astype(np.uint8)
+    cls[0, :] = cls[-1, :] = cls[:, 0] = cls[:, -1] = 2
+    cls[rng.uniform(size=(ny, nx)) < 0.03] = 4
+    cls[10, 20] = 3
+    psi0 = orc.field_init(cls, rng.uniform(size=(ny, nx)), orc.INIT_KEEP)
+    f = rng.normal(size=(ny, nx)) * 1e-3 if with_source else None
+    eps = np.finfo(np.float64).eps
+    a, b = psi0.copy(), psi0.copy()
+    for k in range(1, 11):
+        a = orc.sor_sweep(cls, a, omega, f=f)
+        b = _plain_red_black_sweep(cls, b, omega, f=f)
+        assert np.max(np.abs(a - b)) <= 16 * k * eps, (k, np.max(np.abs(a - b)))
+    # the pin has teeth: black first, or a factor off by one part in 10^4,
+    # differs by far more than rounding
+    black_first = _plain_red_black_sweep(cls, psi0, omega, f=f, order=(1, 0))
+    other_factor = _plain_red_black_sweep(cls, psi0, omega * (1 + 1e-4), f=f)
+    one = orc.sor_sweep(cls, psi0, omega, f=f)
+    assert np.max(np.abs(one - black_first)) > 1e-3
+    assert np.max(np.abs(one - other_factor)) > 1e3 * eps
+
+
+def _tie_grid(values):
+    """3 x 3 FREE block inside walls (5 x 5): the centre (2, 2) at psi 0.1,
+    its E, W, S, N neighbours at the given psi values, every other cell a
+    wall."""
+    cls = np.full((5, 5), 2, np.uint8)
+    psi = np.zeros((5, 5))
+    cls[2, 2] = 0
+    psi[2, 2] = 0.1
+    for (dx, dy), v in zip(((1, 0), (-1, 0), (0, 1), (0, -1)), values):
+        cls[2 + dy, 2 + dx] = 0
+        psi[2 + dy, 2 + dx] = v
+    return cls, psi
+
+
+@pytest.mark.parametrize("values,want", [
+    ((0.7, 0.7, 0.7, 0.7), 0),      # all four tie: E
+    ((0.3, 0.7, 0.7, 0.7), 1),      # W, S, N tie: W
+    ((0.3, 0.2, 0.7, 0.7), 2),      # S, N tie: S
+    ((0.3, 0.2, 0.1, 0.7), 3),      # N alone
+    ((0.7, 0.3, 0.2, 0.7), 0),      # E and N tie: E
+    ((0.3, 0.7, 0.2, 0.7), 1),      # W and N tie: W
+    ((0.1, 0.1, 0.1, 0.1), 4),      # no neighbour strictly better: no move
+    ((0.1, 0.1, 0.1, 0.100001), 3),
+])
+def test_index_tie_break_order(orc, values, want):
+    # R10 (Eq. 3 is garbled): among the neighbours with the highest psi the
+    # first in the order E, W, S, N wins; a move needs a strictly higher psi.
+    # Exact ties, hand-built, so any other order or a non-strict test fails.
+    cls, psi = _tie_grid(values)
+    assert orc.index_matrix(cls, psi)[2, 2] == want
+    # the walk takes the same first step
+    cls2 = cls.copy()
+    if want != 4:
+        dx, dy = ((1, 0), (-1, 0), (0, 1), (0, -1))[want]
+        cls2[2 + dy, 2 + dx] = 3  # the chosen neighbour is the goal
+        status, path = orc.descend(cls2, psi, (2, 2))
+        assert status == orc.OK and path.tolist() == [[2, 2], [2 + dx, 2 + dy]]
+
+
+def test_linear_ramp_init(orc):
+    # the linear-ramp start: 1 at the goal, falling with the Euclidean
+    # distance d to the goal as 1 - d / (max(nx, ny) sqrt 2), so it stays in
+    # (0, 1] on the grid; fixed cells take their Dirichlet values
+    ny, nx = 9, 13
+    cls = np.zeros((ny, nx), np.uint8)
+    cls[0, :] = 2
+    cls[4, 6] = 1
+    cls[2, 3] = 3
+    psi = orc.field_init(cls, None, orc.INIT_LINEAR, goal=(3, 2))
+    span = 13 * np.sqrt(2.0)
+    assert psi[2, 3] == 1.0 and psi[4, 6] == 0.0 and np.all(psi[0] == 0.0)
+    assert psi[2, 4] == 1.0 - 1.0 / span and psi[5, 7] == 1.0 - 5.0 / span  # 3-4-5 triangle
+    assert psi[8, 12] == 1.0 - np.sqrt(81 + 36) / span
+    free = cls == 0
+    assert np.all((psi[free] > 0) & (psi[free] < 1))

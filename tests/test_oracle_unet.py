@@ -126,3 +126,33 @@ def test_training_decreases_loss():
         p = unet.adam_step(p, g, st, lr=2e-3)
         l, g = unet.loss_and_grads(p, xs, ts, ms)
     assert l < 0.5 * l0
+
+
+def test_bf16_gradient_storage_option():
+    # bf16_grads rounds each layer's masked pre-activation gradient to bf16:
+    # the gradients then differ from the FP64 ones by about one 2^-9 rounding
+    # (not by zero, not by more); the loss does not change
+    rng = np.random.default_rng(8)
+    p = unet.init_params(9)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = rng.normal(size=p[k].shape) * 0.1
+    xs = [unet.bf16_round(rng.uniform(size=(3, 16, 16))) for _ in range(2)]
+    ts = [rng.uniform(size=(16, 16)) for _ in range(2)]
+    ms = [rng.uniform(size=(16, 16)) < 0.8 for _ in range(2)]
+    l0, g0 = unet.loss_and_grads(p, xs, ts, ms, bf16_acts=True)
+    l1, g1 = unet.loss_and_grads(p, xs, ts, ms, bf16_acts=True, bf16_grads=True)
+    assert l0 == l1
+    for k in g0:
+        rel = np.linalg.norm(g1[k] - g0[k]) / np.linalg.norm(g0[k])
+        # the head's own gradients come before any rounding
+        if k.startswith("head"):
+            assert rel == 0.0, k
+        else:
+            assert 0.0 < rel < 2.0 ** -7, (k, rel)
+    # one rounding of the head's masked gradient, checked elementwise
+    y, c = unet.forward(p, xs[0], bf16_acts=True)
+    _, dy = unet.masked_mse(y, ts[0], ms[0])
+    want = unet.bf16_round(p["head.w"][0, :, 0, 0][:, None, None] * dy[None] * (c["d0"] > 0))
+    dd0, _, _ = unet.conv_backward(c["d0"], p["head.w"], dy[None])
+    np.testing.assert_array_equal(unet.bf16_round(dd0 * (c["d0"] > 0)), want)
