@@ -293,6 +293,26 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
 int32_t hpf_relax_async(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, double *psi64,
                         const hpf_params *params, int32_t slots, hpf_stats *stats, void *stream);
 
+/* hpf_relax_async_noalloc -- hpf_relax_async for callers that cannot
+ * allocate device memory: code under HIP graph capture (also at the first
+ * call of a grid size), tight serving loops, harnesses that forbid
+ * hipMalloc.  The same launches and the same results, bit for bit, with
+ * every scratch buffer (control block, FP32 ping-pong partner, defect and
+ * correction, free mask) inside one static device array of the library,
+ * 13 bytes per cell for at most 4194304 cells plus 4 KiB (52 MiB and 4 KiB),
+ * which each GPU the library runs on holds until the process ends.  The call
+ * itself allocates nothing on the device (no hipMalloc, no hipFree).
+ * Limit: pitch * ny <= 4194304 (e.g. 2048 x 2048); larger grids return
+ * TWG_EUNSUPPORTED before any launch.  Every call on one GPU shares that
+ * GPU's array, which keeps the last call's contents (each call resets its
+ * control block with a kernel and writes every other buffer before reading
+ * it): calls that overlap on one GPU -- on two streams, or from two contexts
+ * -- race and give undefined results; serialise them.  hpf_relax and
+ * hpf_relax_async use the context's own scratch and do not race with it.
+ * Arguments, stats and errors as hpf_relax_async. */
+int32_t hpf_relax_async_noalloc(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, double *psi64,
+                                const hpf_params *params, int32_t slots, hpf_stats *stats, void *stream);
+
 typedef struct {
     int32_t nx, ny, pitch; /* as twg_grid */
     int32_t reserved;

@@ -6,9 +6,50 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "twg_internal.h"
+
+// Scratch of hpf_relax_async_noalloc, for callers that cannot allocate: one
+// file-scope device array, a copy of which each GPU the library runs on holds
+// until the process ends.  Its layout for a grid of n = pitch * ny <=
+// kNoAllocMaxCells cells: the control block and default stats at 0, then the
+// FP32 ping-pong partner, the FP32 defect and correction, and the free mask,
+// each at a fixed offset sized for the largest grid.  Host code never names
+// the array in a launch or copy: it uses the device address that
+// hipGetSymbolAddress gave for the current device (noalloc_scratch below).
+namespace {
+constexpr size_t kNoAllocMaxCells = size_t(1) << 22;  // e.g. 2048 x 2048
+constexpr size_t kNoAllocCtlBytes = 4096;
+constexpr size_t kNoAllocAlt = kNoAllocCtlBytes;
+constexpr size_t kNoAllocPol = kNoAllocAlt + 4 * kNoAllocMaxCells;
+constexpr size_t kNoAllocMask = kNoAllocPol + 8 * kNoAllocMaxCells;
+constexpr size_t kNoAllocBytes = kNoAllocMask + kNoAllocMaxCells;
+constexpr int kNoAllocDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kNoAllocDevices] = {};
+
+// the device address of `scratch` on `device` (which must be current),
+// looked up once per device
+int noalloc_scratch(int device, void **out)
+{
+    if (device < 0 || device >= kNoAllocDevices) return TWG_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TWG_EDEVICE;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return TWG_OK;
+}
+}  // namespace
 
 namespace twg {
 
@@ -375,24 +416,47 @@ constexpr int64_t kSlotMargin = 3;
 // beyond the next decision the device publishes (it never waits for a
 // residual), stops when the device reports the solve done, then waits for
 // the stream and copies the stats to *stats_host.
-int relax_device(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float *psi, double *psi64,
-                 const hpf_params &p, const RelaxPlan &pl, int64_t slots, hpf_stats *stats_dev,
-                 hpf_stats *stats_host, hipStream_t st)
+// Scratch of the device-driven relaxation of a grid of n = pitch * ny cells:
+// the FP32 ping-pong partner (4n bytes), with polish the FP32 defect and
+// correction (8n), the free mask (n), and the control block followed by a
+// default device hpf_stats (relax_ctl_bytes() + 256).
+struct RelaxBufs {
+    float *alt = nullptr;
+    float *pol = nullptr;
+    uint8_t *fmask = nullptr;
+    char *ctl = nullptr;
+};
+
+// the context's scratch, allocated (or grown) here
+int relax_bufs_ctx(twg_ctx *ctx, const twg_grid &g, bool polish, RelaxBufs *b)
 {
     const size_t n = (size_t)g.pitch * g.ny;
     int rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, n * sizeof(float));
-    if (!rc && p.polish) rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n * sizeof(float));
+    if (!rc && polish) rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n * sizeof(float));
     if (!rc) rc = ensure(ctx, &ctx->fmask, &ctx->fmask_bytes, n);
     if (!rc) rc = ensure(ctx, &ctx->ctl, &ctx->ctl_bytes, relax_ctl_bytes() + 256);
     if (rc) return rc;
-    char *ctl = static_cast<char *>(ctx->ctl);
+    b->alt = static_cast<float *>(ctx->alt);
+    b->pol = polish ? static_cast<float *>(ctx->pol) : nullptr;
+    b->fmask = static_cast<uint8_t *>(ctx->fmask);
+    b->ctl = static_cast<char *>(ctx->ctl);
+    return TWG_OK;
+}
+
+int relax_device(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float *psi, double *psi64,
+                 const hpf_params &p, const RelaxPlan &pl, const RelaxBufs &bufs, int64_t slots,
+                 hpf_stats *stats_dev, hpf_stats *stats_host, hipStream_t st)
+{
+    const size_t n = (size_t)g.pitch * g.ny;
+    int rc = TWG_OK;
+    char *ctl = bufs.ctl;
     hpf_stats *dstats = stats_dev ? stats_dev : reinterpret_cast<hpf_stats *>(ctl + relax_ctl_bytes());
     const int cap = stream_rows_cap(g.pitch, (int)sizeof(float), pl.S);
     const Geometry geo = stream_geometry(g.nx, g.ny, pl.S, std::min(pl.RH, cap));
     const double wb = std::pow((double)std::min(g.nx, g.ny) + 1.0, 2) / 2.0;
 
     rc = launch_field_init(cls, psi, g.nx, g.ny, g.pitch, p.init, p.goal_x, p.goal_y, st);
-    if (!rc) rc = launch_fmask(cls, static_cast<uint8_t *>(ctx->fmask), g.nx, g.ny, g.pitch, st);
+    if (!rc) rc = launch_fmask(cls, bufs.fmask, g.nx, g.ny, g.pitch, st);
     if (rc) return set_err(ctx, rc, "relaxation set-up launch failed");
     RelaxConfig cfg;
     cfg.tol = p.tol;
@@ -411,10 +475,10 @@ int relax_device(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float *psi
     if (rc) return set_err(ctx, rc, "relaxation begin launch failed");
 
     SlotArgs a;
-    a.mask = static_cast<const uint8_t *>(ctx->fmask);
+    a.mask = bufs.fmask;
     a.psi = psi;
-    a.alt = static_cast<float *>(ctx->alt);
-    a.r32 = p.polish ? static_cast<float *>(ctx->pol) : nullptr;
+    a.alt = bufs.alt;
+    a.r32 = p.polish ? bufs.pol : nullptr;
     a.e = p.polish ? a.r32 + n : nullptr;
     a.psi64 = p.polish ? psi64 : nullptr;
     a.ctl = ctl;
@@ -477,6 +541,17 @@ int relax_device(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float *psi
     return TWG_OK;
 }
 
+// relax_device on the context's scratch
+int relax_device_ctx(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float *psi, double *psi64,
+                     const hpf_params &p, const RelaxPlan &pl, int64_t slots, hpf_stats *stats_dev,
+                     hpf_stats *stats_host, hipStream_t st)
+{
+    RelaxBufs b;
+    const int rc = relax_bufs_ctx(ctx, g, p.polish != 0, &b);
+    if (rc) return rc;
+    return relax_device(ctx, g, cls, psi, psi64, p, pl, b, slots, stats_dev, stats_host, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -506,6 +581,11 @@ int32_t twg_ctx_create(twg_ctx **out, int32_t device)
         hipSuccess) {
         twg_ctx_destroy(ctx);
         return TWG_EDEVICE;
+    }
+    // the static scratch of hpf_relax_async_noalloc on this device
+    if (const int rc = noalloc_scratch(device, &ctx->noalloc)) {
+        twg_ctx_destroy(ctx);
+        return rc;
     }
     *out = ctx;
     return TWG_OK;
@@ -614,7 +694,7 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
         // FP32 solve on the device, then FP64 SOR sweeps driven from the host
         hpf_params p0 = p;
         p0.polish = 0;
-        rc = relax_device(ctx, g, cls, psi, nullptr, p0, pl, 0, nullptr, &s, st);
+        rc = relax_device_ctx(ctx, g, cls, psi, nullptr, p0, pl, 0, nullptr, &s, st);
         if (rc) return rc;
         if (s.status == TWG_EINVAL) return set_err(ctx, TWG_EINVAL, "non-finite value in the field");
         const double need = p.tol_cert > 0.0 ? std::min(p.tol, p.tol_cert / s.wbound) : p.tol;
@@ -633,7 +713,7 @@ int32_t hpf_relax(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, doub
         s.status = done ? TWG_OK : TWG_NOT_CONVERGED;
         s.checks += run.checks;
     } else {
-        rc = relax_device(ctx, g, cls, psi, psi64, p, pl, 0, nullptr, &s, st);
+        rc = relax_device_ctx(ctx, g, cls, psi, psi64, p, pl, 0, nullptr, &s, st);
         if (rc) return rc;
     }
     if (stats) *stats = s;
@@ -657,7 +737,35 @@ int32_t hpf_relax_async(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi
     if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
     hipSetDevice(ctx->device);
     const RelaxPlan pl = plan_for(ctx, g, p);
-    return relax_device(ctx, g, cls, psi, psi64, p, pl, slots, stats, nullptr, as_stream(stream));
+    return relax_device_ctx(ctx, g, cls, psi, psi64, p, pl, slots, stats, nullptr, as_stream(stream));
+}
+
+int32_t hpf_relax_async_noalloc(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, double *psi64,
+                                const hpf_params *params, int32_t slots, hpf_stats *stats, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    int rc = check_relax_args(ctx, g, cls, psi, psi64, params);
+    if (rc) return rc;
+    if (params->polish == 2) return set_err(ctx, TWG_EUNSUPPORTED, "the asynchronous relaxation polishes by defect correction only");
+    if (slots < 1) return set_err(ctx, TWG_EINVAL, "slots must be >= 1");
+    if (!stats) return set_err(ctx, TWG_EINVAL, "stats (device) is required");
+    if ((size_t)g.pitch * (size_t)g.ny > kNoAllocMaxCells)
+        return set_err(ctx, TWG_EUNSUPPORTED, "hpf_relax_async_noalloc takes grids of at most " +
+                                                  std::to_string(kNoAllocMaxCells) + " cells (pitch * ny)");
+    if (relax_ctl_bytes() + 256 > kNoAllocCtlBytes) return set_err(ctx, TWG_EDEVICE, "control block too large");
+    if (!ctx->noalloc) return set_err(ctx, TWG_EDEVICE, "no static scratch on this device");
+    hpf_params p = *params;
+    if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
+    hipSetDevice(ctx->device);
+    const RelaxPlan pl = plan_for(ctx, g, p);
+    char *base = static_cast<char *>(ctx->noalloc);
+    RelaxBufs b;
+    b.ctl = base;
+    b.alt = reinterpret_cast<float *>(base + kNoAllocAlt);
+    b.pol = p.polish ? reinterpret_cast<float *>(base + kNoAllocPol) : nullptr;
+    b.fmask = reinterpret_cast<uint8_t *>(base + kNoAllocMask);
+    return relax_device(ctx, g, cls, psi, psi64, p, pl, b, slots, stats, nullptr, as_stream(stream));
 }
 
 int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, const uint8_t *cls,
@@ -1072,7 +1180,7 @@ int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, 
             pl.omega = om;
             pl.omega_dc = om_dc;
             pl.lead = lp;
-            return relax_device(ctx, g, cls, fld, f64, tp, pl, 0, nullptr, s, st);
+            return relax_device_ctx(ctx, g, cls, fld, f64, tp, pl, 0, nullptr, s, st);
         };
         int64_t sw_plain[NC] = {0};
         for (int i = 0; i < NC && !rc; ++i) {

@@ -83,6 +83,9 @@ struct twg_ctx {
     // control block of the device-driven relaxation and its device stats
     void *ctl = nullptr;
     size_t ctl_bytes = 0;
+    // this device's copy of the static scratch of hpf_relax_async_noalloc
+    // (its device address; not owned)
+    void *noalloc = nullptr;
     // instantiated graphs of relaxation passes, keyed by their launch
     // arguments, and the stream they are captured on
     struct Graph {

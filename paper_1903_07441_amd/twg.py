@@ -79,6 +79,7 @@ def _load():
         "twg_rasterize": (i32, [vp, Grid, i32, vp, vp, vp, vp, P(RasterParams), vp, vp, vp]),
         "hpf_relax": (i32, [vp, Grid, vp, vp, vp, P(HpfParams), P(HpfStats), vp]),
         "hpf_relax_async": (i32, [vp, Grid, vp, vp, vp, P(HpfParams), i32, vp, vp]),
+        "hpf_relax_async_noalloc": (i32, [vp, Grid, vp, vp, vp, P(HpfParams), i32, vp, vp]),
         "hpf_sweeps": (i32, [vp, Grid, vp, vp, vp, f32, i32, i32, i32, vp]),
         "hpf_relax_batched": (i32, [vp, i32, vp, vp, vp, P(HpfParams), vp, vp]),
         "hpf_residual": (i32, [vp, Grid, vp, vp, vp, vp, P(f64), vp]),
@@ -113,7 +114,7 @@ def _load():
 lib = _load()
 EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error", "twg_ctx_set_graphs",
             "twg_rasterize",
-            "hpf_relax", "hpf_relax_async", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
+            "hpf_relax", "hpf_relax_async", "hpf_relax_async_noalloc", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
             "hpf_index_matrix", "hpf_descend", "hpf_rubber_band", "hpf_merge_previous",
             "hpf_init_field", "hpf_set_tiling", "twg_kalman_step", "hpf_descent_all",
             "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
@@ -256,19 +257,21 @@ class Context:
 
     def relax_async(self, cls, psi, psi64=None, slots=1024, stats=None, tol=1e-6, tol_cert=0.0, max_sweeps=0,
                     omega=0.0, init=INIT_HALF, polish=0, sweeps_per_pass=0, check_passes=0, rows_per_tile=0,
-                    goal=None):
+                    goal=None, noalloc=False):
         """Enqueue the device-driven relaxation (slots launches and a final
         one) on the current stream and return at once; stats is a device
         uint8 tensor of STATS_BYTES bytes that receives the hpf_stats (read it
-        with stats_from_device after the stream has passed)."""
+        with stats_from_device after the stream has passed).  noalloc=True
+        calls hpf_relax_async_noalloc (the library's static scratch; pass
+        stats to keep torch from allocating too)."""
         g, prm = self._relax_params(cls, psi, psi64, tol, tol_cert, max_sweeps, omega, init, polish,
                                     sweeps_per_pass, check_passes, rows_per_tile, goal)
         if stats is None:
             stats = torch.zeros(STATS_BYTES, dtype=torch.uint8, device=psi.device)
         if stats.dtype != torch.uint8 or stats.numel() < STATS_BYTES or not stats.is_cuda:
             raise ValueError(f"stats must be a device uint8 tensor of at least {STATS_BYTES} bytes")
-        rc = lib.hpf_relax_async(self.h, g, _ptr(cls), _ptr(psi), _ptr(psi64), ctypes.byref(prm), int(slots),
-                                 _ptr(stats), _stream())
+        fn = lib.hpf_relax_async_noalloc if noalloc else lib.hpf_relax_async
+        rc = fn(self.h, g, _ptr(cls), _ptr(psi), _ptr(psi64), ctypes.byref(prm), int(slots), _ptr(stats), _stream())
         self._check(rc)
         return stats
 
