@@ -492,12 +492,21 @@ int relax_device(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float *psi
     const auto al8 = [](const void *q) { return (reinterpret_cast<uintptr_t>(q) & 7) == 0; };
     a.pair = g.nx % 2 == 0 && g.pitch % 2 == 0 && al8(psi) && al8(a.alt) && (!p.polish || (al8(a.r32) && al8(a.e)));
     a.final_slot = 0;
+    a.slot = 0;
+    a.polish = cfg.polish;
+    a.omega = cfg.omega;
+    a.omega_dc = cfg.omega_dc;
+    a.omega_lead = cfg.omega_lead;
+    a.lead_passes = cfg.lead_passes;
 
     if (slots > 0) {
         a.mirror = nullptr;
-        for (int64_t k = 0; k < slots; ++k)
+        for (int64_t k = 0; k < slots; ++k) {
+            a.slot = (int)k;
             if ((rc = launch_relax_slot(a, pl.S, st))) return set_err(ctx, rc, "relaxation slot launch failed");
+        }
         a.final_slot = 1;
+        a.slot = (int)slots;
         rc = launch_relax_slot(a, pl.S, st);
         return rc ? set_err(ctx, rc, "relaxation slot launch failed") : TWG_OK;
     }
@@ -521,6 +530,7 @@ int relax_device(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float *psi
             target = std::max<int64_t>(target, (int64_t)(w & 0xffffffffull) + kSlotMargin);
         }
         if (queued < target) {
+            a.slot = (int)queued;
             if ((rc = launch_relax_slot(a, pl.S, st))) return set_err(ctx, rc, "relaxation slot launch failed");
             ++queued;
             continue;

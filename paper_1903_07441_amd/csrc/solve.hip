@@ -44,22 +44,32 @@ enum : int { PH_PLAIN = 0, PH_DEFECT32, PH_CORR, PH_UPDATE, PH_DEFECT64, PH_FINI
 // gain on its best residual that together span at least this many sweeps
 constexpr int64_t kStallSweeps = 256;
 
-struct RelaxCtl {
-    RelaxConfig c;
+// The words every slot reads when it starts, loaded together (one scalar
+// load): a run of passes of the current solve began at slot run_slot with
+// pass number `pass` and the field (or correction) in buffer parity
+// `parity` (`cparity`); slot k of the run does pass pass + (k - run_slot) on
+// parity ^ ((k - run_slot) & 1), so a pass that does not check writes
+// nothing to the control block.
+struct alignas(32) RelaxHot {
     int32_t phase;
-    int32_t parity;        // FP32 field: 0 in psi, 1 in alt
-    int32_t cparity;       // correction: 0 in e, 1 in alt
+    int32_t parity;        // FP32 field at run_slot: 0 in psi, 1 in alt
+    int32_t cparity;       // correction at run_slot: 0 in e, 1 in alt
+    int32_t pass;          // pass number of slot run_slot
+    int32_t run_slot;
+    int32_t next_check;    // pass of the next residual check
     int32_t fresh;         // psi holds the rounded polished field
     int32_t wide;          // psi64 holds the (widened or polished) field
-    int32_t pass;          // passes of the current solve
-    int32_t next_check;    // pass of the next residual check
+};
+
+struct RelaxCtl {
+    RelaxHot h;
+    RelaxConfig c;
     int32_t last_check;    // pass of the last check
     int32_t lead_check;    // the next check ends a correction start phase
     int32_t solve_checks;  // checks of the current solve
     int32_t stalls;
     int32_t checks;        // residual evaluations of the whole call
     int32_t rounds;        // defect-correction updates
-    int32_t slot;          // slots that did work
     int32_t status;
     int32_t pad;
     uint32_t ticket;       // workgroups of the current slot that have finished
@@ -108,18 +118,19 @@ __device__ int32_t next_passes(RelaxCtl *c, double r)
     }
     int64_t passes = (chunk + S - 1) / S;
     const int64_t pmax = c->c.max_sweeps / S;
-    if (c->pass + passes > pmax) passes = pmax - c->pass;
+    if (c->h.pass + passes > pmax) passes = pmax - c->h.pass;
     if (passes < 1) passes = 1;
     c->last_chunk = passes * S;
     return (int32_t)passes;
 }
 
 // start the correction solve of one defect-correction round from residual r64
-__device__ void start_correction(RelaxCtl *c, double r64)
+__device__ void start_correction(RelaxCtl *c, double r64, int32_t first_slot)
 {
-    c->phase = PH_CORR;
-    c->pass = 0;
-    c->cparity = 0;
+    c->h.phase = PH_CORR;
+    c->h.pass = 0;
+    c->h.cparity = 0;
+    c->h.run_slot = first_slot;
     c->solve_checks = 0;
     // at most four decades per round (the FP32 correction keeps about that
     // much relative accuracy), and no further than a third of what is left
@@ -135,12 +146,12 @@ __device__ void start_correction(RelaxCtl *c, double r64)
         // the start phase runs at the smaller factor, then a check
         int32_t lp = c->c.lead_passes;
         const int32_t pmax = (int32_t)(c->c.max_sweeps / c->c.S);
-        c->next_check = lp < pmax ? lp : pmax;
+        c->h.next_check = lp < pmax ? lp : pmax;
         c->lead_check = 1;
     } else {
         // the defect is the solve's initial residual (e = 0)
         c->solve_checks = 1;
-        c->next_check = next_passes(c, r64);
+        c->h.next_check = next_passes(c, r64);
         c->lead_check = 0;
     }
 }
@@ -148,21 +159,21 @@ __device__ void start_correction(RelaxCtl *c, double r64)
 // end of the FP32 solve at pass p (the result is this pass's input)
 __device__ void end_solve(RelaxCtl *c, bool conv, double r, double rel)
 {
-    if (c->phase == PH_PLAIN) {
-        c->sweeps = (int64_t)c->pass * c->c.S;
+    if (c->h.phase == PH_PLAIN) {
+        c->sweeps = (int64_t)c->h.pass * c->c.S;
         c->residual32 = r;
         c->residual_rel = rel;
         c->residual = r;
         c->status = conv ? TWG_OK : TWG_NOT_CONVERGED;
-        c->phase = c->c.polish ? PH_DEFECT32 : PH_FINISH;
+        c->h.phase = c->c.polish ? PH_DEFECT32 : PH_FINISH;
     } else {
-        c->polish_sweeps += (int64_t)c->pass * c->c.S;
+        c->polish_sweeps += (int64_t)c->h.pass * c->c.S;
         c->rate_dc = c->rate;
-        c->phase = PH_UPDATE;
+        c->h.phase = PH_UPDATE;
     }
 }
 
-// a residual check of an FP32 solve at pass c->pass
+// a residual check of an FP32 solve at pass c->h.pass
 __device__ void on_check(RelaxCtl *c, double r, double rel)
 {
     ++c->checks;
@@ -170,7 +181,7 @@ __device__ void on_check(RelaxCtl *c, double r, double rel)
     ++c->solve_checks;
     if (r != r) {
         c->status = TWG_EINVAL;
-        c->phase = PH_FINISH;
+        c->h.phase = PH_FINISH;
         return;
     }
     if (initial) {
@@ -179,7 +190,7 @@ __device__ void on_check(RelaxCtl *c, double r, double rel)
         c->since = 0;
         c->lead_check = 0;
     } else {
-        const int64_t chunk = (int64_t)(c->pass - c->last_check) * c->c.S;
+        const int64_t chunk = (int64_t)(c->h.pass - c->last_check) * c->c.S;
         if (r < c->r_prev && chunk > 0) {
             const double q = pow(r / c->r_prev, 1.0 / (double)chunk);
             if (q > 0.0 && q < 1.0) c->rate = q;
@@ -196,35 +207,35 @@ __device__ void on_check(RelaxCtl *c, double r, double rel)
         }
     }
     c->r_prev = r;
-    c->last_check = c->pass;
+    c->last_check = c->h.pass;
     if (r <= c->tol_cur) {
         end_solve(c, true, r, rel);
         return;
     }
-    if ((int64_t)c->pass * c->c.S >= c->c.max_sweeps || (c->stalls >= 3 && c->since >= kStallSweeps)) {
+    if ((int64_t)c->h.pass * c->c.S >= c->c.max_sweeps || (c->stalls >= 3 && c->since >= kStallSweeps)) {
         end_solve(c, false, r, rel);
         return;
     }
-    c->next_check = c->pass + next_passes(c, r);
+    c->h.next_check = c->h.pass + next_passes(c, r);
 }
 
 // a defect: polish done, or the next correction round
-__device__ void on_defect(RelaxCtl *c, double r64)
+__device__ void on_defect(RelaxCtl *c, double r64, int32_t slot_now)
 {
     ++c->checks;
     c->residual = r64;
-    c->wide = 1;
+    c->h.wide = 1;
     if (r64 != r64) {
         c->status = TWG_EINVAL;
-        c->phase = PH_FINISH;
+        c->h.phase = PH_FINISH;
     } else if (r64 <= c->c.need) {
         c->status = TWG_OK;
-        c->phase = PH_FINISH;
+        c->h.phase = PH_FINISH;
     } else if (c->rounds >= c->c.max_rounds) {
         c->status = TWG_NOT_CONVERGED;
-        c->phase = PH_FINISH;
+        c->h.phase = PH_FINISH;
     } else {
-        start_correction(c, r64);
+        start_correction(c, r64, slot_now + 1);
     }
 }
 
@@ -249,52 +260,69 @@ __device__ void publish(const RelaxCtl *c, unsigned long long *mirror, int32_t s
 {
     if (!mirror) return;
     unsigned long long w;
-    if (c->phase == PH_DONE) {
+    if (c->h.phase == PH_DONE) {
         w = 1ull << 63;
     } else {
         int64_t next = slot_now + 1;  // DEFECT, UPDATE and FINISH decide in their own slot
-        if (c->phase == PH_PLAIN || c->phase == PH_CORR) next = slot_now + (c->next_check - c->pass) + 1;
+        if (c->h.phase == PH_PLAIN || c->h.phase == PH_CORR) next = slot_now + (c->h.next_check - c->h.pass) + 1;
         w = (unsigned long long)(next + 1);
     }
     *reinterpret_cast<volatile unsigned long long *>(mirror) = w;
     __threadfence_system();
 }
 
-__device__ void controller(RelaxCtl *c, const SlotArgs &a, int phase, bool check, bool forced)
+// The controller of a slot that decides: a checking pass (at pass p, on
+// buffer parity par), a defect, an update, or the finish (`forced`: the
+// final slot ends a solve whose phase was `was`, at pass p on parity par
+// if that phase was a solve).
+__device__ void controller(RelaxCtl *c, const SlotArgs &a, int phase, int was, bool forced, int32_t p, int32_t par)
 {
-    const int32_t slot_now = c->slot++;
+    const int32_t slot_now = a.slot;
     const double r = bitsd(__hip_atomic_exchange(&c->rmax, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const double rel = bitsd(__hip_atomic_exchange(&c->rrel, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    bool decided = true;
     switch (phase) {
     case PH_PLAIN:
     case PH_CORR: {
-        const int32_t pass = c->pass;
-        if (check) on_check(c, r, rel);
+        // the run's state at this pass, then the check
+        c->h.pass = p;
+        c->h.run_slot = slot_now;
+        if (phase == PH_PLAIN) c->h.parity = par;
+        else c->h.cparity = par;
+        on_check(c, r, rel);
         // the pass's output is the field from here on, unless the solve
         // ended at this check (its input is the result)
-        if (c->phase == phase && c->pass == pass) {
-            if (phase == PH_PLAIN) c->parity ^= 1;
-            else c->cparity ^= 1;
-            c->pass = pass + 1;
-            decided = check;
+        if (c->h.phase == phase && c->h.pass == p) {
+            if (phase == PH_PLAIN) c->h.parity = par ^ 1;
+            else c->h.cparity = par ^ 1;
+            c->h.pass = p + 1;
+            c->h.run_slot = slot_now + 1;
         }
         break;
     }
     case PH_DEFECT32:
-    case PH_DEFECT64: on_defect(c, r); break;
+    case PH_DEFECT64: on_defect(c, r, slot_now); break;
     case PH_UPDATE:
         ++c->rounds;
-        c->fresh = 1;
-        c->phase = PH_DEFECT64;
+        c->h.fresh = 1;
+        c->h.phase = PH_DEFECT64;
         break;
     case PH_FINISH:
-        if (forced) c->status = TWG_NOT_CONVERGED;
+        if (forced) {
+            c->status = TWG_NOT_CONVERGED;
+            // a solve cut short between checks: its passes so far count,
+            // and the FP32 field is where its last pass wrote it
+            if (was == PH_PLAIN) {
+                c->h.parity = par;
+                c->sweeps = (int64_t)p * c->c.S;
+            } else if (was == PH_CORR) {
+                c->polish_sweeps += (int64_t)p * c->c.S;
+            }
+        }
         write_stats(c, a.stats);
-        c->phase = PH_DONE;
+        c->h.phase = PH_DONE;
         break;
     }
-    if (decided) publish(c, a.mirror, slot_now);
+    publish(c, a.mirror, slot_now);
 }
 
 // ---- element-wise and stencil phases ----------------------------------------
@@ -342,27 +370,35 @@ template <int S, bool PAIR>
 __global__ __launch_bounds__(256) void k_relax_slot(SlotArgs a)
 {
     RelaxCtl *c = static_cast<RelaxCtl *>(a.ctl);
-    int phase = __builtin_amdgcn_readfirstlane(c->phase);
-    const bool forced = a.final_slot && phase < PH_FINISH;
-    if (forced) phase = PH_FINISH;
-    if (phase == PH_DONE) return;
+    // the hot words in one load; everything below is wave-uniform
+    const RelaxHot h = *static_cast<const RelaxHot *>(a.ctl);
+    const int was = __builtin_amdgcn_readfirstlane(h.phase);
+    // position in the current run of passes (solve phases), derived before
+    // any branch so that the words above arrive in one load
+    const int k = __builtin_amdgcn_readfirstlane(a.slot - h.run_slot);
+    const int pass = __builtin_amdgcn_readfirstlane(h.pass) + k;
+    const int par = (__builtin_amdgcn_readfirstlane(was == PH_CORR ? h.cparity : h.parity) ^ k) & 1;
+    const int next_check = __builtin_amdgcn_readfirstlane(h.next_check);
+    const int hfresh = __builtin_amdgcn_readfirstlane(h.fresh), hwide = __builtin_amdgcn_readfirstlane(h.wide);
+    const int hpar = __builtin_amdgcn_readfirstlane(h.parity), hcpar = __builtin_amdgcn_readfirstlane(h.cparity);
+    if (was == PH_DONE) return;
+    const bool forced = a.final_slot && was < PH_FINISH;
+    const int phase = forced ? (int)PH_FINISH : was;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gw = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
     const int nwaves = gridDim.x * 4;
     double m = 0.0;
     float mr = 0.0f;
-    bool reduce = false, check = false;
+    bool reduce = false;
 
     if (phase == PH_PLAIN || phase == PH_CORR) {
         const bool corr = phase == PH_CORR;
-        const int pass = __builtin_amdgcn_readfirstlane(c->pass);
-        check = pass == __builtin_amdgcn_readfirstlane(c->next_check);
+        const bool check = pass >= next_check;
         reduce = check;
-        const int par = __builtin_amdgcn_readfirstlane(corr ? c->cparity : c->parity);
         float *x0 = corr ? a.e : a.psi;
         float *src = par ? a.alt : x0, *dst = par ? x0 : a.alt;
-        const float om = corr ? (pass < c->c.lead_passes ? c->c.omega_lead : c->c.omega_dc) : c->c.omega;
+        const float om = corr ? (pass < a.lead_passes ? a.omega_lead : a.omega_dc) : a.omega;
         if (gw < a.tiles) {
             constexpr int VW = 128 - 4 * S;
             const int strip = gw % a.strips, seg = gw / a.strips;
@@ -384,11 +420,14 @@ __global__ __launch_bounds__(256) void k_relax_slot(SlotArgs a)
                                                                     a.pitch, xs, ybeg, yend);
             }
         }
+        // a pass that does not check decides nothing: the next slot derives
+        // its pass and buffers from its own slot number
+        if (!check) return;
     } else if (phase == PH_DEFECT32 || phase == PH_DEFECT64) {
         reduce = true;
         const bool first = phase == PH_DEFECT32;
-        const int par = __builtin_amdgcn_readfirstlane(c->parity);
-        const float *u32 = par ? a.alt : a.psi;
+        const int fpar = hpar;
+        const float *u32 = fpar ? a.alt : a.psi;
         for_cells(a, gw, nwaves, [&](int x, int y) {
             const size_t i = (size_t)y * a.pitch + x;
             double cv;
@@ -405,7 +444,7 @@ __global__ __launch_bounds__(256) void k_relax_slot(SlotArgs a)
             mr = nan_maxf(mr, fr && ac >= 1e-30f ? fabsf((float)r) * __builtin_amdgcn_rcpf(ac) : 0.0f);
         });
     } else if (phase == PH_UPDATE) {
-        const int cpar = __builtin_amdgcn_readfirstlane(c->cparity);
+        const int cpar = hcpar;
         const float *ecur = cpar ? a.alt : a.e;
         for_cells(a, gw, nwaves, [&](int x, int y) {
             const size_t i = (size_t)y * a.pitch + x;
@@ -418,8 +457,11 @@ __global__ __launch_bounds__(256) void k_relax_slot(SlotArgs a)
             a.e[i] = 0.0f;
         });
     } else {  // PH_FINISH
-        const bool copy = !__builtin_amdgcn_readfirstlane(c->fresh) && __builtin_amdgcn_readfirstlane(c->parity);
-        const bool widen = a.psi64 && c->c.polish && !__builtin_amdgcn_readfirstlane(c->wide);
+        // the FP32 field's buffer: a solve cut short between checks left it
+        // where its last pass wrote
+        const int fpar = was == PH_PLAIN ? par : hpar;
+        const bool copy = !hfresh && fpar;
+        const bool widen = a.psi64 && a.polish && !hwide;
         if (copy || widen) {
             for_cells(a, gw, nwaves, [&](int x, int y) {
                 const size_t i = (size_t)y * a.pitch + x;
@@ -456,22 +498,23 @@ __global__ __launch_bounds__(256) void k_relax_slot(SlotArgs a)
     const unsigned int ticket = __hip_atomic_fetch_add(&c->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (ticket != gridDim.x - 1) return;
     __hip_atomic_exchange(&c->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    controller(c, a, phase, check, forced);
+    controller(c, a, phase, was, forced, pass, par);
 }
 
 __global__ void k_relax_begin(RelaxCtl *c, RelaxConfig cfg)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     c->c = cfg;
-    c->phase = PH_PLAIN;
-    c->parity = c->cparity = c->fresh = c->wide = 0;
-    c->pass = 0;
-    c->next_check = 0;  // the initial field's residual, fused into pass 0
+    c->h.phase = PH_PLAIN;
+    c->h.parity = c->h.cparity = c->h.fresh = c->h.wide = 0;
+    c->h.pass = 0;
+    c->h.run_slot = 0;
+    c->h.next_check = 0;  // the initial field's residual, fused into pass 0
     c->last_check = 0;
     c->lead_check = 0;
     c->solve_checks = 0;
     c->stalls = 0;
-    c->checks = c->rounds = c->slot = 0;
+    c->checks = c->rounds = 0;
     c->status = TWG_NOT_CONVERGED;
     c->last_chunk = c->since = c->sweeps = c->polish_sweeps = 0;
     c->tol_cur = cfg.tol;

@@ -210,6 +210,10 @@ struct SlotArgs {
     int strips, RH, tiles;  // SOR tiling (S sweeps per pass)
     int pair;             // paired-column access
     int final_slot;       // 1: finish what is left (the solve is then NOT_CONVERGED)
+    int slot;             // this launch's number in the call's sequence (0, 1, ...)
+    int polish;           // RelaxConfig::polish
+    float omega, omega_dc, omega_lead;  // the RelaxConfig factors
+    int lead_passes;      // RelaxConfig::lead_passes
 };
 size_t relax_ctl_bytes();
 int launch_relax_begin(void *ctl, const RelaxConfig &cfg, hipStream_t st);
