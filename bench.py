@@ -3,17 +3,24 @@ one 2048 x 2048 grid with 500 moving obstacles (synthetic, seeded).
 
 A step = rasterise (ring map, Kalman prediction to ring time, disc marking)
 -> FP32 red-black SOR to residual 1e-6 -> FP64 defect-correction polish to a
-certified error bound of 1e-7, with FP64 SOR sweeps added until the descent
-from the robot resolves -> steepest-descent path.  Inputs are resident in HBM
-before the timed region.  Prints one JSON line on stdout.
+certified error bound of 1e-7 (FP64 SOR sweeps added while the descent from
+the robot does not resolve) -> steepest-descent path.  Inputs are resident
+in HBM before the timed region.  Prints one JSON line on stdout.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+                    [--no-learned] [--loop-steps N] [--leg all|roofline]
+                    [--tiling S,RH,S64,RH64,omega,omega_dc]
+
+--leg roofline runs only the set-up and the per-pass kernel timings (the
+command the committed rocprofv3 summaries are taken with); --tiling skips
+the autotuner.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -22,34 +29,75 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ms to converged field (residual 1e-6), learned vs plain; cell-updates/s; HBM %"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_CELL_UPDATE = 9.0  # FP32 read + FP32 write + 1-byte class, one sweep
-BYTES_PER_CELL_UPDATE64 = 17.0  # the same in FP64
-BYTES_PER_CELL_UPDATE_RHS = 13.0  # FP32 with a source term (defect-correction solves): + 4 B
-POLISH_CERT = 1e-7  # certified bound on |psi - psi*| the headline step polishes to
+# method bytes per cell of one pass of the relaxation kernel: the field in
+# and out (FP32) and the one-byte free mask; the correction solves also read
+# their FP32 source; FP64 sweeps move FP64 fields
+PASS_BYTES = {"plain": 9.0, "correction": 13.0, "fp64": 17.0}
+# the single-sweep roofline: FP32 field read + write and a one-bit mask
+SINGLE_SWEEP_BYTES = 8.125
+# 5 VALU instructions per cell-update (3 adds, 2 FMAs) against 256 CU x 4
+# SIMD x 16 lanes x 2.4 GHz lane-instructions per second (packed FP32 off)
+VALU_PER_UPDATE = 5.0
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
+SLOT_KERNEL_SOURCES = ("solve.hip", "stream_tile.h", "update.h")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(kernel, rows):
-    """HBM bytes per launch of `kernel` at `rows` output rows per tile from
-    the committed rocprofv3 PMC summary, or None when the summary has no such
-    entry or the kernel source has changed since the counters were taken."""
+def source_hash(names):
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_sor_stream_replan2048.md")
-    src = os.path.join(ROOT, "paper_1903_07441_amd", "csrc", "sor_stream.hip")
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1903_07441_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel, role, rows):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) of `kernel`
+    in `role` at `rows` output rows per tile from the committed rocprofv3
+    summary, or None when it has no such entry or the kernel's sources have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_relax_slot_replan2048.md")
     try:
         text = open(path).read().splitlines()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = source_hash(SLOT_KERNEL_SOURCES)
     except OSError:
         return None
     for ln in text:
-        f = ln.split()
-        # entry lines: "traffic <kernel> rows_per_tile <RH> source_sha256_16 <sha> bytes_per_launch <B>"
-        if len(f) == 8 and f[0] == "traffic" and f[1] == kernel and f[3] == str(rows) and f[5] == sha:
-            return int(f[7])
+        f = ln.strip("` ").split()
+        # "traffic <kernel> <role> rows_per_tile <RH> source_sha256_16 <sha> bytes_per_launch <B>"
+        if len(f) == 9 and f[0] == "traffic" and f[1] == kernel and f[2] == role and f[4] == str(rows) \
+                and f[6] == sha:
+            return int(f[8])
     return None
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_child(index, sweeps):
+    """Child process (started before the GPU is touched, OMP_NUM_THREADS=1):
+    the oracle's rasterisation and `sweeps` FP64 red-black sweeps of the
+    2048 x 2048 scenario, timed; one JSON line on stdout."""
+    import oracle as orc
+    from paper_1903_07441_amd import scenarios
+    sc = scenarios.scenario("replan2048", index)
+    t0 = time.perf_counter()
+    ocls, _ = orc.rasterize(sc, "perobs")
+    t1 = time.perf_counter()
+    orc.relax(ocls, None, init=orc.INIT_HALF, tol=1e-300, max_sweeps=sweeps, check_every=sweeps)
+    t2 = time.perf_counter()
+    print(json.dumps({"raster_s": t1 - t0, "sweep_s": (t2 - t1) / sweeps, "sweeps": sweeps}), flush=True)
 
 
 def main():
@@ -59,66 +107,162 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-grids leg")
-    ap.add_argument("--loop-steps", type=int, default=20,
-                    help="replanning-loop steps after the first (0 = skip the loop leg)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start legs")
+    ap.add_argument("--loop-steps", type=int, default=100, help="replanning-loop steps (0 = skip the loop)")
     ap.add_argument("--index", type=int, default=1,
                     help="scenario index (seed 5000 + index); index 0's goal is enclosed by a "
                          "predicted disc, so its field is degenerate (no path)")
+    ap.add_argument("--leg", default="all", choices=("all", "roofline"))
+    ap.add_argument("--tiling", default=None, help="S,RH,S64,RH64,omega,omega_dc: skip the autotuner")
+    ap.add_argument("--cpu-child", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_child:
+        cpu_child(args.index, args.cpu_child)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(a batch of grids or one grid's halo exchange would shard across GPUs; "
               "see the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    # the single-thread oracle sample runs in a child process started before
+    # anything touches the GPU (it finishes while the GPU legs run)
+    child = None
+    cpu_on = not args.no_cpu and args.leg == "all"
+    if cpu_on:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        child = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-child", "100",
+                                  "--index", str(args.index)], stdout=subprocess.PIPE, env=env, text=True)
+
     import numpy as np
     import torch
 
-    from paper_1903_07441_amd import scenarios, twg
+    from paper_1903_07441_amd import replan, scenarios, twg
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     sc = scenarios.scenario("replan2048", args.index)
     nx, ny = sc["nx"], sc["ny"]
+    cells = nx * ny
     ctx = twg.Context(0)
+    pl = replan.Planner(ctx, sc)
+    cls, ring, psi, psi64, path, info, cap = pl.cls, pl.ring, pl.psi, pl.psi64, pl.path, pl.info, pl.cap
     pos = torch.as_tensor(sc["pos"], dtype=torch.float64, device=dev).contiguous()
     vel = torch.as_tensor(sc["vel"], dtype=torch.float64, device=dev).contiguous()
-    rad = torch.as_tensor(sc["rad"], dtype=torch.float64, device=dev).contiguous()
-    cls = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
-    ring = torch.empty((ny, nx), dtype=torch.uint16, device=dev)
-    psi = torch.empty((ny, nx), dtype=torch.float32, device=dev)
-    psi64 = torch.empty((ny, nx), dtype=torch.float64, device=dev)
-    cap = nx * ny
-    path = torch.empty((cap, 2), dtype=torch.int32, device=dev)
-    info = torch.empty(2, dtype=torch.int32, device=dev)
-    # one-time setup: rasterise once and tune tiling and SOR factor for this size
-    ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"], robot_speed=sc["vr"],
-                  cls=cls, ring=ring)
-    tuning = ctx.autotune(cls)
-    log(f"autotune: {tuning}")
+    robot = [int(sc["robot"][0]), int(sc["robot"][1])]
+    pl.rasterize(robot, pos, vel)
+    if args.tiling:
+        S, RH, S64, RH64, om, om_dc = (float(v) for v in args.tiling.split(","))
+        ctx.set_tiling(nx, ny, int(S), int(RH), om, int(S64), int(RH64))
+        tuning = {"S": int(S), "RH": int(RH), "omega": om, "omega_dc": om_dc, "S64": int(S64), "RH64": int(RH64),
+                  "lead_dc_omega": 0.0, "lead_dc_sweeps": 0}
+    else:
+        tuning = ctx.autotune(cls)
+    log(f"tuning: {tuning}")
+    S, RH = tuning["S"], tuning["RH"]
     torch.cuda.synchronize()
+
+    # ---- per-pass timings of the relaxation kernels (live, HIP events on
+    # the stream they run on) ----
+    def roofline_leg(n_plain=204, n_corr=255):
+        src = torch.empty_like(psi)
+        ctx.init_field(cls, src, twg.INIT_HALF)
+        src64 = src.double()
+        st = torch.zeros(twg.STATS_BYTES, dtype=torch.uint8, device=dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        omega = tuning["omega"]
+        omega_dc = tuning["omega_dc"]
+
+        # n passes of the slot kernel in one role: the FP32 relaxation
+        # (plain: only the first and last pass check) or a correction solve
+        # (after one plain pass and the first defect); timed at two counts,
+        # the difference is n2 - n1 passes that do not check
+        def run(role, n):
+            if role == "plain":
+                ctx.relax_async(cls, src, None, slots=n + 2, stats=st, tol=1e-300, max_sweeps=n * S,
+                                omega=omega, init=twg.INIT_KEEP, check_passes=1 << 30, sweeps_per_pass=S,
+                                rows_per_tile=RH)
+            else:
+                ctx.relax_async(cls, src, src64, slots=n + 2, stats=st, tol=1e30, tol_cert=1e-300,
+                                max_sweeps=n * S, omega=omega_dc, init=twg.INIT_KEEP, polish=1,
+                                check_passes=1 << 30, sweeps_per_pass=S, rows_per_tile=RH)
+
+        def per_pass(role, n1=40, n2=240, reps=5):
+            run(role, n1)
+            torch.cuda.synchronize()
+            t = {n1: [], n2: []}
+            for _ in range(reps):
+                for n in (n1, n2):
+                    e0.record()
+                    run(role, n)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    t[n].append(e0.elapsed_time(e1))
+            return (float(np.median(t[n2])) - float(np.median(t[n1]))) * 1e-3 / (n2 - n1)
+
+        t_plain = per_pass("plain")
+        t_corr = per_pass("correction")
+        # FP64 sweeps (k_sor_stream<double>, graph replays of 64 passes)
+        S64 = tuning["S64"] or 4
+        scr64 = src64.clone()
+
+        def fp64(k):
+            ctx.sweeps64(cls, scr64, tuning["omega"], k * S64, sweeps_per_pass=S64)
+
+        fp64(128)
+        e0.record()
+        fp64(128)
+        e1.record()
+        torch.cuda.synchronize()
+        t_64 = e0.elapsed_time(e1) * 1e-3 / 128
+        return {"plain": t_plain, "correction": t_corr, "fp64": t_64, "S64": S64}
+
+    def roof_entry(kernel, role, t, sweeps_per_pass, rows, launches, what):
+        alg = PASS_BYTES[role] * cells
+        ach = alg / t / 1e9
+        traffic = profiled_traffic(kernel, role, rows)
+        cups = cells * sweeps_per_pass / t
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_over_method_bytes": round(traffic / alg, 3) if traffic else None,
+                "kernel": kernel, "role": what, "launch_us": round(t * 1e6, 3),
+                "method_bytes_per_cell": PASS_BYTES[role], "method_bytes_per_launch": alg,
+                "sweeps_per_launch": sweeps_per_pass, "rows_per_tile": rows,
+                "launches_in_step": launches, "ms_in_step": round(launches * t * 1e3, 3),
+                "sweep_equivalent": {"cell_updates_per_s": round(cups, 1),
+                                     "single_sweep_roofline_cups": 8e12 / SINGLE_SWEEP_BYTES,
+                                     "frac": round(cups * SINGLE_SWEEP_BYTES / 8e12, 4)}}
+
+    if args.leg == "roofline":
+        tl = roofline_leg()
+        # a device copy of known size (256 MiB read, 256 MiB written) to
+        # calibrate the hardware byte counters of the same run
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"leg": "roofline", "tuning": tuning, "pass_us": {k: round(v * 1e6, 3) if k != "S64" else v
+                                                                           for k, v in tl.items()}}), flush=True)
+        ctx.close()
+        return
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
 
     def step():
         ev[0].record()
-        ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"],
-                      robot_speed=sc["vr"], cls=cls, ring=ring)
+        pl.rasterize(robot, pos, vel)
         ev[1].record()
-        plain = ctx.relax(cls, psi, None, tol=1e-6, init=twg.INIT_HALF)
+        plain = ctx.relax(cls, psi, None, tol=replan.TOL, init=twg.INIT_HALF)
         ev[2].record()
-        # FP64 polish by defect correction (FP64 residual, FP32 correction
-        # solves, FP64 update) to a certified POLISH_CERT, then FP64 SOR
-        # sweeps until the descent from the robot resolves (checked by walking it)
-        pol = ctx.relax(cls, psi, psi64, tol=1e-6, init=twg.INIT_KEEP, polish=1, tol_cert=POLISH_CERT)
+        pol = ctx.relax(cls, psi, psi64, tol=replan.TOL, init=twg.INIT_KEEP, polish=1, tol_cert=replan.POLISH_CERT)
         ev[3].record()
         # the path; while it does not resolve, FP64 sweeps and a new walk
         # (the extra rounds count in the descent's time)
         rounds = 0
-        ctx.descend(cls, psi64=psi64, start=sc["robot"], cap=cap, path=path, info=info)
-        while int(info[1].item()) == twg.NO_PATH and rounds < 8:
-            ctx.sweeps64(cls, psi64, pol["omega"], 256)
-            ctx.descend(cls, psi64=psi64, start=sc["robot"], cap=cap, path=path, info=info)
+        ctx.descend(cls, psi64=psi64, start=robot, cap=cap, path=path, info=info)
+        while int(info[1].item()) == twg.NO_PATH and rounds < pl.max_extra:
+            ctx.sweeps64(cls, psi64, pol["omega"], pl.extra_sweeps)
+            ctx.descend(cls, psi64=psi64, start=robot, cap=cap, path=path, info=info)
             rounds += 1
         ev[4].record()
         pol["descent_rounds"] = rounds
@@ -143,9 +287,55 @@ def main():
     med = np.median(np.array(parts), axis=0)
     plain, pol = stats
     n, status = info.cpu().tolist()
-    cells = nx * ny
-    cell_updates = cells * plain["sweeps"]
-    cups = cell_updates / (med[1] * 1e-3)
+    cups = cells * plain["sweeps"] / (med[1] * 1e-3)
+
+    # ---- the same step captured into one HIP graph (hpf_relax_async with
+    # fixed slot counts), replayed; its results against the eager step's ----
+    graph_step = None
+    try:
+        pg = replan.Planner(ctx, sc)
+        gs = replan.StepGraph(pg, robot, pos, vel, plain, pol, S)
+        g_ms = []
+        for i in range(args.warmup + args.steps):
+            ev[0].record()
+            gs.replay()
+            ev[1].record()
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                g_ms.append(ev[0].elapsed_time(ev[1]))
+        gp, gq = gs.stats()
+        gn, gstat = pg.info.cpu().tolist()
+        same = (bool(torch.equal(pg.psi64, psi64)) and bool(torch.equal(pg.cls, cls)) and gn == n
+                and gstat == status and bool(torch.equal(pg.path[:max(gn, 0)], path[:max(n, 0)])))
+        graph_step = {"ms_p50": round(float(np.median(g_ms)), 3), "slots": [gs.slots_plain, gs.slots_pol],
+                      "sweeps": gp["sweeps"], "polish_sweeps": gq["polish_sweeps"], "status": gstat,
+                      "cert_bound": gq["cert_bound"], "equal_to_eager": same,
+                      "what": "rasterise + FP32 relax + FP64 polish + descent captured once as one HIP graph "
+                              "(surplus relaxation slots return at once; no extra FP64 rounds)"}
+        del gs, pg
+    except Exception as exc:  # reported, not hidden
+        graph_step = {"error": repr(exc)}
+    log(f"graph step: {graph_step}")
+
+    # ---- kernel rooflines ----
+    tl = roofline_leg()
+    kname = f"k_relax_slot<{S}, true>" if nx % 2 == 0 else f"k_relax_slot<{S}, false>"
+    passes_plain = plain["sweeps"] / S
+    passes_corr = pol["polish_sweeps"] / S
+    roofs = [
+        roof_entry(kname, "correction", tl["correction"], S, RH, passes_corr,
+                   "FP32 pass of the defect-correction solves (source term)"),
+        roof_entry(kname, "plain", tl["plain"], S, RH, passes_plain, "FP32 pass of the relaxation"),
+        roof_entry(f"k_sor_stream<double, {tl['S64']}, false, true>", "fp64", tl["fp64"], tl["S64"],
+                   tuning["RH64"], 256 * pol["descent_rounds"] / tl["S64"], "FP64 SOR pass (extra descent rounds)"),
+    ]
+    roofs.sort(key=lambda r: -r["ms_in_step"])
+    roofline, roofline_other = roofs[0], roofs[1:]
+    valu = VALU_PER_UPDATE * cells * S / tl["plain"]
+    roofline_alu = {"bound": "alu", "achieved": round(valu / 1e12, 3), "peak": round(VALU_PEAK / 1e12, 3),
+                    "unit": "T VALU lane-instr/s", "frac": round(valu / VALU_PEAK, 4),
+                    "kernel": kname, "role": "FP32 pass of the relaxation (useful cell-updates only)"}
+    log(f"roofline: {roofline}")
 
     # ---- descent from every cell: what the FP64 polish buys ----
     steps_all = torch.empty((ny, nx), dtype=torch.int32, device=dev)
@@ -156,8 +346,9 @@ def main():
         return round(int(((steps_all >= 0) & (cls == twg.FREE)).sum().item()) / max(1, free_n), 6)
 
     descent_all = {"fp64_polished": reach_frac(psi64=psi64)}
-    ctx.relax(cls, psi, None, tol=1e-6, init=twg.INIT_HALF)
-    descent_all["fp32_residual_1e-6"] = reach_frac(psi=psi)
+    psi_f = torch.empty_like(psi)
+    ctx.relax(cls, psi_f, None, tol=replan.TOL, init=twg.INIT_HALF)
+    descent_all["fp32_residual_1e-6"] = reach_frac(psi=psi_f)
     e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e_a.record()
     ctx.descent_all(cls, psi64=psi64, steps=steps_all)
@@ -165,7 +356,6 @@ def main():
     torch.cuda.synchronize()
     descent_all["ms"] = round(e_a.elapsed_time(e_b), 3)
     descent_all["what"] = "share of FREE cells whose steepest descent reaches the goal"
-    log(f"descent from every cell: {descent_all}")
 
     # ---- the paper's own mode: cleared grid, a fixed 100 Gauss-Seidel iterations ----
     psi_p = torch.empty_like(psi)
@@ -176,264 +366,143 @@ def main():
     torch.cuda.synchronize()
     paper_mode = {"ms": round(e_a.elapsed_time(e_b), 3), "sweeps": 100, "omega": 1.0,
                   "residual": ctx.residual(cls, psi=psi_p), "reach_frac": reach_frac(psi=psi_p)}
-    ctx.descend(cls, psi=psi_p, start=sc["robot"], cap=cap, path=path, info=info)
-    pm_n, pm_s = info.cpu().tolist()
+    p_path, p_info = ctx.descend(cls, psi=psi_p, start=robot, cap=cap)
+    pm_n, pm_s = p_info.cpu().tolist()
     paper_mode["descent_from_robot"] = {"status": pm_s, "length": pm_n, "reached_goal": pm_s == twg.OK}
-    log(f"paper mode: {paper_mode}")
-    ctx.descend(cls, psi64=psi64, start=sc["robot"], cap=cap, path=path, info=info)  # restore the path
+    del p_path
 
-    # ---- the other polish: FP64 SOR sweeps to a certified 5e-7, then more
-    # FP64 sweeps until the descent resolves ----
+    # ---- the other polish: FP64 SOR sweeps to a certified 5e-7 ----
     psi64_d = torch.empty_like(psi64)
-    ctx.relax(cls, psi, None, tol=1e-6, init=twg.INIT_HALF)
+    ctx.relax(cls, psi_f, None, tol=replan.TOL, init=twg.INIT_HALF)
     e_a.record()
-    pol_d = ctx.relax(cls, psi, psi64_d, tol=1e-6, init=twg.INIT_KEEP, polish=2, tol_cert=5e-7)
-    ctx.descend(cls, psi64=psi64_d, start=sc["robot"], cap=cap, path=path, info=info)
-    sor_rounds = 0
-    while int(info[1].item()) == twg.NO_PATH and sor_rounds < 8:
-        ctx.sweeps64(cls, psi64_d, pol_d["omega"], 256)
-        ctx.descend(cls, psi64=psi64_d, start=sc["robot"], cap=cap, path=path, info=info)
-        sor_rounds += 1
+    pol_d = ctx.relax(cls, psi_f, psi64_d, tol=replan.TOL, init=twg.INIT_KEEP, polish=2, tol_cert=5e-7)
+    d_path, d_info = ctx.descend(cls, psi64=psi64_d, start=robot, cap=cap)
     e_b.record()
     torch.cuda.synchronize()
-    dc_n, dc_s = info.cpu().tolist()
+    dc_n, dc_s = d_info.cpu().tolist()
     polish_sor = {"ms": round(e_a.elapsed_time(e_b), 3), "fp64_sweeps": pol_d["polish_sweeps"],
-                  "descent_rounds": sor_rounds, "residual": pol_d["residual"],
-                  "certified_error_bound": pol_d["cert_bound"], "reach_frac": reach_frac(psi64=psi64_d),
+                  "residual": pol_d["residual"], "certified_error_bound": pol_d["cert_bound"],
+                  "reach_frac": reach_frac(psi64=psi64_d),
                   "descent_from_robot": {"status": dc_s, "length": dc_n, "reached_goal": dc_s == twg.OK}}
-    log(f"FP64 SOR polish: {polish_sor}")
-    ctx.descend(cls, psi64=psi64, start=sc["robot"], cap=cap, path=path, info=info)  # restore the path
+    del d_path, psi64_d
 
-    # ---- rooflines of the streamed SOR kernels (FP32 sweeps, FP32 sweeps
-    # with a source term as in the defect-correction solves, FP64 sweeps),
-    # timed live on the stream they run on; `roofline` is the one with the
-    # largest share of the step ----
-    S, S64 = tuning["S"], tuning["S64"]
-    pair = nx % 2 == 0  # pitch == nx here: the paired-column kernels run
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def per_launch(fn, passes):
-        fn(passes)  # warm-up: as many passes, so the replayed graphs are captured before the timing
-        e0.record()
-        fn(passes)
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) * 1e-3 / passes
-
-    scratch = psi.clone()
-    src = torch.zeros_like(psi)
-    scratch64 = psi64.clone()
-    # even pass counts: hpf_sweeps adds a copy after an odd one
-    t_launch = per_launch(lambda k: ctx.sweeps(cls, scratch, plain["omega"], k * S, sweeps_per_pass=S), 200)
-    t_launch_f = per_launch(lambda k: ctx.sweeps(cls, scratch, plain["omega"], k * S, sweeps_per_pass=S,
-                                                 f=src), 200)
-    t_launch64 = per_launch(lambda k: ctx.sweeps64(cls, scratch64, pol["omega"], k * S64,
-                                                   sweeps_per_pass=S64), 100)
-    del scratch, scratch64, src
-
-    def kernel_roofline(kname, bytes_per_update, sweeps, rows, t, launches):
-        alg = bytes_per_update * cells * sweeps
-        ach = alg / t / 1e9
-        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(kname, rows),
-                "kernel": kname, "launch_us": round(t * 1e6, 2), "algorithmic_bytes_per_launch": alg,
-                "ms_in_step": round(launches * t * 1e3, 3)}
-
-    pf = "true" if pair else "false"
-    roofs = [
-        kernel_roofline(f"k_sor_stream<float,{S},false,{pf}>", BYTES_PER_CELL_UPDATE, S, tuning["RH"],
-                        t_launch, plain["sweeps"] / S),
-        kernel_roofline(f"k_sor_stream<float,{S},true,{pf}>", BYTES_PER_CELL_UPDATE_RHS, S, tuning["RH"],
-                        t_launch_f, pol["polish_sweeps"] / S),
-        kernel_roofline(f"k_sor_stream<double,{S64},false,{pf}>", BYTES_PER_CELL_UPDATE64, S64,
-                        tuning["RH64"], t_launch64, 256 * pol["descent_rounds"] / S64),
-    ]
-    roofs.sort(key=lambda r: -r["ms_in_step"])
-    roofline, roofline_other = roofs[0], roofs[1:]
-    # the same launch against the vector-ALU issue rate: 5 VALU instructions
-    # per cell-update (3 adds, 2 FMAs) are the minimum of the update; the chip
-    # issues 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s
-    valu_peak = 256 * 4 * 16 * 2.4e9
-    valu_ach = 5.0 * cells * S / t_launch
-    roofline_alu = {"bound": "alu", "achieved": round(valu_ach / 1e12, 3), "peak": round(valu_peak / 1e12, 3),
-                    "unit": "T VALU lane-instr/s", "frac": round(valu_ach / valu_peak, 4)}
-
-    # ---- learned warm start: network field, then the same FP32 relaxation ----
-    learned = None
-    roofline_mfma = None
+    # ---- learned warm start ----
+    learned = roofline_mfma = ceiling = learned256 = None
     wpath = os.path.join(ROOT, "paper_1903_07441_amd", "weights", "unet_learn256.npz")
-    if os.path.exists(wpath):
+    net = None
+    if not args.no_learned and os.path.exists(wpath):
         from paper_1903_07441_amd import learn
         params, meta = learn.load_weights(wpath)
         net = twg.UNet(ctx, torch.as_tensor(params))
         psi_l = torch.empty_like(psi)
-        el = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        runs = []
-        # the learned path's SOR factor, picked (untimed) from a fixed family
-        l_trials = {}
-        for wc in (1.9, 1.95, 1.98, 0.0):
-            net.warm_start(cls, ring, sc["goal"], psi_l)
-            torch.cuda.synchronize()
-            t_0 = time.perf_counter()
-            ctx.relax(cls, psi_l, None, tol=1e-6, init=twg.INIT_KEEP, omega=wc)
-            torch.cuda.synchronize()
-            l_trials[wc] = time.perf_counter() - t_0
-        w_l = min(l_trials, key=l_trials.get)
-        for i in range(args.warmup + args.steps):
-            el[0].record()
-            net.warm_start(cls, ring, sc["goal"], psi_l)
-            el[1].record()
-            st_l = ctx.relax(cls, psi_l, None, tol=1e-6, init=twg.INIT_KEEP, omega=w_l)
-            el[2].record()
-            torch.cuda.synchronize()
-            if i >= args.warmup:
-                runs.append((el[0].elapsed_time(el[1]), el[0].elapsed_time(el[2]), st_l["sweeps"]))
-        r = np.median(np.array(runs), axis=0)
-        learned = {"ms_to_residual_1e-6": round(float(r[1]), 3), "ms_network": round(float(r[0]), 3),
-                   "sweeps": int(r[2]), "residual": st_l["residual"],
-                   "speedup_vs_plain": round(float(med[1]) / float(r[1]), 3),
-                   "trained_on": meta.get("recipe"), "weights": os.path.relpath(wpath, ROOT),
-                   "omega": w_l, "omega_trials_ms": {str(a): round(b * 1e3, 3) for a, b in l_trials.items()}}
+        psi64_l = torch.empty_like(psi64)
+        el = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+        def time_relax(fill, omegas=(0.0, 1.95, 1.98), include_fill=False):
+            """Best time (and sweeps) to residual 1e-6 over the SOR factors
+            `omegas` (0 = tuned factor) from the field fill() writes; then the
+            FP64 polish of that field to the certified bound, timed too (a
+            factor below the optimum can reach the residual sooner and leave
+            smooth error that the polish pays for)."""
+            best = None
+            for w in omegas:
+                fill(psi_l)
+                torch.cuda.synchronize()
+                el[0].record()
+                if include_fill:
+                    fill(psi_l)
+                el[1].record()
+                st_l = ctx.relax(cls, psi_l, None, tol=replan.TOL, init=twg.INIT_KEEP, omega=w)
+                el[2].record()
+                st_p = ctx.relax(cls, psi_l, psi64_l, tol=replan.TOL, init=twg.INIT_KEEP, polish=1,
+                                 tol_cert=replan.POLISH_CERT, max_sweeps=20000)
+                el[3].record()
+                torch.cuda.synchronize()
+                row = {"omega": w, "ms": round(el[0].elapsed_time(el[2]), 3),
+                       "ms_fill": round(el[0].elapsed_time(el[1]), 3), "sweeps": st_l["sweeps"],
+                       "residual": st_l["residual"], "ms_certified": round(el[0].elapsed_time(el[3]), 3),
+                       "polish_sweeps": st_p["polish_sweeps"], "cert_bound": st_p["cert_bound"]}
+                if best is None or row["ms"] < best["ms"]:
+                    best = row
+            return best
+
+        net_fill = lambda t: net.warm_start(cls, ring, sc["goal"], t)  # noqa: E731
+        runs = [time_relax(net_fill, include_fill=True) for _ in range(3)]
+        best_l = min(runs, key=lambda r: r["ms"])
+        learned = {"ms_to_residual_1e-6": best_l["ms"], "ms_network": best_l["ms_fill"], "sweeps": best_l["sweeps"],
+                   "omega": best_l["omega"], "residual": best_l["residual"],
+                   "speedup_vs_plain": round(float(med[1]) / best_l["ms"], 3),
+                   "trained_on": meta.get("recipe"), "weights": os.path.relpath(wpath, ROOT)}
         # forward FLOPs: 2 * 9 * cin * cout per output pixel and layer (pixels
         # quartered per level), plus the 1x1 head
         hp, wp = (ny + 7) // 8 * 8, (nx + 7) // 8 * 8
         P = hp * wp
         flops = 2.0 * 9 * (3 * 32 * P + 32 * 64 * P / 4 + 64 * 128 * P / 16 + 128 * 128 * P / 64
                             + 256 * 64 * P / 16 + 128 * 32 * P / 4 + 64 * 32 * P) + 2.0 * 32 * P
-        ach = flops / (float(r[0]) * 1e-3) / 1e12
+        ach = flops / (best_l["ms_fill"] * 1e-3) / 1e12
         roofline_mfma = {"bound": "mfma", "achieved": round(ach, 2), "peak": 2500.0, "unit": "TFLOP/s",
                          "frac": round(ach / 2500.0, 4), "kernel": "network forward (features + 7 convs + head)",
                          "flops_per_launch": flops}
-        net.close()
 
-    # ---- replanning loop: the robot advances one cell along its path per
-    # step, obstacles move at constant velocity; each step is warm-started from
-    # the previous step's field (and the network, where the map changed) and
-    # compared with a cold solve of the same map ----
-    # the loop's robot advances along the descent path of the polished field
-    # of the timed steps above (an FP32 field at residual 1e-6 does not
-    # resolve the potential far from the goal, so the loop's own descent is
-    # only reported)
-    route = path[:max(1, n)].cpu().numpy().tolist() if status == twg.OK else [list(sc["robot"])]
+        # ceiling: the sweeps and time to residual 1e-6 from initial fields a
+        # network could at best produce -- the converged field itself rounded
+        # to bf16, and the converged field averaged over 4x4 / 8x8 / 16x16
+        # blocks and interpolated back (a perfect prediction at a coarser
+        # scale) -- next to the plain starts and the trained network
+        import torch.nn.functional as F
+        star = psi64.float()
 
-    def run_loop(net_l, sigma):
-        # true obstacles move at constant velocity; each step the filters
-        # (twg_kalman_step) take a position measurement with noise sigma
-        # (R = 0.25 I) and the map is rasterised from their estimates
-        pos0 = np.asarray(sc["pos"], dtype=np.float64)
-        vel0 = np.asarray(sc["vel"], dtype=np.float64)
-        n_o = len(pos0)
-        meas = np.random.default_rng(sc["seed"] + 77)
-        kx = torch.as_tensor(np.concatenate([pos0, vel0], axis=1), dtype=torch.float64, device=dev).contiguous()
-        kP = torch.as_tensor(np.tile(0.25 * np.eye(4).reshape(16), (n_o, 1)), dtype=torch.float64,
-                             device=dev).contiguous()
-        kR = torch.as_tensor((0.25 * np.eye(2)).reshape(4), dtype=torch.float64, device=dev)
-        est_p = torch.empty((n_o, 2), dtype=torch.float64, device=dev)
-        est_v = torch.empty((n_o, 2), dtype=torch.float64, device=dev)
-        robot = [int(sc["robot"][0]), int(sc["robot"][1])]
-        cls_prev = torch.empty_like(cls)
-        psi_prev = torch.empty_like(psi)
-        cls_k = torch.empty_like(cls)
-        ring_k = torch.empty_like(ring)
-        psi_k = torch.empty_like(psi)
-        psi_c = torch.empty_like(psi)
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        warm, cold, warm_sw, cold_sw, reached = [], [], [], [], 0
-        # SOR factor of the warm path: a warm start's error is local (where
-        # the map changed), which factors below the global optimum damp
-        # fastest; the first warm step picks one from a fixed family
-        w_warm, w_trials, w_cold, c_trials = None, {}, 0.0, {}
-        for k in range(args.loop_steps + 1):
-            zk = torch.as_tensor(pos0 + k * vel0 + sigma * meas.normal(0.0, 1.0, size=(n_o, 2)),
-                                 dtype=torch.float64, device=dev).contiguous()
-            e[0].record()
-            if k == 0:
-                est_p.copy_(kx[:, :2])
-                est_v.copy_(kx[:, 2:])
-            else:
-                ctx.kalman_step(kx, kP, zk, dt=1.0, R=kR, pos=est_p, vel=est_v)
-            ctx.rasterize(nx, ny, robot, sc["goal"], est_p, est_v, rad, W=sc["W"], robot_speed=sc["vr"],
-                          cls=cls_k, ring=ring_k)
-            if net_l is not None:
-                net_l.warm_start(cls_k, ring_k, sc["goal"], psi_k)
-            else:
-                ctx.init_field(cls_k, psi_k, twg.INIT_HALF)
-            if k > 0:
-                ctx.merge_previous(cls_k, cls_prev, psi_prev, psi_k)
-            if k == 1:
-                # untimed step: pick the warm path's SOR factor
-                base = psi_k.clone()
-                for wc in (1.5, 1.7, 1.8, 1.9, 1.95, 0.0):
-                    psi_k.copy_(base)
-                    torch.cuda.synchronize()
-                    t_0 = time.perf_counter()
-                    ctx.relax(cls_k, psi_k, None, tol=1e-6, init=twg.INIT_KEEP, omega=wc)
-                    torch.cuda.synchronize()
-                    w_trials[wc] = time.perf_counter() - t_0
-                w_warm = min(w_trials, key=w_trials.get)
-                psi_k.copy_(base)
-            st_w = ctx.relax(cls_k, psi_k, None, tol=1e-6, init=twg.INIT_KEEP,
-                             omega=w_warm if (k > 0 and w_warm is not None) else 0.0)
-            ctx.descend(cls_k, psi=psi_k, start=robot, cap=cap, path=path, info=info)
-            e[1].record()
-            # the same map solved cold, for comparison (with its own best
-            # factor from the same family, picked on the selection step)
-            if k == 1:
-                c_trials = {}
-                for wc in (1.9, 1.95, 1.98, 0.0):
-                    torch.cuda.synchronize()
-                    t_0 = time.perf_counter()
-                    ctx.relax(cls_k, psi_c, None, tol=1e-6, init=twg.INIT_HALF, omega=wc)
-                    torch.cuda.synchronize()
-                    c_trials[wc] = time.perf_counter() - t_0
-                w_cold = min(c_trials, key=c_trials.get)
-            e[2].record()
-            st_c = ctx.relax(cls_k, psi_c, None, tol=1e-6, init=twg.INIT_HALF,
-                             omega=w_cold if k >= 1 else 0.0)
-            e[3].record()
-            torch.cuda.synchronize()
-            n_k, s_k = info.cpu().tolist()
-            if k > 1:
-                warm.append(e[0].elapsed_time(e[1]))
-                cold.append(e[2].elapsed_time(e[3]))
-                warm_sw.append(st_w["sweeps"])
-                cold_sw.append(st_c["sweeps"])
-                reached += int(s_k == twg.OK)
-            robot = [int(v) for v in route[min(k + 1, len(route) - 1)]]
-            cls_prev, cls_k = cls_k, cls_prev
-            psi_prev, psi_k = psi_k, psi_prev
-        w, c = np.array(warm), np.array(cold)
-        loop = {"steps": args.loop_steps - 1,
-                "warm_ms_p50": round(float(np.percentile(w, 50)), 3),
-                "warm_ms_p95": round(float(np.percentile(w, 95)), 3),
-                "warm_ms_max": round(float(w.max()), 3),
-                "cold_relax_ms_p50": round(float(np.percentile(c, 50)), 3),
-                "warm_sweeps_p50": int(np.median(warm_sw)), "cold_sweeps_p50": int(np.median(cold_sw)),
-                "speedup_relax_p50": round(float(np.percentile(c, 50) / np.percentile(w, 50)), 3),
-                "fp32_descent_reached_goal": f"{reached}/{args.loop_steps - 1}",
-                "warm_omega": w_warm, "warm_omega_trials_ms": {str(a): round(b * 1e3, 3) for a, b in w_trials.items()},
-                "cold_omega": w_cold, "cold_omega_trials_ms": {str(a): round(b * 1e3, 3) for a, b in c_trials.items()},
-                "warm_start": ("previous field + network where the map changed" if net_l is not None
-                               else "previous field + 0.5 where the map changed"),
-                "measurement_sigma": sigma,
-                "step": "Kalman update of all obstacles from noisy positions + rasterise + warm start + "
-                        "FP32 relax to residual 1e-6 + descent (FP32 field)"}
-        log(f"loop: {loop}")
-        return loop
+        def coarse(fct):
+            def fill(t):
+                c = F.avg_pool2d(star[None, None], fct)
+                t.copy_(F.interpolate(c, size=(ny, nx), mode="bilinear", align_corners=False)[0, 0])
+            return fill
 
+        def plain_fill(mode):
+            return lambda t: ctx.init_field(cls, t, mode, goal=sc["goal"])
+
+        ceiling = {}
+        for name, fill in (("half", plain_fill(twg.INIT_HALF)), ("zero", plain_fill(twg.INIT_ZERO)),
+                           ("linear", plain_fill(twg.INIT_LINEAR)), ("network", net_fill),
+                           ("converged_bf16", lambda t: t.copy_(star.bfloat16().float())),
+                           ("converged_coarse4", coarse(4)), ("converged_coarse8", coarse(8)),
+                           ("converged_coarse16", coarse(16))):
+            ceiling[name] = time_relax(fill)
+        ceiling["what"] = ("relaxation only (the fill is not timed), best of the tuned factor, 1.95 and 1.98; "
+                           "converged_* start from the certified field itself")
+        log(f"learned: {learned}")
+        log(f"ceiling: {ceiling}")
+
+        # config-4 comparison: held-out 256 x 256 scenarios, the network's
+        # start (time includes it) against the best plain start
+        data = learn.make_dataset(ctx, net, 100000, 16)
+        learned256 = learn.evaluate(ctx, net, data)
+
+    # ---- replanning loop (Algorithm 1): the robot follows its own
+    # polished descent, one cell per step ----
     loop = None
     if args.loop_steps > 0:
-        net_l = None
-        if learned is not None:
-            from paper_1903_07441_amd import learn as _learn
-            net_l = twg.UNet(ctx, torch.as_tensor(_learn.load_weights(wpath)[0]))
         loop = {}
         for sigma, tag in ((0.0, "exact_measurements"), (0.5, "noisy_measurements")):
-            loop[tag] = {"previous_field": run_loop(None, sigma)}
-            if net_l is not None:
-                loop[tag]["previous_field_and_network"] = run_loop(net_l, sigma)
-        if net_l is not None:
-            net_l.close()
+            loop[tag] = {}
+            variants = [("previous_field", "previous", "the previous field on every FREE cell (0 where an "
+                                                       "obstacle was)"),
+                        ("previous_field_and_half", "half", "previous field where the cell was and is FREE, "
+                                                            "0.5 elsewhere")]
+            if net is not None:
+                variants.append(("previous_field_and_network", "network", "previous field where the cell was "
+                                 "and is FREE, the network's field elsewhere"))
+            for vname, fill, what in variants:
+                res = replan.run_loop(ctx, sc, args.loop_steps, sigma=sigma, net=net, cold_every=10, log=log,
+                                      fill=fill)
+                loop[tag][vname] = replan.summarize(res, what)
+                log(f"loop {tag} {vname}: {loop[tag][vname]}")
+        loop["step"] = ("Kalman update of all obstacles (position measurements, R = 0.25 I) + rasterise + warm "
+                        "start + FP32 relax to residual 1e-6 + FP64 defect correction to a certified 1e-7 + "
+                        "descent from the robot (FP64 rounds while it does not resolve); the robot then moves "
+                        "one cell along that path; obstacles move at constant velocity and reflect at walls")
+    if net is not None:
+        net.close()
 
     # ---- batched leg: 256 grids of uneven size, one relaxation call ----
     batch = None
@@ -454,20 +523,12 @@ def main():
                           W=b["W"], robot_speed=b["vr"], cls=bcls[o:o + n_b].view(b["ny"], b["nx"]),
                           want_ring=False)
         descs = [(b["nx"], b["ny"], b["nx"], o) for b, o in zip(scs, offs)]
-        # SOR factors per size class (untimed set-up): the autotuner on the
-        # first grid of each size; the batch takes each grid's factor from it
-        # (untuned sizes would get the open square's factor, far above the
-        # optimum of a grid with obstacles)
         tuned_sizes = {}
         for b, o in zip(scs, offs):
             key = (b["nx"], b["ny"])
             if key not in tuned_sizes:
                 tb_ = ctx.autotune(bcls[o:o + b["nx"] * b["ny"]].view(b["ny"], b["nx"]))
                 tuned_sizes[key] = round(tb_["omega"], 6)
-        log(f"batch size classes tuned: {tuned_sizes}")
-        # tiling of the batch, picked (untimed) from a few candidates: the
-        # batch has far more tiles than the chip has SIMDs, so taller tiles
-        # (less halo) pay off here, unlike on one grid
         b_trials = {}
         for S_b, RH_b in ((4, 16), (6, 64), (8, 64), (6, 128), (8, 128)):
             ctx.relax_batched(bcls, bpsi, descs, tol=1e-6, sweeps_per_pass=S_b, rows_per_tile=RH_b)
@@ -496,28 +557,37 @@ def main():
                              "(radius 2-5), FP32 red-black SOR to residual 1e-6 with FP64 residuals"}
         log(f"batch: {batch}")
 
-    # ---- CPU baseline: the oracle on a bounded sample ----
+    # ---- CPU baseline: the oracle on the same step ----
     cpu = None
-    if not args.no_cpu:
+    if cpu_on:
         import oracle as orc
         cores = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "1000")))
-        os.environ.setdefault("OMP_NUM_THREADS", str(cores))
         ta = time.perf_counter()
         ocls, _ = orc.rasterize(sc, "perobs")
-        tb = time.perf_counter()
-        field = orc.field_init(ocls, None, orc.INIT_HALF)
-        k_sweeps = 60
+        tb_ = time.perf_counter()
+        opsi, oinfo = orc.relax(ocls, None, init=orc.INIT_HALF, tol=replan.TOL, tol_cert=replan.POLISH_CERT)
         tc = time.perf_counter()
-        _, oi = orc.relax(ocls, field, init=orc.INIT_KEEP, tol=1e-300, max_sweeps=k_sweeps,
-                          check_every=k_sweeps)
+        o_st, o_path = orc.descend(ocls, opsi, robot)
         td = time.perf_counter()
-        t_sweep = (td - tc) / k_sweeps
-        t_field = (tb - ta) + plain["sweeps"] * t_sweep
-        cpu = {"value": round(1.0 / t_field, 6), "unit": "fields/s", "cores": cores, "kind": "oracle",
-               "sample": (f"oracle rasterisation of the 2048x2048 scenario ({tb - ta:.2f} s) plus "
-                          f"{k_sweeps} FP64 red-black sweeps ({t_sweep * 1e3:.1f} ms each), scaled to "
-                          f"the {plain['sweeps']} sweeps the GPU's plain solve needs"),
-               "cell_updates_per_s": round(cells / t_sweep, 1)}
+        t_full = td - ta
+        one = json.loads(child.communicate(timeout=600)[0].strip().splitlines()[-1])
+        t_one = one["raster_s"] + oinfo["sweeps"] * one["sweep_s"] + (td - tc)
+        cpu = {"value": round(1.0 / t_full, 6), "unit": "fields/s (same step: rasterise + FP64 SOR to residual "
+                                                         "1e-6 and a certified 1e-7 + descent)",
+               "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": (f"one full step of the 2048x2048 scenario on {cores} threads: rasterisation "
+                          f"{tb_ - ta:.2f} s, {oinfo['sweeps']} FP64 red-black sweeps at the open-grid "
+                          f"factor to residual {oinfo['residual']:.2e} (bound {oinfo['bound']:.2e}) "
+                          f"{tc - tb_:.1f} s, descent {td - tc:.3f} s"),
+               "seconds": round(t_full, 3), "cell_updates_per_s": round(cells * oinfo["sweeps"] / (tc - tb_), 1),
+               "descent_status": o_st, "path_length": int(len(o_path)),
+               "single_thread": {"value": round(1.0 / t_one, 6), "cores": 1,
+                                 "sample": (f"rasterisation ({one['raster_s']:.2f} s) and {one['sweeps']} sweeps "
+                                            f"({one['sweep_s'] * 1e3:.1f} ms each) on one thread, scaled to the "
+                                            f"{oinfo['sweeps']} sweeps of the full step")}}
+        log(f"cpu: {cpu}")
+    elif child is not None:
+        child.kill()
 
     out = {
         "metric": METRIC,
@@ -536,6 +606,8 @@ def main():
         "ms_to_residual_1e-6": {"plain": round(float(med[1]), 3),
                                 "learned": learned["ms_to_residual_1e-6"] if learned else None},
         "learned": learned,
+        "learned_ceiling_2048": ceiling,
+        "learned_256": learned256,
         "ms_breakdown": {"rasterize": round(float(med[0]), 3), "plain_relax": round(float(med[1]), 3),
                          "fp64_polish": round(float(med[2]), 3),
                          "descent_and_fp64_rounds": round(float(med[3]), 3)},
@@ -544,13 +616,13 @@ def main():
         "descent_rounds": pol["descent_rounds"],
         "certified_error_bound": pol["cert_bound"],
         "cell_updates_per_s": round(cups, 1),
-        "hbm_frac_algorithmic": round(cups * BYTES_PER_CELL_UPDATE / (HBM_PEAK_GBS * 1e9), 4),
         "descent": {"status": status, "length": n, "reached_goal": status == 0},
         "tuning": {"sweeps_per_pass": tuning["S"], "rows_per_tile": tuning["RH"],
                    "omega": round(tuning["omega"], 6), "omega_dc": round(tuning["omega_dc"], 6),
                    "dc_start_phase": {"omega": round(tuning["lead_dc_omega"], 6),
                                       "sweeps": tuning["lead_dc_sweeps"]},
                    "fp64_sweeps_per_pass": tuning["S64"], "fp64_rows_per_tile": tuning["RH64"]},
+        "graph_step": graph_step,
         "roofline": roofline,
         "roofline_other": roofline_other,
         "roofline_alu": roofline_alu,

@@ -348,8 +348,10 @@ int32_t hpf_init_field(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi,
  * step's field: every cell that is FREE in cls and was FREE in cls_prev takes
  * psi_prev's value; all other cells of psi are left as they are (so a
  * network warm start, or Dirichlet values, written to psi beforehand remain
- * where the map changed).  All arrays device, pitch g.pitch.  Asynchronous.
- * Errors: TWG_EINVAL. */
+ * where the map changed).  cls_prev NULL: every FREE cell of cls takes
+ * psi_prev's value (a cell freed since the previous step starts from the
+ * previous field there: 0 where an obstacle was).  All arrays device, pitch
+ * g.pitch.  Asynchronous.  Errors: TWG_EINVAL (NULL cls, psi_prev or psi). */
 int32_t hpf_merge_previous(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const uint8_t *cls_prev,
                            const float *psi_prev, float *psi, void *stream);
 

@@ -1419,7 +1419,7 @@ int32_t hpf_merge_previous(twg_ctx *ctx, twg_grid g, const uint8_t *cls, const u
     ctx->err.clear();
     int rc = check_grid(ctx, g);
     if (rc) return rc;
-    if (!cls || !cls_prev || !psi_prev || !psi) return set_err(ctx, TWG_EINVAL, "missing argument");
+    if (!cls || !psi_prev || !psi) return set_err(ctx, TWG_EINVAL, "missing argument");
     hipSetDevice(ctx->device);
     rc = launch_merge_prev(cls, cls_prev, psi_prev, psi, g.nx, g.ny, g.pitch, as_stream(stream));
     return rc ? set_err(ctx, rc, "merge launch failed") : TWG_OK;

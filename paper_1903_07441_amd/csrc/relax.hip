@@ -221,7 +221,8 @@ __global__ void k_merge_prev(const uint8_t *__restrict__ cls, const uint8_t *__r
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= nx || y >= ny) return;
     const size_t i = (size_t)y * pitch + x;
-    if (cls[i] == TWG_CELL_FREE && cls_prev[i] == TWG_CELL_FREE) psi[i] = psi_prev[i];
+    // without a previous class map every FREE cell takes the previous value
+    if (cls[i] == TWG_CELL_FREE && (!cls_prev || cls_prev[i] == TWG_CELL_FREE)) psi[i] = psi_prev[i];
 }
 
 // ---- element-wise helpers --------------------------------------------------

@@ -137,7 +137,7 @@ OMEGAS = (1.6, 1.8, 1.9, 1.95, 0.0)  # 0 = the open-rectangle optimum of the gri
 
 def evaluate(ctx, net, data, tol=1e-6, omegas=OMEGAS):
     """Relax every scenario of `data` to `tol` from the plain initial fields
-    (half, zero) and from the network's field, each with every SOR factor of
+    (half, zero, linear ramp) and from the network's field, each with every SOR factor of
     `omegas`; per-mode median sweeps and times (the learned time includes
     features and network).  Both paths are credited with their best factor:
     obstacles shrink the domain, so the best factor is below the open-grid
@@ -147,7 +147,7 @@ def evaluate(ctx, net, data, tol=1e-6, omegas=OMEGAS):
     dev = data["cls"].device
     psi = torch.empty((H, W), dtype=torch.float32, device=dev)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    kinds = ("half", "zero", "learned")
+    kinds = ("half", "zero", "linear", "learned")
     out = {(kd, w): [] for kd in kinds for w in omegas}
     net_ms, net_err = [], []
     for k in range(n):
@@ -161,11 +161,12 @@ def evaluate(ctx, net, data, tol=1e-6, omegas=OMEGAS):
             free = cls == twg.FREE
             net_err.append(float((psi - data["target"][k]).abs()[free].max().item()))
         for w in omegas:
-            for kd, init in (("half", twg.INIT_HALF), ("zero", twg.INIT_ZERO), ("learned", twg.INIT_KEEP)):
+            for kd, init in (("half", twg.INIT_HALF), ("zero", twg.INIT_ZERO), ("linear", twg.INIT_LINEAR),
+                             ("learned", twg.INIT_KEEP)):
                 ev0.record()
                 if kd == "learned":
                     net.warm_start(cls, ring, goal, psi)
-                st = ctx.relax(cls, psi, None, tol=tol, init=init, omega=w)
+                st = ctx.relax(cls, psi, None, tol=tol, init=init, omega=w, goal=goal)
                 ev1.record()
                 torch.cuda.synchronize()
                 out[(kd, w)].append((st["sweeps"], ev0.elapsed_time(ev1), st["residual"]))
@@ -181,8 +182,9 @@ def evaluate(ctx, net, data, tol=1e-6, omegas=OMEGAS):
     summ["net_median_ms"] = float(np.median(net_ms))
     if net_err:
         summ["net_median_max_err"] = float(np.median(net_err))
-    plain = min((summ["half"], summ["zero"]), key=lambda r: r["median_ms"])
-    summ["plain_best"] = {"init": "half" if plain is summ["half"] else "zero", "omega": plain["best_omega"],
+    plain_kd = min(("half", "zero", "linear"), key=lambda kd: summ[kd]["median_ms"])
+    plain = summ[plain_kd]
+    summ["plain_best"] = {"init": plain_kd, "omega": plain["best_omega"],
                           "median_ms": plain["median_ms"], "median_sweeps": plain["median_sweeps"]}
     summ["time_ratio_plain_over_learned"] = plain["median_ms"] / max(1e-9, summ["learned"]["median_ms"])
     summ["sweep_ratio_plain_over_learned"] = plain["median_sweeps"] / max(1.0, summ["learned"]["median_sweeps"])

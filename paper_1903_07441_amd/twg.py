@@ -392,9 +392,10 @@ def _rubber(ctx, cls, psi, psi64, path, info, k, iters):
 
 
 def _merge_previous(ctx, cls, cls_prev, psi_prev, psi):
+    """cls_prev None: every FREE cell of cls takes psi_prev's value."""
     nx, ny, pitch = _grid_of(psi)
     for t in (cls, cls_prev, psi_prev):
-        if t.stride(0) != pitch:
+        if t is not None and t.stride(0) != pitch:
             raise ValueError("all maps must share psi's pitch")
     ctx._check(lib.hpf_merge_previous(ctx.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(cls_prev), _ptr(psi_prev),
                                       _ptr(psi), _stream()))
