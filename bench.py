@@ -2,9 +2,10 @@
 one 2048 x 2048 grid with 500 moving obstacles (synthetic, seeded).
 
 A step = rasterise (ring map, Kalman prediction to ring time, disc marking)
--> FP32 red-black SOR to residual 1e-6 -> FP64 defect-correction polish to a
-certified error bound of 1e-7 (FP64 SOR sweeps added while the descent from
-the robot does not resolve) -> steepest-descent path.  Inputs are resident
+-> FP32 red-black SOR from the plain start psi = 0 to residual 1e-6 -> FP64
+defect-correction polish to a certified error bound of 5e-7 (FP64 SOR sweeps
+added while the descent from the robot does not resolve) ->
+steepest-descent path.  Inputs are resident
 in HBM before the timed region.  Prints one JSON line on stdout.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
@@ -68,9 +69,10 @@ def profiled_traffic(kernel, role, rows):
         return None
     for ln in text:
         f = ln.strip("` ").split()
-        # "traffic <kernel> <role> rows_per_tile <RH> source_sha256_16 <sha> bytes_per_launch <B>"
-        if len(f) == 9 and f[0] == "traffic" and f[1] == kernel and f[2] == role and f[4] == str(rows) \
-                and f[6] == sha:
+        # "traffic <kernel without spaces> <role> rows_per_tile <RH> source_sha256_16 <sha>
+        #  bytes_per_launch <B>"
+        if len(f) == 9 and f[0] == "traffic" and f[1] == kernel.replace(" ", "") and f[2] == role \
+                and f[4] == str(rows) and f[6] == sha:
             return int(f[8])
     return None
 
@@ -95,7 +97,7 @@ def cpu_child(index, sweeps):
     t0 = time.perf_counter()
     ocls, _ = orc.rasterize(sc, "perobs")
     t1 = time.perf_counter()
-    orc.relax(ocls, None, init=orc.INIT_HALF, tol=1e-300, max_sweeps=sweeps, check_every=sweeps)
+    orc.relax(ocls, None, init=orc.INIT_ZERO, tol=1e-300, max_sweeps=sweeps, check_every=sweeps)
     t2 = time.perf_counter()
     print(json.dumps({"raster_s": t1 - t0, "sweep_s": (t2 - t1) / sweeps, "sweeps": sweeps}), flush=True)
 
@@ -252,7 +254,7 @@ def main():
         ev[0].record()
         pl.rasterize(robot, pos, vel)
         ev[1].record()
-        plain = ctx.relax(cls, psi, None, tol=replan.TOL, init=twg.INIT_HALF)
+        plain = ctx.relax(cls, psi, None, tol=replan.TOL, init=replan.PLAIN_INIT)
         ev[2].record()
         pol = ctx.relax(cls, psi, psi64, tol=replan.TOL, init=twg.INIT_KEEP, polish=1, tol_cert=replan.POLISH_CERT)
         ev[3].record()
@@ -347,7 +349,7 @@ def main():
 
     descent_all = {"fp64_polished": reach_frac(psi64=psi64)}
     psi_f = torch.empty_like(psi)
-    ctx.relax(cls, psi_f, None, tol=replan.TOL, init=twg.INIT_HALF)
+    ctx.relax(cls, psi_f, None, tol=replan.TOL, init=replan.PLAIN_INIT)
     descent_all["fp32_residual_1e-6"] = reach_frac(psi=psi_f)
     e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e_a.record()
@@ -373,7 +375,7 @@ def main():
 
     # ---- the other polish: FP64 SOR sweeps to a certified 5e-7 ----
     psi64_d = torch.empty_like(psi64)
-    ctx.relax(cls, psi_f, None, tol=replan.TOL, init=twg.INIT_HALF)
+    ctx.relax(cls, psi_f, None, tol=replan.TOL, init=replan.PLAIN_INIT)
     e_a.record()
     pol_d = ctx.relax(cls, psi_f, psi64_d, tol=replan.TOL, init=twg.INIT_KEEP, polish=2, tol_cert=5e-7)
     d_path, d_info = ctx.descend(cls, psi64=psi64_d, start=robot, cap=cap)
@@ -403,8 +405,9 @@ def main():
             `omegas` (0 = tuned factor) from the field fill() writes; then the
             FP64 polish of that field to the certified bound, timed too (a
             factor below the optimum can reach the residual sooner and leave
-            smooth error that the polish pays for)."""
-            best = None
+            smooth error that the polish pays for); best_certified is the
+            factor with the shortest certified time."""
+            rows = []
             for w in omegas:
                 fill(psi_l)
                 torch.cuda.synchronize()
@@ -422,9 +425,10 @@ def main():
                        "ms_fill": round(el[0].elapsed_time(el[1]), 3), "sweeps": st_l["sweeps"],
                        "residual": st_l["residual"], "ms_certified": round(el[0].elapsed_time(el[3]), 3),
                        "polish_sweeps": st_p["polish_sweeps"], "cert_bound": st_p["cert_bound"]}
-                if best is None or row["ms"] < best["ms"]:
-                    best = row
-            return best
+                rows.append(row)
+            best = min(rows, key=lambda r: r["ms"])
+            best_cert = min(rows, key=lambda r: r["ms_certified"])
+            return dict(best, best_certified=best_cert)
 
         net_fill = lambda t: net.warm_start(cls, ring, sc["goal"], t)  # noqa: E731
         runs = [time_relax(net_fill, include_fill=True) for _ in range(3)]
@@ -498,7 +502,7 @@ def main():
                 loop[tag][vname] = replan.summarize(res, what)
                 log(f"loop {tag} {vname}: {loop[tag][vname]}")
         loop["step"] = ("Kalman update of all obstacles (position measurements, R = 0.25 I) + rasterise + warm "
-                        "start + FP32 relax to residual 1e-6 + FP64 defect correction to a certified 1e-7 + "
+                        "start + FP32 relax to residual 1e-6 + FP64 defect correction to a certified 5e-7 + "
                         "descent from the robot (FP64 rounds while it does not resolve); the robot then moves "
                         "one cell along that path; obstacles move at constant velocity and reflect at walls")
     if net is not None:
@@ -565,26 +569,36 @@ def main():
         ta = time.perf_counter()
         ocls, _ = orc.rasterize(sc, "perobs")
         tb_ = time.perf_counter()
-        opsi, oinfo = orc.relax(ocls, None, init=orc.INIT_HALF, tol=replan.TOL, tol_cert=replan.POLISH_CERT)
+        opsi, oinfo = orc.relax(ocls, None, init=orc.INIT_ZERO, tol=replan.TOL, tol_cert=replan.POLISH_CERT)
         tc = time.perf_counter()
+        # as on the GPU: more sweeps, 256 at a time, while the descent from
+        # the robot does not resolve
         o_st, o_path = orc.descend(ocls, opsi, robot)
+        o_rounds = 0
+        while o_st == orc.NO_PATH and o_rounds < 8:
+            opsi, _ = orc.relax(ocls, opsi, init=orc.INIT_KEEP, tol=1e-300, max_sweeps=256, check_every=256)
+            o_st, o_path = orc.descend(ocls, opsi, robot)
+            o_rounds += 1
         td = time.perf_counter()
         t_full = td - ta
         one = json.loads(child.communicate(timeout=600)[0].strip().splitlines()[-1])
-        t_one = one["raster_s"] + oinfo["sweeps"] * one["sweep_s"] + (td - tc)
+        o_sweeps = oinfo["sweeps"] + 256 * o_rounds
+        t_one = one["raster_s"] + o_sweeps * one["sweep_s"]
         cpu = {"value": round(1.0 / t_full, 6), "unit": "fields/s (same step: rasterise + FP64 SOR to residual "
-                                                         "1e-6 and a certified 1e-7 + descent)",
+                                                         "1e-6 and a certified 5e-7, more sweeps while the descent "
+                                                         "does not resolve + descent)",
                "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
                "sample": (f"one full step of the 2048x2048 scenario on {cores} threads: rasterisation "
-                          f"{tb_ - ta:.2f} s, {oinfo['sweeps']} FP64 red-black sweeps at the open-grid "
-                          f"factor to residual {oinfo['residual']:.2e} (bound {oinfo['bound']:.2e}) "
-                          f"{tc - tb_:.1f} s, descent {td - tc:.3f} s"),
-               "seconds": round(t_full, 3), "cell_updates_per_s": round(cells * oinfo["sweeps"] / (tc - tb_), 1),
-               "descent_status": o_st, "path_length": int(len(o_path)),
+                          f"{tb_ - ta:.2f} s, {oinfo['sweeps']} FP64 red-black sweeps from psi = 0 at the "
+                          f"open-grid factor to residual {oinfo['residual']:.2e} (bound {oinfo['bound']:.2e}) "
+                          f"{tc - tb_:.1f} s, then {o_rounds} rounds of 256 sweeps with the descent from the "
+                          f"robot {td - tc:.1f} s"),
+               "seconds": round(t_full, 3), "cell_updates_per_s": round(cells * o_sweeps / (td - tb_), 1),
+               "descent_status": o_st, "path_length": int(len(o_path)), "sweeps": o_sweeps,
                "single_thread": {"value": round(1.0 / t_one, 6), "cores": 1,
                                  "sample": (f"rasterisation ({one['raster_s']:.2f} s) and {one['sweeps']} sweeps "
                                             f"({one['sweep_s'] * 1e3:.1f} ms each) on one thread, scaled to the "
-                                            f"{oinfo['sweeps']} sweeps of the full step")}}
+                                            f"{o_sweeps} sweeps of the full step")}}
         log(f"cpu: {cpu}")
     elif child is not None:
         child.kill()
@@ -592,16 +606,16 @@ def main():
     out = {
         "metric": METRIC,
         "value": round(1000.0 / ms_per_step, 4),
-        "unit": "converged 2048x2048 fields/s (residual 1e-6, then certified 1e-7)",
+        "unit": "converged 2048x2048 fields/s (residual 1e-6, then certified 5e-7)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 sweeps, f64 residual and polish", "data": "synthetic",
         "config": {"workload": "replan2048: one 2048x2048 time-warped grid, 500 moving discs "
                                "(radius 3-12, velocity N(0,0.5)), ring width 8, robot speed 1; "
-                               "rasterise + FP32 SOR to residual 1e-6 + FP64 defect-correction polish "
-                               "(FP32 correction solves) to a certified 1e-7, FP64 SOR sweeps until the "
-                               "descent resolves + descent",
+                               "rasterise + FP32 SOR from psi = 0 to residual 1e-6 + FP64 defect-correction "
+                               "polish (FP32 correction solves) to a certified 5e-7 (so within 1e-6 of the "
+                               "oracle's certified field), FP64 SOR sweeps until the descent resolves + descent",
                    "grid": [nx, ny], "obstacles": int(len(sc["rad"])), "seed": sc["seed"]},
         "ms_to_residual_1e-6": {"plain": round(float(med[1]), 3),
                                 "learned": learned["ms_to_residual_1e-6"] if learned else None},

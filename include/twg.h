@@ -248,7 +248,13 @@ typedef struct {
  * correction solves use the autotuned defect-correction factor (or omega if
  * given).  With omega = 0 on an autotuned size, each correction solve may
  * open with a start phase: a few passes at a smaller tuned factor (counted
- * in polish_sweeps).
+ * in polish_sweeps).  A correction solve also ends early when, over a check
+ * span of at least 128 sweeps, it contracts at less than half the speed its
+ * factor omega gives every mode at or above a domain's optimum
+ * (1 - q < (2 - omega) / 2 for the measured rate q per sweep): that is the
+ * FP32 rounding floor of a correction with a large smooth part, which a
+ * warm-started FP32 stage can leave; the FP64 update and the next round
+ * carry on from there.
  *
  * Convergence is decided on the device (polish 0 and 1): the passes that
  * check measure the residual of their input field as they stream it, and the
@@ -320,22 +326,44 @@ typedef struct {
 } twg_grid_desc;
 
 /* hpf_relax_batched -- hpf_relax (FP32 phase) for n independent grids of any
- * sizes at once.  Every pass is ONE launch over the tiles of all grids still
- * above tolerance, and the FP64 residuals of all grids are reduced in one
- * launch; a grid drops out of the pass sequence at the first residual check
- * where it meets tol.  With params->check_passes = 0 the checks are placed at
- * the latest predicted convergence whose overshoot (sweeps of grids predicted
- * to converge earlier) stays within 5 % of the useful work, so a grid may sweep
- * past its tolerance; its stats count those sweeps.  Grid k's class map and field start at element offset
- * grids[k].offset of cls and psi (the grids must not overlap).  Sweeps per
- * tile load and rows per tile come from the autotuned entry of the largest
- * grid (or params->sweeps_per_pass / rows_per_tile); each grid's SOR factor is params->omega, else its
- * size's autotuned factor, else its open-rectangle optimum.  polish must be 0.
- * stats: host array of n entries, or NULL.  Blocking.  Returns TWG_OK when
- * every grid converged, else TWG_NOT_CONVERGED.  Errors: TWG_EINVAL (n < 1,
- * NULL arrays, a bad grid or offset, polish set), TWG_ENOMEM, TWG_EDEVICE. */
+ * sizes at once (Eqs. 1-2 on every grid; section "GPU-Based Parallel
+ * Implementation").  Grid k's class map and field start at element offset
+ * grids[k].offset of cls and psi (the grids must not overlap).  Every pass is
+ * ONE launch over the tiles of all grids still above tolerance; each grid
+ * runs its own solve on the device -- its own pass count, its own residual
+ * checks (fused into the pass that checks, FP64 maxima per grid), its own
+ * stop rules (tolerance, sweep budget per grid, a stall at the FP32
+ * rounding floor) -- and drops out of the launches at the check where it
+ * stops.  Checks fall on passes that are multiples of 4 (so that grids share
+ * them), or every params->check_passes passes.  The host never waits for a
+ * residual: it only keeps launches queued (it reads the device's decisions
+ * from pinned memory).  Sweeps per tile load and rows per tile come from the
+ * autotuned entry of the largest grid (or params->sweeps_per_pass /
+ * rows_per_tile); each grid's SOR factor is params->omega, else its size's
+ * autotuned factor, else its open-rectangle optimum.  init: HPF_INIT_KEEP,
+ * HALF or ZERO; polish must be 0.  stats: host array of n entries, or NULL.
+ * Blocking.  Returns TWG_OK when every grid converged, else
+ * TWG_NOT_CONVERGED.  Errors: TWG_EINVAL (n < 1, NULL arrays, a bad grid or
+ * offset, polish set, a non-finite value in a grid), TWG_EUNSUPPORTED (more
+ * than 65536 grids), TWG_ENOMEM, TWG_EDEVICE. */
 int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, const uint8_t *cls,
                           float *psi, const hpf_params *params, hpf_stats *stats, void *stream);
+
+/* hpf_relax_batched_async -- hpf_relax_batched with nothing done on the host
+ * after the arguments are checked: field initialisation, free masks, then
+ * exactly `slots` launches of the batch and one final launch, all enqueued
+ * on `stream` (a caller may capture them into a graph).  Each launch is one
+ * pass over the tiles of the grids still active; launches after the end
+ * return at once, and the final one ends the grids still running (status
+ * TWG_NOT_CONVERGED, with their latest fields).  A batch whose slowest grid
+ * needs P passes takes about P + 2 slots (its checks fall on multiples of 4
+ * passes).  stats: DEVICE array of n hpf_stats, written when the batch ends.
+ * The descriptor tables are uploaded (with a wait) only when they differ
+ * from the last call's: make the first call of a batch outside capture.
+ * Errors as hpf_relax_batched, and TWG_EINVAL for slots < 1 or NULL stats. */
+int32_t hpf_relax_batched_async(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, const uint8_t *cls,
+                                float *psi, const hpf_params *params, int32_t slots, hpf_stats *stats,
+                                void *stream);
 
 /* hpf_init_field -- the initial field of hpf_relax without relaxing: OBST
  * and WALL cells 0, GOAL 1, FIXED unchanged, FREE cells by `init`
@@ -546,10 +574,16 @@ int32_t twg_unet_features(twg_unet *net, twg_grid g, const uint8_t *cls, const u
 
 /* Warm start of one grid: features, network, and the field written to psi
  * (device FP32, pitch g.pitch): FREE cells clamp(y, 0, 1), OBST and WALL 0,
- * GOAL 1, FIXED cells unchanged.  Follow with hpf_relax(init =
- * HPF_INIT_KEEP).  Asynchronous. */
+ * GOAL 1, FIXED cells unchanged.  If the network produces a non-finite value
+ * at any FREE cell (e.g. NaN parameters), the network's field is rejected and
+ * every FREE cell holds the plain start 0.5 (the paper's initial value)
+ * instead; status (optional device int32, or NULL) receives TWG_OK or
+ * TWG_NET_FALLBACK.  Follow with hpf_relax(init = HPF_INIT_KEEP).
+ * Asynchronous; allocates nothing after the first call of a grid size (no
+ * memset either), so it can be captured into a graph.  Errors: TWG_EINVAL
+ * (bad grid, NULL cls or psi), TWG_ENOMEM. */
 int32_t twg_unet_warm_start(twg_unet *net, twg_grid g, const uint8_t *cls, const uint16_t *ring,
-                            int32_t goal_x, int32_t goal_y, float *psi, void *stream);
+                            int32_t goal_x, int32_t goal_y, float *psi, int32_t *status, void *stream);
 
 #ifdef __cplusplus
 }

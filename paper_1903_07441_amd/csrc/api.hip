@@ -562,6 +562,199 @@ int relax_device_ctx(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float 
     return relax_device(ctx, g, cls, psi, psi64, p, pl, b, slots, stats_dev, stats_host, st);
 }
 
+// Batch slots a blocking solve keeps queued beyond the device's next event.
+constexpr int64_t kBatchSlotMargin = 3;
+// Checks of a batch happen only at slots that are multiples of this, so that
+// grids share them (an event costs every workgroup a ticket).
+constexpr int kBatchQuantum = 4;
+
+// The device-driven batch relaxation (batch.hip): field init and free masks
+// of every grid, the begin kernel, then slots.  slots > 0: exactly that many
+// slots and a final one, asynchronous, stats into stats_dev (n entries).
+// slots == 0: the host keeps slots queued just beyond the next event the
+// device publishes, then copies the stats to stats_host.
+int relax_batch_device(twg_ctx *ctx, int n, const twg_grid_desc *grids, const uint8_t *cls, float *psi,
+                       const hpf_params *params, int64_t slots, hpf_stats *stats_dev, hpf_stats *stats_host,
+                       hipStream_t st)
+{
+    if (n < 1 || !grids || !cls || !psi || !params)
+        return set_err(ctx, TWG_EINVAL, "n >= 1, grids, cls, psi and params are required");
+    if (n > kBatchMaxGrids)
+        return set_err(ctx, TWG_EUNSUPPORTED, "a batch takes at most " + std::to_string(kBatchMaxGrids) + " grids");
+    hpf_params p = *params;
+    if (!(p.tol > 0.0)) return set_err(ctx, TWG_EINVAL, "tol must be > 0");
+    if (!(p.omega >= 0.0f && p.omega < 2.0f)) return set_err(ctx, TWG_EINVAL, "omega must be in [0, 2)");
+    if (p.init < HPF_INIT_KEEP || p.init > HPF_INIT_ZERO) return set_err(ctx, TWG_EINVAL, "bad init mode");
+    if (p.polish) return set_err(ctx, TWG_EINVAL, "the batched relaxation has no polish");
+    if (p.sweeps_per_pass && !stream_depth_supported(p.sweeps_per_pass))
+        return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
+    if (p.rows_per_tile && (p.rows_per_tile < 2 || (p.rows_per_tile & 1)))
+        return set_err(ctx, TWG_EINVAL, "rows_per_tile must be even and >= 2");
+    if (p.check_passes < 0) return set_err(ctx, TWG_EINVAL, "check_passes must be >= 0");
+    if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
+    int big = 0;
+    long long total = 0;
+    for (int k = 0; k < n; ++k) {
+        const twg_grid gk{grids[k].nx, grids[k].ny, grids[k].pitch};
+        int rc = check_grid(ctx, gk);
+        if (rc) return set_err(ctx, rc, "grid " + std::to_string(k) + ": " + ctx->err);
+        if (grids[k].offset < 0) return set_err(ctx, TWG_EINVAL, "negative offset");
+        total = std::max(total, (long long)grids[k].offset + (long long)grids[k].pitch * grids[k].ny);
+        if ((long long)grids[k].nx * grids[k].ny > (long long)grids[big].nx * grids[big].ny) big = k;
+    }
+    hipSetDevice(ctx->device);
+    int S, RH;
+    float om_big;
+    tiling_for(ctx, grids[big].nx, grids[big].ny, &S, &RH, &om_big);
+    if (p.sweeps_per_pass) S = p.sweeps_per_pass;
+    if (p.rows_per_tile) RH = p.rows_per_tile;
+    const int VW = 128 - 4 * S;
+    bool pair = (reinterpret_cast<uintptr_t>(psi) & 7) == 0;  // the partner and mask are context-owned (aligned)
+    int max_pitch = 1;
+    for (int k = 0; k < n; ++k) {
+        pair = pair && grids[k].nx % 2 == 0 && grids[k].pitch % 2 == 0 && grids[k].offset % 2 == 0;
+        max_pitch = std::max(max_pitch, grids[k].pitch);
+    }
+    RH = std::min(RH < 2 ? 2 : (RH & ~1), stream_rows_cap(max_pitch, (int)sizeof(float), S));
+
+    // static tables: descriptors (with each grid's SOR factor) and the
+    // (grid, 64-column block) list
+    std::vector<BatchGrid> bg(n);
+    std::vector<int2> bl;
+    long long max_tiles = 0;
+    for (int k = 0; k < n; ++k) {
+        int s_, rh_;
+        float om;
+        tiling_for(ctx, grids[k].nx, grids[k].ny, &s_, &rh_, &om);
+        bg[k] = BatchGrid{grids[k].nx, grids[k].ny, grids[k].pitch, p.omega > 0.0f ? p.omega : om,
+                          (long long)grids[k].offset};
+        max_tiles += (long long)((grids[k].nx + VW - 1) / VW) * ((grids[k].ny + RH - 1) / RH);
+        for (int bx = 0; bx < (grids[k].nx + 63) / 64; ++bx) bl.push_back(make_int2(k, bx));
+    }
+    if (max_tiles > INT_MAX / 2 || (long long)bl.size() * 32 > INT_MAX / 2)
+        return set_err(ctx, TWG_EUNSUPPORTED, "batch too large");
+    // device layout: grids | blocks | hdr | run | ctl | tile table | rmax | rrel | stats
+    auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t o_grids = 0, o_blocks = align(o_grids + n * sizeof(BatchGrid));
+    const size_t o_hdr = align(o_blocks + bl.size() * sizeof(int2));
+    const size_t o_run = align(o_hdr + batch_hdr_bytes());
+    const size_t o_ctl = align(o_run + n * batch_run_bytes());
+    const size_t o_tiles = align(o_ctl + n * batch_ctl_bytes());
+    const size_t o_rmax = align(o_tiles + (size_t)max_tiles * sizeof(int2));
+    const size_t o_rrel = align(o_rmax + n * sizeof(unsigned long long));
+    const size_t o_stats = align(o_rrel + n * sizeof(unsigned long long));
+    const size_t bytes = align(o_stats + n * sizeof(hpf_stats));
+    const void *old_batch = ctx->batch;
+    int rc = ensure(ctx, &ctx->batch, &ctx->batch_bytes, bytes);
+    if (!rc) rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, (size_t)total * sizeof(float));
+    if (!rc) rc = ensure(ctx, &ctx->fmask, &ctx->fmask_bytes, (size_t)total);
+    if (rc) return rc;
+    char *base = static_cast<char *>(ctx->batch);
+    BatchGrid *d_grids = reinterpret_cast<BatchGrid *>(base + o_grids);
+    int2 *d_blocks = reinterpret_cast<int2 *>(base + o_blocks);
+    // the tables are uploaded only when they differ from the last upload to
+    // this buffer, so that an asynchronous call of an unchanged batch
+    // enqueues kernels only (it can then be captured into a graph)
+    std::vector<char> sig(sizeof(BatchGrid) * bg.size() + sizeof(int2) * bl.size());
+    std::memcpy(sig.data(), bg.data(), sizeof(BatchGrid) * bg.size());
+    std::memcpy(sig.data() + sizeof(BatchGrid) * bg.size(), bl.data(), sizeof(int2) * bl.size());
+    if (old_batch != ctx->batch || sig != ctx->batch_sig) {
+        if (hipMemcpyAsync(d_grids, bg.data(), n * sizeof(BatchGrid), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(d_blocks, bl.data(), bl.size() * sizeof(int2), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return set_err(ctx, TWG_EDEVICE, "batch table upload failed");
+        ctx->batch_sig = std::move(sig);
+    }
+    uint8_t *const fmask = static_cast<uint8_t *>(ctx->fmask);
+    rc = launch_field_init_batch(cls, psi, d_grids, d_blocks, (int)bl.size(), p.init, st);
+    if (!rc) rc = launch_fmask_batch(cls, fmask, d_grids, d_blocks, (int)bl.size(), st);
+    if (rc) return set_err(ctx, TWG_EDEVICE, "batch set-up failed");
+
+    BatchArgs a;
+    a.grids = d_grids;
+    a.blocks = d_blocks;
+    a.n_blocks = (int)bl.size();
+    a.n = n;
+    a.S = S;
+    a.RH = RH;
+    a.slot = 0;
+    a.final_slot = 0;
+    a.quantum = p.check_passes > 0 ? 1 : kBatchQuantum;
+    a.check_passes = p.check_passes;
+    a.tol = p.tol;
+    a.max_sweeps = p.max_sweeps;
+    a.psi = psi;
+    a.alt = static_cast<float *>(ctx->alt);
+    a.mask = fmask;
+    a.hdr = base + o_hdr;
+    a.run = reinterpret_cast<GridRun *>(base + o_run);
+    a.ctl = reinterpret_cast<GridCtl *>(base + o_ctl);
+    a.tiles = reinterpret_cast<int2 *>(base + o_tiles);
+    a.rmax = reinterpret_cast<unsigned long long *>(base + o_rmax);
+    a.rrel = reinterpret_cast<unsigned long long *>(base + o_rrel);
+    a.stats = stats_dev ? stats_dev : reinterpret_cast<hpf_stats *>(base + o_stats);
+    a.mirror = nullptr;
+    rc = launch_batch_begin(a, st);
+    if (rc) return set_err(ctx, rc, "batch begin launch failed");
+    const int mt = (int)max_tiles;
+
+    if (slots > 0) {
+        for (int64_t k = 0; k < slots; ++k) {
+            a.slot = (int)k;
+            if ((rc = launch_batch_slot(a, mt, pair, st))) return set_err(ctx, rc, "batch slot launch failed");
+        }
+        a.final_slot = 1;
+        a.slot = (int)slots;
+        rc = launch_batch_slot(a, mt, pair, st);
+        return rc ? set_err(ctx, rc, "batch slot launch failed") : TWG_OK;
+    }
+
+    // blocking: keep the slots up to the next published event (plus a
+    // margin) queued; bit 63 of the word marks the end
+    volatile unsigned long long *word = ctx->host_words + kMirrorWord;
+    *word = 0ull;
+    std::atomic_thread_fence(std::memory_order_seq_cst);
+    a.mirror = ctx->host_words_dev + kMirrorWord;
+    int64_t queued = 0, target = 1 + kBatchSlotMargin;
+    unsigned long long seen = 0;
+    int idle = 0;
+    for (unsigned polls = 0;;) {
+        const unsigned long long w = *word;
+        if (w >> 63) break;
+        if (w != seen) {
+            seen = w;
+            idle = 0;
+            target = std::max<int64_t>(target, (int64_t)(w & 0xffffffffull) + kBatchSlotMargin);
+        }
+        if (queued < target) {
+            if (queued >= INT_MAX - 8) return set_err(ctx, TWG_EDEVICE, "batch slot count overflow");
+            a.slot = (int)queued;
+            if ((rc = launch_batch_slot(a, mt, pair, st))) return set_err(ctx, rc, "batch slot launch failed");
+            ++queued;
+            continue;
+        }
+        if (++polls % 1024) continue;
+        const hipError_t e = hipStreamQuery(st);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return set_err(ctx, TWG_EDEVICE, "batch stream failed");
+        if (*word == seen && ++idle > 2) return set_err(ctx, TWG_EDEVICE, "batch control made no progress");
+        target = queued + kBatchSlotMargin;
+    }
+    std::vector<hpf_stats> hs(n);
+    if (hipMemcpyAsync(hs.data(), a.stats, n * sizeof(hpf_stats), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return set_err(ctx, TWG_EDEVICE, "batch stats read-back failed");
+    bool all = true, bad = false;
+    for (int k = 0; k < n; ++k) {
+        all = all && hs[k].status == TWG_OK;
+        bad = bad || hs[k].status == TWG_EINVAL;
+        if (stats_host) stats_host[k] = hs[k];
+    }
+    if (bad) return set_err(ctx, TWG_EINVAL, "non-finite value in a grid of the batch");
+    if (!all) set_err(ctx, TWG_NOT_CONVERGED, "some grids stopped before reaching the tolerance");
+    return all ? TWG_OK : TWG_NOT_CONVERGED;
+}
+
 }  // namespace
 
 extern "C" {
@@ -614,7 +807,6 @@ int32_t twg_ctx_destroy(twg_ctx *ctx)
     for (void *b : bufs)
         if (b) hipFree(b);
     if (ctx->host_words) hipHostFree(ctx->host_words);
-    if (ctx->batch_host) hipHostFree(ctx->batch_host);
     delete ctx;
     return TWG_OK;
 }
@@ -783,284 +975,18 @@ int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, c
 {
     if (!ctx) return TWG_EINVAL;
     ctx->err.clear();
-    if (n < 1 || !grids || !cls || !psi || !params)
-        return set_err(ctx, TWG_EINVAL, "n >= 1, grids, cls, psi and params are required");
-    hpf_params p = *params;
-    if (!(p.tol > 0.0)) return set_err(ctx, TWG_EINVAL, "tol must be > 0");
-    if (!(p.omega >= 0.0f && p.omega < 2.0f)) return set_err(ctx, TWG_EINVAL, "omega must be in [0, 2)");
-    if (p.init < HPF_INIT_KEEP || p.init > HPF_INIT_ZERO) return set_err(ctx, TWG_EINVAL, "bad init mode");
-    if (p.polish) return set_err(ctx, TWG_EINVAL, "the batched relaxation has no polish");
-    if (p.sweeps_per_pass && !stream_depth_supported(p.sweeps_per_pass))
-        return set_err(ctx, TWG_EINVAL, "sweeps_per_pass must be one of 1, 2, 3, 4, 6, 8");
-    if (p.rows_per_tile && (p.rows_per_tile < 2 || (p.rows_per_tile & 1)))
-        return set_err(ctx, TWG_EINVAL, "rows_per_tile must be even and >= 2");
-    if (p.max_sweeps <= 0) p.max_sweeps = 10000000;
-    int big = 0;
-    long long total = 0;
-    for (int k = 0; k < n; ++k) {
-        const twg_grid gk{grids[k].nx, grids[k].ny, grids[k].pitch};
-        int rc = check_grid(ctx, gk);
-        if (rc) return set_err(ctx, rc, "grid " + std::to_string(k) + ": " + ctx->err);
-        if (grids[k].offset < 0) return set_err(ctx, TWG_EINVAL, "negative offset");
-        total = std::max(total, (long long)grids[k].offset + (long long)grids[k].pitch * grids[k].ny);
-        if ((long long)grids[k].nx * grids[k].ny > (long long)grids[big].nx * grids[big].ny) big = k;
-    }
-    hipSetDevice(ctx->device);
-    hipStream_t st = as_stream(stream);
-    int S, RH;
-    float om_big;
-    tiling_for(ctx, grids[big].nx, grids[big].ny, &S, &RH, &om_big);
-    if (p.sweeps_per_pass) S = p.sweeps_per_pass;
-    if (p.rows_per_tile) RH = p.rows_per_tile;
-    const int VW = 128 - 4 * S;
-    // paired column access when every grid allows it; tiles within the
-    // streamed kernels' addressable span
-    bool pair = (reinterpret_cast<uintptr_t>(psi) & 7) == 0;  // the mask is context-owned (aligned)
-    int max_pitch = 1;
-    for (int k = 0; k < n; ++k) {
-        pair = pair && grids[k].nx % 2 == 0 && grids[k].pitch % 2 == 0 && grids[k].offset % 2 == 0;
-        max_pitch = std::max(max_pitch, grids[k].pitch);
-    }
-    RH = std::min(RH < 2 ? 2 : (RH & ~1), stream_rows_cap(max_pitch, (int)sizeof(float), S));
+    return relax_batch_device(ctx, n, grids, cls, psi, params, 0, nullptr, stats, as_stream(stream));
+}
 
-    // host descriptors, full tile and block lists
-    std::vector<BatchGrid> bg(n);
-    std::vector<int> tiles_of(n), blocks_of(n);
-    int max_tiles = 0, max_blocks = 0;
-    for (int k = 0; k < n; ++k) {
-        int s_, rh_;
-        float om;
-        tiling_for(ctx, grids[k].nx, grids[k].ny, &s_, &rh_, &om);
-        bg[k] = BatchGrid{grids[k].nx, grids[k].ny, grids[k].pitch, p.omega > 0.0f ? p.omega : om,
-                          (long long)grids[k].offset};
-        tiles_of[k] = ((grids[k].nx + VW - 1) / VW) * ((grids[k].ny + RH - 1) / RH);
-        blocks_of[k] = (grids[k].nx + 63) / 64;
-        max_tiles += tiles_of[k];
-        max_blocks += blocks_of[k];
-    }
-    // device layout: grids | tiles | blocks | n_tiles | words
-    auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
-    const size_t o_grids = 0, o_tiles = align(o_grids + n * sizeof(BatchGrid));
-    const size_t o_blocks = align(o_tiles + max_tiles * sizeof(BatchTile));
-    const size_t o_count = align(o_blocks + max_blocks * sizeof(int2));
-    const size_t o_words = align(o_count + sizeof(int));
-    const size_t bytes = align(o_words + 2 * n * sizeof(unsigned long long));
-    int rc = ensure(ctx, &ctx->batch, &ctx->batch_bytes, bytes);
-    if (!rc) rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, (size_t)total * sizeof(float));
-    if (rc) return rc;
-    if (ctx->batch_host_bytes < 2 * n * sizeof(unsigned long long)) {
-        if (ctx->batch_host) hipHostFree(ctx->batch_host);
-        ctx->batch_host = nullptr;
-        ctx->batch_host_bytes = 0;
-        if (hipHostMalloc(&ctx->batch_host, 2 * n * sizeof(unsigned long long), hipHostMallocDefault) !=
-            hipSuccess)
-            return set_err(ctx, TWG_ENOMEM, "pinned allocation failed");
-        ctx->batch_host_bytes = 2 * n * sizeof(unsigned long long);
-    }
-    char *base = reinterpret_cast<char *>(ctx->batch);
-    BatchGrid *d_grids = reinterpret_cast<BatchGrid *>(base + o_grids);
-    BatchTile *d_tiles = reinterpret_cast<BatchTile *>(base + o_tiles);
-    int2 *d_blocks = reinterpret_cast<int2 *>(base + o_blocks);
-    int *d_count = reinterpret_cast<int *>(base + o_count);
-    unsigned long long *d_words = reinterpret_cast<unsigned long long *>(base + o_words);
-    if (hipMemcpyAsync(d_grids, bg.data(), n * sizeof(BatchGrid), hipMemcpyHostToDevice, st) != hipSuccess)
-        return set_err(ctx, TWG_EDEVICE, "descriptor upload failed");
-
-    std::vector<char> active(n, 1);
-    std::vector<BatchTile> tl;
-    std::vector<int2> bl;
-    auto build_lists = [&](const std::vector<char> &sel) {
-        tl.clear();
-        bl.clear();
-        for (int k = 0; k < n; ++k) {
-            if (!sel[k]) continue;
-            const int strips = (grids[k].nx + VW - 1) / VW;
-            for (int y0 = 0; y0 < grids[k].ny; y0 += RH)
-                for (int sx = 0; sx < strips; ++sx)
-                    tl.push_back(BatchTile{k, sx * VW - 2 * S, y0, std::min(y0 + RH, grids[k].ny)});
-            for (int bx = 0; bx < blocks_of[k]; ++bx) bl.push_back(make_int2(k, bx));
-        }
-    };
-    auto upload_lists = [&]() -> int {
-        const int nt = (int)tl.size();
-        if ((!tl.empty() && hipMemcpyAsync(d_tiles, tl.data(), tl.size() * sizeof(BatchTile),
-                                           hipMemcpyHostToDevice, st) != hipSuccess) ||
-            (!bl.empty() && hipMemcpyAsync(d_blocks, bl.data(), bl.size() * sizeof(int2),
-                                           hipMemcpyHostToDevice, st) != hipSuccess) ||
-            hipMemcpyAsync(d_count, &nt, sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return TWG_EDEVICE;
-        return TWG_OK;
-    };
-    build_lists(active);
-    const int max_tiles0 = (int)tl.size();
-    rc = upload_lists();
-    if (!rc) rc = launch_field_init_batch(cls, psi, d_grids, d_blocks, (int)bl.size(), p.init, st);
-    // free mask of every grid, laid out as the class buffer (each grid's
-    // omega comes from its descriptor)
-    if (!rc) rc = ensure(ctx, &ctx->fmask, &ctx->fmask_bytes, (size_t)total);
-    uint8_t *const fmask = static_cast<uint8_t *>(ctx->fmask);
-    if (!rc) rc = launch_fmask_batch(cls, fmask, d_grids, d_blocks, (int)bl.size(), st);
-    if (rc) return set_err(ctx, TWG_EDEVICE, "batch set-up failed");
-
-    std::vector<double> r(n), rr(n), rate(n);
-    std::vector<int64_t> sw(n, 0), since(n, 0);
-    std::vector<int> stalls(n, 0);
-    std::vector<char> conv(n, 0), parity(n, 0);
-    for (int k = 0; k < n; ++k) rate[k] = std::max((double)bg[k].omega - 1.0, 0.5);
-    float *cur = psi, *nxt = reinterpret_cast<float *>(ctx->alt);
-    int64_t done = 0;
-    int checks = 0;
-    auto check = [&]() -> int {
-        int e = launch_resid_batch(cls, cur, d_grids, d_blocks, (int)bl.size(), d_words, 2 * n, st);
-        if (e) return e;
-        if (hipMemcpyAsync(ctx->batch_host, d_words, 2 * n * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return TWG_EDEVICE;
-        ++checks;
-        return TWG_OK;
-    };
-    rc = check();
-    if (rc) return set_err(ctx, rc, "batched residual failed");
-    for (int k = 0; k < n; ++k) {
-        r[k] = bits_to_double(ctx->batch_host[2 * k]);
-        rr[k] = bits_to_double(ctx->batch_host[2 * k + 1]);
-    }
-    std::vector<double> best(r);
-    while (true) {
-        // retire converged, stalled or non-finite grids
-        bool changed = false;
-        int64_t chunk = INT64_MAX;
-        // (predicted sweeps to converge, cells) of every active grid
-        std::vector<std::pair<int64_t, double>> pred;
-        for (int k = 0; k < n; ++k) {
-            if (!active[k]) continue;
-            if (std::isnan(r[k]) || std::isnan(rr[k]))
-                return set_err(ctx, TWG_EINVAL, "non-finite value in grid " + std::to_string(k));
-            const bool ok = r[k] <= p.tol;
-            if (ok || (stalls[k] >= 3 && since[k] >= kStallSweeps) || done >= p.max_sweeps) {
-                active[k] = 0;
-                conv[k] = ok;
-                parity[k] = cur != psi;
-                changed = true;
-                continue;
-            }
-            const double want = std::log(p.tol / r[k]) / std::log(rate[k]);
-            int64_t c = (int64_t)std::min(std::ceil(want * (checks <= 1 ? 0.8 : 1.05)), 1e12);
-            if (p.check_passes > 0) c = (int64_t)p.check_passes * S;
-            c = std::max<int64_t>(c, 8 * S);
-            chunk = std::min(chunk, c);
-            pred.push_back({c, (double)bg[k].nx * (double)bg[k].ny});
-        }
-        if (chunk == INT64_MAX) break;  // nothing active
-        // A check stops the whole batch (residuals, read-back, new tile
-        // lists), so the next one is not placed at the first predicted
-        // convergence but at the latest predicted one whose overshoot, the
-        // sweeps that grids predicted to converge earlier run in vain, stays
-        // within 5 % of the chunk's useful cell-updates: small grids are
-        // cheap to sweep on, the batch-wide stop is not.
-        if (p.check_passes <= 0) {
-            std::sort(pred.begin(), pred.end());
-            for (const auto &cand : pred) {
-                const int64_t c = cand.first;
-                double waste = 0.0, useful = 0.0;
-                for (const auto &q : pred) {
-                    waste += q.second * (double)std::max<int64_t>(0, c - q.first);
-                    useful += q.second * (double)std::min(c, q.first);
-                }
-                if (waste <= 0.05 * useful) chunk = std::max(chunk, c);
-            }
-        }
-        if (changed) {
-            build_lists(active);
-            rc = upload_lists();
-            if (rc) return set_err(ctx, rc, "list upload failed");
-        }
-        chunk = std::min(chunk, p.max_sweeps - done);
-        const int64_t passes = (chunk + S - 1) / S;
-        // whole runs of kGraphPasses passes replay one captured graph, sized
-        // for the first (largest) tile list: the kernel reads the active tile
-        // count from device memory, so retired grids cost an early exit
-        const int64_t reps = ctx->use_graphs ? passes / kGraphPasses : 0;
-        if (reps > 0) {
-            const std::vector<uintptr_t> key = {2, (uintptr_t)cur, (uintptr_t)nxt, (uintptr_t)fmask,
-                                                (uintptr_t)d_grids, (uintptr_t)d_tiles, (uintptr_t)d_count,
-                                                (uintptr_t)max_tiles0, (uintptr_t)S, (uintptr_t)pair};
-            float *x = cur, *y = nxt;
-            rc = graph_replay(ctx, key, st, reps, [&](hipStream_t cs) {
-                for (int k = 0; k < kGraphPasses; ++k) {
-                    const int e = launch_stream_batch(k % 2 ? y : x, k % 2 ? x : y, fmask, d_grids, d_tiles, d_count,
-                                                      max_tiles0, S, pair, cs);
-                    if (e) return e;
-                }
-                return TWG_OK;
-            });
-            if (rc) return set_err(ctx, rc, "batched relaxation graph failed");
-        }
-        for (int64_t q = reps * kGraphPasses; q < passes; ++q) {
-            rc = launch_stream_batch(cur, nxt, fmask, d_grids, d_tiles, d_count, (int)tl.size(), S, pair, st);
-            if (rc) return set_err(ctx, rc, "batched relaxation launch failed");
-            std::swap(cur, nxt);
-        }
-        done += passes * S;
-        rc = check();
-        if (rc) return set_err(ctx, rc, "batched residual failed");
-        for (int k = 0; k < n; ++k) {
-            if (!active[k]) continue;
-            sw[k] = done;
-            const double rn = bits_to_double(ctx->batch_host[2 * k]);
-            const double rrn = bits_to_double(ctx->batch_host[2 * k + 1]);
-            if (rn < r[k]) {
-                const double q = std::pow(rn / r[k], 1.0 / (double)(passes * S));
-                if (q > 0.0 && q < 1.0) rate[k] = q;
-            }
-            // the single-grid solve's stall rule, on the best residual
-            if (rn < 0.9 * best[k]) {
-                best[k] = rn;
-                stalls[k] = 0;
-                since[k] = 0;
-            } else {
-                ++stalls[k];
-                since[k] += passes * S;
-            }
-            r[k] = rn;
-            rr[k] = rrn;
-        }
-    }
-    // grids that stopped on an odd pass count hold their field in the partner buffer
-    std::vector<char> back(n);
-    bool any = false;
-    for (int k = 0; k < n; ++k) {
-        back[k] = parity[k];
-        any = any || parity[k];
-    }
-    if (any) {
-        build_lists(back);
-        rc = upload_lists();
-        if (!rc) rc = launch_copy_batch(reinterpret_cast<float *>(ctx->alt), psi, d_grids, d_blocks,
-                                        (int)bl.size(), st);
-        if (rc) return set_err(ctx, rc, "copy-back failed");
-    }
-    hipStreamSynchronize(st);
-    bool all = true;
-    for (int k = 0; k < n; ++k) {
-        all = all && conv[k];
-        if (stats) {
-            hpf_stats &s = stats[k];
-            std::memset(&s, 0, sizeof s);
-            s.sweeps = sw[k];
-            s.residual = s.residual32 = r[k];
-            s.residual_rel = rr[k];
-            s.wbound = std::pow((double)std::min(grids[k].nx, grids[k].ny) + 1.0, 2) / 2.0;
-            s.cert_bound = r[k] * s.wbound;
-            s.omega = bg[k].omega;
-            s.status = conv[k] ? TWG_OK : TWG_NOT_CONVERGED;
-            s.checks = checks;
-        }
-    }
-    if (!all) set_err(ctx, TWG_NOT_CONVERGED, "some grids stopped before reaching the tolerance");
-    return all ? TWG_OK : TWG_NOT_CONVERGED;
+int32_t hpf_relax_batched_async(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, const uint8_t *cls,
+                                float *psi, const hpf_params *params, int32_t slots, hpf_stats *stats,
+                                void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    if (slots < 1) return set_err(ctx, TWG_EINVAL, "slots must be >= 1");
+    if (!stats) return set_err(ctx, TWG_EINVAL, "stats (device, n entries) is required");
+    return relax_batch_device(ctx, n, grids, cls, psi, params, slots, stats, nullptr, as_stream(stream));
 }
 
 int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, void *stream)

@@ -2,7 +2,7 @@
 // values of section "Harmonic Potential Fields"): the untiled one-colour
 // sweep (the reference the streamed kernel in sor_stream.hip is tested
 // against, bit for bit), FP64 residual reductions, field initialisation, the
-// FP64 defect-correction kernels and the batched residual.
+// FP64 defect-correction kernels and the per-grid set-up of a batch.
 //
 // Field layout: row-major, x fastest, pitch in elements; psi = 1 - phi.
 // Red cells are (x + y) even.
@@ -125,51 +125,6 @@ __global__ __launch_bounds__(256) void k_resid_reduce(const unsigned long long *
     }
 }
 
-// Batched residual: block b handles 64 columns of one grid (all rows);
-// out[2 g] and out[2 g + 1] receive grid g's max |r| and max |r| / |u|.
-__global__ __launch_bounds__(256) void k_resid_batch(const uint8_t *__restrict__ cls,
-                                                     const float *__restrict__ u,
-                                                     const BatchGrid *__restrict__ grids,
-                                                     const int2 *__restrict__ blocks,
-                                                     unsigned long long *out)
-{
-    const int2 bk = blocks[blockIdx.x];
-    const BatchGrid g = grids[bk.x];
-    const uint8_t *c = cls + g.off;
-    const float *v = u + g.off;
-    const int x = bk.y * 64 + (threadIdx.x & 63);
-    double m = 0.0, mr = 0.0;
-    if (x < g.nx) {
-        // unconditional loads, as in k_resid
-        const int xe = min(x + 1, g.nx - 1), xw = max(x - 1, 0);
-#pragma unroll 4
-        for (int y = threadIdx.x >> 6; y < g.ny; y += 4) {
-            const size_t row = (size_t)y * g.pitch, i = row + x;
-            const bool free_cell = c[i] == TWG_CELL_FREE;
-            const double ue = (double)v[row + xe], uw = (double)v[row + xw];
-            const double us = (double)v[(size_t)min(y + 1, g.ny - 1) * g.pitch + x];
-            const double un = (double)v[(size_t)max(y - 1, 0) * g.pitch + x];
-            const double cc = (double)v[i];
-            const double e = x + 1 < g.nx ? ue : 0.0;
-            const double w = x > 0 ? uw : 0.0;
-            const double s = y + 1 < g.ny ? us : 0.0;
-            const double n = y > 0 ? un : 0.0;
-            const double r = free_cell ? ((e + w) + (s + n)) * 0.25 - cc : 0.0;
-            m = nanmax(m, fabs(r));
-            const float ac = fabsf((float)cc);
-            const float q = fabsf((float)r) / ac;
-            mr = nanmax(mr, free_cell && ac >= 1e-30f ? (double)q : 0.0);
-        }
-    }
-    m = block_max(m);
-    __syncthreads();
-    mr = block_max(mr);
-    if (threadIdx.x == 0) {
-        atomicMax(out + 2 * bk.x, (unsigned long long)__double_as_longlong(m));
-        atomicMax(out + 2 * bk.x + 1, (unsigned long long)__double_as_longlong(mr));
-    }
-}
-
 __global__ void k_field_init_batch(const uint8_t *__restrict__ cls, float *psi,
                                    const BatchGrid *__restrict__ grids,
                                    const int2 *__restrict__ blocks, int mode)
@@ -190,24 +145,6 @@ __global__ void k_field_init_batch(const uint8_t *__restrict__ cls, float *psi,
             break;
         default: break;
         }
-    }
-}
-
-__global__ void k_zero_words_n(unsigned long long *w, int n)
-{
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) w[i] = 0ull;
-}
-
-__global__ void k_copy_batch(const float *__restrict__ s, float *__restrict__ d,
-                             const BatchGrid *__restrict__ grids, const int2 *__restrict__ blocks)
-{
-    const int2 bk = blocks[blockIdx.x];
-    const BatchGrid g = grids[bk.x];
-    const int x = bk.y * 64 + (threadIdx.x & 63);
-    if (x >= g.nx) return;
-    for (int y = threadIdx.x >> 6; y < g.ny; y += 4) {
-        const size_t i = g.off + (size_t)y * g.pitch + x;
-        d[i] = s[i];
     }
 }
 
@@ -339,17 +276,6 @@ int last_status()
 
 }  // namespace
 
-int launch_resid_batch(const uint8_t *cls, const float *u, const BatchGrid *grids,
-                       const int2 *blocks, int n_blocks, unsigned long long *out, int n_words,
-                       hipStream_t st)
-{
-    hipLaunchKernelGGL(k_zero_words_n, dim3(std::max(1, std::min(64, (n_words + 255) / 256))),
-                       dim3(256), 0, st, out, n_words);
-    if (n_blocks > 0)
-        hipLaunchKernelGGL(k_resid_batch, dim3(n_blocks), dim3(256), 0, st, cls, u, grids, blocks, out);
-    return last_status();
-}
-
 int launch_field_init_batch(const uint8_t *cls, float *psi, const BatchGrid *grids,
                             const int2 *blocks, int n_blocks, int mode, hipStream_t st)
 {
@@ -359,13 +285,6 @@ int launch_field_init_batch(const uint8_t *cls, float *psi, const BatchGrid *gri
     return last_status();
 }
 
-int launch_copy_batch(const float *src, float *dst, const BatchGrid *grids, const int2 *blocks,
-                      int n_blocks, hipStream_t st)
-{
-    if (n_blocks > 0)
-        hipLaunchKernelGGL(k_copy_batch, dim3(n_blocks), dim3(256), 0, st, src, dst, grids, blocks);
-    return last_status();
-}
 
 int launch_fmask(const uint8_t *cls, uint8_t *fmask, int nx, int ny, int pitch, hipStream_t st)
 {

@@ -191,9 +191,28 @@ __device__ void on_check(RelaxCtl *c, double r, double rel)
         c->lead_check = 0;
     } else {
         const int64_t chunk = (int64_t)(c->h.pass - c->last_check) * c->c.S;
+        double q = 1.0;
         if (r < c->r_prev && chunk > 0) {
-            const double q = pow(r / c->r_prev, 1.0 / (double)chunk);
+            q = pow(r / c->r_prev, 1.0 / (double)chunk);
             if (q > 0.0 && q < 1.0) c->rate = q;
+        }
+        // A correction solve that contracts at less than half the speed its
+        // factor gives every mode once the factor is at or above a domain's
+        // optimum (omega - 1 per sweep) has met the FP32 rounding floor of
+        // its correction: a correction with a large smooth part leaves FP32
+        // residual noise of ~1e-7 times its own size, which can lie above
+        // the solve's target.  The round ends there; the FP64 update and
+        // the next round's exact defect carry on from it.  Judged over at
+        // least 128 sweeps.
+        if (c->h.phase == PH_CORR && chunk >= 128) {
+            const double w = (double)c->c.omega_dc;
+            if (q > 1.0 - 0.5 * (2.0 - w)) {
+                // the next round's first prediction starts from the nominal
+                // rate, not from the floor's
+                c->rate = fmax(w - 1.0, 0.5);
+                end_solve(c, false, r, rel);
+                return;
+            }
         }
         // the max-norm residual is not monotone, so progress is judged
         // against the best residual, over a span of sweeps

@@ -54,25 +54,6 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
 // Batched form: the tiles of many grids in one launch.  Grid g's arrays start
 // at element offset desc.off of the batch base pointers; the tile count is
 // read from device memory so that one captured launch serves any active set.
-template <int S, bool PAIR>
-__global__ __launch_bounds__(256) void k_sor_stream_batch(const float *__restrict__ src,
-                                                          float *__restrict__ dst,
-                                                          const uint8_t *__restrict__ fmask,
-                                                          const BatchGrid *__restrict__ grids,
-                                                          const BatchTile *__restrict__ tiles,
-                                                          const int *__restrict__ n_tiles)
-{
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-    if (tile >= *n_tiles) return;  // whole wave
-    const BatchTile t = tiles[tile];
-    const BatchGrid g = grids[t.grid];
-    stream_tile<float, S, false, PAIR, true>(src + g.off, dst + g.off, fmask + g.off, g.omega, nullptr,
-                                             g.nx, g.ny, g.pitch, t.x0, t.ybeg, t.yend);
-}
-
-// Pair access needs even pitch and nx (a pair never leaves its row or the
-// grid) and bases aligned to a pair (wsrc holds elements of wbytes bytes).
 template <typename T>
 bool pairable(const T *src, const T *dst, const void *wsrc, size_t wbytes, const T *f, int nx, int pitch)
 {
@@ -107,34 +88,6 @@ int launch_stream(const T *src, T *dst, const void *wsrc, T omega, const T *f, i
 }
 
 }  // namespace
-
-int launch_stream_batch(const float *src, float *dst, const uint8_t *fmask, const BatchGrid *grids,
-                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S, bool pair,
-                        hipStream_t st)
-{
-    const int blocks = (max_tiles + 3) / 4;
-    if (blocks == 0) return TWG_OK;
-#define TWG_BATCH_CASE(SV)                                                                             \
-    case SV:                                                                                           \
-        if (pair)                                                                                      \
-            hipLaunchKernelGGL((k_sor_stream_batch<SV, true>), dim3(blocks), dim3(256), 0, st, src, dst, \
-                               fmask, grids, tiles, n_tiles);                                          \
-        else                                                                                           \
-            hipLaunchKernelGGL((k_sor_stream_batch<SV, false>), dim3(blocks), dim3(256), 0, st, src,     \
-                               dst, fmask, grids, tiles, n_tiles);                                     \
-        break;
-    switch (S) {
-        TWG_BATCH_CASE(1)
-        TWG_BATCH_CASE(2)
-        TWG_BATCH_CASE(3)
-        TWG_BATCH_CASE(4)
-        TWG_BATCH_CASE(6)
-        TWG_BATCH_CASE(8)
-    default: return TWG_EUNSUPPORTED;
-    }
-#undef TWG_BATCH_CASE
-    return last_status();
-}
 
 int stream_rows_cap(int pitch, int elem_bytes, int S)
 {

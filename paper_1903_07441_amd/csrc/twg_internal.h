@@ -61,11 +61,11 @@ struct twg_ctx {
     // pointer-jumping buffers of hpf_descent_all (4 int32 per cell)
     void *jumpbuf = nullptr;
     size_t jumpbuf_bytes = 0;
-    // batched relaxation: descriptors, tile and block lists, per-grid words
+    // batched relaxation: descriptors, block list, control state and stats
     void *batch = nullptr;
     size_t batch_bytes = 0;
-    unsigned long long *batch_host = nullptr;  // pinned mirror of the per-grid words
-    size_t batch_host_bytes = 0;
+    // bytes of the descriptor and block tables last uploaded to `batch`
+    std::vector<char> batch_sig;
     // small device words: counters of the rasteriser
     unsigned long long *words = nullptr;
     // per-block partial maxima of the residual kernels (2 kResidBlocks words)
@@ -109,22 +109,8 @@ struct BatchGrid {
     float omega;
     long long off;
 };
-// one tile of the batched relaxation kernel
-struct BatchTile {
-    int grid, x0, ybeg, yend;
-};
-
-// pair: every grid has even nx, pitch and offset (PAIR tiles)
-int launch_stream_batch(const float *src, float *dst, const uint8_t *fmask, const BatchGrid *grids,
-                        const BatchTile *tiles, const int *n_tiles, int max_tiles, int S, bool pair,
-                        hipStream_t st);
-int launch_resid_batch(const uint8_t *cls, const float *u, const BatchGrid *grids,
-                       const int2 *blocks, int n_blocks, unsigned long long *out, int n_words,
-                       hipStream_t st);
 int launch_field_init_batch(const uint8_t *cls, float *psi, const BatchGrid *grids,
                             const int2 *blocks, int n_blocks, int mode, hipStream_t st);
-int launch_copy_batch(const float *src, float *dst, const BatchGrid *grids, const int2 *blocks,
-                      int n_blocks, hipStream_t st);
 
 int set_err(twg_ctx *ctx, int code, const std::string &msg);
 int ensure(twg_ctx *ctx, void **buf, size_t *have, size_t need);
@@ -218,6 +204,37 @@ struct SlotArgs {
 size_t relax_ctl_bytes();
 int launch_relax_begin(void *ctl, const RelaxConfig &cfg, hipStream_t st);
 int launch_relax_slot(const SlotArgs &a, int S, hipStream_t st);
+
+// batch.hip: the device-driven relaxation of a batch of grids.  BatchArgs
+// are the arguments of the begin kernel and of every slot launch.
+constexpr int kBatchMaxGrids = 65536;
+struct GridRun;  // per-grid run state (batch.hip)
+struct GridCtl;  // per-grid controller state (batch.hip)
+struct BatchArgs {
+    const BatchGrid *grids;  // n descriptors
+    const int2 *blocks;      // static (grid, 64-column block) list of every grid
+    int n_blocks, n;
+    int S, RH;               // sweeps per pass, output rows per tile
+    int slot, final_slot;    // this launch's number; 1: finish what is left
+    int quantum;             // checks only at slots that are multiples of this
+    int check_passes;        // > 0: a check every this many passes
+    double tol;
+    int64_t max_sweeps;      // per grid
+    float *psi, *alt;        // batch fields and their ping-pong partner
+    const uint8_t *mask;     // free masks, laid out as the fields
+    void *hdr;               // batch_hdr_bytes()
+    GridRun *run;            // n
+    GridCtl *ctl;            // n
+    int2 *tiles;             // one entry per tile of the batch: (grid, tile of the grid)
+    unsigned long long *rmax, *rrel;  // n each: maxima of the checking passes
+    hpf_stats *stats;        // n, device, written when the batch ends
+    unsigned long long *mirror;       // host-mapped decision word, or null
+};
+size_t batch_hdr_bytes();
+size_t batch_run_bytes();
+size_t batch_ctl_bytes();
+int launch_batch_begin(const BatchArgs &a, hipStream_t st);
+int launch_batch_slot(const BatchArgs &a, int max_tiles, bool pair, hipStream_t st);
 
 // raster.hip
 int launch_rasterize(twg_ctx *ctx, const twg_grid &g, int n_obs, const double *pos,

@@ -44,7 +44,7 @@ struct twg_unet {
           *f_p0 = nullptr;
     float *part = nullptr, *bpart = nullptr;
     unsigned int *counts = nullptr;  // FREE cells per image
-    // small device words: [0] ring maximum
+    // small device words: [0] ring maximum, [1] non-finite network output flag
     unsigned int *words = nullptr;
 };
 
@@ -59,7 +59,13 @@ int net_params_out(twg_unet *n, float *ext, hipStream_t st);
 int net_grads_out(twg_unet *n, float *ext, hipStream_t st);
 int net_pack_input(twg_unet *n, const float *x, long long total, hipStream_t st);
 int net_head_plain(twg_unet *n, float *y, int total, hipStream_t st);
-int net_head_psi(twg_unet *n, const uint8_t *cls, float *psi, int nx, int ny, int pitch, int Wp, hipStream_t st);
+// the field of a warm start; a non-finite network output at a FREE cell
+// makes every FREE cell 0.5 instead, and *status (if given) receives
+// TWG_OK or TWG_NET_FALLBACK
+int net_head_psi(twg_unet *n, const uint8_t *cls, float *psi, int nx, int ny, int pitch, int Wp, int32_t *status,
+                 hipStream_t st);
+// zero the first `count` (<= 64) words of n->words
+int net_zero_words(twg_unet *n, int count, hipStream_t st);
 int net_features(const uint8_t *cls, const uint16_t *ring, int nx, int ny, int pitch, int Hp, int Wp, int gx,
                  int gy, const unsigned int *jmax, float *xf, uint16_t *xp, hipStream_t st);
 int net_ring_max(const uint16_t *ring, int nx, int ny, int pitch, unsigned int *out, hipStream_t st);

@@ -68,6 +68,9 @@ __device__ __forceinline__ uint32_t f2bf(float f)
 __device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 __device__ __forceinline__ uint32_t pack2(float lo, float hi) { return f2bf(lo) | (f2bf(hi) << 16); }
+// ReLU that keeps a NaN a NaN (the hardware max would turn it into 0), so a
+// broken parameter shows up in the network's output
+__device__ __forceinline__ float relu(float v) { return v != v ? v : fmaxf(v, 0.f); }
 __device__ __forceinline__ bool bf_pos(uint32_t h) { return (h & 0x8000u) == 0 && (h & 0x7fffu) != 0; }
 
 __device__ __forceinline__ bf16x8 as_bf8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
@@ -181,8 +184,8 @@ __device__ __forceinline__ void store_tile(const f32x4 (&acc)[4][COB / 16], cons
             for (int q = 0; q < RTS; ++q) {
                 const int rt = sl * RTS + q, o = co0 + rt * 16 + g * 4;
                 const f32x4 v = acc[ct][rt];
-                const float r0 = fmaxf(v[0] + bias[o], 0.f), r1 = fmaxf(v[1] + bias[o + 1], 0.f);
-                const float r2 = fmaxf(v[2] + bias[o + 2], 0.f), r3 = fmaxf(v[3] + bias[o + 3], 0.f);
+                const float r0 = relu(v[0] + bias[o]), r1 = relu(v[1] + bias[o + 1]);
+                const float r2 = relu(v[2] + bias[o + 2]), r3 = relu(v[3] + bias[o + 3]);
                 *reinterpret_cast<uint2 *>(&stg[(ct * 16 + j) * PSO + q * 16 + g * 4]) =
                     make_uint2(pack2(r0, r1), pack2(r2, r3));
             }
@@ -579,9 +582,12 @@ __global__ __launch_bounds__(256) void k_head_loss(const uint16_t *__restrict__ 
 // Inference head into a field: FREE cells get clamp(y, 0, 1); OBST/WALL 0,
 // GOAL 1; FIXED cells keep their value.  The network runs on a padded
 // Hp x Wp frame; only the grid's nx x ny cells are written.
+// A non-finite output at a FREE cell sets *bad (the whole field then falls
+// back to the plain start, k_net_fallback).
 __global__ __launch_bounds__(256) void k_head_psi(const uint16_t *__restrict__ d0, const float *__restrict__ hw,
                                                   const float *__restrict__ hb, const uint8_t *__restrict__ cls,
-                                                  float *__restrict__ psi, int nx, int ny, int pitch, int Wp)
+                                                  float *__restrict__ psi, int nx, int ny, int pitch, int Wp,
+                                                  unsigned int *bad)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -591,12 +597,38 @@ __global__ __launch_bounds__(256) void k_head_psi(const uint16_t *__restrict__ d
     if (c == TWG_CELL_FREE) {
         float d[32];
         const float v = head_value(d0 + ((size_t)y * Wp + x) * 32, hw, hb[0], d);
+        if (!isfinite(v)) atomicOr(bad, 1u);
         psi[i] = fminf(fmaxf(v, 0.f), 1.f);
     } else if (c == TWG_CELL_OBST || c == TWG_CELL_WALL) {
         psi[i] = 0.f;
     } else if (c == TWG_CELL_GOAL) {
         psi[i] = 1.f;
     }
+}
+
+// Fallback of a warm start whose network produced a non-finite value: every
+// FREE cell gets the plain start 0.5 (the fixed cells are already set);
+// *status (if given) receives TWG_OK or TWG_NET_FALLBACK.
+__global__ __launch_bounds__(256) void k_net_fallback(const uint8_t *__restrict__ cls, float *__restrict__ psi,
+                                                      int nx, int ny, int pitch, const unsigned int *bad,
+                                                      int32_t *status)
+{
+    const bool fall = *bad != 0u;
+    if (status && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        *status = fall ? TWG_NET_FALLBACK : TWG_OK;
+    if (!fall) return;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= nx || y >= ny) return;
+    const size_t i = (size_t)y * pitch + x;
+    if (cls[i] == TWG_CELL_FREE) psi[i] = 0.5f;
+}
+
+// Zero n device words (a kernel, so that the call can be captured into a
+// graph without memset nodes).
+__global__ void k_zero_words(unsigned int *w, int n)
+{
+    if (blockIdx.x == 0 && (int)threadIdx.x < n) w[threadIdx.x] = 0u;
 }
 
 // Plain head output y[p] (no field semantics).
@@ -1075,10 +1107,19 @@ int net_head_plain(twg_unet *n, float *y, int total, hipStream_t st)
     return last_status();
 }
 
-int net_head_psi(twg_unet *n, const uint8_t *cls, float *psi, int nx, int ny, int pitch, int Wp, hipStream_t st)
+int net_head_psi(twg_unet *n, const uint8_t *cls, float *psi, int nx, int ny, int pitch, int Wp, int32_t *status,
+                 hipStream_t st)
 {
-    hipLaunchKernelGGL(k_head_psi, dim3((nx + 63) / 64, (ny + 3) / 4), dim3(256), 0, st, n->d0,
-                       n->master + n->L.offw[7], n->master + n->L.offb[7], cls, psi, nx, ny, pitch, Wp);
+    const dim3 grid((nx + 63) / 64, (ny + 3) / 4);
+    hipLaunchKernelGGL(k_head_psi, grid, dim3(256), 0, st, n->d0, n->master + n->L.offw[7],
+                       n->master + n->L.offb[7], cls, psi, nx, ny, pitch, Wp, n->words + 1);
+    hipLaunchKernelGGL(k_net_fallback, grid, dim3(256), 0, st, cls, psi, nx, ny, pitch, n->words + 1, status);
+    return last_status();
+}
+
+int net_zero_words(twg_unet *n, int count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, n->words, count);
     return last_status();
 }
 

@@ -239,17 +239,14 @@ int32_t twg_unet_features(twg_unet *n, twg_grid g, const uint8_t *cls, const uin
     if (H < g.ny || W < g.nx || H % 8 || W % 8) return set_err(n->ctx, TWG_EINVAL, "frame must cover the grid, sides multiples of 8");
     hipSetDevice(n->ctx->device);
     hipStream_t st = as_stream(stream);
-    if (ring) {
-        if (hipMemsetAsync(n->words, 0, sizeof(unsigned int), st) != hipSuccess)
-            return set_err(n->ctx, TWG_EDEVICE, "reset failed");
-        rc = net_ring_max(ring, g.nx, g.ny, g.pitch, n->words, st);
-    }
+    rc = net_zero_words(n, 2, st);
+    if (!rc && ring) rc = net_ring_max(ring, g.nx, g.ny, g.pitch, n->words, st);
     if (!rc) rc = net_features(cls, ring, g.nx, g.ny, g.pitch, H, W, goal_x, goal_y, n->words, x, nullptr, st);
     return rc ? set_err(n->ctx, rc, "feature kernel failed") : TWG_OK;
 }
 
 int32_t twg_unet_warm_start(twg_unet *n, twg_grid g, const uint8_t *cls, const uint16_t *ring, int32_t goal_x,
-                            int32_t goal_y, float *psi, void *stream)
+                            int32_t goal_y, float *psi, int32_t *status, void *stream)
 {
     if (!n) return TWG_EINVAL;
     n->ctx->err.clear();
@@ -264,14 +261,11 @@ int32_t twg_unet_warm_start(twg_unet *n, twg_grid g, const uint8_t *cls, const u
     const int H = std::max(Hp, 8), W = std::max(Wp, 8);
     rc = ensure_fwd(n, (long long)H * W);
     if (rc) return rc;
-    if (ring) {
-        if (hipMemsetAsync(n->words, 0, sizeof(unsigned int), st) != hipSuccess)
-            return set_err(n->ctx, TWG_EDEVICE, "reset failed");
-        rc = net_ring_max(ring, g.nx, g.ny, g.pitch, n->words, st);
-    }
+    rc = net_zero_words(n, 2, st);
+    if (!rc && ring) rc = net_ring_max(ring, g.nx, g.ny, g.pitch, n->words, st);
     if (!rc) rc = net_features(cls, ring, g.nx, g.ny, g.pitch, H, W, goal_x, goal_y, n->words, nullptr, n->xp, st);
     if (!rc) rc = net_forward(n, 1, H, W, st);
-    if (!rc) rc = net_head_psi(n, cls, psi, g.nx, g.ny, g.pitch, W, st);
+    if (!rc) rc = net_head_psi(n, cls, psi, g.nx, g.ny, g.pitch, W, status, st);
     return rc ? set_err(n->ctx, rc, "warm start failed") : TWG_OK;
 }
 

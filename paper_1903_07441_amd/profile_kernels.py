@@ -92,7 +92,8 @@ def main(argv=None):
             ctx.relax(cls, psi, psi64, tol=1e-6, init=twg.INIT_KEEP, polish=1, tol_cert=1e-7)
             ctx.descend(cls, psi64=psi64, start=sc["robot"], cap=cap, path=path, info=info)
         torch.cuda.synchronize()
-        print(f"profiled {args.passes} replanning steps on {nx}x{ny}; last descent {info.tolist()}", flush=True)
+        print(f"profiled {args.passes} replanning steps on {nx}x{ny} (each opens with k_raster_base; the "
+              f"autotuner before them rasterises nothing); last descent {info.tolist()}", flush=True)
         ctx.close()
         return 0
     if args.S and args.RH:

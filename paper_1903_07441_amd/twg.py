@@ -57,6 +57,13 @@ def stats_from_device(t):
     return HpfStats.from_buffer_copy(raw).as_dict()
 
 
+def batch_stats_from_device(t, n):
+    """hpf_stats dicts of a batch from a device tensor written by
+    relax_batched(slots=...) (copies to the host, which waits for the stream)."""
+    raw = bytes(t[:n * STATS_BYTES].cpu().numpy().tobytes())
+    return [HpfStats.from_buffer_copy(raw[k * STATS_BYTES:(k + 1) * STATS_BYTES]).as_dict() for k in range(n)]
+
+
 class GridDesc(ctypes.Structure):
     _fields_ = [("nx", i32), ("ny", i32), ("pitch", i32), ("reserved", i32), ("offset", i64)]
 
@@ -82,6 +89,7 @@ def _load():
         "hpf_relax_async_noalloc": (i32, [vp, Grid, vp, vp, vp, P(HpfParams), i32, vp, vp]),
         "hpf_sweeps": (i32, [vp, Grid, vp, vp, vp, f32, i32, i32, i32, vp]),
         "hpf_relax_batched": (i32, [vp, i32, vp, vp, vp, P(HpfParams), vp, vp]),
+        "hpf_relax_batched_async": (i32, [vp, i32, vp, vp, vp, vp, i32, vp, vp]),
         "hpf_residual": (i32, [vp, Grid, vp, vp, vp, vp, P(f64), vp]),
         "hpf_autotune": (i32, [vp, Grid, vp, vp, vp]),
         "hpf_sweeps64": (i32, [vp, Grid, vp, vp, f64, i32, i32, i32, vp]),
@@ -102,7 +110,7 @@ def _load():
         "twg_unet_loss_grad": (i32, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "twg_unet_adam_step": (i32, [vp, f32, vp]),
         "twg_unet_features": (i32, [vp, Grid, vp, vp, i32, i32, i32, i32, vp, vp]),
-        "twg_unet_warm_start": (i32, [vp, Grid, vp, vp, i32, i32, vp, vp]),
+        "twg_unet_warm_start": (i32, [vp, Grid, vp, vp, i32, i32, vp, vp, vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -114,7 +122,8 @@ def _load():
 lib = _load()
 EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error", "twg_ctx_set_graphs",
             "twg_rasterize",
-            "hpf_relax", "hpf_relax_async", "hpf_relax_async_noalloc", "hpf_relax_batched", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
+            "hpf_relax", "hpf_relax_async", "hpf_relax_async_noalloc", "hpf_relax_batched",
+            "hpf_relax_batched_async", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
             "hpf_index_matrix", "hpf_descend", "hpf_rubber_band", "hpf_merge_previous",
             "hpf_init_field", "hpf_set_tiling", "twg_kalman_step", "hpf_descent_all",
             "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
@@ -276,10 +285,13 @@ class Context:
         return stats
 
     def relax_batched(self, cls_flat, psi_flat, descs, tol=1e-6, max_sweeps=0, omega=0.0,
-                      init=INIT_HALF, sweeps_per_pass=0, check_passes=0, rows_per_tile=0):
+                      init=INIT_HALF, sweeps_per_pass=0, check_passes=0, rows_per_tile=0, slots=0, stats=None):
         """Relax many grids packed in one flat uint8 class buffer and one flat
         float32 field buffer; descs = [(nx, ny, pitch, offset), ...] (offsets in
-        elements).  Returns one stats dict per grid."""
+        elements).  Returns one stats dict per grid.  slots > 0: enqueue
+        hpf_relax_batched_async (slots launches and a final one) on the
+        current stream and return the device stats tensor (n hpf_stats; read
+        with batch_stats_from_device)."""
         if cls_flat.dtype != torch.uint8 or psi_flat.dtype != torch.float32:
             raise ValueError("class buffer must be uint8 and field buffer float32")
         if not (cls_flat.is_cuda and psi_flat.is_cuda):
@@ -291,6 +303,15 @@ class Context:
                 raise ValueError("a grid extends past the batch buffers")
         prm = HpfParams(float(tol), 0.0, int(max_sweeps), float(omega), int(init), 0,
                         int(sweeps_per_pass), int(check_passes), int(rows_per_tile), -1, -1)
+        if slots:
+            if stats is None:
+                stats = torch.zeros(n * STATS_BYTES, dtype=torch.uint8, device=psi_flat.device)
+            if stats.dtype != torch.uint8 or stats.numel() < n * STATS_BYTES or not stats.is_cuda:
+                raise ValueError(f"stats must be a device uint8 tensor of at least {n * STATS_BYTES} bytes")
+            rc = lib.hpf_relax_batched_async(self.h, n, arr, _ptr(cls_flat), _ptr(psi_flat), ctypes.byref(prm),
+                                             int(slots), _ptr(stats), _stream())
+            self._check(rc)
+            return stats
         st = (HpfStats * n)()
         rc = lib.hpf_relax_batched(self.h, n, arr, _ptr(cls_flat), _ptr(psi_flat), ctypes.byref(prm),
                                    st, _stream())
@@ -507,12 +528,17 @@ class UNet:
                                               int(goal[1]), int(H), int(W), _ptr(out), _stream()))
         return out
 
-    def warm_start(self, cls, ring, goal, psi):
+    def warm_start(self, cls, ring, goal, psi, status=None):
+        """Network field into psi.  status: optional device int32 tensor that
+        receives OK, or NET_FALLBACK when the network's output was not finite
+        (psi then holds the plain start 0.5 on FREE cells)."""
         nx, ny, pitch = _grid_of(psi)
         if cls.stride(0) != pitch or (ring is not None and ring.stride(0) != pitch):
             raise ValueError("class and ring maps must share psi's pitch")
+        if status is not None and (status.dtype != torch.int32 or not status.is_cuda):
+            raise ValueError("status must be an int32 device tensor")
         self.ctx._check(lib.twg_unet_warm_start(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(ring), int(goal[0]),
-                                                int(goal[1]), _ptr(psi), _stream()))
+                                                int(goal[1]), _ptr(psi), _ptr(status), _stream()))
         return psi
 
 

@@ -1,6 +1,7 @@
 """GPU parity of the batched relaxation: every grid of an uneven batch meets the
 tolerance (residual recomputed by the oracle) and equals, bit for bit, the same
-number of sweeps run on that grid alone."""
+number of sweeps run on that grid alone; the asynchronous and graph-captured
+batch equal the blocking one."""
 import numpy as np
 import pytest
 import torch
@@ -56,26 +57,82 @@ def test_batch_matches_solo_and_converges(ctx, orc, pad):
         assert np.array_equal(solo.cpu().numpy(), got[k]), k
 
 
-def test_batch_graphs_equal_eager(ctx, orc):
-    """The batched relaxation gives identical fields and statistics with its
-    passes replayed from a captured graph and launched one by one."""
+def test_batch_async_and_graph_equal_blocking(ctx, orc):
+    """The asynchronous batch (fixed slot count, device-side stop) gives the
+    fields and statistics of the blocking call, and so does the same call
+    captured into a graph and replayed, on every replay, with eager work
+    between the replays."""
+    from paper_1903_07441_amd import twg
     sides = [64, 256, 128, 512, 96]
     classes = [orc.rasterize(scenarios.scenario("batch", seed=3100 + k, side=n))[0] for k, n in enumerate(sides)]
     flat_c, descs = pack(classes, 0)
     cls = torch.as_tensor(flat_c).cuda()
-    out = []
-    try:
-        for graphs in (False, True, True):
-            ctx.set_graphs(graphs)
-            psi = torch.zeros(len(flat_c), dtype=torch.float32, device="cuda")
-            st = ctx.relax_batched(cls, psi, descs, tol=1e-6, sweeps_per_pass=2)
-            torch.cuda.synchronize()
-            out.append((psi.cpu().numpy(), [(s["sweeps"], s["residual"], s["status"]) for s in st]))
-    finally:
-        ctx.set_graphs(True)
-    for psi, st in out[1:]:
-        assert np.array_equal(psi, out[0][0])
-        assert st == out[0][1]
+    n = len(sides)
+    psi = torch.zeros(len(flat_c), dtype=torch.float32, device="cuda")
+    want = ctx.relax_batched(cls, psi, descs, tol=1e-6, sweeps_per_pass=2)
+    torch.cuda.synchronize()
+    want_psi = psi.clone()
+    slots = max(s["sweeps"] for s in want) // 2 + 16
+    print(f"async batch of {n} grids: {slots} slots", flush=True)
+    psi_a = torch.zeros_like(psi)
+    stats = ctx.relax_batched(cls, psi_a, descs, tol=1e-6, sweeps_per_pass=2, slots=slots)
+    got = twg.batch_stats_from_device(stats, n)
+    assert torch.equal(psi_a, want_psi)
+    assert [(s["sweeps"], s["residual"], s["status"]) for s in got] == \
+        [(s["sweeps"], s["residual"], s["status"]) for s in want]
+    # the same enqueue captured once and replayed
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        g.capture_begin()
+        ctx.relax_batched(cls, psi_a, descs, tol=1e-6, sweeps_per_pass=2, slots=slots, stats=stats)
+        g.capture_end()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    scratch = torch.zeros_like(psi)
+    for rep in range(3):
+        psi_a.fill_(-1.0)
+        stats.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        # eager work between replays (the same context scratch)
+        ctx.relax_batched(cls, scratch, descs, tol=1e-3, sweeps_per_pass=2)
+        got = twg.batch_stats_from_device(stats, n)
+        print(f"replay {rep}: sweeps {[s['sweeps'] for s in got]}", flush=True)
+        # every grid cell rewritten (the padding between grids is not part
+        # of any grid)
+        for a_k, w_k in zip(unpack(psi_a.cpu().numpy(), descs), unpack(want_psi.cpu().numpy(), descs)):
+            assert np.array_equal(a_k, w_k)
+        assert [s["sweeps"] for s in got] == [s["sweeps"] for s in want]
+
+
+def test_batch_async_budget_ends_grids(ctx, orc):
+    """Too few slots: the final launch ends the grids still running with
+    status NOT_CONVERGED and their fields as their last pass left them (the
+    same sweeps run alone), while grids that finished keep their result."""
+    from paper_1903_07441_amd import twg
+    sides = [64, 512]
+    classes = [orc.rasterize(scenarios.scenario("batch", seed=3300 + k, side=n))[0] for k, n in enumerate(sides)]
+    flat_c, descs = pack(classes, 0)
+    cls = torch.as_tensor(flat_c).cuda()
+    psi = torch.zeros(len(flat_c), dtype=torch.float32, device="cuda")
+    full = ctx.relax_batched(cls, psi, descs, tol=1e-6, sweeps_per_pass=2)
+    slots = full[0]["sweeps"] // 2 + 10  # the small grid finishes, the large one does not
+    assert slots * 2 < full[1]["sweeps"]
+    psi.zero_()
+    stats = ctx.relax_batched(cls, psi, descs, tol=1e-6, sweeps_per_pass=2, slots=slots)
+    st = twg.batch_stats_from_device(stats, 2)
+    print(f"budget {slots} slots: {[(s['status'], s['sweeps']) for s in st]}", flush=True)
+    assert st[0]["status"] == twg.OK and st[0]["sweeps"] == full[0]["sweeps"]
+    assert st[1]["status"] == twg.NOT_CONVERGED and st[1]["sweeps"] == 2 * slots
+    got = unpack(psi.cpu().numpy(), descs)
+    for k in (0, 1):
+        c = torch.as_tensor(classes[k]).cuda()
+        solo = torch.where(c == 3, 1.0, torch.where(c == 0, 0.5, 0.0)).float()
+        ctx.sweeps(c, solo, st[k]["omega"], st[k]["sweeps"], sweeps_per_pass=2)
+        torch.cuda.synchronize()
+        assert np.array_equal(solo.cpu().numpy(), got[k]), k
 
 
 def test_batch_checked_often_converges(ctx, orc):

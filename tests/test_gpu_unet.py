@@ -260,6 +260,49 @@ def test_warm_start_field(ctx):
     net.close()
 
 
+@pytest.mark.parametrize("where,value", [("conv", float("nan")), ("head_bias", float("inf"))])
+def test_warm_start_falls_back_on_non_finite_network(ctx, where, value):
+    # a network whose output is not finite (NaN parameters, an infinite
+    # bias) is rejected: every FREE cell holds the plain start 0.5, the
+    # status word reads NET_FALLBACK, and the relaxation converges from that
+    # field as from the plain start; the same call with finite parameters
+    # reports OK
+    import torch
+    from paper_1903_07441_amd import scenarios, twg
+    from conftest import scenario_tensors
+    sc = scenarios.scenario("warped512", 4, side=128)
+    pos, vel, rad = scenario_tensors(sc)
+    nx, ny = sc["nx"], sc["ny"]
+    cls, ring = ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"], robot_speed=sc["vr"])
+    params = flat(bf16_params(5)).astype(np.float32)
+    net = twg.UNet(ctx)
+    net.set_params(torch.as_tensor(params))
+    status = torch.full((1,), -99, dtype=torch.int32, device="cuda")
+    psi = torch.full((ny, nx), -7.0, dtype=torch.float32, device="cuda")
+    net.warm_start(cls, ring, sc["goal"], psi, status=status)
+    assert int(status.item()) == twg.OK
+    bad = params.copy()
+    if where == "conv":
+        bad[100] = np.float32(value)      # a weight of the first conv
+    else:
+        bad[-1] = np.float32(value)       # the head's bias
+    net.set_params(torch.as_tensor(bad))
+    psi.fill_(-7.0)
+    net.warm_start(cls, ring, sc["goal"], psi, status=status)
+    print(f"fallback {where}={value}: status {int(status.item())}", flush=True)
+    assert int(status.item()) == twg.NET_FALLBACK
+    got = psi.cpu().numpy()
+    c = cls.cpu().numpy()
+    assert np.all(got[c == twg.FREE] == 0.5)
+    assert np.all(got[(c == twg.OBST) | (c == twg.WALL)] == 0)
+    assert np.all(got[c == twg.GOAL] == 1)
+    st = ctx.relax(cls, psi, None, tol=1e-6, init=twg.INIT_KEEP)
+    ref = torch.empty_like(psi)
+    st_ref = ctx.relax(cls, ref, None, tol=1e-6, init=twg.INIT_HALF)
+    assert st["status"] == twg.OK and st["sweeps"] == st_ref["sweeps"] and torch.equal(psi, ref)
+    net.close()
+
+
 def test_training_lowers_loss(ctx, orc):
     """A few Adam steps on relaxed 64x64 fields lower the masked MSE."""
     import torch
