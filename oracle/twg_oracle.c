@@ -729,7 +729,11 @@ int32_t orc_goal_reachable(int32_t nx, int32_t ny, const uint8_t *cls, int32_t s
  *     so that it resists moves towards obstacles (lower psi);
  *   - the point moves to the candidate with the smallest |F + T|^2 (Eq. 4),
  *     the first one in order on a tie (Eq. 5 moves it one cell at most).
- * Points whose own psi is not positive do not move. */
+ * Points whose own psi is not positive do not move.
+ * Parity unpinned beyond its properties (fixed endpoints, walkable and
+ * 8-connected points, zero tension keeps the path, tension straightens a
+ * bump, the force resists moves towards obstacles): Eq. (6) is garbled and
+ * this reading is a heuristic. */
 static const int rb_dx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
 static const int rb_dy[9] = {0, 0, 0, 1, -1, 1, 1, -1, -1};
 
