@@ -533,19 +533,15 @@ def main():
             if key not in tuned_sizes:
                 tb_ = ctx.autotune(bcls[o:o + b["nx"] * b["ny"]].view(b["ny"], b["nx"]))
                 tuned_sizes[key] = round(tb_["omega"], 6)
-        b_trials = {}
-        for S_b, RH_b in ((4, 16), (6, 64), (8, 64), (6, 128), (8, 128)):
-            ctx.relax_batched(bcls, bpsi, descs, tol=1e-6, sweeps_per_pass=S_b, rows_per_tile=RH_b)
-            torch.cuda.synchronize()
-            t_0 = time.perf_counter()
-            ctx.relax_batched(bcls, bpsi, descs, tol=1e-6, sweeps_per_pass=S_b, rows_per_tile=RH_b)
-            torch.cuda.synchronize()
-            b_trials[(S_b, RH_b)] = time.perf_counter() - t_0
-        S_b, RH_b = min(b_trials, key=b_trials.get)
+        # the batch's tiling from the library's batch autotuner (untimed set-up)
+        bt = ctx.autotune_batched(bcls, descs)
+        S_b, RH_b = bt["S"], bt["RH"]
+        ctx.relax_batched(bcls, bpsi, descs, tol=1e-6)
+        torch.cuda.synchronize()
         tb0 = time.perf_counter()
         reps = 3
         for _ in range(reps):
-            bst = ctx.relax_batched(bcls, bpsi, descs, tol=1e-6, sweeps_per_pass=S_b, rows_per_tile=RH_b)
+            bst = ctx.relax_batched(bcls, bpsi, descs, tol=1e-6)
         torch.cuda.synchronize()
         tb = (time.perf_counter() - tb0) / reps
         cu = sum(d[0] * d[1] * st_b["sweeps"] for d, st_b in zip(descs, bst))
@@ -553,8 +549,7 @@ def main():
                  "ms_per_batch": round(tb * 1e3, 3), "cell_updates_per_s": round(cu / tb, 1),
                  "converged": sum(1 for st_b in bst if st_b["status"] == twg.OK),
                  "max_residual": max(st_b["residual"] for st_b in bst),
-                 "tiling": {"sweeps_per_pass": S_b, "rows_per_tile": RH_b},
-                 "tiling_trials_ms": {f"S{a}_RH{b}": round(v * 1e3, 2) for (a, b), v in b_trials.items()},
+                 "tiling": {"sweeps_per_pass": S_b, "rows_per_tile": RH_b, "autotuned_ms": round(bt["ms"], 3)},
                  "omega_per_size": {f"{a}x{b}": v for (a, b), v in tuned_sizes.items()},
                  "sweeps_max": max(st_b["sweeps"] for st_b in bst),
                  "workload": "256 grids, sides uniform over {64,128,256,512,1024}, 10-200 moving discs "

@@ -337,7 +337,8 @@ typedef struct {
  * stops.  Checks fall on passes that are multiples of 4 (so that grids share
  * them), or every params->check_passes passes.  The host never waits for a
  * residual: it only keeps launches queued (it reads the device's decisions
- * from pinned memory).  Sweeps per tile load and rows per tile come from the
+ * from pinned memory).  Sweeps per tile load and rows per tile come from
+ * hpf_autotune_batched if it ran on this context, else from the
  * autotuned entry of the largest grid (or params->sweeps_per_pass /
  * rows_per_tile); each grid's SOR factor is params->omega, else its size's
  * autotuned factor, else its open-rectangle optimum.  init: HPF_INIT_KEEP,
@@ -430,6 +431,19 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
  * (sweeps 0: no start phase).
  * Blocking.  Errors: TWG_EINVAL, TWG_ENOMEM, TWG_EDEVICE. */
 int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, void *stream);
+
+/* hpf_autotune_batched -- time the batched relaxation of this batch (n grid
+ * descriptors and the packed class maps, as hpf_relax_batched takes them)
+ * for the tilings (S, RH) = (4, 32), (6, 64), (8, 64), (6, 128), (8, 128):
+ * each a whole solve from the 0.5 field to residual 1e-6 on a context-owned
+ * field, timed with HIP events after an untimed set-up run.  The fastest is
+ * remembered: later hpf_relax_batched(_async) calls on this context with
+ * sweeps_per_pass = 0 use it (in place of the largest grid's single-grid
+ * tiling).  Grids' SOR factors come from hpf_autotune of their sizes, as in
+ * hpf_relax_batched.  out (host, optional, 3 doubles): [S, RH, ms of the
+ * fastest].  Blocking.  Errors: TWG_EINVAL, TWG_ENOMEM, TWG_EDEVICE. */
+int32_t hpf_autotune_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, const uint8_t *cls,
+                             double *out, void *stream);
 
 /* hpf_set_tiling -- set, for grids of size nx x ny on this context, what
  * hpf_autotune would remember: FP32 sweeps per tile load S and rows per tile

@@ -606,6 +606,10 @@ int relax_batch_device(twg_ctx *ctx, int n, const twg_grid_desc *grids, const ui
     int S, RH;
     float om_big;
     tiling_for(ctx, grids[big].nx, grids[big].ny, &S, &RH, &om_big);
+    if (ctx->batch_S > 0) {
+        S = ctx->batch_S;
+        RH = ctx->batch_RH;
+    }
     if (p.sweeps_per_pass) S = p.sweeps_per_pass;
     if (p.rows_per_tile) RH = p.rows_per_tile;
     const int VW = 128 - 4 * S;
@@ -987,6 +991,69 @@ int32_t hpf_relax_batched_async(twg_ctx *ctx, int32_t n, const twg_grid_desc *gr
     if (slots < 1) return set_err(ctx, TWG_EINVAL, "slots must be >= 1");
     if (!stats) return set_err(ctx, TWG_EINVAL, "stats (device, n entries) is required");
     return relax_batch_device(ctx, n, grids, cls, psi, params, slots, stats, nullptr, as_stream(stream));
+}
+
+int32_t hpf_autotune_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, const uint8_t *cls,
+                             double *out, void *stream)
+{
+    if (!ctx) return TWG_EINVAL;
+    ctx->err.clear();
+    if (n < 1 || !grids || !cls) return set_err(ctx, TWG_EINVAL, "n >= 1, grids and cls are required");
+    long long total = 0;
+    for (int k = 0; k < n; ++k) {
+        if (grids[k].offset < 0 || grids[k].pitch < 1 || grids[k].ny < 1)
+            return set_err(ctx, TWG_EINVAL, "bad grid " + std::to_string(k));
+        total = std::max(total, (long long)grids[k].offset + (long long)grids[k].pitch * grids[k].ny);
+    }
+    hipSetDevice(ctx->device);
+    hipStream_t st = as_stream(stream);
+    int rc = ensure(ctx, &ctx->tunebuf, &ctx->tunebuf_bytes, (size_t)total * sizeof(float));
+    if (rc) return rc;
+    float *fld = static_cast<float *>(ctx->tunebuf);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return set_err(ctx, TWG_EDEVICE, "event creation failed");
+    // candidates: deeper passes and taller tiles pay off in a batch, which
+    // has far more tiles than the device has SIMDs
+    const int cand[][2] = {{4, 32}, {6, 64}, {8, 64}, {6, 128}, {8, 128}};
+    int bS = 0, bRH = 0;
+    float best = 0.0f;
+    for (const auto &c : cand) {
+        hpf_params p = {};
+        p.tol = 1e-6;
+        p.init = HPF_INIT_HALF;
+        p.sweeps_per_pass = c[0];
+        p.rows_per_tile = c[1];
+        // once to set up (tables, scratch), once timed
+        rc = relax_batch_device(ctx, n, grids, cls, fld, &p, 0, nullptr, nullptr, st);
+        if (rc < 0) break;
+        hipEventRecord(e0, st);
+        rc = relax_batch_device(ctx, n, grids, cls, fld, &p, 0, nullptr, nullptr, st);
+        hipEventRecord(e1, st);
+        if (rc < 0 || hipEventSynchronize(e1) != hipSuccess) {
+            rc = rc < 0 ? rc : TWG_EDEVICE;
+            break;
+        }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (bS == 0 || ms < best) {
+            bS = c[0];
+            bRH = c[1];
+            best = ms;
+        }
+        rc = TWG_OK;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    ctx->batch_S = bS;
+    ctx->batch_RH = bRH;
+    if (out) {
+        out[0] = bS;
+        out[1] = bRH;
+        out[2] = best;
+    }
+    return TWG_OK;
 }
 
 int32_t hpf_autotune(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *out, void *stream)

@@ -66,6 +66,8 @@ struct twg_ctx {
     size_t batch_bytes = 0;
     // bytes of the descriptor and block tables last uploaded to `batch`
     std::vector<char> batch_sig;
+    // tiling of batched relaxations picked by hpf_autotune_batched (0: none)
+    int batch_S = 0, batch_RH = 0;
     // small device words: counters of the rasteriser
     unsigned long long *words = nullptr;
     // per-block partial maxima of the residual kernels (2 kResidBlocks words)

@@ -92,6 +92,7 @@ def _load():
         "hpf_relax_batched_async": (i32, [vp, i32, vp, vp, vp, vp, i32, vp, vp]),
         "hpf_residual": (i32, [vp, Grid, vp, vp, vp, vp, P(f64), vp]),
         "hpf_autotune": (i32, [vp, Grid, vp, vp, vp]),
+        "hpf_autotune_batched": (i32, [vp, i32, vp, vp, vp, vp]),
         "hpf_sweeps64": (i32, [vp, Grid, vp, vp, f64, i32, i32, i32, vp]),
         "hpf_index_matrix": (i32, [vp, Grid, vp, vp, vp, vp, vp]),
         "hpf_descend": (i32, [vp, Grid, vp, vp, vp, P(DescendParams), vp, vp, vp]),
@@ -124,6 +125,7 @@ EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error"
             "twg_rasterize",
             "hpf_relax", "hpf_relax_async", "hpf_relax_async_noalloc", "hpf_relax_batched",
             "hpf_relax_batched_async", "hpf_sweeps", "hpf_sweeps64", "hpf_residual", "hpf_autotune",
+            "hpf_autotune_batched",
             "hpf_index_matrix", "hpf_descend", "hpf_rubber_band", "hpf_merge_previous",
             "hpf_init_field", "hpf_set_tiling", "twg_kalman_step", "hpf_descent_all",
             "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
@@ -342,6 +344,16 @@ class Context:
         return dict(S=int(out[0]), RH=int(out[1]), omega=float(out[2]), cups=float(out[3]), S64=int(out[4]),
                     RH64=int(out[5]), cups64=float(out[6]), omega_dc=float(out[7]), lead_dc_omega=float(out[8]),
                     lead_dc_sweeps=int(out[9]))
+
+    def autotune_batched(self, cls_flat, descs):
+        """Pick the batch tiling (sweeps per pass, rows per tile) for this
+        batch by timing whole solves; later relax_batched calls with
+        sweeps_per_pass = 0 use it.  Returns dict(S, RH, ms)."""
+        n = len(descs)
+        arr = (GridDesc * n)(*[GridDesc(int(a), int(b), int(c), 0, int(d)) for a, b, c, d in descs])
+        out = (ctypes.c_double * 3)()
+        self._check(lib.hpf_autotune_batched(self.h, n, arr, _ptr(cls_flat), out, _stream()))
+        return dict(S=int(out[0]), RH=int(out[1]), ms=float(out[2]))
 
     def set_tiling(self, nx, ny, S, RH, omega=0.0, S64=0, RH64=0):
         """Fix the tiling (and SOR factor) used for grids of this size."""

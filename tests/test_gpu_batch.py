@@ -153,6 +153,27 @@ def test_batch_checked_often_converges(ctx, orc):
         assert r <= 1e-6 and abs(r - st["residual"]) <= 1e-12, (k, r, st)
 
 
+def test_batch_autotune_picks_a_tiling_the_batch_then_uses(ctx, orc):
+    """hpf_autotune_batched remembers the fastest of its candidate tilings;
+    a later batch call without a tiling of its own runs with it, bit for bit
+    as the same call with that tiling given."""
+    sides = [64, 256, 128, 512]
+    classes = [orc.rasterize(scenarios.scenario("batch", seed=3400 + k, side=n))[0] for k, n in enumerate(sides)]
+    flat_c, descs = pack(classes, 0)
+    cls = torch.as_tensor(flat_c).cuda()
+    bt = ctx.autotune_batched(cls, descs)
+    print(f"batch tiling {bt}", flush=True)
+    assert (bt["S"], bt["RH"]) in {(4, 32), (6, 64), (8, 64), (6, 128), (8, 128)} and bt["ms"] > 0
+    a = torch.zeros(len(flat_c), dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    sa = ctx.relax_batched(cls, a, descs, tol=1e-6)
+    sb = ctx.relax_batched(cls, b, descs, tol=1e-6, sweeps_per_pass=bt["S"], rows_per_tile=bt["RH"])
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert [s["sweeps"] for s in sa] == [s["sweeps"] for s in sb]
+    assert all(s["sweeps"] % bt["S"] == 0 for s in sa)
+
+
 def test_batch_rejects_bad_arguments(ctx):
     from paper_1903_07441_amd import twg
     cls = torch.zeros(100, dtype=torch.uint8, device="cuda")
