@@ -33,7 +33,7 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile twg_oracle.c into liboracle.so next to it."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
+        tmp = _LIB + f".tmp{os.getpid()}"  # one per process: parallel test workers may build at once
         cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off",
                "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
