@@ -599,6 +599,46 @@ int32_t twg_unet_features(twg_unet *net, twg_grid g, const uint8_t *cls, const u
 int32_t twg_unet_warm_start(twg_unet *net, twg_grid g, const uint8_t *cls, const uint16_t *ring,
                             int32_t goal_x, int32_t goal_y, float *psi, int32_t *status, void *stream);
 
+/* Coarse-scale warm start: the network sees the grid at 1/factor of its
+ * resolution (factor 2, 4, 8 or 16) on an Hc x Wc frame, the coarse sides
+ * ceil(n / factor) rounded up to multiples of 8 (at least 8).  Coarse cell
+ * (X, Y) covers the fine cells [factor X, factor X + factor) x [factor Y,
+ * factor Y + factor), cells outside the grid reading as walls.  Its inputs:
+ * occupancy = share of OBST, WALL and outside cells in the block; distance of
+ * the block's centre (factor X + (factor - 1) / 2, ...) to the goal cell /
+ * (max(nx, ny) sqrt 2); ring of the fine cell at (factor X + factor / 2,
+ * factor Y + factor / 2), clamped into the grid, / largest ring (0 without a
+ * ring map).  The network's output at that scale is interpolated back
+ * (bilinear) to the grid's FREE cells. */
+
+/* Hc and Wc of the coarse frame.  Host only.  Errors: TWG_EINVAL. */
+int32_t twg_unet_coarse_frame(twg_grid g, int32_t factor, int32_t *Hc, int32_t *Wc);
+
+/* Coarse input channels of a grid: x (device FP32 [Hc][Wc][3], or NULL) and
+ * ccls (device uint8 [Hc][Wc], or NULL), the mask of the training loss:
+ * TWG_CELL_FREE where the block holds a FREE cell, else TWG_CELL_OBST.
+ * Asynchronous.  Errors: TWG_EINVAL. */
+int32_t twg_unet_features_coarse(twg_unet *net, twg_grid g, const uint8_t *cls, const uint16_t *ring,
+                                 int32_t goal_x, int32_t goal_y, int32_t factor, float *x, uint8_t *ccls,
+                                 void *stream);
+
+/* Coarse training target: out[Y][X] (device FP32 [Hc][Wc]) = the mean of psi
+ * (device FP32, pitch g.pitch) over the FREE cells of block (X, Y), summed in
+ * row order in FP32; 0 when the block has none.  Asynchronous.  Errors:
+ * TWG_EINVAL. */
+int32_t twg_unet_coarse_target(twg_unet *net, twg_grid g, const uint8_t *cls, const float *psi, int32_t factor,
+                               float *out, void *stream);
+
+/* Warm start of one grid from the network run at the coarse scale: coarse
+ * features, network, then each FREE cell (x, y) of psi takes the bilinear
+ * interpolation of the coarse output y at ((x + 1/2) / factor - 1/2,
+ * (y + 1/2) / factor - 1/2), clamped to the frame, then to [0, 1]; OBST and
+ * WALL 0, GOAL 1, FIXED unchanged; the same fallback and status as
+ * twg_unet_warm_start.  Asynchronous.  Errors: TWG_EINVAL, TWG_ENOMEM. */
+int32_t twg_unet_warm_start_coarse(twg_unet *net, twg_grid g, const uint8_t *cls, const uint16_t *ring,
+                                   int32_t goal_x, int32_t goal_y, int32_t factor, float *psi, int32_t *status,
+                                   void *stream);
+
 #ifdef __cplusplus
 }
 #endif

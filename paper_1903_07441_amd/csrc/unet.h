@@ -46,6 +46,9 @@ struct twg_unet {
     unsigned int *counts = nullptr;  // FREE cells per image
     // small device words: [0] ring maximum, [1] non-finite network output flag
     unsigned int *words = nullptr;
+    // coarse output of a coarse-scale warm start (yc_pixels floats)
+    float *yc = nullptr;
+    long long yc_pixels = 0;
 };
 
 namespace twg {
@@ -64,6 +67,17 @@ int net_head_plain(twg_unet *n, float *y, int total, hipStream_t st);
 // TWG_OK or TWG_NET_FALLBACK
 int net_head_psi(twg_unet *n, const uint8_t *cls, float *psi, int nx, int ny, int pitch, int Wp, int32_t *status,
                  hipStream_t st);
+// coarse-scale warm start: input channels (xf FP32 and/or xp bf16) and the
+// training mask ccls of a grid seen at 1/f on an Hc x Wc frame; the coarse
+// training target (mean of psi over each block's FREE cells); the fine field
+// from a coarse output (bilinear, then the fallback of net_head_psi)
+int net_features_coarse(const uint8_t *cls, const uint16_t *ring, int nx, int ny, int pitch, int f, int Hc, int Wc,
+                        int gx, int gy, const unsigned int *jmax, float *xf, uint16_t *xp, uint8_t *ccls,
+                        hipStream_t st);
+int net_coarse_target(const float *psi, const uint8_t *cls, int nx, int ny, int pitch, int f, int Hc, int Wc,
+                      float *out, hipStream_t st);
+int net_up_psi(twg_unet *n, const float *yc, int Hc, int Wc, int f, const uint8_t *cls, float *psi, int nx, int ny,
+               int pitch, int32_t *status, hipStream_t st);
 // zero the first `count` (<= 64) words of n->words
 int net_zero_words(twg_unet *n, int count, hipStream_t st);
 int net_features(const uint8_t *cls, const uint16_t *ring, int nx, int ny, int pitch, int Hp, int Wp, int gx,

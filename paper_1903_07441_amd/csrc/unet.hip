@@ -756,6 +756,121 @@ __global__ __launch_bounds__(256) void k_features(const uint8_t *__restrict__ cl
     if (xp) *reinterpret_cast<uint2 *>(xp + p * 4) = make_uint2(pack2(occ, gd), pack2(rt, 0.f));
 }
 
+// ---- coarse-scale warm start ------------------------------------------------
+// Input channels of a grid seen at 1/f of its resolution on an Hc x Wc frame:
+// coarse cell (X, Y) covers the fine cells [fX, fX + f) x [fY, fY + f),
+// cells outside the grid reading as walls.  Occupancy = share of OBST, WALL
+// and outside cells in the block; goal distance of the block's centre
+// (fX + (f - 1) / 2, fY + (f - 1) / 2) / (max(nx, ny) sqrt 2), the fine
+// scale's normalisation; ring of the fine cell at the block's centre
+// (fX + f / 2, fY + f / 2), clamped into the grid, / max ring (0 without a
+// ring map).  ccls (optional): FREE where the block holds a FREE cell, else
+// OBST (the training loss's mask at the coarse scale).
+__global__ __launch_bounds__(256) void k_features_coarse(const uint8_t *__restrict__ cls,
+                                                         const uint16_t *__restrict__ ring, int nx, int ny,
+                                                         int pitch, int f, int Hc, int Wc, int gx, int gy,
+                                                         float inv_diag, const unsigned int *__restrict__ jmax,
+                                                         float *__restrict__ xf, uint16_t *__restrict__ xp,
+                                                         uint8_t *__restrict__ ccls)
+{
+    const unsigned int jm = ring ? *jmax : 0u;
+    const float inv_jmax = jm > 0u ? 1.f / (float)jm : 0.f;
+    const int X = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int Y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (X >= Wc || Y >= Hc) return;
+    int blocked = 0, nfree = 0;
+    for (int dy = 0; dy < f; ++dy) {
+        const int y = Y * f + dy;
+        for (int dx = 0; dx < f; ++dx) {
+            const int x = X * f + dx;
+            if (x >= nx || y >= ny) {
+                ++blocked;
+                continue;
+            }
+            const uint8_t c = cls[(size_t)y * pitch + x];
+            blocked += (c == TWG_CELL_OBST || c == TWG_CELL_WALL) ? 1 : 0;
+            nfree += c == TWG_CELL_FREE ? 1 : 0;
+        }
+    }
+    const float occ = (float)blocked / (float)(f * f);
+    const float half = 0.5f * (float)(f - 1);
+    const float ddx = ((float)(X * f) + half) - (float)gx, ddy = ((float)(Y * f) + half) - (float)gy;
+    const float gd = sqrtf(ddx * ddx + ddy * ddy) * inv_diag;
+    float rt = 0.f;
+    if (ring && X * f < nx && Y * f < ny) {
+        const int xc = min(X * f + f / 2, nx - 1), yc = min(Y * f + f / 2, ny - 1);
+        rt = (float)ring[(size_t)yc * pitch + xc] * inv_jmax;
+    }
+    const size_t p = (size_t)Y * Wc + X;
+    if (xf) {
+        xf[3 * p] = occ;
+        xf[3 * p + 1] = gd;
+        xf[3 * p + 2] = rt;
+    }
+    if (xp) *reinterpret_cast<uint2 *>(xp + p * 4) = make_uint2(pack2(occ, gd), pack2(rt, 0.f));
+    if (ccls) ccls[p] = nfree > 0 ? TWG_CELL_FREE : TWG_CELL_OBST;
+}
+
+// Coarse training target: out[Y][X] = mean of psi over the FREE fine cells of
+// block (X, Y), summed in row order in FP32 (0 when the block has none).
+__global__ __launch_bounds__(256) void k_coarse_target(const float *__restrict__ psi, const uint8_t *__restrict__ cls,
+                                                       int nx, int ny, int pitch, int f, int Hc, int Wc,
+                                                       float *__restrict__ out)
+{
+    const int X = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int Y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (X >= Wc || Y >= Hc) return;
+    float sum = 0.f;
+    int cnt = 0;
+    for (int dy = 0; dy < f; ++dy) {
+        const int y = Y * f + dy;
+        if (y >= ny) break;
+        for (int dx = 0; dx < f; ++dx) {
+            const int x = X * f + dx;
+            if (x >= nx) break;
+            const size_t i = (size_t)y * pitch + x;
+            if (cls[i] == TWG_CELL_FREE) {
+                sum = sum + psi[i];
+                ++cnt;
+            }
+        }
+    }
+    out[(size_t)Y * Wc + X] = cnt > 0 ? sum / (float)cnt : 0.f;
+}
+
+// Warm-start field from a coarse output yc [Hc][Wc]: a FREE cell (x, y) takes
+// the bilinear interpolation of yc at coarse coordinates
+// ((x + 1/2) / f - 1/2, (y + 1/2) / f - 1/2), clamped to the frame, then to
+// [0, 1]; OBST and WALL 0, GOAL 1, FIXED unchanged.  A non-finite value at a
+// FREE cell sets *bad.
+__global__ __launch_bounds__(256) void k_up_psi(const float *__restrict__ yc, int Hc, int Wc, int f,
+                                                const uint8_t *__restrict__ cls, float *__restrict__ psi, int nx,
+                                                int ny, int pitch, unsigned int *bad)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= nx || y >= ny) return;
+    const size_t i = (size_t)y * pitch + x;
+    const uint8_t c = cls[i];
+    if (c == TWG_CELL_FREE) {
+        const float inv_f = 1.f / (float)f;  // f is a power of two: exact
+        const float u = fminf(fmaxf(((float)x + 0.5f) * inv_f - 0.5f, 0.f), (float)(Wc - 1));
+        const float v = fminf(fmaxf(((float)y + 0.5f) * inv_f - 0.5f, 0.f), (float)(Hc - 1));
+        const int x0 = (int)u, y0 = (int)v;
+        const int x1 = min(x0 + 1, Wc - 1), y1 = min(y0 + 1, Hc - 1);
+        const float a = u - (float)x0, b = v - (float)y0;
+        const float top = (1.f - a) * yc[(size_t)y0 * Wc + x0] + a * yc[(size_t)y0 * Wc + x1];
+        const float bot = (1.f - a) * yc[(size_t)y1 * Wc + x0] + a * yc[(size_t)y1 * Wc + x1];
+        const float val = (1.f - b) * top + b * bot;
+        if (!isfinite(val)) atomicOr(bad, 1u);
+        psi[i] = fminf(fmaxf(val, 0.f), 1.f);
+    } else if (c == TWG_CELL_OBST || c == TWG_CELL_WALL) {
+        psi[i] = 0.f;
+    } else if (c == TWG_CELL_GOAL) {
+        psi[i] = 1.f;
+    }
+}
+
 // largest ring number of a grid; *out must be zero beforehand.  Grid-stride
 // over rows, wave and block maxima, one atomic per block.
 __global__ __launch_bounds__(256) void k_ring_max(const uint16_t *__restrict__ ring, int nx, int ny, int pitch,
@@ -1113,6 +1228,33 @@ int net_head_psi(twg_unet *n, const uint8_t *cls, float *psi, int nx, int ny, in
     const dim3 grid((nx + 63) / 64, (ny + 3) / 4);
     hipLaunchKernelGGL(k_head_psi, grid, dim3(256), 0, st, n->d0, n->master + n->L.offw[7],
                        n->master + n->L.offb[7], cls, psi, nx, ny, pitch, Wp, n->words + 1);
+    hipLaunchKernelGGL(k_net_fallback, grid, dim3(256), 0, st, cls, psi, nx, ny, pitch, n->words + 1, status);
+    return last_status();
+}
+
+int net_features_coarse(const uint8_t *cls, const uint16_t *ring, int nx, int ny, int pitch, int f, int Hc, int Wc,
+                        int gx, int gy, const unsigned int *jmax, float *xf, uint16_t *xp, uint8_t *ccls,
+                        hipStream_t st)
+{
+    const float inv_diag = (float)(1.0 / ((double)std::max(nx, ny) * std::sqrt(2.0)));
+    hipLaunchKernelGGL(k_features_coarse, dim3((Wc + 63) / 64, (Hc + 3) / 4), dim3(256), 0, st, cls, ring, nx, ny,
+                       pitch, f, Hc, Wc, gx, gy, inv_diag, jmax, xf, xp, ccls);
+    return last_status();
+}
+
+int net_coarse_target(const float *psi, const uint8_t *cls, int nx, int ny, int pitch, int f, int Hc, int Wc,
+                      float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_coarse_target, dim3((Wc + 63) / 64, (Hc + 3) / 4), dim3(256), 0, st, psi, cls, nx, ny,
+                       pitch, f, Hc, Wc, out);
+    return last_status();
+}
+
+int net_up_psi(twg_unet *n, const float *yc, int Hc, int Wc, int f, const uint8_t *cls, float *psi, int nx, int ny,
+               int pitch, int32_t *status, hipStream_t st)
+{
+    const dim3 grid((nx + 63) / 64, (ny + 3) / 4);
+    hipLaunchKernelGGL(k_up_psi, grid, dim3(256), 0, st, yc, Hc, Wc, f, cls, psi, nx, ny, pitch, n->words + 1);
     hipLaunchKernelGGL(k_net_fallback, grid, dim3(256), 0, st, cls, psi, nx, ny, pitch, n->words + 1, status);
     return last_status();
 }

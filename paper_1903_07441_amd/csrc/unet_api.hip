@@ -148,6 +148,7 @@ int32_t twg_unet_destroy(twg_unet *n)
     if (n->pblock) hipFree(n->pblock);
     if (n->fblock) hipFree(n->fblock);
     if (n->bblock) hipFree(n->bblock);
+    if (n->yc) hipFree(n->yc);
     delete n;
     return TWG_OK;
 }
@@ -267,6 +268,107 @@ int32_t twg_unet_warm_start(twg_unet *n, twg_grid g, const uint8_t *cls, const u
     if (!rc) rc = net_forward(n, 1, H, W, st);
     if (!rc) rc = net_head_psi(n, cls, psi, g.nx, g.ny, g.pitch, W, status, st);
     return rc ? set_err(n->ctx, rc, "warm start failed") : TWG_OK;
+}
+
+namespace {
+
+// the coarse frame of a grid at 1/f: sides rounded up to multiples of 8
+void coarse_frame(const twg_grid &g, int f, int *Hc, int *Wc)
+{
+    *Hc = std::max(8, ((g.ny + f - 1) / f + 7) / 8 * 8);
+    *Wc = std::max(8, ((g.nx + f - 1) / f + 7) / 8 * 8);
+}
+
+bool coarse_factor_ok(int f) { return f == 2 || f == 4 || f == 8 || f == 16; }
+
+}  // namespace
+
+int32_t twg_unet_coarse_frame(twg_grid g, int32_t factor, int32_t *Hc, int32_t *Wc)
+{
+    if (!Hc || !Wc || !coarse_factor_ok(factor) || g.nx < 1 || g.ny < 1) return TWG_EINVAL;
+    int h, w;
+    coarse_frame(g, factor, &h, &w);
+    *Hc = h;
+    *Wc = w;
+    return TWG_OK;
+}
+
+int32_t twg_unet_features_coarse(twg_unet *n, twg_grid g, const uint8_t *cls, const uint16_t *ring, int32_t goal_x,
+                                 int32_t goal_y, int32_t factor, float *x, uint8_t *ccls, void *stream)
+{
+    if (!n) return TWG_EINVAL;
+    n->ctx->err.clear();
+    int rc = check_grid(n->ctx, g);
+    if (rc) return rc;
+    if (!cls || (!x && !ccls)) return set_err(n->ctx, TWG_EINVAL, "cls and x or ccls are required");
+    if (!coarse_factor_ok(factor)) return set_err(n->ctx, TWG_EINVAL, "factor must be 2, 4, 8 or 16");
+    int Hc, Wc;
+    coarse_frame(g, factor, &Hc, &Wc);
+    hipSetDevice(n->ctx->device);
+    hipStream_t st = as_stream(stream);
+    rc = net_zero_words(n, 2, st);
+    if (!rc && ring) rc = net_ring_max(ring, g.nx, g.ny, g.pitch, n->words, st);
+    if (!rc) rc = net_features_coarse(cls, ring, g.nx, g.ny, g.pitch, factor, Hc, Wc, goal_x, goal_y, n->words, x,
+                                      nullptr, ccls, st);
+    return rc ? set_err(n->ctx, rc, "coarse feature kernel failed") : TWG_OK;
+}
+
+int32_t twg_unet_coarse_target(twg_unet *n, twg_grid g, const uint8_t *cls, const float *psi, int32_t factor,
+                               float *out, void *stream)
+{
+    if (!n) return TWG_EINVAL;
+    n->ctx->err.clear();
+    int rc = check_grid(n->ctx, g);
+    if (rc) return rc;
+    if (!cls || !psi || !out) return set_err(n->ctx, TWG_EINVAL, "cls, psi and out are required");
+    if (!coarse_factor_ok(factor)) return set_err(n->ctx, TWG_EINVAL, "factor must be 2, 4, 8 or 16");
+    int Hc, Wc;
+    coarse_frame(g, factor, &Hc, &Wc);
+    hipSetDevice(n->ctx->device);
+    rc = net_coarse_target(psi, cls, g.nx, g.ny, g.pitch, factor, Hc, Wc, out, as_stream(stream));
+    return rc ? set_err(n->ctx, rc, "coarse target kernel failed") : TWG_OK;
+}
+
+int32_t twg_unet_warm_start_coarse(twg_unet *n, twg_grid g, const uint8_t *cls, const uint16_t *ring,
+                                   int32_t goal_x, int32_t goal_y, int32_t factor, float *psi, int32_t *status,
+                                   void *stream)
+{
+    if (!n) return TWG_EINVAL;
+    n->ctx->err.clear();
+    int rc = check_grid(n->ctx, g);
+    if (rc) return rc;
+    if (!cls || !psi) return set_err(n->ctx, TWG_EINVAL, "cls and psi are required");
+    if (!coarse_factor_ok(factor)) return set_err(n->ctx, TWG_EINVAL, "factor must be 2, 4, 8 or 16");
+    int Hc, Wc;
+    coarse_frame(g, factor, &Hc, &Wc);
+    rc = check_shape(n, 1, Hc, Wc);
+    if (rc) return rc;
+    hipSetDevice(n->ctx->device);
+    hipStream_t st = as_stream(stream);
+    const long long P = (long long)Hc * Wc;
+    rc = ensure_fwd(n, P);
+    if (rc) return rc;
+    if (P > n->yc_pixels) {
+        if (n->yc) {
+            hipDeviceSynchronize();
+            hipFree(n->yc);
+            n->yc = nullptr;
+            n->yc_pixels = 0;
+        }
+        if (hipMalloc(&n->yc, (size_t)P * sizeof(float)) != hipSuccess) {
+            n->yc = nullptr;
+            return set_err(n->ctx, TWG_ENOMEM, "coarse output allocation failed");
+        }
+        n->yc_pixels = P;
+    }
+    rc = net_zero_words(n, 2, st);
+    if (!rc && ring) rc = net_ring_max(ring, g.nx, g.ny, g.pitch, n->words, st);
+    if (!rc) rc = net_features_coarse(cls, ring, g.nx, g.ny, g.pitch, factor, Hc, Wc, goal_x, goal_y, n->words,
+                                      nullptr, n->xp, nullptr, st);
+    if (!rc) rc = net_forward(n, 1, Hc, Wc, st);
+    if (!rc) rc = net_head_plain(n, n->yc, (int)P, st);
+    if (!rc) rc = net_up_psi(n, n->yc, Hc, Wc, factor, cls, psi, g.nx, g.ny, g.pitch, status, st);
+    return rc ? set_err(n->ctx, rc, "coarse warm start failed") : TWG_OK;
 }
 
 }  // extern "C"

@@ -10,6 +10,15 @@ plain initial fields and from the network's field and reports sweeps and time.
     python -m paper_1903_07441_amd.learn --train 4096 --eval 64 --epochs 4 \\
         --out paper_1903_07441_amd/weights/unet_learn256.npz
 
+With --coarse F the network is trained at 1/F of full-size replanning maps
+(2048 x 2048, 500 moving discs): inputs and targets are the maps' block-level
+views (twg_unet_features_coarse, twg_unet_coarse_target of fields the library
+relaxed), and the warm start interpolates the coarse output back
+(twg_unet_warm_start_coarse):
+
+    python -m paper_1903_07441_amd.learn --coarse 8 --train 2048 --eval 8 \\
+        --epochs 10 --out paper_1903_07441_amd/weights/unet_coarse8_replan2048.npz
+
 Weights are stored as an .npz with one FP32 array ``params`` (the C ABI's
 parameter order) and a text array ``meta`` (JSON); load with
 ``np.load(path)`` (no pickles).
@@ -104,6 +113,87 @@ def relax_targets(ctx, data, tol=3e-7, chunk=256, max_sweeps=20000):
             f"{sum(d['status'] == twg.OK for d in st)}/{len(st)} at tol)")
     data["target"] = psi
     return psi
+
+
+def make_coarse_dataset(ctx, net, first, n, factor, name="replan2048", tol=3e-7):
+    """Scenarios first .. first + n - 1 of recipe `name` seen at 1/factor:
+    each is rasterised and relaxed at full resolution by the library (FP32,
+    from psi = 0, to residual `tol`), and its coarse inputs, coarse training
+    mask and coarse target (the relaxed field's mean over each block's FREE
+    cells) are kept.  Returns dict(x, cls, target, H, W, factor, ...)."""
+    dev = torch.device("cuda", ctx.device)
+    sc0 = scenarios.scenario(name, first)
+    ny, nx = sc0["ny"], sc0["nx"]
+    Hc, Wc = twg.UNet.coarse_frame(nx, ny, factor)
+    x = torch.empty((n, Hc, Wc, 3), dtype=torch.float32, device=dev)
+    ccls = torch.empty((n, Hc, Wc), dtype=torch.uint8, device=dev)
+    target = torch.empty((n, Hc, Wc), dtype=torch.float32, device=dev)
+    cls = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
+    ring = torch.empty((ny, nx), dtype=torch.uint16, device=dev)
+    psi = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    sweeps = []
+    for k in range(n):
+        sc = scenarios.scenario(name, first + k)
+        pos = torch.as_tensor(sc["pos"], dtype=torch.float64).reshape(-1, 2).to(dev)
+        vel = torch.as_tensor(sc["vel"], dtype=torch.float64).reshape(-1, 2).to(dev)
+        rad = torch.as_tensor(sc["rad"], dtype=torch.float64).to(dev)
+        ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"], robot_speed=sc["vr"],
+                      cls=cls, ring=ring)
+        st = ctx.relax(cls, psi, None, tol=tol, init=twg.INIT_ZERO)
+        sweeps.append(st["sweeps"])
+        net.features_coarse(cls, ring, sc["goal"], factor, x=x[k], ccls=ccls[k])
+        net.coarse_target(cls, psi, factor, out=target[k])
+        if (k + 1) % 256 == 0 or k + 1 == n:
+            log(f"  coarse data {k + 1}/{n} (median sweeps {int(np.median(sweeps))})")
+    return dict(x=x, cls=ccls, target=target, H=Hc, W=Wc, factor=factor, first=first, name=name)
+
+
+def evaluate_coarse(ctx, net, first, n, factor, name="replan2048", omegas=(0.0, 1.95, 1.98), tol=1e-6):
+    """Held-out scenarios at full resolution: time (and sweeps) to residual
+    `tol` from the plain start psi = 0 and from the coarse network's field
+    (its forward pass and interpolation counted), each with its best factor
+    of `omegas` (0 = tuned), median over the scenarios."""
+    dev = torch.device("cuda", ctx.device)
+    sc0 = scenarios.scenario(name, first)
+    ny, nx = sc0["ny"], sc0["nx"]
+    cls = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
+    ring = torch.empty((ny, nx), dtype=torch.uint16, device=dev)
+    psi = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    ev0, ev1, ev2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    rows = {"zero": [], "coarse_net": []}
+    net_ms = []
+    for k in range(n):
+        sc = scenarios.scenario(name, first + k)
+        pos = torch.as_tensor(sc["pos"], dtype=torch.float64).reshape(-1, 2).to(dev)
+        vel = torch.as_tensor(sc["vel"], dtype=torch.float64).reshape(-1, 2).to(dev)
+        rad = torch.as_tensor(sc["rad"], dtype=torch.float64).to(dev)
+        ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"], robot_speed=sc["vr"],
+                      cls=cls, ring=ring)
+        for kind in rows:
+            best = None
+            for w in omegas:
+                torch.cuda.synchronize()
+                ev0.record()
+                if kind == "coarse_net":
+                    net.warm_start_coarse(cls, ring, sc["goal"], psi, factor)
+                ev1.record()
+                st = ctx.relax(cls, psi, None, tol=tol, init=twg.INIT_KEEP if kind == "coarse_net" else twg.INIT_ZERO,
+                               omega=w)
+                ev2.record()
+                torch.cuda.synchronize()
+                r = (ev0.elapsed_time(ev2), st["sweeps"], w)
+                if kind == "coarse_net":
+                    net_ms.append(ev0.elapsed_time(ev1))
+                if best is None or r[0] < best[0]:
+                    best = r
+            rows[kind].append(best)
+    out = {"scenarios": [first, first + n], "factor": factor, "net_median_ms": float(np.median(net_ms))}
+    for kind, v in rows.items():
+        a = np.array([(t, s) for t, s, _ in v])
+        out[kind] = {"median_ms": float(np.median(a[:, 0])), "median_sweeps": float(np.median(a[:, 1])),
+                     "omegas": [w for _, _, w in v]}
+    out["time_ratio_zero_over_net"] = out["zero"]["median_ms"] / out["coarse_net"]["median_ms"]
+    return out
 
 
 def train(net, data, epochs=4, batch=16, lr=1e-3, lr_min=2e-5, log_every=100):
@@ -201,7 +291,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--init", default=None, help="start from these weights instead of He init")
+    ap.add_argument("--coarse", type=int, default=0,
+                    help="train the coarse-scale warm start at 1/COARSE of the replan2048 grids instead")
     args = ap.parse_args()
+    if args.coarse:
+        return main_coarse(args)
 
     torch.cuda.set_device(0)
     ctx = twg.Context(0)
@@ -221,6 +315,44 @@ def main():
     after = evaluate(ctx, net, ev)
     meta = {"train_scenarios": [0, args.train], "eval_scenarios": [100000, 100000 + args.eval],
             "recipe": "learn256", "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+            "ms_per_step": ms_step, "loss_history": hist, "eval": after}
+    save_weights(args.out, net.get_params().cpu().numpy(), meta)
+    print(json.dumps({"data_s": round(t_data, 1), "ms_per_train_step": round(ms_step * 1e3, 3),
+                      "final_loss": hist[-1][1] if hist else None, "eval_untrained": before,
+                      "eval_trained": after}), flush=True)
+    net.close()
+    ctx.close()
+
+
+def main_coarse(args):
+    """Coarse-scale training on full-size replanning maps (2048 x 2048, 500
+    moving discs): the network learns the field's mean over factor x factor
+    blocks from block-level inputs; the warm start interpolates it back."""
+    torch.cuda.set_device(0)
+    ctx = twg.Context(0)
+    net = twg.UNet(ctx)
+    params = load_weights(args.init)[0] if args.init else he_init(args.seed)
+    net.set_params(torch.as_tensor(params))
+    f = args.coarse
+    t0 = time.perf_counter()
+    # the relaxation's tiling and factors for this size, tuned on one map
+    sc = scenarios.scenario("replan2048", 2)
+    dev = torch.device("cuda", 0)
+    cls, _ = ctx.rasterize(sc["nx"], sc["ny"], sc["robot"], sc["goal"],
+                           torch.as_tensor(sc["pos"], dtype=torch.float64, device=dev).contiguous(),
+                           torch.as_tensor(sc["vel"], dtype=torch.float64, device=dev).contiguous(),
+                           torch.as_tensor(sc["rad"], dtype=torch.float64, device=dev).contiguous(),
+                           W=sc["W"], robot_speed=sc["vr"], want_ring=False)
+    ctx.autotune(cls)
+    log(f"coarse dataset: {args.train} training scenarios of replan2048 at 1/{f}")
+    tr = make_coarse_dataset(ctx, net, 1000, args.train, f)
+    t_data = time.perf_counter() - t0
+    before = evaluate_coarse(ctx, net, 100, args.eval, f) if args.init is None else None
+    hist, ms_step = train(net, tr, epochs=args.epochs, batch=args.batch, lr=args.lr)
+    after = evaluate_coarse(ctx, net, 100, args.eval, f)
+    meta = {"train_scenarios": ["replan2048", 1000, 1000 + args.train], "eval_scenarios": ["replan2048", 100,
+                                                                                          100 + args.eval],
+            "recipe": "replan2048", "coarse_factor": f, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
             "ms_per_step": ms_step, "loss_history": hist, "eval": after}
     save_weights(args.out, net.get_params().cpu().numpy(), meta)
     print(json.dumps({"data_s": round(t_data, 1), "ms_per_train_step": round(ms_step * 1e3, 3),

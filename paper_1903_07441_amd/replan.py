@@ -146,14 +146,15 @@ class StepGraph:
 
 
 def run_loop(ctx, sc, steps, sigma=0.0, net=None, omega_warm=None, keep_first=0, cold_every=0,
-             meas_seed=77, log=None, fill="half"):
+             meas_seed=77, log=None, fill="half", net_factor=0):
     """The replanning loop of Algorithm 1 for `steps` steps on scenario sc.
 
     Each step: Kalman update of every obstacle from a position measurement
     with noise sigma (R = 0.25 I; step 0 starts from the scenario's state),
     rasterise around the robot, initial field = the previous step's field
     where the cell was and is FREE and, elsewhere, by `fill`: "half" the
-    paper's 0.5, "network" the network's field (net), "previous" the
+    paper's 0.5, "network" the network's field (net; at 1/net_factor of the
+    grid's resolution when net_factor > 0), "previous" the
     previous field there too (0 where an obstacle was; step 0 starts from
     PLAIN_INIT), FP32 relaxation to
     TOL, FP64 polish to
@@ -190,7 +191,9 @@ def run_loop(ctx, sc, steps, sigma=0.0, net=None, omega_warm=None, keep_first=0,
         if k > 0:
             ctx.kalman_step(kx, kP, zk, dt=1.0, R=kR, pos=est_p, vel=est_v)
         a.rasterize(robot, est_p, est_v)
-        if fill == "network":
+        if fill == "network" and net_factor:
+            net.warm_start_coarse(a.cls, a.ring, sc["goal"], a.psi, net_factor)
+        elif fill == "network":
             net.warm_start(a.cls, a.ring, sc["goal"], a.psi)
         else:
             ctx.init_field(a.cls, a.psi, twg.INIT_HALF if fill == "half" else PLAIN_INIT)

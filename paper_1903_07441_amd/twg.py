@@ -112,6 +112,10 @@ def _load():
         "twg_unet_adam_step": (i32, [vp, f32, vp]),
         "twg_unet_features": (i32, [vp, Grid, vp, vp, i32, i32, i32, i32, vp, vp]),
         "twg_unet_warm_start": (i32, [vp, Grid, vp, vp, i32, i32, vp, vp, vp]),
+        "twg_unet_coarse_frame": (i32, [Grid, i32, P(i32), P(i32)]),
+        "twg_unet_features_coarse": (i32, [vp, Grid, vp, vp, i32, i32, i32, vp, vp, vp]),
+        "twg_unet_coarse_target": (i32, [vp, Grid, vp, vp, i32, vp, vp]),
+        "twg_unet_warm_start_coarse": (i32, [vp, Grid, vp, vp, i32, i32, i32, vp, vp, vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -130,7 +134,8 @@ EXPORTED = ("twg_version", "twg_ctx_create", "twg_ctx_destroy", "twg_last_error"
             "hpf_init_field", "hpf_set_tiling", "twg_kalman_step", "hpf_descent_all",
             "twg_unet_num_params", "twg_unet_create", "twg_unet_destroy",
             "twg_unet_set_params", "twg_unet_get_params", "twg_unet_forward", "twg_unet_loss_grad",
-            "twg_unet_adam_step", "twg_unet_features", "twg_unet_warm_start")
+            "twg_unet_adam_step", "twg_unet_features", "twg_unet_warm_start", "twg_unet_coarse_frame",
+            "twg_unet_features_coarse", "twg_unet_coarse_target", "twg_unet_warm_start_coarse")
 
 
 class TwgError(RuntimeError):
@@ -539,6 +544,59 @@ class UNet:
         self.ctx._check(lib.twg_unet_features(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(ring), int(goal[0]),
                                               int(goal[1]), int(H), int(W), _ptr(out), _stream()))
         return out
+
+    @staticmethod
+    def coarse_frame(nx, ny, factor):
+        """(Hc, Wc) of the coarse frame of an nx x ny grid at 1/factor."""
+        h, w = i32(), i32()
+        rc = lib.twg_unet_coarse_frame(Grid(int(nx), int(ny), int(nx)), int(factor), ctypes.byref(h), ctypes.byref(w))
+        if rc != OK:
+            raise TwgError(rc, "bad grid or factor")
+        return h.value, w.value
+
+    def features_coarse(self, cls, ring, goal, factor, x=None, ccls=None):
+        """Coarse input channels FP32 [Hc][Wc][3] and the coarse training mask
+        uint8 [Hc][Wc] of a grid seen at 1/factor."""
+        nx, ny, pitch = _grid_of(cls)
+        if ring is not None and ring.stride(0) != pitch:
+            raise ValueError("ring map must share the class map's pitch")
+        Hc, Wc = self.coarse_frame(nx, ny, factor)
+        if x is None:
+            x = torch.empty((Hc, Wc, 3), dtype=torch.float32, device=self._dev())
+        if ccls is None:
+            ccls = torch.empty((Hc, Wc), dtype=torch.uint8, device=self._dev())
+        if x.numel() != Hc * Wc * 3 or ccls.numel() != Hc * Wc or not (x.is_contiguous() and ccls.is_contiguous()):
+            raise ValueError("x must be [Hc, Wc, 3] float32 and ccls [Hc, Wc] uint8, contiguous")
+        self.ctx._check(lib.twg_unet_features_coarse(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(ring), int(goal[0]),
+                                                     int(goal[1]), int(factor), _ptr(x), _ptr(ccls), _stream()))
+        return x, ccls
+
+    def coarse_target(self, cls, psi, factor, out=None):
+        """Mean of psi over the FREE cells of every coarse block, FP32 [Hc][Wc]."""
+        nx, ny, pitch = _grid_of(psi)
+        if cls.stride(0) != pitch:
+            raise ValueError("class map must share psi's pitch")
+        Hc, Wc = self.coarse_frame(nx, ny, factor)
+        if out is None:
+            out = torch.empty((Hc, Wc), dtype=torch.float32, device=self._dev())
+        if out.numel() != Hc * Wc or not out.is_contiguous():
+            raise ValueError("out must be a contiguous [Hc, Wc] float32 tensor")
+        self.ctx._check(lib.twg_unet_coarse_target(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(psi), int(factor),
+                                                   _ptr(out), _stream()))
+        return out
+
+    def warm_start_coarse(self, cls, ring, goal, psi, factor, status=None):
+        """Network field at 1/factor of the grid's resolution, interpolated
+        into psi's FREE cells (fallback and status as warm_start)."""
+        nx, ny, pitch = _grid_of(psi)
+        if cls.stride(0) != pitch or (ring is not None and ring.stride(0) != pitch):
+            raise ValueError("class and ring maps must share psi's pitch")
+        if status is not None and (status.dtype != torch.int32 or not status.is_cuda):
+            raise ValueError("status must be an int32 device tensor")
+        self.ctx._check(lib.twg_unet_warm_start_coarse(self.h, Grid(nx, ny, pitch), _ptr(cls), _ptr(ring),
+                                                       int(goal[0]), int(goal[1]), int(factor), _ptr(psi),
+                                                       _ptr(status), _stream()))
+        return psi
 
     def warm_start(self, cls, ring, goal, psi, status=None):
         """Network field into psi.  status: optional device int32 tensor that

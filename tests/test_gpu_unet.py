@@ -341,3 +341,58 @@ def test_rejects_bad_arguments(ctx):
     with pytest.raises(twg.TwgError):
         net.adam_step(0.0)
     net.close()
+
+
+@pytest.mark.parametrize("factor", [4, 8])
+def test_coarse_features_and_target_match_oracle(ctx, orc, factor):
+    # the coarse inputs, the training mask and the coarse target of a ragged
+    # grid against the oracle's definitions (FP32 on the GPU)
+    import torch
+    from paper_1903_07441_amd import scenarios, twg
+    from conftest import scenario_tensors
+    sc = scenarios.custom(100, 70, 30, rad=(2.0, 6.0), seed=5)
+    pos, vel, rad = scenario_tensors(sc)
+    nx, ny = sc["nx"], sc["ny"]
+    cls, ring = ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"], robot_speed=sc["vr"])
+    net = twg.UNet(ctx)
+    x, ccls = net.features_coarse(cls, ring, sc["goal"], factor)
+    c, r = cls.cpu().numpy(), ring.cpu().numpy()
+    wx, wmask = ou.coarse_features(c, r, sc["goal"], factor)
+    print(f"coarse features factor {factor}: frame {tuple(x.shape[:2])}", flush=True)
+    assert x.shape == wx.shape
+    xg = x.cpu().numpy()
+    assert np.array_equal(xg[..., 0], wx[..., 0].astype(np.float32))
+    assert np.allclose(xg[..., 1], wx[..., 1], rtol=0, atol=2e-7)
+    assert np.allclose(xg[..., 2], wx[..., 2], rtol=0, atol=2e-7)
+    assert np.array_equal(ccls.cpu().numpy(), wmask)
+    psi = torch.rand((ny, nx), generator=torch.Generator().manual_seed(factor)).cuda()
+    t = net.coarse_target(cls, psi, factor).cpu().numpy()
+    want = ou.coarse_target(psi.cpu().numpy().astype(np.float64), c, factor)
+    assert np.allclose(t, want, rtol=0, atol=1e-6)
+    net.close()
+
+
+def test_coarse_warm_start_is_the_network_output_interpolated(ctx, orc):
+    # warm_start_coarse = the oracle's interpolation of the network's own
+    # coarse output (the forward pass is checked against the FP64 reference
+    # elsewhere)
+    import torch
+    from paper_1903_07441_amd import scenarios, twg
+    from conftest import scenario_tensors
+    sc = scenarios.scenario("warped512", 6, side=120)
+    pos, vel, rad = scenario_tensors(sc)
+    nx, ny = sc["nx"], sc["ny"]
+    cls, ring = ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"], robot_speed=sc["vr"])
+    net = gpu_net(ctx, bf16_params(21))
+    f = 4
+    x, _ = net.features_coarse(cls, ring, sc["goal"], f)
+    yc = net.forward(x[None].contiguous())[0].cpu().numpy().astype(np.float64)
+    psi = torch.full((ny, nx), -3.0, dtype=torch.float32, device="cuda")
+    status = torch.full((1,), -9, dtype=torch.int32, device="cuda")
+    net.warm_start_coarse(cls, ring, sc["goal"], psi, f, status=status)
+    want = ou.upsample_field_f(yc, cls.cpu().numpy(), f)
+    got = psi.cpu().numpy()
+    print(f"coarse warm start: max |gpu - oracle| {np.max(np.abs(got - want)):.2e}", flush=True)
+    assert int(status.item()) == twg.OK
+    assert np.allclose(got, want, rtol=0, atol=1e-6)
+    net.close()

@@ -156,3 +156,80 @@ def test_bf16_gradient_storage_option():
     want = unet.bf16_round(p["head.w"][0, :, 0, 0][:, None, None] * dy[None] * (c["d0"] > 0))
     dd0, _, _ = unet.conv_backward(c["d0"], p["head.w"], dy[None])
     np.testing.assert_array_equal(unet.bf16_round(dd0 * (c["d0"] > 0)), want)
+
+
+# ---- coarse-scale warm start ------------------------------------------------
+
+def _fine_features(cls, ring, goal):
+    """The fine-scale input channels written out from their definition."""
+    ny, nx = cls.shape
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    occ = np.isin(cls, (unet.OBST, unet.WALL)).astype(np.float64)
+    gd = np.hypot(xx - goal[0], yy - goal[1]) / (max(nx, ny) * np.sqrt(2.0))
+    rt = ring / ring.max()
+    return np.stack([occ, gd, rt], -1)
+
+
+def test_coarse_features_at_factor_one_are_the_fine_features():
+    rng = np.random.default_rng(3)
+    ny, nx = 16, 24  # multiples of 8: the frame is the grid
+    cls = rng.choice([0, 0, 0, 1, 2, 3], size=(ny, nx)).astype(np.uint8)
+    ring = rng.integers(0, 9, size=(ny, nx))
+    ring[0, 0] = 8
+    x, mask = unet.coarse_features(cls, ring, (5, 7), 1)
+    assert np.allclose(x, _fine_features(cls, ring, (5, 7)), rtol=0, atol=1e-15)
+    assert np.array_equal(mask == unet.FREE, cls == unet.FREE)
+
+
+def test_coarse_features_counts_and_outside_cells():
+    # a 10 x 6 grid at f = 4: the frame is 8 x 8 blocks; block (2, 1) holds
+    # fine columns 8..11 (10, 11 outside) and rows 4..7 (6, 7 outside)
+    cls = np.zeros((6, 10), np.uint8)
+    cls[4, 8] = unet.OBST
+    cls[5, 9] = unet.GOAL
+    x, mask = unet.coarse_features(cls, None, (0, 0), 4)
+    assert x.shape == (8, 8, 3)
+    outside = 16 - 4  # 4 cells inside the grid
+    assert x[1, 2, 0] == (outside + 1) / 16.0
+    assert mask[1, 2] == unet.FREE  # (9, 4) is FREE
+    assert x[5, 5, 0] == 1.0 and mask[5, 5] == unet.OBST  # wholly outside
+    assert x[0, 0, 0] == 0.0 and np.all(x[..., 2] == 0.0)
+    # block centre (1.5, 1.5) for block (0, 0): distance to the goal (0, 0)
+    assert np.isclose(x[0, 0, 1], np.hypot(1.5, 1.5) / (10 * np.sqrt(2.0)))
+
+
+def test_coarse_target_of_a_linear_field_is_its_value_at_block_centres():
+    # the mean of a linear function over a full block is its value at the
+    # block's centre; blocks without FREE cells read 0
+    f, ny, nx = 4, 16, 16
+    cls = np.zeros((ny, nx), np.uint8)
+    cls[12:, 12:] = unet.OBST
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    psi = 0.25 + 0.01 * xx - 0.02 * yy
+    t = unet.coarse_target(psi, cls, f)
+    for Y in range(3):
+        for X in range(3):
+            cx, cy = X * f + 1.5, Y * f + 1.5
+            assert np.isclose(t[Y, X], 0.25 + 0.01 * cx - 0.02 * cy, rtol=0, atol=1e-14)
+    assert t[3, 3] == 0.0
+
+
+def test_upsample_reproduces_linear_fields_and_the_round_trip():
+    # bilinear interpolation is exact on linear functions, so a linear field
+    # pooled to block centres and interpolated back is the field itself away
+    # from the clamped border; fixed cells take their Dirichlet values
+    f, ny, nx = 4, 32, 32
+    cls = np.zeros((ny, nx), np.uint8)
+    cls[0, :] = unet.WALL
+    cls[20, 20] = unet.GOAL
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    psi = 0.2 + 0.005 * xx + 0.01 * yy
+    t = unet.coarse_target(psi, np.zeros_like(cls), f)
+    back = unet.upsample_field_f(t, cls, f)
+    inner = (slice(2, ny - 2), slice(2, nx - 2))
+    free = cls[inner] == unet.FREE
+    assert np.allclose(back[inner][free], psi[inner][free], rtol=0, atol=1e-13)
+    assert np.all(back[0, :] == 0.0) and back[20, 20] == 1.0
+    # clamping to [0, 1] and to the frame
+    yc = np.full((8, 8), 3.0)
+    assert np.all(unet.upsample_field_f(yc, np.zeros((32, 32), np.uint8), 4) == 1.0)
