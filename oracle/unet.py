@@ -220,3 +220,103 @@ def adam_step(p, g, state, lr, b1=0.9, b2=0.999, eps=1e-8):
         vh = v / (1 - b2 ** t)
         p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
     return p
+
+
+# ---------------------------------------------------------------------------
+# Coarse-scale warm start: the grid seen at 1/f of its resolution, and the
+# network's coarse output interpolated back to the grid.  Plain loops over
+# blocks and cells (small grids only), float64.
+# ---------------------------------------------------------------------------
+
+FREE, OBST, WALL, GOAL, FIXED = 0, 1, 2, 3, 4
+
+
+def coarse_frame(nx, ny, f):
+    """(Hc, Wc): the coarse sides ceil(n / f) rounded up to multiples of 8
+    (at least 8)."""
+    hc = max(8, (-(-ny // f) + 7) // 8 * 8)
+    wc = max(8, (-(-nx // f) + 7) // 8 * 8)
+    return hc, wc
+
+
+def coarse_features(cls, ring, goal, f):
+    """Input channels [Hc, Wc, 3] and training mask [Hc, Wc] of the grid
+    `cls` [ny, nx] seen at 1/f.  Block (X, Y) covers fine cells
+    [fX, fX + f) x [fY, fY + f); cells outside the grid count as walls.
+    Occupancy = share of OBST / WALL / outside cells in the block; goal
+    distance of the block's centre (fX + (f - 1)/2, fY + (f - 1)/2) over
+    max(nx, ny) sqrt 2; ring of the fine cell (fX + f // 2, fY + f // 2)
+    clamped into the grid, over the largest ring (0 without a ring map, and
+    for blocks wholly outside the grid).  Mask: FREE where the block holds a
+    FREE cell, else OBST."""
+    ny, nx = cls.shape
+    hc, wc = coarse_frame(nx, ny, f)
+    x = np.zeros((hc, wc, 3))
+    mask = np.full((hc, wc), OBST, np.uint8)
+    diag = max(nx, ny) * np.sqrt(2.0)
+    jmax = float(ring.max()) if ring is not None and ring.size else 0.0
+    gx, gy = goal
+    for Y in range(hc):
+        for X in range(wc):
+            blocked = 0
+            free = 0
+            for y in range(Y * f, Y * f + f):
+                for xx in range(X * f, X * f + f):
+                    if xx >= nx or y >= ny:
+                        blocked += 1
+                        continue
+                    c = cls[y, xx]
+                    blocked += c in (OBST, WALL)
+                    free += c == FREE
+            x[Y, X, 0] = blocked / (f * f)
+            cx, cy = X * f + (f - 1) / 2.0, Y * f + (f - 1) / 2.0
+            x[Y, X, 1] = np.hypot(cx - gx, cy - gy) / diag
+            if ring is not None and jmax > 0 and X * f < nx and Y * f < ny:
+                rx, ry = min(X * f + f // 2, nx - 1), min(Y * f + f // 2, ny - 1)
+                x[Y, X, 2] = ring[ry, rx] / jmax
+            if free:
+                mask[Y, X] = FREE
+    return x, mask
+
+
+def coarse_target(psi, cls, f):
+    """[Hc, Wc]: the mean of psi over the FREE cells of each block (0 when the
+    block has none)."""
+    ny, nx = cls.shape
+    hc, wc = coarse_frame(nx, ny, f)
+    out = np.zeros((hc, wc))
+    for Y in range(hc):
+        for X in range(wc):
+            blk_c = cls[Y * f:Y * f + f, X * f:X * f + f]
+            blk_p = psi[Y * f:Y * f + f, X * f:X * f + f]
+            sel = blk_c == FREE
+            if sel.any():
+                out[Y, X] = blk_p[sel].mean()
+    return out
+
+
+def upsample_field_f(yc, cls, f, psi_in=None):
+    """FREE cell (x, y) takes the bilinear interpolation of yc at
+    ((x + 1/2)/f - 1/2, (y + 1/2)/f - 1/2), each coordinate clamped to the
+    frame, the value then clamped to [0, 1]; OBST and WALL 0, GOAL 1, FIXED
+    keep psi_in's value."""
+    ny, nx = cls.shape
+    hc, wc = yc.shape
+    out = np.zeros((ny, nx)) if psi_in is None else np.array(psi_in, dtype=np.float64)
+    for y in range(ny):
+        for x in range(nx):
+            c = cls[y, x]
+            if c == FREE:
+                u = min(max((x + 0.5) / f - 0.5, 0.0), wc - 1.0)
+                v = min(max((y + 0.5) / f - 0.5, 0.0), hc - 1.0)
+                x0, y0 = int(np.floor(u)), int(np.floor(v))
+                x1, y1 = min(x0 + 1, wc - 1), min(y0 + 1, hc - 1)
+                a, b = u - x0, v - y0
+                top = (1 - a) * yc[y0, x0] + a * yc[y0, x1]
+                bot = (1 - a) * yc[y1, x0] + a * yc[y1, x1]
+                out[y, x] = min(max((1 - b) * top + b * bot, 0.0), 1.0)
+            elif c in (OBST, WALL):
+                out[y, x] = 0.0
+            elif c == GOAL:
+                out[y, x] = 1.0
+    return out
