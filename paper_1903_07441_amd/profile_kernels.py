@@ -15,8 +15,8 @@ network on the rasterised grid, then `--passes` training steps (forward,
 backward, Adam) on a batch of 16 random 256 x 256 inputs.
 
 With --step: after autotuning, `--passes` whole replanning steps as bench.py
-times them (rasterise, FP32 relaxation to residual 1e-6, FP64 defect
-correction to a certified 1e-7, descent from the robot).
+times them (rasterise, FP32 relaxation from psi = 0 to residual 1e-6, FP64
+defect correction to a certified 5e-7, descent from the robot).
 """
 from __future__ import annotations
 
@@ -78,20 +78,15 @@ def main(argv=None):
         ctx.close()
         return 0
     if args.step:
+        from . import replan
         ctx.autotune(cls)
-        ring = torch.empty((ny, nx), dtype=torch.uint16, device=dev)
-        psi = torch.empty((ny, nx), dtype=torch.float32, device=dev)
-        psi64 = torch.empty((ny, nx), dtype=torch.float64, device=dev)
-        cap = nx * ny
-        path = torch.empty((cap, 2), dtype=torch.int32, device=dev)
-        info = torch.empty(2, dtype=torch.int32, device=dev)
+        pl = replan.Planner(ctx, sc)
+        robot = [int(sc["robot"][0]), int(sc["robot"][1])]
         for _ in range(args.passes):
-            ctx.rasterize(nx, ny, sc["robot"], sc["goal"], pos, vel, rad, W=sc["W"], robot_speed=sc["vr"],
-                          cls=cls, ring=ring)
-            ctx.relax(cls, psi, None, tol=1e-6, init=twg.INIT_HALF)
-            ctx.relax(cls, psi, psi64, tol=1e-6, init=twg.INIT_KEEP, polish=1, tol_cert=1e-7)
-            ctx.descend(cls, psi64=psi64, start=sc["robot"], cap=cap, path=path, info=info)
+            pl.rasterize(robot, pos, vel)
+            pl.solve(robot)
         torch.cuda.synchronize()
+        info = pl.info
         print(f"profiled {args.passes} replanning steps on {nx}x{ny} (each opens with k_raster_base; the "
               f"autotuner before them rasterises nothing); last descent {info.tolist()}", flush=True)
         ctx.close()
