@@ -425,18 +425,18 @@ __global__ __launch_bounds__(256) void k_relax_slot(SlotArgs a)
             const int xs = strip * VW - 2 * S;
             if (corr) {
                 if (check)
-                    stream_tile<float, S, true, PAIR, true, true>(src, dst, a.mask, om, a.r32, a.nx, a.ny, a.pitch,
-                                                                  xs, ybeg, yend, &m, &mr);
+                    stream_tile<float, S, true, PAIR, true>(src, dst, a.mask, om, a.r32, a.nx, a.ny, a.pitch,
+                                                            xs, ybeg, yend, &m, &mr);
                 else
-                    stream_tile<float, S, true, PAIR, true, false>(src, dst, a.mask, om, a.r32, a.nx, a.ny, a.pitch,
-                                                                   xs, ybeg, yend);
+                    stream_tile<float, S, true, PAIR, false>(src, dst, a.mask, om, a.r32, a.nx, a.ny, a.pitch,
+                                                             xs, ybeg, yend);
             } else {
                 if (check)
-                    stream_tile<float, S, false, PAIR, true, true>(src, dst, a.mask, om, nullptr, a.nx, a.ny,
-                                                                   a.pitch, xs, ybeg, yend, &m, &mr);
+                    stream_tile<float, S, false, PAIR, true>(src, dst, a.mask, om, nullptr, a.nx, a.ny,
+                                                             a.pitch, xs, ybeg, yend, &m, &mr);
                 else
-                    stream_tile<float, S, false, PAIR, true, false>(src, dst, a.mask, om, nullptr, a.nx, a.ny,
-                                                                    a.pitch, xs, ybeg, yend);
+                    stream_tile<float, S, false, PAIR, false>(src, dst, a.mask, om, nullptr, a.nx, a.ny,
+                                                              a.pitch, xs, ybeg, yend);
             }
         }
         // a pass that does not check decides nothing: the next slot derives

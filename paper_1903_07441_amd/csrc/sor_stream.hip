@@ -18,8 +18,8 @@
 // adjacent lane through wave-wide DPP shifts (no LDS traffic).  The row loop
 // has no per-row branches (its trip count is padded to whole windows, halo
 // lanes store out of range) and is fenced so that each prefetch stays in its
-// row step: the compiler can then keep the prefetch queue in fixed registers
-// and never has to wait for a load in flight before the window comes round.  Each
+// row step; rows live in a register ring of two windows, so no value moves
+// between registers and no row step waits for a load younger than a window.  Each
 // half-sweep invalidates one column at each edge of the strip, so S lanes on
 // each side are halo and 128 - 4S columns are written; the rows of a tile are
 // likewise extended by 2S halo rows above and below.  Reads come from `src`
@@ -47,8 +47,8 @@ __global__ __launch_bounds__(256) void k_sor_stream(const T *__restrict__ src, T
     if (tile >= tiles) return;  // whole wave
     const int strip = tile % strips, seg = tile / strips;
     const int ybeg = seg * RH;
-    stream_tile<T, S, RHS, PAIR, true>(src, dst, wsrc, omega, f, nx, ny, pitch, strip * VW - 2 * S, ybeg,
-                                       min(ybeg + RH, ny));
+    stream_tile<T, S, RHS, PAIR>(src, dst, static_cast<const uint8_t *>(wsrc), omega, f, nx, ny, pitch,
+                                 strip * VW - 2 * S, ybeg, min(ybeg + RH, ny));
 }
 
 // Batched form: the tiles of many grids in one launch.  Grid g's arrays start

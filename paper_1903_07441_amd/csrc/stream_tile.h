@@ -115,16 +115,24 @@ __device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc
 }
 
 // ---- streamed temporal-blocked red-black SOR ----------------------------
-// Rows are prefetched one window (NW rows) ahead into a register queue, so a
-// load has NW row-steps of arithmetic to arrive.  Cells outside the grid are
-// zeroed with a fixed-cell factor when they are taken from the queue.
 // One wave relaxes one tile: output columns [x0 + 2S, x0 + 128 - 2S) and
 // rows [ybeg, yend) of a grid; x0 and ybeg are even, all tile values are
-// wave-uniform.  PAIR tiles move each lane's two columns in one access (three
-// memory operations per row instead of six), which keeps a whole window of
-// prefetches within the hardware's count of outstanding vector memory
-// operations, so no row step ever waits for the loads of the rows after it.
-// MASK: wsrc is the one-byte free mask (else the factor map of T).
+// wave-uniform.  wsrc is the one-byte free mask (1 on FREE cells, else 0): a
+// FREE cell takes the factor omega, any other cell 0 (it is rewritten
+// unchanged).  PAIR tiles move each
+// lane's two columns in one access (three memory operations per row instead
+// of six), which keeps a whole window of prefetches within the hardware's
+// count of outstanding vector memory operations.
+//
+// Registers.  The pipeline needs NW = 2S + 2 rows at a time (the rows its
+// stages touch and the row the last stage finishes), and each row is fetched
+// NW row steps before it enters the pipeline.  Rows therefore live in a ring
+// of 2 NW register slots: row t sits in slot t mod 2NW from its fetch to its
+// last use, and the fetch of row t + NW refills the slot row t - NW has just
+// left.  The loop body covers one turn of the ring, so every slot is a fixed
+// register across iterations: no value is copied at the back edge, and no
+// row step waits for a load younger than NW row steps.  Cells outside the
+// grid read as zeros with factor 0, straight from the out-of-range loads.
 //
 // CHECK: the pass also measures the residual of its INPUT field, in FP64:
 // r = ((E + W) + (S + N)) / 4 (+ f) - c over the FREE cells of its output
@@ -138,14 +146,15 @@ __device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc
 __device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
 __device__ __forceinline__ float nan_maxf(float a, float b) { return (b > a || b != b) ? b : a; }
 
-template <typename T, int S, bool RHS, bool PAIR, bool MASK, bool CHECK = false>
+template <typename T, int S, bool RHS, bool PAIR, bool CHECK = false>
 __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__restrict__ dst,
-                                            const void *__restrict__ wsrc, T omega,
+                                            const uint8_t *__restrict__ wsrc, T omega,
                                             const T *__restrict__ f, int nx, int ny, int pitch,
                                             int x0, int ybeg, int yend, double *rmax = nullptr,
                                             float *rrel = nullptr)
 {
-    constexpr int NW = 2 * S + 2;      // rolling window of rows (even)
+    constexpr int NW = 2 * S + 2;      // rows the pipeline holds (even)
+    constexpr int NR = 2 * NW;         // ring slots
     const int lane = threadIdx.x & (kWave - 1);
     const int r0 = ybeg - 2 * S;                   // first row streamed (even)
     const int T_rows = (yend - ybeg) + 4 * S;
@@ -159,9 +168,7 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     const uint32_t outc = (uint32_t)(yend - ybeg - 1) * (uint32_t)pitch + (uint32_t)nx;
     const size_t base = (size_t)lo * pitch;
     const __amdgpu_buffer_rsrc_t rs = rsrc(src + base, cells * sizeof(T));
-    const __amdgpu_buffer_rsrc_t rw =
-        MASK ? rsrc(static_cast<const uint8_t *>(wsrc) + base, cells)
-             : rsrc(static_cast<const T *>(wsrc) + base, cells * sizeof(T));
+    const __amdgpu_buffer_rsrc_t rw = rsrc(wsrc + base, cells);
     const __amdgpu_buffer_rsrc_t rf = rsrc(RHS ? f + base : src + base, cells * sizeof(T));
     const __amdgpu_buffer_rsrc_t rd = rsrc(dst + (size_t)ybeg * pitch, outc * sizeof(T));
     // per-lane constants: a column outside the grid gets an out-of-range
@@ -180,47 +187,42 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     const int vrow0 = (r0 - lo) * (int)rowb, mrow0 = (r0 - lo) * pitch;
     const int orow0 = (r0 - 2 * S - ybeg) * (int)rowb;
 
-    T qv0[NW], qv1[NW], qw0[NW], qw1[NW], qf0[NW], qf1[NW];
-    uint32_t qm0[NW], qm1[NW];
+    // ring: the two columns of a row (P0 = column 2 lane, P1 = 2 lane + 1),
+    // its raw mask bytes and, with a source term, its f values
+    T P0[NR], P1[NR], F0[NR], F1[NR];
+    uint32_t M0[NR], M1[NR];
+    // factors of the rows in the pipeline, by row mod NW (red, black)
+    T wR[NW], wB[NW];
     auto fetch = [&](int slot, int t) {
         const uint32_t vo = (uint32_t)(vrow0 + t * (int)rowb), mo = (uint32_t)(mrow0 + t * pitch);
-        if constexpr (MASK) {
-            if constexpr (PAIR) {
-                qm0[slot] = __builtin_amdgcn_raw_buffer_load_b16(rw, (int)xm0, (int)mo, 0);
-            } else {
-                qm0[slot] = __builtin_amdgcn_raw_buffer_load_b8(rw, (int)xm0, (int)mo, 0);
-                qm1[slot] = __builtin_amdgcn_raw_buffer_load_b8(rw, (int)xm1, (int)mo, 0);
-            }
-        }
         if constexpr (PAIR) {
+            M0[slot] = __builtin_amdgcn_raw_buffer_load_b16(rw, (int)xm0, (int)mo, 0);
             const Pair<T> v = bload2((T *)nullptr, rs, xb0, vo);
-            qv0[slot] = v.a;
-            qv1[slot] = v.b;
-            if constexpr (!MASK) {
-                const Pair<T> w = bload2((T *)nullptr, rw, xb0, vo);
-                qw0[slot] = w.a;
-                qw1[slot] = w.b;
-            }
+            P0[slot] = v.a;
+            P1[slot] = v.b;
             if (RHS) {
                 const Pair<T> h = bload2((T *)nullptr, rf, xb0, vo);
-                qf0[slot] = h.a;
-                qf1[slot] = h.b;
+                F0[slot] = h.a;
+                F1[slot] = h.b;
             }
         } else {
-            qv0[slot] = bload((T *)nullptr, rs, xb0, vo);
-            qv1[slot] = bload((T *)nullptr, rs, xb1, vo);
-            if constexpr (!MASK) {
-                qw0[slot] = bload((T *)nullptr, rw, xb0, vo);
-                qw1[slot] = bload((T *)nullptr, rw, xb1, vo);
-            }
+            M0[slot] = __builtin_amdgcn_raw_buffer_load_b8(rw, (int)xm0, (int)mo, 0);
+            M1[slot] = __builtin_amdgcn_raw_buffer_load_b8(rw, (int)xm1, (int)mo, 0);
+            P0[slot] = bload((T *)nullptr, rs, xb0, vo);
+            P1[slot] = bload((T *)nullptr, rs, xb1, vo);
             if (RHS) {
-                qf0[slot] = bload((T *)nullptr, rf, xb0, vo);
-                qf1[slot] = bload((T *)nullptr, rf, xb1, vo);
+                F0[slot] = bload((T *)nullptr, rf, xb0, vo);
+                F1[slot] = bload((T *)nullptr, rf, xb1, vo);
             }
         }
     };
+    // red and black cells of the row in ring slot s (red is the first
+    // column on even rows; r0 is even, so a row's parity is its slot's)
+    auto red = [&](int s) -> T & { return (s & 1) == 0 ? P0[s] : P1[s]; };
+    auto blk = [&](int s) -> T & { return (s & 1) == 0 ? P1[s] : P0[s]; };
+    auto fred = [&](int s) -> T { return (s & 1) == 0 ? F0[s] : F1[s]; };
+    auto fblk = [&](int s) -> T { return (s & 1) == 0 ? F1[s] : F0[s]; };
 
-    T R[NW], B[NW], wR[NW], wB[NW], fR[NW], fB[NW];
     // CHECK: loaded values of the row above the checked one (columns 2 lane
     // and 2 lane + 1), and the running maxima
     T upa = T(0), upb = T(0);
@@ -228,124 +230,136 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     float crel = 0.0f;
     // rows t - 1 checked at row step t: t - 1 in [ybeg - r0, yend - r0)
     const int tchk0 = ybeg - r0 + 1, tchk1 = yend - r0 + 1;
-    // the first window is fetched in slot order, so that slot 0's loads are
-    // the oldest in flight when the loop starts, as on every later pass
+    // rows before the first streamed one are zeros with factor 0; the first
+    // window is fetched in slot order, so that slot 0's loads are the oldest
+    // in flight when the loop starts
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        P0[i] = P1[i] = F0[i] = F1[i] = T(0);
+        M0[i] = M1[i] = 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < NW; ++i) wR[i] = wB[i] = T(0);
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
-        R[i] = B[i] = wR[i] = wB[i] = fR[i] = fB[i] = T(0);
-        qf0[i] = qf1[i] = T(0);
         fetch(i, i);
         __builtin_amdgcn_sched_barrier(0);
     }
 
-    // the trip count is padded to whole windows so that the unrolled body
-    // has no per-row branches: fetches are unconditional (rows past the grid
-    // read zeros) and rows past the tile are computed but never stored
-    const int T_pad = ((T_rows + NW - 1) / NW) * NW;
-    for (int base = 0; base < T_pad; base += NW) {
-#pragma unroll
-        for (int u = 0; u < NW; ++u) {
-            const int t = base + u;
-            const T v0 = qv0[u], v1 = qv1[u];
-            T w0, w1;
-            if constexpr (!MASK) {
-                w0 = qw0[u];
-                w1 = qw1[u];
-            } else if constexpr (PAIR) {
-                w0 = (qm0[u] & 0xffu) ? omega : T(0);
-                w1 = (qm0[u] >> 8) ? omega : T(0);
+    // One row step: row t (ring slot u, pipeline index u mod NW) enters the
+    // pipeline, row t + NW is fetched, the 2S stages advance and row t - 2S
+    // is stored.  u is a constant wherever the step is inlined.
+    auto step = [&](const int u, const int t, const bool prefetch) __attribute__((always_inline)) {
+        const int uw = u % NW;
+        {
+            // factor = omega x mask byte (0 or 1): exact, and free of the
+            // compare-and-select hazard
+            const uint32_t m0 = M0[u] & 0xffu, m1 = PAIR ? (M0[u] >> 8) & 0xffu : M1[u] & 0xffu;
+            const T w0 = omega * (T)(float)m0, w1 = omega * (T)(float)m1;
+            if ((u & 1) == 0) {
+                wR[uw] = w0;
+                wB[uw] = w1;
             } else {
-                w0 = qm0[u] ? omega : T(0);
-                w1 = qm1[u] ? omega : T(0);
+                wR[uw] = w1;
+                wB[uw] = w0;
             }
-            T f0 = T(0), f1 = T(0);
-            if (RHS) {
-                f0 = qf0[u];
-                f1 = qf1[u];
-            }
-            // the slot is refilled only after its values are taken, so the
-            // queue keeps fixed registers across iterations
-            __builtin_amdgcn_sched_barrier(0);
-            fetch(u, t + NW);
-            if ((u & 1) == 0) {  // even row: red = first column
-                R[u] = v0; B[u] = v1; wR[u] = w0; wB[u] = w1; fR[u] = f0; fB[u] = f1;
-            } else {
-                R[u] = v1; B[u] = v0; wR[u] = w1; wB[u] = w0; fR[u] = f1; fB[u] = f0;
-            }
-            if constexpr (CHECK) {
-                // residual of row t - 1 (slot um, not yet touched by any
-                // stage) from the kept row t - 2 and the new row t (slot u)
-                const int um = (u + NW - 1) % NW;
-                const bool ev = (um & 1) == 0;
-                const T ca = ev ? R[um] : B[um], cb = ev ? B[um] : R[um];
-                const T wa = ev ? wR[um] : wB[um], wb = ev ? wB[um] : wR[um];
-                const T dna = (u & 1) == 0 ? R[u] : B[u], dnb = (u & 1) == 0 ? B[u] : R[u];
-                const double ea = (double)cb, wwa = (double)shr1(cb);
-                const double eb = (double)shl1(ca), wwb = (double)ca;
-                double ga = ((ea + wwa) + ((double)dna + (double)upa)) * 0.25;
-                double gb = ((eb + wwb) + ((double)dnb + (double)upb)) * 0.25;
-                if constexpr (RHS) {
-                    ga = ga + (double)(ev ? fR[um] : fB[um]);
-                    gb = gb + (double)(ev ? fB[um] : fR[um]);
-                }
-                const double ra = ga - (double)ca, rb = gb - (double)cb;
-                const bool rowin = t >= tchk0 && t < tchk1;
-                const bool oka = rowin && writer && wa != T(0), okb = rowin && writer && wb != T(0);
-                cmax = nan_max(cmax, oka ? fabs(ra) : 0.0);
-                cmax = nan_max(cmax, okb ? fabs(rb) : 0.0);
-                const float aa = fabsf((float)ca), ab = fabsf((float)cb);
-                const float qa = fabsf((float)ra) * __builtin_amdgcn_rcpf(aa);
-                const float qb = fabsf((float)rb) * __builtin_amdgcn_rcpf(ab);
-                crel = nan_maxf(crel, oka && aa >= 1e-30f ? qa : 0.0f);
-                crel = nan_maxf(crel, okb && ab >= 1e-30f ? qb : 0.0f);
-                upa = ca;
-                upb = cb;
-            }
-            // stage k: half-sweep k of the pass (red for even k) at row
-            // y - 1 - k (slot s).  Its E, W and N (row above, slot sm)
-            // neighbours were finished in earlier row steps, so their sums
-            // are formed first for all stages; S (row below, slot sp) is the
-            // value stage k - 1 produces in this row step and is added last.
-            T ewn[2 * S];
-#pragma unroll
-            for (int k = 0; k < 2 * S; ++k) {
-                const int s = (u - 1 - k + 4 * NW) % NW;
-                const int sm = (s + NW - 1) % NW;
-                if ((k & 1) == 0) {
-                    const T b = B[s];
-                    ewn[k] = ((s & 1) == 0 ? b + shr1(b) : shl1(b) + b) + B[sm];
-                } else {
-                    const T r = R[s];
-                    ewn[k] = ((s & 1) == 0 ? shl1(r) + r : r + shr1(r)) + R[sm];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 2 * S; ++k) {
-                const int s = (u - 1 - k + 4 * NW) % NW;
-                const int sp = (s + 1) % NW;
-                if ((k & 1) == 0)
-                    R[s] = upd<RHS>(R[s], ewn[k], B[sp], wR[s], fR[s]);
-                else
-                    B[s] = upd<RHS>(B[s], ewn[k], R[sp], wB[s], fB[s]);
-            }
-            // the row finished by this step (row y - 2S) is stored; rows
-            // outside [ybeg, yend) fall outside the write resource
-            {
-                const int s = (u - 2 * S + 4 * NW) % NW;
-                const uint32_t ro = (uint32_t)(orow0 + t * (int)rowb);
-                const T o0 = (s & 1) == 0 ? R[s] : B[s];
-                const T o1 = (s & 1) == 0 ? B[s] : R[s];
-                if constexpr (PAIR) {
-                    bstore2(o0, o1, rd, so0, ro);
-                } else {
-                    bstore(o0, rd, so0, ro);
-                    bstore(o1, rd, so1, ro);
-                }
-            }
-            // keep this row's prefetch in this row step: without the fence
-            // the scheduler sinks every prefetch of the window to its end
-            __builtin_amdgcn_sched_barrier(0);
         }
+        if constexpr (CHECK) {
+            // residual of row t - 1 (slot um, not yet touched by any
+            // stage) from the kept row t - 2 and the new row t (slot u)
+            const int um = (u + NR - 1) % NR, uwm = (uw + NW - 1) % NW;
+            const T ca = P0[um], cb = P1[um];
+            const bool ev = (um & 1) == 0;
+            const T wa = ev ? wR[uwm] : wB[uwm], wb = ev ? wB[uwm] : wR[uwm];
+            const T dna = P0[u], dnb = P1[u];
+            const double ea = (double)cb, wwa = (double)shr1(cb);
+            const double eb = (double)shl1(ca), wwb = (double)ca;
+            double ga = ((ea + wwa) + ((double)dna + (double)upa)) * 0.25;
+            double gb = ((eb + wwb) + ((double)dnb + (double)upb)) * 0.25;
+            if constexpr (RHS) {
+                ga = ga + (double)F0[um];
+                gb = gb + (double)F1[um];
+            }
+            const double ra = ga - (double)ca, rb = gb - (double)cb;
+            const bool rowin = t >= tchk0 && t < tchk1;
+            const bool oka = rowin && writer && wa != T(0), okb = rowin && writer && wb != T(0);
+            cmax = nan_max(cmax, oka ? fabs(ra) : 0.0);
+            cmax = nan_max(cmax, okb ? fabs(rb) : 0.0);
+            const float aa = fabsf((float)ca), ab = fabsf((float)cb);
+            const float qa = fabsf((float)ra) * __builtin_amdgcn_rcpf(aa);
+            const float qb = fabsf((float)rb) * __builtin_amdgcn_rcpf(ab);
+            crel = nan_maxf(crel, oka && aa >= 1e-30f ? qa : 0.0f);
+            crel = nan_maxf(crel, okb && ab >= 1e-30f ? qb : 0.0f);
+            upa = ca;
+            upb = cb;
+        }
+        // row t + NW goes to the slot row t - NW left at the last step
+        __builtin_amdgcn_sched_barrier(0);
+        if (prefetch) fetch((u + NW) % NR, t + NW);
+        // stage k: half-sweep k of the pass (red for even k) at row
+        // t - 1 - k (slot s).  Its E, W and N (row above, slot sm)
+        // neighbours were finished in earlier row steps; S (row below, slot
+        // sp) is the value stage k - 1 produces in this row step and is
+        // added last, so the chain through the stages is three operations
+        // deep per stage.
+        // E + W + N of stage k (red cells for even k, black for odd)
+        auto ewn = [&](const int k) __attribute__((always_inline)) -> T {
+            const int s = (u - 1 - k + 2 * NR) % NR;
+            const int sm = (s + NR - 1) % NR;
+            if ((k & 1) == 0) {
+                const T b = blk(s);
+                return ((s & 1) == 0 ? shr1(b) + b : shl1(b) + b) + blk(sm);
+            }
+            const T r = red(s);
+            return ((s & 1) == 0 ? shl1(r) + r : shr1(r) + r) + red(sm);
+        };
+        // each stage's sum is formed one stage ahead of its update, which
+        // gives the scheduler two independent chains to interleave
+        T e_next = ewn(0);
+#pragma unroll
+        for (int k = 0; k < 2 * S; ++k) {
+            const int s = (u - 1 - k + 2 * NR) % NR;
+            const int sp = (s + 1) % NR;
+            const int sw = (uw - 1 - k + 2 * NW) % NW;
+            const T e = e_next;
+            if (k + 1 < 2 * S) e_next = ewn(k + 1);
+            if ((k & 1) == 0)
+                red(s) = upd<RHS>(red(s), e, blk(sp), wR[sw], fred(s));
+            else
+                blk(s) = upd<RHS>(blk(s), e, red(sp), wB[sw], fblk(s));
+        }
+        // the row finished by this step (row t - 2S) is stored; rows
+        // outside [ybeg, yend) fall outside the write resource
+        {
+            const int s = (u - 2 * S + 2 * NR) % NR;
+            const uint32_t ro = (uint32_t)(orow0 + t * (int)rowb);
+            if constexpr (PAIR) {
+                bstore2(P0[s], P1[s], rd, so0, ro);
+            } else {
+                bstore(P0[s], rd, so0, ro);
+                bstore(P1[s], rd, so1, ro);
+            }
+        }
+        // keep this row's prefetch in this row step: without the fence
+        // the scheduler sinks every prefetch of the window to its end
+        __builtin_amdgcn_sched_barrier(0);
+    };
+
+    // The trip count is padded to whole windows so that the unrolled body
+    // has no per-row branches: fetches are unconditional (rows past the grid
+    // read zeros) and rows past the tile are computed but never stored.  The
+    // loop body is one turn of the ring (two windows); an odd window count
+    // ends with one more window, which fetches nothing.
+    const int windows = (T_rows + NW - 1) / NW;
+    const int T_turns = (windows / 2) * NR;
+    int tb = 0;
+    for (; tb < T_turns; tb += NR) {
+#pragma unroll
+        for (int u = 0; u < NR; ++u) step(u, tb + u, true);
+    }
+    if (windows & 1) {
+#pragma unroll
+        for (int u = 0; u < NW; ++u) step(u, tb + u, false);
     }
     if constexpr (CHECK) {
         *rmax = nan_max(*rmax, cmax);
