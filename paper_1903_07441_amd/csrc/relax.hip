@@ -28,7 +28,10 @@ __global__ __launch_bounds__(256) void k_sweep_color(const uint8_t *__restrict__
     const T s = y + 1 < ny ? psi[i + pitch] : T(0);
     const T n = y > 0 ? psi[i - pitch] : T(0);
     const T om = cls[i] == TWG_CELL_FREE ? omega : T(0);
-    psi[i] = upd<RHS>(psi[i], (e + w) + n, s, om, RHS ? f[i] : T(0));
+    if constexpr (RHS)
+        psi[i] = upd_src(psi[i], (e + w) + n, s, src_const(om, f[i]));
+    else
+        psi[i] = upd(psi[i], (e + w) + n, s, om);
 }
 
 // ---- residual, FP64 arithmetic ------------------------------------------

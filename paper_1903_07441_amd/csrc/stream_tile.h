@@ -191,8 +191,10 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     // its raw mask bytes and, with a source term, its f values
     T P0[NR], P1[NR], F0[NR], F1[NR];
     uint32_t M0[NR], M1[NR];
-    // factors of the rows in the pipeline, by row mod NW (red, black)
+    // factors of the rows in the pipeline, by row mod NW (red, black), and
+    // with a source term the update constants of update.h
     T wR[NW], wB[NW];
+    SrcConst<T> kR[NW], kB[NW];
     auto fetch = [&](int slot, int t) {
         const uint32_t vo = (uint32_t)(vrow0 + t * (int)rowb), mo = (uint32_t)(mrow0 + t * pitch);
         if constexpr (PAIR) {
@@ -220,8 +222,6 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     // column on even rows; r0 is even, so a row's parity is its slot's)
     auto red = [&](int s) -> T & { return (s & 1) == 0 ? P0[s] : P1[s]; };
     auto blk = [&](int s) -> T & { return (s & 1) == 0 ? P1[s] : P0[s]; };
-    auto fred = [&](int s) -> T { return (s & 1) == 0 ? F0[s] : F1[s]; };
-    auto fblk = [&](int s) -> T { return (s & 1) == 0 ? F1[s] : F0[s]; };
 
     // CHECK: loaded values of the row above the checked one (columns 2 lane
     // and 2 lane + 1), and the running maxima
@@ -256,12 +256,13 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
             // compare-and-select hazard
             const uint32_t m0 = M0[u] & 0xffu, m1 = PAIR ? (M0[u] >> 8) & 0xffu : M1[u] & 0xffu;
             const T w0 = omega * (T)(float)m0, w1 = omega * (T)(float)m1;
-            if ((u & 1) == 0) {
-                wR[uw] = w0;
-                wB[uw] = w1;
-            } else {
-                wR[uw] = w1;
-                wB[uw] = w0;
+            const bool ev = (u & 1) == 0;
+            wR[uw] = ev ? w0 : w1;
+            wB[uw] = ev ? w1 : w0;
+            if constexpr (RHS) {
+                const SrcConst<T> k0 = src_const(w0, F0[u]), k1 = src_const(w1, F1[u]);
+                kR[uw] = ev ? k0 : k1;
+                kB[uw] = ev ? k1 : k0;
             }
         }
         if constexpr (CHECK) {
@@ -323,10 +324,17 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
             const int sw = (uw - 1 - k + 2 * NW) % NW;
             const T e = e_next;
             if (k + 1 < 2 * S) e_next = ewn(k + 1);
-            if ((k & 1) == 0)
-                red(s) = upd<RHS>(red(s), e, blk(sp), wR[sw], fred(s));
-            else
-                blk(s) = upd<RHS>(blk(s), e, red(sp), wB[sw], fblk(s));
+            if constexpr (RHS) {
+                if ((k & 1) == 0)
+                    red(s) = upd_src(red(s), e, blk(sp), kR[sw]);
+                else
+                    blk(s) = upd_src(blk(s), e, red(sp), kB[sw]);
+            } else {
+                if ((k & 1) == 0)
+                    red(s) = upd(red(s), e, blk(sp), wR[sw]);
+                else
+                    blk(s) = upd(blk(s), e, red(sp), wB[sw]);
+            }
         }
         // the row finished by this step (row t - 2S) is stored; rows
         // outside [ybeg, yend) fall outside the write resource
