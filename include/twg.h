@@ -202,7 +202,7 @@ typedef struct {
     int32_t init;            /* HPF_INIT_* */
     int32_t polish;          /* 0: FP32 only; 1: FP64 defect correction (FP32 correction
                                 solves); 2: FP64 red-black SOR sweeps */
-    int32_t sweeps_per_pass; /* red-black sweeps per tile load (1, 2, 3, 4, 6, 8); 0 = tuned */
+    int32_t sweeps_per_pass; /* red-black sweeps per tile load (1 to 8); 0 = tuned */
     int32_t check_passes;    /* passes between residual checks; 0 = adaptive */
     int32_t rows_per_tile;   /* output rows per tile (even, >= 2); 0 = tuned */
     int32_t goal_x, goal_y;  /* goal cell of HPF_INIT_LINEAR (else unused) */
@@ -397,7 +397,7 @@ int32_t hpf_sweeps(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi, con
  * psi64, the update evaluated as fma(omega, fma(1/4, ((E + W) + N) + S,
  * -psi), psi) (N the row above, S the row below, each operation rounded
  * once), the expression the oracle's FP64 sweep evaluates, bit for bit.  tiled = 0: one launch per colour;
- * tiled = 1: sweeps_per_pass (1, 2, 3, 4, 6 or 8; 0 = the autotuned FP64
+ * tiled = 1: sweeps_per_pass (1 to 8; 0 = the autotuned FP64
  * tiling of this grid size, else 4) sweeps per tile load, bit-identical.  Asynchronous.  Errors: TWG_EINVAL. */
 int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64, double omega,
                      int32_t sweeps, int32_t tiled, int32_t sweeps_per_pass, void *stream);
@@ -406,10 +406,12 @@ int32_t hpf_sweeps64(twg_ctx *ctx, twg_grid g, const uint8_t *cls, double *psi64
  * and remember, for grids of this exact size, the fastest tiling and an SOR
  * factor; later hpf_relax calls on this context with sweeps_per_pass = 0
  * and omega = 0 use them.  Tilings: sweeps per tile load S in
- * {1, 2, 3, 4, 6, 8} x output rows per tile RH in {8, 16, 32, 64, 128} plus,
+ * 1 to 8 x output rows per tile RH in {8, 16, 32, 64, 128} plus,
  * for k = 1..4, the smallest height whose tile count (one wave per tile) fits
  * k rounds of the device's SIMDs; each timed with HIP events over repeated
- * passes on context scratch.  SOR factors:
+ * passes on context scratch, with and without a source term, and ranked by
+ * the sum of the two times per sweep (the correction solves of a polish run
+ * the passes with a source).  SOR factors:
  * omega = 2 / (1 + c sin(pi / (n + 1))), n = max(nx, ny), c in
  * {1, 1.4, 2, 2.4, 2.8, 3, 3.3, 3.6, 4, 4.5, 5, 6} (obstacles shrink the
  * effective domain, so the best factor is below the open-rectangle one):
@@ -449,7 +451,7 @@ int32_t hpf_autotune_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids
  * hpf_autotune would remember: FP32 sweeps per tile load S and rows per tile
  * RH, SOR factor omega (0 = the open-rectangle optimum), FP64 tiling S64 and
  * RH64 (S64 = 0: the FP64 default), and no start phase.  Host only.  Errors: TWG_EINVAL (S or
- * S64 not in {1, 2, 3, 4, 6, 8}, RH < 2, omega outside [0, 2)). */
+ * S64 not in 1 to 8, RH < 2, omega outside [0, 2)). */
 int32_t hpf_set_tiling(twg_ctx *ctx, int32_t nx, int32_t ny, int32_t S, int32_t RH, float omega, int32_t S64,
                        int32_t RH64);
 

@@ -431,7 +431,9 @@ int launch_batch_slot(const BatchArgs &a, int max_tiles, bool pair, hipStream_t 
         TWG_BSLOT_CASE(2)
         TWG_BSLOT_CASE(3)
         TWG_BSLOT_CASE(4)
+        TWG_BSLOT_CASE(5)
         TWG_BSLOT_CASE(6)
+        TWG_BSLOT_CASE(7)
         TWG_BSLOT_CASE(8)
     default: return TWG_EUNSUPPORTED;
     }

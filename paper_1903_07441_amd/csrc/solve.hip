@@ -573,7 +573,9 @@ int launch_relax_slot(const SlotArgs &a, int S, hipStream_t st)
         TWG_SLOT_CASE(2)
         TWG_SLOT_CASE(3)
         TWG_SLOT_CASE(4)
+        TWG_SLOT_CASE(5)
         TWG_SLOT_CASE(6)
+        TWG_SLOT_CASE(7)
         TWG_SLOT_CASE(8)
     default: return TWG_EUNSUPPORTED;
     }

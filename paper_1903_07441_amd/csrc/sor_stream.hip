@@ -79,7 +79,9 @@ int launch_stream(const T *src, T *dst, const void *wsrc, T omega, const T *f, i
         TWG_STREAM_CASE(2)
         TWG_STREAM_CASE(3)
         TWG_STREAM_CASE(4)
+        TWG_STREAM_CASE(5)
         TWG_STREAM_CASE(6)
+        TWG_STREAM_CASE(7)
         TWG_STREAM_CASE(8)
     default: return TWG_EUNSUPPORTED;
     }
@@ -96,7 +98,7 @@ int stream_rows_cap(int pitch, int elem_bytes, int S)
     return (int)std::max(2LL, (rows - 4 * S - 2) & ~1LL);
 }
 
-bool stream_depth_supported(int S) { return S == 1 || S == 2 || S == 3 || S == 4 || S == 6 || S == 8; }
+bool stream_depth_supported(int S) { return S >= 1 && S <= 8; }
 
 Geometry stream_geometry(int nx, int ny, int S, int RH)
 {

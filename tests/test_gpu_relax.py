@@ -36,7 +36,7 @@ def to_dev(a, pitch=None, dtype=None):
 
 @pytest.mark.parametrize("nx,ny,pitch", [(64, 64, 64), (300, 211, 320), (129, 1000, 130),
                                          (1, 7, 1), (7, 1, 8), (2047, 33, 2048)])
-@pytest.mark.parametrize("S", [1, 2, 3, 4, 6, 8])
+@pytest.mark.parametrize("S", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_tiled_equals_untiled(ctx, nx, ny, pitch, S):
     # P12: S sweeps per tile load give the same bits as one launch per colour.
     rng = np.random.default_rng(nx * 7 + ny + S)
@@ -54,7 +54,7 @@ def test_tiled_equals_untiled(ctx, nx, ny, pitch, S):
     assert not torch.equal(a, to_dev(psi0, pitch))
 
 
-@pytest.mark.parametrize("S", [1, 4, 8])
+@pytest.mark.parametrize("S", [1, 4, 5, 8])
 @pytest.mark.parametrize("nx", [257, 256])  # odd: per-column access; even: paired columns
 def test_tiled_equals_untiled_with_source(ctx, S, nx):
     rng = np.random.default_rng(S)
@@ -251,7 +251,7 @@ def test_relax_not_converged_and_errors(ctx):
         ctx.relax(c, psi, None, omega=2.5)
     assert e.value.code == twg.EINVAL
     with pytest.raises(twg.TwgError) as e:
-        ctx.relax(c, psi, None, sweeps_per_pass=5)
+        ctx.relax(c, psi, None, sweeps_per_pass=9)
     assert e.value.code == twg.EINVAL
 
 
@@ -288,7 +288,7 @@ def test_relax_checked_every_pass_stops_at_the_first_converged_pass(ctx, orc):
 
 
 @pytest.mark.parametrize("nx,ny,pitch", [(96, 80, 96), (301, 129, 320), (3, 40, 4)])
-@pytest.mark.parametrize("S", [1, 3, 4])
+@pytest.mark.parametrize("S", [1, 3, 4, 5, 7])
 def test_fp64_sweep_bit_exact_vs_oracle(ctx, orc, nx, ny, pitch, S):
     # P11: the GPU's FP64 red-black sweep equals the oracle's FP64 sweep bit for bit
     rng = np.random.default_rng(nx + S)
@@ -351,7 +351,7 @@ def test_autotune_factors_converge(orc):
         c = to_dev(cls)
         tune = ctx.autotune(c)
         print(f"autotune {tune}", flush=True)
-        assert tune["S"] in (1, 2, 3, 4, 6, 8) and tune["S64"] in (2, 3, 4, 6, 8)
+        assert 1 <= tune["S"] <= 8 and 2 <= tune["S64"] <= 8
         assert tune["RH"] >= 2 and tune["RH"] % 2 == 0
         assert 1.9 < tune["omega"] < 2.0 and 1.9 < tune["omega_dc"] < 2.0
         ny, nx = cls.shape
