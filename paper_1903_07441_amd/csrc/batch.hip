@@ -297,8 +297,8 @@ __global__ __launch_bounds__(256, 3) void k_batch_slot(BatchArgs a)
             if (check) {
                 double rm = 0.0;
                 float rr = 0.0f;
-                stream_tile<float, S, false, PAIR, true>(src, dst, m, g.omega, nullptr, g.nx, g.ny, g.pitch,
-                                                         xs, ybeg, yend, &rm, &rr);
+                stream_tile<float, S, false, PAIR, true, kStoreBack>(src, dst, m, g.omega, nullptr, g.nx, g.ny,
+                                                                     g.pitch, xs, ybeg, yend, &rm, &rr);
                 for (int o = 32; o > 0; o >>= 1) {
                     rm = nan_max(rm, __shfl_xor(rm, o));
                     rr = nan_maxf(rr, __shfl_xor(rr, o));
@@ -309,8 +309,8 @@ __global__ __launch_bounds__(256, 3) void k_batch_slot(BatchArgs a)
                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
             } else {
-                stream_tile<float, S, false, PAIR, false>(src, dst, m, g.omega, nullptr, g.nx, g.ny, g.pitch,
-                                                          xs, ybeg, yend);
+                stream_tile<float, S, false, PAIR, false, kStoreBack>(src, dst, m, g.omega, nullptr, g.nx,
+                                                                      g.ny, g.pitch, xs, ybeg, yend);
             }
         }
     } else {

@@ -70,24 +70,29 @@ __device__ __forceinline__ double bload(double *, __amdgpu_buffer_rsrc_t r, uint
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
 }
-// Field rows are stored with the sc1 cache policy: the L2 writes them
-// through at agent scope, so its lines are clean when the kernel ends and the
-// release between two passes has nothing to write back.  Measured at
-// 2048 x 2048: the gap from one pass's last wave to the next pass's first
-// falls from 2.2 to 0.9 us, while a wave's own time grows by 0.15 us.
-constexpr int kStoreThrough = 16;
+// Store cache policy of the field rows.  kStoreThrough (sc1): the L2 writes
+// them through at agent scope, so its lines are clean when the kernel ends
+// and the release between two passes has nothing to write back.  Measured
+// on one 2048 x 2048 grid (one wave per SIMD): the gap from one pass's last
+// wave to the next pass's first falls from 2.2 to 0.9 us, while a wave's own
+// time grows by 0.15 us.  A batch pass (several waves per SIMD, long passes)
+// is faster with the default write-back policy (kStoreBack): 44.8 against
+// 47.4 ms for 256 grids.
+constexpr int kStoreThrough = 16, kStoreBack = 0;
 
 // the 64- and 128-bit buffer builtins take and return these (GCC-style)
 // vector types; they are only ever bit-cast or subscripted
 typedef uint32_t bv2 __attribute__((__vector_size__(8)));
 typedef uint32_t bv4 __attribute__((__vector_size__(16)));
+template <int AUX>
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)vo, (int)so, kStoreThrough);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)vo, (int)so, AUX);
 }
+template <int AUX>
 __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
 {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bv2, v), r, (int)vo, (int)so, kStoreThrough);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bv2, v), r, (int)vo, (int)so, AUX);
 }
 
 // two adjacent elements in one access (PAIR tiles: even pitch, even nx and
@@ -108,17 +113,19 @@ __device__ __forceinline__ Pair<double> bload2(double *, __amdgpu_buffer_rsrc_t 
     const D2 v = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
     return {v.a, v.b};
 }
+template <int AUX>
 __device__ __forceinline__ void bstore2(float a, float b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
 {
     bv2 v;
     v[0] = __builtin_bit_cast(uint32_t, a);
     v[1] = __builtin_bit_cast(uint32_t, b);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)vo, (int)so, kStoreThrough);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)vo, (int)so, AUX);
 }
+template <int AUX>
 __device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
 {
     struct D2 { double a, b; };
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(bv4, D2{a, b}), r, (int)vo, (int)so, kStoreThrough);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(bv4, D2{a, b}), r, (int)vo, (int)so, AUX);
 }
 
 // ---- streamed temporal-blocked red-black SOR ----------------------------
@@ -153,7 +160,7 @@ __device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc
 __device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
 __device__ __forceinline__ float nan_maxf(float a, float b) { return (b > a || b != b) ? b : a; }
 
-template <typename T, int S, bool RHS, bool PAIR, bool CHECK = false>
+template <typename T, int S, bool RHS, bool PAIR, bool CHECK = false, int STORE = kStoreThrough>
 __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__restrict__ dst,
                                             const uint8_t *__restrict__ wsrc, T omega,
                                             const T *__restrict__ f, int nx, int ny, int pitch,
@@ -349,10 +356,10 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
             const int s = (u - 2 * S + 2 * NR) % NR;
             const uint32_t ro = (uint32_t)(orow0 + t * (int)rowb);
             if constexpr (PAIR) {
-                bstore2(P0[s], P1[s], rd, so0, ro);
+                bstore2<STORE>(P0[s], P1[s], rd, so0, ro);
             } else {
-                bstore(P0[s], rd, so0, ro);
-                bstore(P1[s], rd, so1, ro);
+                bstore<STORE>(P0[s], rd, so0, ro);
+                bstore<STORE>(P1[s], rd, so1, ro);
             }
         }
         // keep this row's prefetch in this row step: without the fence
