@@ -4,6 +4,9 @@
 // scheme.
 #pragma once
 
+#include <type_traits>
+#include <utility>
+
 #include "twg_internal.h"
 #include "update.h"
 
@@ -158,6 +161,15 @@ __device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc
 // evaluated with the hardware reciprocal: a diagnostic), both per lane; a
 // NaN residual propagates.
 __device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// f(integral_constant<int, U>) for U = 0, 1, ..., one inlined copy each: the
+// row loop's body is one of these, so it is unrolled whatever its size (a
+// rolled body would index the register ring at run time, i.e. in scratch)
+template <class F, int... U>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, U...>, F &&f)
+{
+    (f(std::integral_constant<int, U>{}), ...);
+}
 __device__ __forceinline__ float nan_maxf(float a, float b) { return (b > a || b != b) ? b : a; }
 
 template <typename T, int S, bool RHS, bool PAIR, bool CHECK = false, int STORE = kStoreThrough>
@@ -375,14 +387,12 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     const int windows = (T_rows + NW - 1) / NW;
     const int T_turns = (windows / 2) * NR;
     int tb = 0;
-    for (; tb < T_turns; tb += NR) {
-#pragma unroll
-        for (int u = 0; u < NR; ++u) step(u, tb + u, true);
-    }
-    if (windows & 1) {
-#pragma unroll
-        for (int u = 0; u < NW; ++u) step(u, tb + u, false);
-    }
+    for (; tb < T_turns; tb += NR)
+        static_for(std::make_integer_sequence<int, NR>{},
+                   [&](auto U) __attribute__((always_inline)) { step(decltype(U)::value, tb + U, true); });
+    if (windows & 1)
+        static_for(std::make_integer_sequence<int, NW>{},
+                   [&](auto U) __attribute__((always_inline)) { step(decltype(U)::value, tb + U, false); });
     if constexpr (CHECK) {
         *rmax = nan_max(*rmax, cmax);
         *rrel = nan_maxf(*rrel, crel);
