@@ -216,7 +216,11 @@ def run_loop(ctx, sc, steps, sigma=0.0, net=None, omega_warm=None, keep_first=0,
                 e_b.record()
                 torch.cuda.synchronize()
                 w_trials[wc] = e_a.elapsed_time(e_b)
-            omega_warm = min(w_trials, key=w_trials.get)
+            # another factor replaces the tuned one only when it wins
+            # clearly: its polish cost varies from step to step with the
+            # smooth error it leaves, which one step's trial cannot see
+            best = min(w_trials, key=w_trials.get)
+            omega_warm = best if w_trials[best] < 0.95 * w_trials[0.0] else 0.0
             a.psi.copy_(base)
             ev[0].record()  # the step's time starts after the trials
         w = 0.0 if k == 0 else (omega_warm or 0.0)
