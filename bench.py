@@ -581,6 +581,45 @@ def main():
                              "(radius 2-5), FP32 red-black SOR to residual 1e-6 with FP64 residuals"}
         log(f"batch: {batch}")
 
+        # many small grids: the tiled passes (the default) against the same
+        # batch with each grid solved whole in one workgroup's LDS
+        small_sides = (64, 96, 128, 160)
+        scs_s = [scenarios.scenario("batch", seed=4000 + k, side=small_sides[k % len(small_sides)])
+                 for k in range(1024)]
+        offs_s, off_s = [], 0
+        for b in scs_s:
+            offs_s.append(off_s)
+            off_s += b["nx"] * b["ny"]
+        scls = torch.empty(off_s, dtype=torch.uint8, device=dev)
+        spsi = torch.empty(off_s, dtype=torch.float32, device=dev)
+        for b, o in zip(scs_s, offs_s):
+            n_b = b["nx"] * b["ny"]
+            ctx.rasterize(b["nx"], b["ny"], b["robot"], b["goal"],
+                          torch.as_tensor(b["pos"], dtype=torch.float64, device=dev).contiguous(),
+                          torch.as_tensor(b["vel"], dtype=torch.float64, device=dev).contiguous(),
+                          torch.as_tensor(b["rad"], dtype=torch.float64, device=dev).contiguous(),
+                          W=b["W"], robot_speed=b["vr"], cls=scls[o:o + n_b].view(b["ny"], b["nx"]),
+                          want_ring=False)
+        sdescs = [(b["nx"], b["ny"], b["nx"], o) for b, o in zip(scs_s, offs_s)]
+        small = {"grids": len(scs_s), "sides": list(small_sides), "cells": off_s,
+                 "workload": "1024 grids, sides cycling over {64,96,128,160}, 10-200 moving discs (radius 2-5), "
+                             "FP32 red-black SOR to residual 1e-6 with FP64 residuals"}
+        for name, lds in (("tiled_passes", False), ("lds_worker", True)):
+            ctx.relax_batched(scls, spsi, sdescs, tol=1e-6, lds=lds)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                sst = ctx.relax_batched(scls, spsi, sdescs, tol=1e-6, lds=lds)
+            torch.cuda.synchronize()
+            ts = (time.perf_counter() - t0) / reps
+            small[name] = {"ms_per_batch": round(ts * 1e3, 3), "fields_per_s": round(len(scs_s) / ts, 1),
+                           "converged": sum(1 for x in sst if x["status"] == twg.OK),
+                           "sweeps_max": max(x["sweeps"] for x in sst)}
+        small["lds_worker_time_over_tiled"] = round(small["lds_worker"]["ms_per_batch"] /
+                                                    small["tiled_passes"]["ms_per_batch"], 3)
+        batch["small_grids"] = small
+        log(f"small-grid batch: {small}")
+
     # ---- CPU baseline: the oracle on the same step ----
     cpu = None
     if cpu_on:

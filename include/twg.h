@@ -321,9 +321,13 @@ int32_t hpf_relax_async_noalloc(twg_ctx *ctx, twg_grid g, const uint8_t *cls, fl
 
 typedef struct {
     int32_t nx, ny, pitch; /* as twg_grid */
-    int32_t reserved;
+    int32_t flags;  /* 0, or TWG_GRID_LDS */
     int64_t offset; /* element offset of this grid's arrays from the batch base pointers */
 } twg_grid_desc;
+
+/* twg_grid_desc.flags: solve the grid whole in one workgroup's LDS when it
+ * fits there, instead of by the tiled passes */
+#define TWG_GRID_LDS 1
 
 /* hpf_relax_batched -- hpf_relax (FP32 phase) for n independent grids of any
  * sizes at once (Eqs. 1-2 on every grid; section "GPU-Based Parallel
@@ -335,7 +339,15 @@ typedef struct {
  * stop rules (tolerance, sweep budget per grid, a stall at the FP32
  * rounding floor) -- and drops out of the launches at the check where it
  * stops.  Checks fall on passes that are multiples of 4 (so that grids share
- * them), or every params->check_passes passes.  The host never waits for a
+ * them), or every params->check_passes passes.  A grid whose descriptor
+ * sets TWG_GRID_LDS and whose field and free mask fit in one workgroup's LDS
+ * (5 bytes per cell: up to about 176 x 176 with 160 KiB of LDS) takes no part
+ * in the passes: one workgroup loads it, checks its FP64 residual every S
+ * sweeps and sweeps it in LDS until the same stop rules hold, and writes it
+ * back once, before the first pass.  Its field after N sweeps has the bits
+ * of N sweeps on the tiled path (its sweep count is a multiple of S).  On
+ * MI355X the tiled passes are faster even for grids of 64 to 160 cells a
+ * side (1024 such grids: 8.6 against 19.8 ms), so it is not the default.  The host never waits for a
  * residual: it only keeps launches queued (it reads the device's decisions
  * from pinned memory).  Sweeps per tile load and rows per tile come from
  * hpf_autotune_batched if it ran on this context, else from the
@@ -344,9 +356,9 @@ typedef struct {
  * autotuned factor, else its open-rectangle optimum.  init: HPF_INIT_KEEP,
  * HALF or ZERO; polish must be 0.  stats: host array of n entries, or NULL.
  * Blocking.  Returns TWG_OK when every grid converged, else
- * TWG_NOT_CONVERGED.  Errors: TWG_EINVAL (n < 1, NULL arrays, a bad grid or
- * offset, polish set, a non-finite value in a grid), TWG_EUNSUPPORTED (more
- * than 65536 grids), TWG_ENOMEM, TWG_EDEVICE. */
+ * TWG_NOT_CONVERGED.  Errors: TWG_EINVAL (n < 1, NULL arrays, a bad grid,
+ * offset or flags, polish set, a non-finite value in a grid),
+ * TWG_EUNSUPPORTED (more than 65536 grids), TWG_ENOMEM, TWG_EDEVICE. */
 int32_t hpf_relax_batched(twg_ctx *ctx, int32_t n, const twg_grid_desc *grids, const uint8_t *cls,
                           float *psi, const hpf_params *params, hpf_stats *stats, void *stream);
 

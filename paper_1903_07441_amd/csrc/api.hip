@@ -567,6 +567,8 @@ constexpr int64_t kBatchSlotMargin = 3;
 // Checks of a batch happen only at slots that are multiples of this, so that
 // grids share them (an event costs every workgroup a ticket).
 constexpr int kBatchQuantum = 4;
+// LDS (bytes) left for the LDS worker's static variables (3 KiB at present)
+constexpr size_t kLdsReserve = 8192;
 
 // The device-driven batch relaxation (batch.hip): field init and free masks
 // of every grid, the begin kernel, then slots.  slots > 0: exactly that many
@@ -599,6 +601,7 @@ int relax_batch_device(twg_ctx *ctx, int n, const twg_grid_desc *grids, const ui
         int rc = check_grid(ctx, gk);
         if (rc) return set_err(ctx, rc, "grid " + std::to_string(k) + ": " + ctx->err);
         if (grids[k].offset < 0) return set_err(ctx, TWG_EINVAL, "negative offset");
+        if (grids[k].flags & ~TWG_GRID_LDS) return set_err(ctx, TWG_EINVAL, "unknown grid flags");
         total = std::max(total, (long long)grids[k].offset + (long long)grids[k].pitch * grids[k].ny);
         if ((long long)grids[k].nx * grids[k].ny > (long long)grids[big].nx * grids[big].ny) big = k;
     }
@@ -621,26 +624,38 @@ int relax_batch_device(twg_ctx *ctx, int n, const twg_grid_desc *grids, const ui
     }
     RH = std::min(RH < 2 ? 2 : (RH & ~1), stream_rows_cap(max_pitch, (int)sizeof(float), S));
 
-    // static tables: descriptors (with each grid's SOR factor) and the
-    // (grid, 64-column block) list
+    // static tables: descriptors (with each grid's SOR factor), the
+    // (grid, 64-column block) list and the grids small enough for one
+    // workgroup's LDS that ask for it (TWG_GRID_LDS: solved whole there)
     std::vector<BatchGrid> bg(n);
     std::vector<int2> bl;
+    std::vector<int> lds;
     long long max_tiles = 0;
+    size_t lds_bytes = 0;
+    const size_t lds_budget = ctx->lds_per_block > kLdsReserve ? ctx->lds_per_block - kLdsReserve : 0;
     for (int k = 0; k < n; ++k) {
         int s_, rh_;
         float om;
         tiling_for(ctx, grids[k].nx, grids[k].ny, &s_, &rh_, &om);
+        const size_t need = batch_lds_bytes((long long)grids[k].nx * grids[k].ny);
+        const int in_lds = (grids[k].flags & TWG_GRID_LDS) && need <= lds_budget;
         bg[k] = BatchGrid{grids[k].nx, grids[k].ny, grids[k].pitch, p.omega > 0.0f ? p.omega : om,
-                          (long long)grids[k].offset};
-        max_tiles += (long long)((grids[k].nx + VW - 1) / VW) * ((grids[k].ny + RH - 1) / RH);
+                          (long long)grids[k].offset, in_lds, 0};
+        if (in_lds) {
+            lds.push_back(k);
+            lds_bytes = std::max(lds_bytes, need);
+        } else {
+            max_tiles += (long long)((grids[k].nx + VW - 1) / VW) * ((grids[k].ny + RH - 1) / RH);
+        }
         for (int bx = 0; bx < (grids[k].nx + 63) / 64; ++bx) bl.push_back(make_int2(k, bx));
     }
     if (max_tiles > INT_MAX / 2 || (long long)bl.size() * 32 > INT_MAX / 2)
         return set_err(ctx, TWG_EUNSUPPORTED, "batch too large");
-    // device layout: grids | blocks | hdr | run | ctl | tile table | rmax | rrel | stats
+    // device layout: grids | blocks | LDS list | hdr | run | ctl | tile table | rmax | rrel | stats
     auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
     const size_t o_grids = 0, o_blocks = align(o_grids + n * sizeof(BatchGrid));
-    const size_t o_hdr = align(o_blocks + bl.size() * sizeof(int2));
+    const size_t o_lds = align(o_blocks + bl.size() * sizeof(int2));
+    const size_t o_hdr = align(o_lds + lds.size() * sizeof(int));
     const size_t o_run = align(o_hdr + batch_hdr_bytes());
     const size_t o_ctl = align(o_run + n * batch_run_bytes());
     const size_t o_tiles = align(o_ctl + n * batch_ctl_bytes());
@@ -656,15 +671,20 @@ int relax_batch_device(twg_ctx *ctx, int n, const twg_grid_desc *grids, const ui
     char *base = static_cast<char *>(ctx->batch);
     BatchGrid *d_grids = reinterpret_cast<BatchGrid *>(base + o_grids);
     int2 *d_blocks = reinterpret_cast<int2 *>(base + o_blocks);
+    int *d_lds = reinterpret_cast<int *>(base + o_lds);
     // the tables are uploaded only when they differ from the last upload to
     // this buffer, so that an asynchronous call of an unchanged batch
     // enqueues kernels only (it can then be captured into a graph)
-    std::vector<char> sig(sizeof(BatchGrid) * bg.size() + sizeof(int2) * bl.size());
-    std::memcpy(sig.data(), bg.data(), sizeof(BatchGrid) * bg.size());
-    std::memcpy(sig.data() + sizeof(BatchGrid) * bg.size(), bl.data(), sizeof(int2) * bl.size());
+    const size_t sz_g = sizeof(BatchGrid) * bg.size(), sz_b = sizeof(int2) * bl.size(),
+                 sz_l = sizeof(int) * lds.size();
+    std::vector<char> sig(sz_g + sz_b + sz_l);
+    std::memcpy(sig.data(), bg.data(), sz_g);
+    std::memcpy(sig.data() + sz_g, bl.data(), sz_b);
+    if (sz_l) std::memcpy(sig.data() + sz_g + sz_b, lds.data(), sz_l);
     if (old_batch != ctx->batch || sig != ctx->batch_sig) {
-        if (hipMemcpyAsync(d_grids, bg.data(), n * sizeof(BatchGrid), hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(d_blocks, bl.data(), bl.size() * sizeof(int2), hipMemcpyHostToDevice, st) != hipSuccess ||
+        if (hipMemcpyAsync(d_grids, bg.data(), sz_g, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(d_blocks, bl.data(), sz_b, hipMemcpyHostToDevice, st) != hipSuccess ||
+            (sz_l && hipMemcpyAsync(d_lds, lds.data(), sz_l, hipMemcpyHostToDevice, st) != hipSuccess) ||
             hipStreamSynchronize(st) != hipSuccess)
             return set_err(ctx, TWG_EDEVICE, "batch table upload failed");
         ctx->batch_sig = std::move(sig);
@@ -698,7 +718,10 @@ int relax_batch_device(twg_ctx *ctx, int n, const twg_grid_desc *grids, const ui
     a.rrel = reinterpret_cast<unsigned long long *>(base + o_rrel);
     a.stats = stats_dev ? stats_dev : reinterpret_cast<hpf_stats *>(base + o_stats);
     a.mirror = nullptr;
+    a.lds_list = d_lds;
+    a.n_lds = (int)lds.size();
     rc = launch_batch_begin(a, st);
+    if (!rc) rc = launch_batch_lds(a, lds_bytes, &ctx->lds_attr, st);
     if (rc) return set_err(ctx, rc, "batch begin launch failed");
     const int mt = (int)max_tiles;
 
@@ -775,7 +798,10 @@ int32_t twg_ctx_create(twg_ctx **out, int32_t device)
     twg_ctx *ctx = new twg_ctx();
     ctx->device = device;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        ctx->num_cu = prop.multiProcessorCount;
+        ctx->lds_per_block = prop.sharedMemPerBlock;
+    }
     if (hipMalloc(&ctx->words, kWords * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&ctx->rpart, 2 * kResidBlocks * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc(&ctx->host_words, kWords * sizeof(unsigned long long), hipHostMallocDefault) !=

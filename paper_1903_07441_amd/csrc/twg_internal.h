@@ -36,6 +36,8 @@ struct twg_ctx {
     // autotuned tiling per grid size (nx, ny)
     std::map<std::pair<int, int>, twg_tuning> tuned;
     int num_cu = 0;
+    size_t lds_per_block = 0;  // the device's LDS per workgroup (bytes)
+    size_t lds_attr = 0;       // dynamic LDS the batch's LDS worker is allowed so far
     std::string err;
     // FP32 ping-pong partner of a relaxed field
     void *alt = nullptr;
@@ -110,6 +112,8 @@ struct BatchGrid {
     int nx, ny, pitch;
     float omega;
     long long off;
+    int lds;  // 1: solved whole in one workgroup's LDS (k_batch_lds), not by tiles
+    int pad_;
 };
 int launch_field_init_batch(const uint8_t *cls, float *psi, const BatchGrid *grids,
                             const int2 *blocks, int n_blocks, int mode, hipStream_t st);
@@ -231,12 +235,18 @@ struct BatchArgs {
     unsigned long long *rmax, *rrel;  // n each: maxima of the checking passes
     hpf_stats *stats;        // n, device, written when the batch ends
     unsigned long long *mirror;       // host-mapped decision word, or null
+    const int *lds_list;     // the grids solved in LDS (BatchGrid::lds), n_lds of them
+    int n_lds;
 };
 size_t batch_hdr_bytes();
 size_t batch_run_bytes();
 size_t batch_ctl_bytes();
 int launch_batch_begin(const BatchArgs &a, hipStream_t st);
 int launch_batch_slot(const BatchArgs &a, int max_tiles, bool pair, hipStream_t st);
+// LDS bytes k_batch_lds needs for a grid of `cells` cells; the solve of the
+// LDS grids (one workgroup each), launched after launch_batch_begin
+size_t batch_lds_bytes(long long cells);
+int launch_batch_lds(const BatchArgs &a, size_t lds_bytes, size_t *lds_attr, hipStream_t st);
 
 // raster.hip
 int launch_rasterize(twg_ctx *ctx, const twg_grid &g, int n_obs, const double *pos,

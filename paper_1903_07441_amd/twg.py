@@ -17,6 +17,7 @@ OK, NOT_CONVERGED, NO_PATH, START_BLOCKED, NET_FALLBACK, PATH_TRUNCATED = 0, 1, 
 EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4
 FREE, OBST, WALL, GOAL, FIXED = 0, 1, 2, 3, 4
 INIT_KEEP, INIT_HALF, INIT_ZERO, INIT_LINEAR = 0, 1, 2, 3
+GRID_LDS = 1  # twg_grid_desc.flags
 
 i32, i64, f32, f64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_void_p
 
@@ -65,7 +66,7 @@ def batch_stats_from_device(t, n):
 
 
 class GridDesc(ctypes.Structure):
-    _fields_ = [("nx", i32), ("ny", i32), ("pitch", i32), ("reserved", i32), ("offset", i64)]
+    _fields_ = [("nx", i32), ("ny", i32), ("pitch", i32), ("flags", i32), ("offset", i64)]
 
 
 class DescendParams(ctypes.Structure):
@@ -292,19 +293,23 @@ class Context:
         return stats
 
     def relax_batched(self, cls_flat, psi_flat, descs, tol=1e-6, max_sweeps=0, omega=0.0,
-                      init=INIT_HALF, sweeps_per_pass=0, check_passes=0, rows_per_tile=0, slots=0, stats=None):
+                      init=INIT_HALF, sweeps_per_pass=0, check_passes=0, rows_per_tile=0, slots=0, stats=None,
+                      lds=False):
         """Relax many grids packed in one flat uint8 class buffer and one flat
         float32 field buffer; descs = [(nx, ny, pitch, offset), ...] (offsets in
         elements).  Returns one stats dict per grid.  slots > 0: enqueue
         hpf_relax_batched_async (slots launches and a final one) on the
         current stream and return the device stats tensor (n hpf_stats; read
-        with batch_stats_from_device)."""
+        with batch_stats_from_device).  lds: every grid that fits in one
+        workgroup's LDS is solved whole there (TWG_GRID_LDS) instead of by the
+        tiled passes."""
         if cls_flat.dtype != torch.uint8 or psi_flat.dtype != torch.float32:
             raise ValueError("class buffer must be uint8 and field buffer float32")
         if not (cls_flat.is_cuda and psi_flat.is_cuda):
             raise ValueError("batch buffers must be device tensors")
         n = len(descs)
-        arr = (GridDesc * n)(*[GridDesc(int(a), int(b), int(c), 0, int(d)) for a, b, c, d in descs])
+        flags = GRID_LDS if lds else 0
+        arr = (GridDesc * n)(*[GridDesc(int(a), int(b), int(c), flags, int(d)) for a, b, c, d in descs])
         for a, b, c, d in descs:
             if d + c * b > min(cls_flat.numel(), psi_flat.numel()):
                 raise ValueError("a grid extends past the batch buffers")

@@ -1,7 +1,10 @@
 """GPU parity of the batched relaxation: every grid of an uneven batch meets the
 tolerance (residual recomputed by the oracle) and equals, bit for bit, the same
-number of sweeps run on that grid alone; the asynchronous and graph-captured
-batch equal the blocking one."""
+number of sweeps run on that grid alone, whether the tiled passes or the
+LDS-resident worker (small grids) solved it; the asynchronous and
+graph-captured batch equal the blocking one."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -182,3 +185,67 @@ def test_batch_rejects_bad_arguments(ctx):
         ctx.relax_batched(cls, psi, [(10, 20, 10, 0)])
     with pytest.raises(twg.TwgError):
         ctx.relax_batched(cls, psi, [(10, 5, 9, 0)])
+
+
+@pytest.mark.parametrize("lds", [True, False])
+def test_batch_small_grids_in_lds(ctx, orc, lds):
+    """Small grids solved whole in one workgroup's LDS (TWG_GRID_LDS) and the
+    same grids through the tiled passes (the default): both meet the
+    tolerance (oracle residual), and every field equals, bit for bit, its own
+    sweep count run on the grid alone.  The LDS worker checks every S sweeps,
+    so its check count is sweeps / S + 1; the tiled passes check far less
+    often."""
+    sides = [64, 96, 128, 130, 176, 64, 256]
+    S = 4
+    classes = [orc.rasterize(scenarios.scenario("batch", seed=3500 + k, side=n))[0] for k, n in enumerate(sides)]
+    flat_c, descs = pack(classes, 0)
+    cls = torch.as_tensor(flat_c).cuda()
+    psi = torch.zeros(len(flat_c), dtype=torch.float32, device="cuda")
+    stats = ctx.relax_batched(cls, psi, descs, tol=1e-6, sweeps_per_pass=S, lds=lds)
+    torch.cuda.synchronize()
+    got = unpack(psi.cpu().numpy(), descs)
+    in_lds = [st["checks"] == st["sweeps"] // S + 1 for st in stats]
+    print(f"lds={lds}: sweeps {[st['sweeps'] for st in stats]} checks {[st['checks'] for st in stats]} "
+          f"LDS-solved {in_lds}", flush=True)
+    for k, (c, st, g) in enumerate(zip(classes, stats, got)):
+        assert st["status"] == 0, (k, st)
+        assert st["sweeps"] % S == 0
+        r = orc.residual(c, g.astype(np.float64))
+        assert r <= 1e-6 and abs(r - st["residual"]) <= 1e-12, (k, r, st)
+        cd = torch.as_tensor(c).cuda()
+        solo = torch.where(cd == 3, 1.0, torch.where(cd == 0, 0.5, 0.0)).float()
+        ctx.sweeps(cd, solo, st["omega"], st["sweeps"], tiled=False)
+        torch.cuda.synchronize()
+        assert np.array_equal(solo.cpu().numpy(), g), k
+    if lds:
+        # 64 x 64 needs 20 KiB: it fits in any workgroup's LDS
+        assert in_lds[0] and in_lds[5]
+    else:
+        assert not in_lds[0] and not in_lds[5]
+
+
+@pytest.mark.parametrize("lds", [True, False])
+def test_batch_non_finite_field_is_rejected(ctx, orc, lds):
+    """A NaN in a kept field: the grid's check finds it, on either path, and
+    the call reports TWG_EINVAL."""
+    from paper_1903_07441_amd import twg
+    classes = [orc.rasterize(scenarios.scenario("batch", seed=3600 + k, side=n))[0] for k, n in enumerate([64, 128])]
+    flat_c, descs = pack(classes, 0)
+    cls = torch.as_tensor(flat_c).cuda()
+    psi = torch.zeros(len(flat_c), dtype=torch.float32, device="cuda")
+    free = np.flatnonzero(flat_c[:64 * 64] == 0)
+    psi[int(free[len(free) // 2])] = float("nan")
+    with pytest.raises(twg.TwgError) as e:
+        ctx.relax_batched(cls, psi, descs, tol=1e-6, init=twg.INIT_KEEP, sweeps_per_pass=4, lds=lds)
+    assert e.value.code == twg.EINVAL
+
+
+def test_batch_rejects_unknown_grid_flags(ctx):
+    from paper_1903_07441_amd import twg
+    cls = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    psi = torch.zeros(100, dtype=torch.float32, device="cuda")
+    arr = (twg.GridDesc * 1)(twg.GridDesc(10, 10, 10, 2, 0))
+    prm = twg.HpfParams(1e-6, 0.0, 0, 0.0, twg.INIT_HALF, 0, 0, 0, 0, -1, -1)
+    rc = twg.lib.hpf_relax_batched(ctx.h, 1, arr, twg._ptr(cls), twg._ptr(psi), ctypes.byref(prm), None,
+                                   twg._stream())
+    assert rc == twg.EINVAL
