@@ -294,11 +294,10 @@ __device__ void publish(const RelaxCtl *c, unsigned long long *mirror, int32_t s
 // buffer parity par), a defect, an update, or the finish (`forced`: the
 // final slot ends a solve whose phase was `was`, at pass p on parity par
 // if that phase was a solve).
-__device__ void controller(RelaxCtl *c, const SlotArgs &a, int phase, int was, bool forced, int32_t p, int32_t par)
+__device__ void controller_on(RelaxCtl *c, const SlotArgs &a, int phase, int was, bool forced, int32_t p,
+                              int32_t par, double r, double rel)
 {
     const int32_t slot_now = a.slot;
-    const double r = bitsd(__hip_atomic_exchange(&c->rmax, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    const double rel = bitsd(__hip_atomic_exchange(&c->rrel, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     switch (phase) {
     case PH_PLAIN:
     case PH_CORR: {
@@ -344,6 +343,39 @@ __device__ void controller(RelaxCtl *c, const SlotArgs &a, int phase, int was, b
     publish(c, a.mirror, slot_now);
 }
 
+// The controller works on a copy of the control block in registers: read in
+// one batch of independent loads and written back once, instead of a chain
+// of dependent global accesses (each a memory latency).  The words other
+// workgroups update atomically (ticket, maxima) are read and reset here with
+// atomics and not written back.
+__device__ void controller(RelaxCtl *cg, const SlotArgs &a, int phase, int was, bool forced, int32_t p, int32_t par)
+{
+    const double r = bitsd(__hip_atomic_exchange(&cg->rmax, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const double rel = bitsd(__hip_atomic_exchange(&cg->rrel, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    RelaxCtl c = *cg;
+    controller_on(&c, a, phase, was, forced, p, par, r, rel);
+    cg->h = c.h;
+    cg->last_check = c.last_check;
+    cg->lead_check = c.lead_check;
+    cg->solve_checks = c.solve_checks;
+    cg->stalls = c.stalls;
+    cg->checks = c.checks;
+    cg->rounds = c.rounds;
+    cg->status = c.status;
+    cg->last_chunk = c.last_chunk;
+    cg->since = c.since;
+    cg->sweeps = c.sweeps;
+    cg->polish_sweeps = c.polish_sweeps;
+    cg->tol_cur = c.tol_cur;
+    cg->r_prev = c.r_prev;
+    cg->best = c.best;
+    cg->rate = c.rate;
+    cg->rate_dc = c.rate_dc;
+    cg->residual32 = c.residual32;
+    cg->residual_rel = c.residual_rel;
+    cg->residual = c.residual;
+}
+
 // ---- element-wise and stencil phases ----------------------------------------
 
 // the cells of a slot's elementwise phases: work items are (row, run of 256
@@ -364,6 +396,60 @@ __device__ __forceinline__ void for_cells(const SlotArgs &a, int gw, int nwaves,
         }
     }
 }
+
+// The same cells, K work items at a time, each cell split into `load`
+// (reads and arithmetic, returning a value) and `store` (writes): every load
+// of the 4K cells is issued before the first store, so a wave has that many
+// cells' loads in flight instead of one cell's (the stores could alias the
+// loads, so the compiler keeps them in program order).  A cell outside the
+// grid loads cell (0, 0) and stores nothing.
+template <int K, typename L, typename St>
+__device__ __forceinline__ void for_cells_batched(const SlotArgs &a, int gw, int nwaves, L load, St store)
+{
+    using V = decltype(load(0, 0));
+    const int lane = threadIdx.x & 63;
+    const int runs = (a.nx + 255) / 256;
+    const int items = a.ny * runs;
+    for (int it0 = gw; it0 < items; it0 += K * nwaves) {
+        V v[K][4];
+        int ys[K], xs[K][4];
+        bool ok[K][4];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const int it = it0 + q * nwaves;
+            const bool in = it < items;
+            const int y = in ? it / runs : 0;
+            const int x0 = in ? (it - y * runs) * 256 + lane : 0;
+            ys[q] = y;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                xs[q][j] = x0 + 64 * j;
+                ok[q][j] = in && xs[q][j] < a.nx;
+                v[q][j] = load(ok[q][j] ? xs[q][j] : 0, ok[q][j] ? y : 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (ok[q][j]) store(xs[q][j], ys[q], v[q][j]);
+    }
+}
+// a store written through L2 at agent scope (sc1)
+template <typename T>
+__device__ __forceinline__ void st_through(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+struct DefectCell {
+    double c, r;
+    bool fr;
+};
+struct UpdateCell {
+    double v;
+    float e;
+    bool fr;
+};
 
 // FP64 residual of u at (x, y) with the neighbours outside the grid at 0;
 // every load unconditional (clamped, then zeroed), as in the standalone
@@ -447,34 +533,51 @@ __global__ __launch_bounds__(256) void k_relax_slot(SlotArgs a)
         const bool first = phase == PH_DEFECT32;
         const int fpar = hpar;
         const float *u32 = fpar ? a.alt : a.psi;
-        for_cells(a, gw, nwaves, [&](int x, int y) {
+        // the defect's maxima, and its outputs written through L2 (as the
+        // passes' field rows are, so the kernel's end has nothing to write
+        // back): the widened field and a cleared correction the first time
+        auto store = [&](int x, int y, const DefectCell &d) {
             const size_t i = (size_t)y * a.pitch + x;
-            double cv;
-            const double r = first ? defect_at(u32, a.nx, a.ny, a.pitch, x, y, &cv)
-                                   : defect_at(a.psi64, a.nx, a.ny, a.pitch, x, y, &cv);
-            const bool fr = a.mask[i] != 0;
             if (first) {
-                a.psi64[i] = cv;
-                a.e[i] = 0.0f;
+                st_through(a.psi64 + i, d.c);
+                st_through(a.e + i, 0.0f);
             }
-            a.r32[i] = fr ? (float)r : 0.0f;
-            m = nan_max(m, fr ? fabs(r) : 0.0);
-            const float ac = fabsf((float)cv);
-            mr = nan_maxf(mr, fr && ac >= 1e-30f ? fabsf((float)r) * __builtin_amdgcn_rcpf(ac) : 0.0f);
-        });
+            st_through(a.r32 + i, d.fr ? (float)d.r : 0.0f);
+            m = nan_max(m, d.fr ? fabs(d.r) : 0.0);
+            const float ac = fabsf((float)d.c);
+            mr = nan_maxf(mr, d.fr && ac >= 1e-30f ? fabsf((float)d.r) * __builtin_amdgcn_rcpf(ac) : 0.0f);
+        };
+        auto load = [&](const auto *u, int x, int y) {
+            DefectCell d;
+            d.r = defect_at(u, a.nx, a.ny, a.pitch, x, y, &d.c);
+            d.fr = a.mask[(size_t)y * a.pitch + x] != 0;
+            return d;
+        };
+        if (first)
+            for_cells_batched<2>(a, gw, nwaves, [&](int x, int y) { return load(u32, x, y); }, store);
+        else
+            for_cells_batched<2>(a, gw, nwaves, [&](int x, int y) { return load(a.psi64, x, y); }, store);
     } else if (phase == PH_UPDATE) {
         const int cpar = hcpar;
         const float *ecur = cpar ? a.alt : a.e;
-        for_cells(a, gw, nwaves, [&](int x, int y) {
-            const size_t i = (size_t)y * a.pitch + x;
-            double v = a.psi64[i];
-            if (a.mask[i]) {
-                v = v + (double)ecur[i];
-                a.psi64[i] = v;
-            }
-            a.psi[i] = (float)v;
-            a.e[i] = 0.0f;
-        });
+        // ecur may be e itself: every cell's correction is read before any
+        // cell's is cleared
+        for_cells_batched<2>(
+            a, gw, nwaves,
+            [&](int x, int y) {
+                const size_t i = (size_t)y * a.pitch + x;
+                return UpdateCell{a.psi64[i], ecur[i], a.mask[i] != 0};
+            },
+            [&](int x, int y, const UpdateCell &u) {
+                const size_t i = (size_t)y * a.pitch + x;
+                double v = u.v;
+                if (u.fr) {
+                    v = v + (double)u.e;
+                    st_through(a.psi64 + i, v);
+                }
+                st_through(a.psi + i, (float)v);
+                st_through(a.e + i, 0.0f);
+            });
     } else {  // PH_FINISH
         // the FP32 field's buffer: a solve cut short between checks left it
         // where its last pass wrote
