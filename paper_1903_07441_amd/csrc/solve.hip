@@ -61,6 +61,8 @@ struct alignas(32) RelaxHot {
     int32_t wide;          // psi64 holds the (widened or polished) field
 };
 
+constexpr int kParts = 128;
+
 struct RelaxCtl {
     RelaxHot h;
     RelaxConfig c;
@@ -74,10 +76,13 @@ struct RelaxCtl {
     int32_t pad;
     uint32_t ticket;       // workgroups of the current slot that have finished
     uint32_t pad2;
-    unsigned long long rmax, rrel;  // bit patterns of the slot's maxima (atomic max)
     int64_t last_chunk, since, sweeps, polish_sweeps;
     double tol_cur, r_prev, best, rate, rate_dc;
     double residual32, residual_rel, residual;
+    // bit patterns of the slot's maxima, spread over kParts words so that
+    // the workgroups' atomics seldom meet on one address (workgroup b uses
+    // part[b % kParts]); the slot's last workgroup combines and clears them
+    unsigned long long part[kParts][2];
 };
 
 __device__ __forceinline__ unsigned long long dbits(double d) { return (unsigned long long)__double_as_longlong(d); }
@@ -348,10 +353,9 @@ __device__ void controller_on(RelaxCtl *c, const SlotArgs &a, int phase, int was
 // of dependent global accesses (each a memory latency).  The words other
 // workgroups update atomically (ticket, maxima) are read and reset here with
 // atomics and not written back.
-__device__ void controller(RelaxCtl *cg, const SlotArgs &a, int phase, int was, bool forced, int32_t p, int32_t par)
+__device__ void controller(RelaxCtl *cg, const SlotArgs &a, int phase, int was, bool forced, int32_t p, int32_t par,
+                           double r, double rel)
 {
-    const double r = bitsd(__hip_atomic_exchange(&cg->rmax, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    const double rel = bitsd(__hip_atomic_exchange(&cg->rrel, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     RelaxCtl c = *cg;
     controller_on(&c, a, phase, was, forced, p, par, r, rel);
     cg->h = c.h;
@@ -600,6 +604,7 @@ __global__ __launch_bounds__(256) void k_relax_slot(SlotArgs a)
     // reads the maxima of every block
     __shared__ double bm[4];
     __shared__ float br[4];
+    __shared__ int last;
     if (reduce) {
         m = wave_max(m);
         mr = wave_maxf(mr);
@@ -609,23 +614,55 @@ __global__ __launch_bounds__(256) void k_relax_slot(SlotArgs a)
         }
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    if (reduce) {
-        m = nan_max(nan_max(bm[0], bm[1]), nan_max(bm[2], bm[3]));
-        mr = nan_maxf(nan_maxf(br[0], br[1]), nan_maxf(br[2], br[3]));
-        __hip_atomic_fetch_max(&c->rmax, dbits(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_max(&c->rrel, dbits((double)mr), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_s_waitcnt(0);
+    if (threadIdx.x == 0) {
+        if (reduce) {
+            m = nan_max(nan_max(bm[0], bm[1]), nan_max(bm[2], bm[3]));
+            mr = nan_maxf(nan_maxf(br[0], br[1]), nan_maxf(br[2], br[3]));
+            unsigned long long *pp = c->part[blockIdx.x % kParts];
+            __hip_atomic_fetch_max(pp, dbits(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(pp + 1, dbits((double)mr), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+        }
+        const unsigned int ticket =
+            __hip_atomic_fetch_add(&c->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = ticket == gridDim.x - 1;
     }
-    const unsigned int ticket = __hip_atomic_fetch_add(&c->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (ticket != gridDim.x - 1) return;
+    __syncthreads();
+    if (!last) return;
+    // the last workgroup: the slot's maxima from the kParts words (one
+    // thread each, read and cleared), combined as bit patterns like the
+    // atomics (non-negative doubles order like their patterns; a NaN's is
+    // larger than +inf's)
+    unsigned long long pr = 0ull, pq = 0ull;
+    if (threadIdx.x < kParts) {
+        pr = __hip_atomic_exchange(&c->part[threadIdx.x][0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pq = __hip_atomic_exchange(&c->part[threadIdx.x][1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        pr = max(pr, (unsigned long long)__shfl_xor((long long)pr, o));
+        pq = max(pq, (unsigned long long)__shfl_xor((long long)pq, o));
+    }
+    __shared__ unsigned long long wr[4], wq[4];
+    if (lane == 0) {
+        wr[wave] = pr;
+        wq[wave] = pq;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    pr = max(max(wr[0], wr[1]), max(wr[2], wr[3]));
+    pq = max(max(wq[0], wq[1]), max(wq[2], wq[3]));
     __hip_atomic_exchange(&c->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    controller(c, a, phase, was, forced, pass, par);
+    controller(c, a, phase, was, forced, pass, par, bitsd(pr), bitsd(pq));
 }
 
 __global__ void k_relax_begin(RelaxCtl *c, RelaxConfig cfg)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (blockIdx.x != 0) return;
+    for (int i = threadIdx.x; i < kParts; i += blockDim.x) {
+        __hip_atomic_store(&c->part[i][0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&c->part[i][1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x != 0) return;
     c->c = cfg;
     c->h.phase = PH_PLAIN;
     c->h.parity = c->h.cparity = c->h.fresh = c->h.wide = 0;
@@ -645,8 +682,6 @@ __global__ void k_relax_begin(RelaxCtl *c, RelaxConfig cfg)
     c->rate_dc = 0.0;
     c->residual32 = c->residual_rel = c->residual = 0.0;
     __hip_atomic_exchange(&c->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_exchange(&c->rmax, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_exchange(&c->rrel, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 int last_status() { return hipGetLastError() == hipSuccess ? TWG_OK : TWG_EDEVICE; }
