@@ -138,8 +138,11 @@ __device__ void start_correction(RelaxCtl *c, double r64, int32_t first_slot)
     c->h.run_slot = first_slot;
     c->solve_checks = 0;
     // at most four decades per round (the FP32 correction keeps about that
-    // much relative accuracy), and no further than a third of what is left
-    c->tol_cur = fmax(r64 * 1e-4, c->c.need / 3.0);
+    // much relative accuracy), and no further than the target with a 25 %
+    // margin: after the FP64 update the field's residual is the correction
+    // solve's own residual plus the rounding of the defect to FP32 (a
+    // relative 6e-8) and of the update (about 1e-16)
+    c->tol_cur = fmax(r64 * 1e-4, c->c.need / 1.25);
     c->r_prev = r64;
     c->best = r64;
     c->stalls = 0;
