@@ -15,7 +15,8 @@
 // file-scope device array, a copy of which each GPU the library runs on holds
 // until the process ends.  Its layout for a grid of n = pitch * ny <=
 // kNoAllocMaxCells cells: the control block and default stats at 0, then the
-// FP32 ping-pong partner, the FP32 defect and correction, and the free mask,
+// FP32 ping-pong partner, the FP32 defect, correction and products of the
+// defect with the correction factors, and the free mask,
 // each at a fixed offset sized for the largest grid.  Host code never names
 // the array in a launch or copy: it uses the device address that
 // hipGetSymbolAddress gave for the current device (noalloc_scratch below).
@@ -24,7 +25,7 @@ constexpr size_t kNoAllocMaxCells = size_t(1) << 22;  // e.g. 2048 x 2048
 constexpr size_t kNoAllocCtlBytes = 4096;
 constexpr size_t kNoAllocAlt = kNoAllocCtlBytes;
 constexpr size_t kNoAllocPol = kNoAllocAlt + 4 * kNoAllocMaxCells;
-constexpr size_t kNoAllocMask = kNoAllocPol + 8 * kNoAllocMaxCells;
+constexpr size_t kNoAllocMask = kNoAllocPol + 16 * kNoAllocMaxCells;
 constexpr size_t kNoAllocBytes = kNoAllocMask + kNoAllocMaxCells;
 constexpr int kNoAllocDevices = 64;
 }  // namespace
@@ -195,18 +196,25 @@ void tiling_for(twg_ctx *ctx, int nx, int ny, int *S, int *RH, float *omega)
 
 // Tile heights to try for S sweeps per load: a fixed set plus, for k = 1..kmax,
 // the smallest even height whose tile count (one wave per tile) fits k rounds
-// of the device's SIMDs.
+// of the device's SIMDs, and the tallest height with the same row steps per
+// tile.  A tile streams RH + 4S rows in whole windows of 2S + 2 row steps, so
+// that height fills the last window: the same time per wave, fewer tiles.
 std::vector<int> tile_heights(const twg_ctx *ctx, int nx, int ny, int S, int kmax)
 {
     std::vector<int> RHs = {8, 16, 32, 64, 128};
     const int simds = 4 * std::max(1, ctx->num_cu);
     const int strips = (nx + (128 - 4 * S) - 1) / (128 - 4 * S);
+    const int NW = 2 * S + 2;
+    auto add = [&](int RH) {
+        if (RH >= 2 && std::find(RHs.begin(), RHs.end(), RH) == RHs.end()) RHs.push_back(RH);
+    };
     for (int k = 1; k <= kmax; ++k) {
         const int segs = (k * simds) / strips;
         if (segs < 1) continue;
         int RH = (ny + segs - 1) / segs;
         RH += RH & 1;
-        if (RH >= 2 && std::find(RHs.begin(), RHs.end(), RH) == RHs.end()) RHs.push_back(RH);
+        add(RH);
+        add((RH + 4 * S + NW - 1) / NW * NW - 4 * S);  // even: NW and 4S are
     }
     return RHs;
 }
@@ -417,9 +425,10 @@ constexpr int64_t kSlotMargin = 3;
 // residual), stops when the device reports the solve done, then waits for
 // the stream and copies the stats to *stats_host.
 // Scratch of the device-driven relaxation of a grid of n = pitch * ny cells:
-// the FP32 ping-pong partner (4n bytes), with polish the FP32 defect and
-// correction (8n), the free mask (n), and the control block followed by a
-// default device hpf_stats (relax_ctl_bytes() + 256).
+// the FP32 ping-pong partner (4n bytes), with polish the FP32 defect, the
+// correction and the defect's products with the two correction factors
+// (16n), the free mask (n), and the control block followed by a default
+// device hpf_stats (relax_ctl_bytes() + 256).
 struct RelaxBufs {
     float *alt = nullptr;
     float *pol = nullptr;
@@ -432,7 +441,7 @@ int relax_bufs_ctx(twg_ctx *ctx, const twg_grid &g, bool polish, RelaxBufs *b)
 {
     const size_t n = (size_t)g.pitch * g.ny;
     int rc = ensure(ctx, &ctx->alt, &ctx->alt_bytes, n * sizeof(float));
-    if (!rc && polish) rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 2 * n * sizeof(float));
+    if (!rc && polish) rc = ensure(ctx, &ctx->pol, &ctx->pol_bytes, 4 * n * sizeof(float));
     if (!rc) rc = ensure(ctx, &ctx->fmask, &ctx->fmask_bytes, n);
     if (!rc) rc = ensure(ctx, &ctx->ctl, &ctx->ctl_bytes, relax_ctl_bytes() + 256);
     if (rc) return rc;
@@ -480,6 +489,8 @@ int relax_device(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float *psi
     a.alt = bufs.alt;
     a.r32 = p.polish ? bufs.pol : nullptr;
     a.e = p.polish ? a.r32 + n : nullptr;
+    a.cdc = p.polish ? a.r32 + 2 * n : nullptr;
+    a.clead = p.polish ? a.r32 + 3 * n : nullptr;
     a.psi64 = p.polish ? psi64 : nullptr;
     a.ctl = ctl;
     a.stats = dstats;
@@ -490,7 +501,7 @@ int relax_device(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float *psi
     a.RH = geo.RH;
     a.tiles = geo.tiles;
     const auto al8 = [](const void *q) { return (reinterpret_cast<uintptr_t>(q) & 7) == 0; };
-    a.pair = g.nx % 2 == 0 && g.pitch % 2 == 0 && al8(psi) && al8(a.alt) && (!p.polish || (al8(a.r32) && al8(a.e)));
+    a.pair = g.nx % 2 == 0 && g.pitch % 2 == 0 && al8(psi) && al8(a.alt) && (!p.polish || (al8(a.r32) && al8(a.e) && al8(a.cdc) && al8(a.clead)));
     a.final_slot = 0;
     a.slot = 0;
     a.polish = cfg.polish;

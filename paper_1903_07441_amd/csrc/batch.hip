@@ -297,8 +297,9 @@ __global__ __launch_bounds__(256, 3) void k_batch_slot(BatchArgs a)
             if (check) {
                 double rm = 0.0;
                 float rr = 0.0f;
-                stream_tile<float, S, false, PAIR, true, kStoreBack>(src, dst, m, g.omega, nullptr, g.nx, g.ny,
-                                                                     g.pitch, xs, ybeg, yend, &rm, &rr);
+                stream_tile<float, S, kSrcNone, PAIR, true, kStoreBack, false>(src, dst, m, g.omega, nullptr, g.nx,
+                                                                               g.ny, g.pitch, xs, ybeg, yend, &rm,
+                                                                               &rr);
                 for (int o = 32; o > 0; o >>= 1) {
                     rm = nan_max(rm, __shfl_xor(rm, o));
                     rr = nan_maxf(rr, __shfl_xor(rr, o));
@@ -309,8 +310,9 @@ __global__ __launch_bounds__(256, 3) void k_batch_slot(BatchArgs a)
                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
             } else {
-                stream_tile<float, S, false, PAIR, false, kStoreBack>(src, dst, m, g.omega, nullptr, g.nx,
-                                                                      g.ny, g.pitch, xs, ybeg, yend);
+                stream_tile<float, S, kSrcNone, PAIR, false, kStoreBack, false>(src, dst, m, g.omega, nullptr,
+                                                                                g.nx, g.ny, g.pitch, xs, ybeg,
+                                                                                yend);
             }
         }
     } else {
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_batch_lds(BatchArgs a)
                 const int i = y * nx + x;
                 float e, w, s, n_;
                 nbrs(x, y, i, e, w, s, n_);
-                u[i] = upd(u[i], (e + w) + n_, s, omega * (float)m[i]);
+                u[i] = upd(u[i], (e + w) + n_, s, m[i] ? omega : 0.0f);
             }
         }
         __syncthreads();

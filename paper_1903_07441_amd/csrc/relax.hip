@@ -248,7 +248,7 @@ __global__ void k_copy(const float *__restrict__ s, float *__restrict__ d, int n
 
 dim3 cell_grid(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); }
 
-// free mask of the streamed sweeps: 1 on FREE cells, 0 on the others
+// free mask of the streamed sweeps: 0xFF on FREE cells, 0 on the others
 template <typename T>
 __global__ void k_wmap(const uint8_t *__restrict__ cls, T *__restrict__ w, T omega, int nx, int ny, int pitch)
 {
@@ -268,7 +268,7 @@ __global__ void k_fmask_batch(const uint8_t *__restrict__ cls, uint8_t *__restri
     if (x >= g.nx) return;
     for (int y = threadIdx.x >> 6; y < g.ny; y += 4) {
         const size_t i = g.off + (size_t)y * g.pitch + x;
-        m[i] = cls[i] == TWG_CELL_FREE ? 1 : 0;
+        m[i] = cls[i] == TWG_CELL_FREE ? 0xff : 0;
     }
 }
 
@@ -291,7 +291,7 @@ int launch_field_init_batch(const uint8_t *cls, float *psi, const BatchGrid *gri
 
 int launch_fmask(const uint8_t *cls, uint8_t *fmask, int nx, int ny, int pitch, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_wmap<uint8_t>, cell_grid(nx, ny), dim3(256), 0, st, cls, fmask, (uint8_t)1, nx, ny,
+    hipLaunchKernelGGL(k_wmap<uint8_t>, cell_grid(nx, ny), dim3(256), 0, st, cls, fmask, (uint8_t)0xff, nx, ny,
                        pitch);
     return last_status();
 }

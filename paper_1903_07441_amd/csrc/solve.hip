@@ -518,18 +518,19 @@ __global__ __launch_bounds__(256) void k_relax_slot(SlotArgs a)
             const int xs = strip * VW - 2 * S;
             if (corr) {
                 if (check)
-                    stream_tile<float, S, true, PAIR, true>(src, dst, a.mask, om, a.r32, a.nx, a.ny, a.pitch,
-                                                            xs, ybeg, yend, &m, &mr);
+                    stream_tile<float, S, kSrcF, PAIR, true>(src, dst, a.mask, om, a.r32, a.nx, a.ny, a.pitch,
+                                                             xs, ybeg, yend, &m, &mr);
                 else
-                    stream_tile<float, S, true, PAIR, false>(src, dst, a.mask, om, a.r32, a.nx, a.ny, a.pitch,
-                                                             xs, ybeg, yend);
+                    stream_tile<float, S, kSrcC, PAIR, false>(src, dst, a.mask, om,
+                                                              pass < a.lead_passes ? a.clead : a.cdc, a.nx,
+                                                              a.ny, a.pitch, xs, ybeg, yend);
             } else {
                 if (check)
-                    stream_tile<float, S, false, PAIR, true>(src, dst, a.mask, om, nullptr, a.nx, a.ny,
-                                                             a.pitch, xs, ybeg, yend, &m, &mr);
+                    stream_tile<float, S, kSrcNone, PAIR, true>(src, dst, a.mask, om, nullptr, a.nx, a.ny,
+                                                                a.pitch, xs, ybeg, yend, &m, &mr);
                 else
-                    stream_tile<float, S, false, PAIR, false>(src, dst, a.mask, om, nullptr, a.nx, a.ny,
-                                                              a.pitch, xs, ybeg, yend);
+                    stream_tile<float, S, kSrcNone, PAIR, false>(src, dst, a.mask, om, nullptr, a.nx, a.ny,
+                                                                 a.pitch, xs, ybeg, yend);
             }
         }
         // a pass that does not check decides nothing: the next slot derives
@@ -549,7 +550,12 @@ __global__ __launch_bounds__(256) void k_relax_slot(SlotArgs a)
                 st_through(a.psi64 + i, d.c);
                 st_through(a.e + i, 0.0f);
             }
-            st_through(a.r32 + i, d.fr ? (float)d.r : 0.0f);
+            // the correction solves' source, and its products with their
+            // two factors, formed here once instead of in every pass
+            const float f = d.fr ? (float)d.r : 0.0f;
+            st_through(a.r32 + i, f);
+            st_through(a.cdc + i, a.omega_dc * f);
+            if (a.lead_passes > 0) st_through(a.clead + i, a.omega_lead * f);
             m = nan_max(m, d.fr ? fabs(d.r) : 0.0);
             const float ac = fabsf((float)d.c);
             mr = nan_maxf(mr, d.fr && ac >= 1e-30f ? fabsf((float)d.r) * __builtin_amdgcn_rcpf(ac) : 0.0f);

@@ -131,12 +131,26 @@ __device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(bv4, D2{a, b}), r, (int)vo, (int)so, AUX);
 }
 
+// v where the sign-extended mask byte m is all ones (a FREE cell), +0 where it
+// is zero: one AND (the compiler folds the byte's sign extension into it)
+__device__ __forceinline__ float keep(float v, int32_t m) { return __int_as_float(__float_as_int(v) & m); }
+__device__ __forceinline__ double keep(double v, int32_t m)
+{
+    return __hiloint2double(__double2hiint(v) & m, __double2loint(v) & m);
+}
+
+// Source term of a tile: none; f (the constants of update.h are formed from
+// f as the rows arrive); or c = omega f already formed (0 on fixed cells),
+// from which a row needs only a and b.  kSrcC gives the bits of kSrcF with
+// c = fl(omega f): a = w / 4 and b = 1 - w = fma(a, -4, 1) are exact.
+constexpr int kSrcNone = 0, kSrcF = 1, kSrcC = 2;
+
 // ---- streamed temporal-blocked red-black SOR ----------------------------
 // One wave relaxes one tile: output columns [x0 + 2S, x0 + 128 - 2S) and
 // rows [ybeg, yend) of a grid; x0 and ybeg are even, all tile values are
-// wave-uniform.  wsrc is the one-byte free mask (1 on FREE cells, else 0): a
-// FREE cell takes the factor omega, any other cell 0 (it is rewritten
-// unchanged).  PAIR tiles move each
+// wave-uniform.  wsrc is the one-byte free mask (0xFF on FREE cells, else
+// 0): a FREE cell takes the factor omega, any other cell 0 (it is rewritten
+// unchanged).  f is the source term of mode RHS.  PAIR tiles move each
 // lane's two columns in one access (three memory operations per row instead
 // of six), which keeps a whole window of prefetches within the hardware's
 // count of outstanding vector memory operations.
@@ -172,15 +186,18 @@ __device__ __forceinline__ void static_for(std::integer_sequence<int, U...>, F &
 }
 __device__ __forceinline__ float nan_maxf(float a, float b) { return (b > a || b != b) ? b : a; }
 
-template <typename T, int S, bool RHS, bool PAIR, bool CHECK = false, int STORE = kStoreThrough>
+template <typename T, int S, int RHS, bool PAIR, bool CHECK = false, int STORE = kStoreThrough, bool SLOT_OFS = true>
 __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__restrict__ dst,
                                             const uint8_t *__restrict__ wsrc, T omega,
                                             const T *__restrict__ f, int nx, int ny, int pitch,
                                             int x0, int ybeg, int yend, double *rmax = nullptr,
                                             float *rrel = nullptr)
 {
+    static_assert(RHS == kSrcNone || RHS == kSrcF || RHS == kSrcC, "source mode");
+    static_assert(!(CHECK && RHS == kSrcC), "the residual check needs f");
     constexpr int NW = 2 * S + 2;      // rows the pipeline holds (even)
     constexpr int NR = 2 * NW;         // ring slots
+    const T quarter = omega * T(0.25);  // exact
     const int lane = threadIdx.x & (kWave - 1);
     const int r0 = ybeg - 2 * S;                   // first row streamed (even)
     const int T_rows = (yend - ybeg) + 4 * S;
@@ -214,35 +231,73 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     const int orow0 = (r0 - 2 * S - ybeg) * (int)rowb;
 
     // ring: the two columns of a row (P0 = column 2 lane, P1 = 2 lane + 1),
-    // its raw mask bytes and, with a source term, its f values
+    // its raw mask bytes and, with a source term, its f (or c) values
     T P0[NR], P1[NR], F0[NR], F1[NR];
     uint32_t M0[NR], M1[NR];
     // factors of the rows in the pipeline, by row mod NW (red, black), and
     // with a source term the update constants of update.h
     T wR[NW], wB[NW];
     SrcConst<T> kR[NW], kB[NW];
-    auto fetch = [&](int slot, int t) {
-        const uint32_t vo = (uint32_t)(vrow0 + t * (int)rowb), mo = (uint32_t)(mrow0 + t * pitch);
+    // loads of a row into ring slot `slot`: lane offsets (columns 2 lane and
+    // 2 lane + 1 of the field, then of the mask) and scalar row offsets.
+    // The field is loaded before the mask: the row step that takes the row
+    // in needs both, and loads complete in order, so one wait (for the
+    // mask) covers the two.
+    auto fetch_at = [&](int slot, uint32_t b0, uint32_t b1, uint32_t m0, uint32_t m1, uint32_t vo, uint32_t mo) {
         if constexpr (PAIR) {
-            M0[slot] = __builtin_amdgcn_raw_buffer_load_b16(rw, (int)xm0, (int)mo, 0);
-            const Pair<T> v = bload2((T *)nullptr, rs, xb0, vo);
+            const Pair<T> v = bload2((T *)nullptr, rs, b0, vo);
             P0[slot] = v.a;
             P1[slot] = v.b;
+            M0[slot] = __builtin_amdgcn_raw_buffer_load_b16(rw, (int)m0, (int)mo, 0);
             if (RHS) {
-                const Pair<T> h = bload2((T *)nullptr, rf, xb0, vo);
+                const Pair<T> h = bload2((T *)nullptr, rf, b0, vo);
                 F0[slot] = h.a;
                 F1[slot] = h.b;
             }
         } else {
-            M0[slot] = __builtin_amdgcn_raw_buffer_load_b8(rw, (int)xm0, (int)mo, 0);
-            M1[slot] = __builtin_amdgcn_raw_buffer_load_b8(rw, (int)xm1, (int)mo, 0);
-            P0[slot] = bload((T *)nullptr, rs, xb0, vo);
-            P1[slot] = bload((T *)nullptr, rs, xb1, vo);
+            P0[slot] = bload((T *)nullptr, rs, b0, vo);
+            P1[slot] = bload((T *)nullptr, rs, b1, vo);
+            M0[slot] = __builtin_amdgcn_raw_buffer_load_b8(rw, (int)m0, (int)mo, 0);
+            M1[slot] = __builtin_amdgcn_raw_buffer_load_b8(rw, (int)m1, (int)mo, 0);
             if (RHS) {
-                F0[slot] = bload((T *)nullptr, rf, xb0, vo);
-                F1[slot] = bload((T *)nullptr, rf, xb1, vo);
+                F0[slot] = bload((T *)nullptr, rf, b0, vo);
+                F1[slot] = bload((T *)nullptr, rf, b1, vo);
             }
         }
+    };
+    // The first window (stream rows 0 .. NW - 1, some of them above the
+    // grid) puts the whole row offset, negative for rows above the grid, in
+    // the scalar part.  The loop fetches stream rows from NW on, which lie
+    // at or below the tile's first in-grid row lo (r0 + NW > ybeg >= lo), so
+    // there the row offset of stream row tb + NW + u (tb: the turn's first
+    // step) splits into u rows, added to the lane offsets once per tile,
+    // and tb + NW rows in one scalar offset per turn.  Both parts are
+    // non-negative and the sums are the same as in one piece, so the range
+    // check sees the same offsets and no sum wraps; the row steps spend no
+    // scalar instruction on load offsets.  That costs 2 NR registers (4 NR
+    // unpaired); SLOT_OFS = false (kernels that run several waves per SIMD)
+    // forms every fetch's offsets in the scalar part instead.
+    uint32_t lb0[NR], lb1[NR], lm0[NR], lm1[NR];
+#pragma unroll
+    for (int u = 0; u < NR && SLOT_OFS; ++u) {
+        lb0[u] = xb0 + (uint32_t)u * rowb;
+        lm0[u] = xm0 + (uint32_t)u * (uint32_t)pitch;
+        lb1[u] = PAIR ? 0u : xb1 + (uint32_t)u * rowb;
+        lm1[u] = PAIR ? 0u : xm1 + (uint32_t)u * (uint32_t)pitch;
+        // kept as registers (not re-formed in the loop, where they would
+        // cost an instruction each)
+        asm volatile("" : "+v"(lb0[u]), "+v"(lm0[u]));
+        if constexpr (!PAIR) asm volatile("" : "+v"(lb1[u]), "+v"(lm1[u]));
+    }
+    auto fetch = [&](int slot, int t) {
+        fetch_at(slot, xb0, xb1, xm0, xm1, (uint32_t)(vrow0 + t * (int)rowb), (uint32_t)(mrow0 + t * pitch));
+    };
+    auto fetch_loop = [&](int slot, int u, int tb) {
+        if constexpr (SLOT_OFS)
+            fetch_at(slot, lb0[u], lb1[u], lm0[u], lm1[u], (uint32_t)(vrow0 + (tb + NW) * (int)rowb),
+                     (uint32_t)(mrow0 + (tb + NW) * pitch));
+        else
+            fetch(slot, tb + u + NW);
     };
     // red and black cells of the row in ring slot s (red is the first
     // column on even rows; r0 is even, so a row's parity is its slot's)
@@ -278,15 +333,23 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
     auto step = [&](const int u, const int t, const bool prefetch) __attribute__((always_inline)) {
         const int uw = u % NW;
         {
-            // factor = omega x mask byte (0 or 1): exact, and free of the
-            // compare-and-select hazard
-            const uint32_t m0 = M0[u] & 0xffu, m1 = PAIR ? (M0[u] >> 8) & 0xffu : M1[u] & 0xffu;
-            const T w0 = omega * (T)(float)m0, w1 = omega * (T)(float)m1;
+            // the mask bytes sign-extended (all ones on a FREE cell); the
+            // factor is omega or +0, bit for bit omega x (0 or 1)
+            const int32_t e0 = (int32_t)(M0[u] << 24) >> 24;
+            const int32_t e1 = PAIR ? (int32_t)(M0[u] << 16) >> 24 : (int32_t)(M1[u] << 24) >> 24;
             const bool ev = (u & 1) == 0;
-            wR[uw] = ev ? w0 : w1;
-            wB[uw] = ev ? w1 : w0;
-            if constexpr (RHS) {
-                const SrcConst<T> k0 = src_const(w0, F0[u]), k1 = src_const(w1, F1[u]);
+            if constexpr (RHS != kSrcC) {
+                const T w0 = keep(omega, e0), w1 = keep(omega, e1);
+                wR[uw] = ev ? w0 : w1;
+                wB[uw] = ev ? w1 : w0;
+                if constexpr (RHS == kSrcF) {
+                    const SrcConst<T> k0 = src_const(w0, F0[u]), k1 = src_const(w1, F1[u]);
+                    kR[uw] = ev ? k0 : k1;
+                    kB[uw] = ev ? k1 : k0;
+                }
+            } else {
+                const T a0 = keep(quarter, e0), a1 = keep(quarter, e1);
+                const SrcConst<T> k0{a0, fused(a0, T(-4), T(1)), F0[u]}, k1{a1, fused(a1, T(-4), T(1)), F1[u]};
                 kR[uw] = ev ? k0 : k1;
                 kB[uw] = ev ? k1 : k0;
             }
@@ -306,7 +369,7 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
                 const double eb = (double)shl1(ca), wwb = (double)ca;
                 double ga = ((ea + wwa) + ((double)dna + (double)upa)) * 0.25;
                 double gb = ((eb + wwb) + ((double)dnb + (double)upb)) * 0.25;
-                if constexpr (RHS) {
+                if constexpr (RHS == kSrcF) {
                     ga = ga + (double)F0[um];
                     gb = gb + (double)F1[um];
                 }
@@ -325,7 +388,7 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
         }
         // row t + NW goes to the slot row t - NW left at the last step
         __builtin_amdgcn_sched_barrier(0);
-        if (prefetch) fetch((u + NW) % NR, t + NW);
+        if (prefetch) fetch_loop((u + NW) % NR, u, t - u);
         // stage k: half-sweep k of the pass (red for even k) at row
         // t - 1 - k (slot s).  Its E, W and N (row above, slot sm)
         // neighbours were finished in earlier row steps; S (row below, slot
@@ -353,7 +416,7 @@ __device__ __forceinline__ void stream_tile(const T *__restrict__ src, T *__rest
             const int sw = (uw - 1 - k + 2 * NW) % NW;
             const T e = e_next;
             if (k + 1 < 2 * S) e_next = ewn(k + 1);
-            if constexpr (RHS) {
+            if constexpr (RHS != kSrcNone) {
                 if ((k & 1) == 0)
                     red(s) = upd_src(red(s), e, blk(sp), kR[sw]);
                 else

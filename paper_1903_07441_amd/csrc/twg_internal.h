@@ -142,8 +142,8 @@ bool stream_depth_supported(int S);
 // largest RH whose tiles the streamed kernels can address (RH above it is
 // lowered at launch)
 int stream_rows_cap(int pitch, int elem_bytes, int S);
-// streamed sweeps: fmask is the free mask (1 on FREE cells, 0 on the others)
-// built by launch_fmask; w = omega on FREE cells, 0 elsewhere
+// streamed sweeps: fmask is the free mask (0xFF on FREE cells, 0 on the
+// others) built by launch_fmask; w = omega on FREE cells, 0 elsewhere
 int launch_stream_f32(const float *src, float *dst, const uint8_t *fmask, float omega, const float *f, int nx,
                       int ny, int pitch, const Geometry &geo, hipStream_t st);
 int launch_stream_f64(const double *src, double *dst, const uint8_t *fmask, double omega, int nx, int ny,
@@ -189,11 +189,12 @@ struct RelaxConfig {
     int32_t max_rounds;  // defect-correction rounds at most
 };
 struct SlotArgs {
-    const uint8_t *mask;  // free mask (1 on FREE cells), the grid's layout
+    const uint8_t *mask;  // free mask (0xFF on FREE cells), the grid's layout
     float *psi;           // caller's FP32 field
     float *alt;           // its ping-pong partner (and the correction's)
     float *e;             // correction
-    float *r32;           // FP32 defect
+    float *r32;           // FP32 defect f
+    float *cdc, *clead;   // omega_dc f and omega_lead f (0 on fixed cells)
     double *psi64;        // caller's FP64 field (polish) or null
     void *ctl;            // device control block (relax_ctl_bytes())
     hpf_stats *stats;     // device stats, written when the solve ends
