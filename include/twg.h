@@ -303,9 +303,10 @@ int32_t hpf_relax_async(twg_ctx *ctx, twg_grid g, const uint8_t *cls, float *psi
  * allocate device memory: code under HIP graph capture (also at the first
  * call of a grid size), tight serving loops, harnesses that forbid
  * hipMalloc.  The same launches and the same results, bit for bit, with
- * every scratch buffer (control block, FP32 ping-pong partner, defect and
- * correction, free mask) inside one static device array of the library,
- * 13 bytes per cell for at most 4194304 cells plus 4 KiB (52 MiB and 4 KiB),
+ * every scratch buffer (control block, FP32 ping-pong partner, defect,
+ * correction and the defect's products with the two correction factors,
+ * free mask) inside one static device array of the library, 21 bytes per
+ * cell for at most 4194304 cells plus 4 KiB (84 MiB and 4 KiB),
  * which each GPU the library runs on holds until the process ends.  The call
  * itself allocates nothing on the device (no hipMalloc, no hipFree).
  * Limit: pitch * ny <= 4194304 (e.g. 2048 x 2048); larger grids return
