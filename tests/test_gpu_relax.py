@@ -122,6 +122,37 @@ def test_relax_parity_static64(ctx, orc, idx):
     assert orc.residual(cls, psi64) <= st["residual"] * (1 + 1e-9) + 1e-300
 
 
+@pytest.mark.parametrize("nx,ny,pitch", [(201, 151, 201), (200, 151, 203)])
+@pytest.mark.parametrize("tuned", [False, True])
+def test_relax_parity_unpaired_polish(orc, nx, ny, pitch, tuned):
+    # an odd width or an odd pitch: every pass loads each lane's two columns
+    # separately, also the correction passes that read the defect's products
+    # with the correction factors; tuned: the autotuner's plan, which may add
+    # a start phase (and its own product plane)
+    from paper_1903_07441_amd import twg
+    rng = np.random.default_rng(nx * 1000 + pitch)
+    cls = random_classes(rng, nx, ny, p=0.15)
+    ref, info = orc.relax(cls, tol=1e-13, tol_cert=1e-10)
+    assert info["status"] == orc.OK
+    ctx = twg.Context(0)
+    try:
+        c = to_dev(cls, pitch)
+        if tuned:
+            tune = ctx.autotune(c)
+            print(f"{nx}x{ny}/{pitch} tuned {tune}", flush=True)
+        psi = to_dev(np.zeros((ny, nx), np.float32), pitch)
+        psi64 = to_dev(np.zeros((ny, nx)), pitch, dtype=torch.float64)
+        st = ctx.relax(c, psi, psi64, tol=1e-6, polish=True, tol_cert=1e-9)
+        torch.cuda.synchronize()
+        print(f"{nx}x{ny}/{pitch} tuned={tuned} stats={st}", flush=True)
+        assert st["status"] == 0 and st["cert_bound"] <= 1e-9
+        f64 = psi64.cpu().numpy()
+        assert np.max(np.abs(f64 - ref)) <= 1e-6
+        assert orc.residual(cls, f64) * orc.wbound(nx, ny) <= 1e-9 * (1 + 1e-9)
+    finally:
+        ctx.close()
+
+
 def test_relax_parity_warped512(ctx, orc):
     sc = scenarios.scenario("warped512", 0)
     cls, _ = orc.rasterize(sc)
