@@ -60,6 +60,46 @@ def test_batch_matches_solo_and_converges(ctx, orc, pad):
         assert np.array_equal(solo.cpu().numpy(), got[k]), k
 
 
+def test_batch_full_workload_as_benchmarked(orc):
+    # the benchmark's batch at full size: 256 grids of sides {64, ..., 1024}
+    # (seed 3000), factors per size and the batch tiling from the library's
+    # autotuners, tolerance 1e-6; every grid's residual recomputed by the
+    # oracle, and one grid of each size equal, bit for bit, to the same
+    # sweeps run on it alone
+    from paper_1903_07441_amd import twg
+    scs = scenarios.batch(256, seed=3000)
+    classes = [orc.rasterize(sc)[0] for sc in scs]
+    flat_c, descs = pack(classes)
+    ctx = twg.Context(0)
+    try:
+        cls = torch.as_tensor(flat_c).cuda()
+        psi = torch.zeros(len(flat_c), dtype=torch.float32, device="cuda")
+        first = {}
+        for k, (nx, ny, p, o) in enumerate(descs):
+            if (nx, ny) not in first:
+                first[(nx, ny)] = k
+                ctx.autotune(cls[o:o + p * ny].view(ny, p)[:, :nx])
+        bt = ctx.autotune_batched(cls, descs)
+        print(f"batch of {len(descs)} grids, {len(flat_c)} cells, tiling {bt}", flush=True)
+        stats = ctx.relax_batched(cls, psi, descs, tol=1e-6)
+        torch.cuda.synchronize()
+        got = unpack(psi.cpu().numpy(), descs)
+        for k, (c, st, g) in enumerate(zip(classes, stats, got)):
+            assert st["status"] == 0, (k, st)
+            r = orc.residual(c, g.astype(np.float64))
+            assert r <= 1e-6 and abs(r - st["residual"]) <= 1e-12, (k, r, st)
+        for (nx, ny), k in sorted(first.items()):
+            c = torch.as_tensor(classes[k]).cuda()
+            solo = torch.where(c == 3, 1.0, torch.where(c == 0, 0.5, 0.0)).float()
+            st = stats[k]
+            assert st["sweeps"] % bt["S"] == 0
+            ctx.sweeps(c, solo, st["omega"], st["sweeps"], sweeps_per_pass=bt["S"])
+            torch.cuda.synchronize()
+            assert np.array_equal(solo.cpu().numpy(), got[k]), (nx, ny, k)
+    finally:
+        ctx.close()
+
+
 def test_batch_async_and_graph_equal_blocking(ctx, orc):
     """The asynchronous batch (fixed slot count, device-side stop) gives the
     fields and statistics of the blocking call, and so does the same call
