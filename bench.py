@@ -122,9 +122,9 @@ def main():
         cpu_child(args.index, args.cpu_child)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(a batch of grids or one grid's halo exchange would shard across GPUs; "
-              "see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(a batch of grids, or one grid with a halo exchange per pass, would shard "
+              "across GPUs). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     # the single-thread oracle sample runs in a child process started before
