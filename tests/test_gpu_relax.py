@@ -153,6 +153,60 @@ def test_relax_parity_unpaired_polish(orc, nx, ny, pitch, tuned):
         ctx.close()
 
 
+def _degenerate_grids():
+    cases = []
+    cases.append(("goal_only_1x1", np.array([[3]], np.uint8), None))
+    c = np.full((2, 3), 2, np.uint8)
+    c[1, 1] = 3
+    cases.append(("no_free_cell_3x2", c, None))
+    c = np.zeros((1, 9), np.uint8)
+    c[0, 0] = c[0, -1] = 2
+    c[0, 4] = 3
+    cases.append(("one_row_9x1", c, None))
+    c = np.zeros((13, 1), np.uint8)
+    c[6, 0] = 3
+    cases.append(("one_column_1x13", c, None))
+    c = np.zeros((2, 8), np.uint8)
+    c[1, 5] = 3
+    cases.append(("two_rows_open_8x2", c, None))
+    c = np.zeros((5, 6), np.uint8)
+    c[2, 3] = 3
+    cases.append(("open_no_walls_6x5", c, None))
+    cases.append(("all_free_no_goal_7x7", np.zeros((7, 7), np.uint8), None))
+    c = np.zeros((17, 33), np.uint8)
+    c[0, :] = c[-1, :] = c[:, 0] = c[:, -1] = 2
+    c[8, 5] = c[3, 20] = 4
+    c[12, 28] = 3
+    v = np.zeros((17, 33))
+    v[8, 5], v[3, 20] = 0.75, 0.25
+    cases.append(("fixed_values_33x17", c, v))
+    return cases
+
+
+@pytest.mark.parametrize("name,cls,vals", _degenerate_grids(), ids=[g[0] for g in _degenerate_grids()])
+def test_relax_degenerate_grids(ctx, orc, name, cls, vals):
+    # the device-driven solve and its polish on grids a tile barely covers or
+    # that hold no FREE cell, no wall or no goal (cells outside the grid act
+    # as fixed zeros), and FIXED cells keeping the caller's values
+    from paper_1903_07441_amd import twg
+    ny, nx = cls.shape
+    v0 = np.zeros((ny, nx)) if vals is None else vals
+    ref, info = orc.relax(cls, psi=v0, init=orc.INIT_ZERO, tol=1e-12, tol_cert=1e-10)
+    assert info["status"] == orc.OK
+    c = to_dev(cls)
+    psi = to_dev(v0.astype(np.float32))
+    psi64 = to_dev(v0, dtype=torch.float64)
+    st = ctx.relax(c, psi, psi64, tol=1e-6, init=twg.INIT_ZERO, polish=1, tol_cert=1e-7)
+    torch.cuda.synchronize()
+    print(f"{name} stats={st}", flush=True)
+    assert st["status"] == twg.OK and st["cert_bound"] <= 1e-7
+    f64 = psi64.cpu().numpy()
+    assert np.max(np.abs(f64 - ref)) <= 1e-6
+    assert orc.residual(cls, f64) * orc.wbound(nx, ny) <= 1e-7 * (1 + 1e-9)
+    fixed = cls != 0
+    assert np.array_equal(f64[fixed], ref[fixed])
+
+
 def test_relax_parity_warped512(ctx, orc):
     sc = scenarios.scenario("warped512", 0)
     cls, _ = orc.rasterize(sc)
