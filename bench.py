@@ -40,7 +40,7 @@ SINGLE_SWEEP_BYTES = 8.125
 # SIMD x 16 lanes x 2.4 GHz lane-instructions per second (packed FP32 off)
 VALU_PER_UPDATE = 5.0
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
-SLOT_KERNEL_SOURCES = ("solve.hip", "stream_tile.h", "update.h")
+TRAFFIC_SOURCES = ("solve.hip", "sor_stream.hip", "stream_tile.h", "update.h")
 
 
 def log(msg):
@@ -64,7 +64,7 @@ def profiled_traffic(kernel, role, rows):
     path = os.path.join(ROOT, "profiles", "k_relax_slot_replan2048.md")
     try:
         text = open(path).read().splitlines()
-        sha = source_hash(SLOT_KERNEL_SOURCES)
+        sha = source_hash(TRAFFIC_SOURCES)
     except OSError:
         return None
     for ln in text:
