@@ -264,8 +264,12 @@ typedef struct {
  * that check measured.  The sweep budget counts whole passes (max_sweeps is
  * rounded up to a multiple of the sweeps per pass).  The host only keeps
  * enough launches queued (it reads the device's decisions from pinned
- * memory and never waits for a residual).  polish = 2 runs the FP64 sweeps
- * with host-side checks.
+ * memory and never waits for a residual).  With polish = 1 and
+ * HPF_INIT_KEEP the solve opens with the first FP64 defect of the kept
+ * field, which also gives the FP32 stage's initial residual: when that meets
+ * tol the FP32 stage sweeps nothing (the usual call after an FP32 solve),
+ * else the FP32 solve runs and the first defect comes again.  polish = 2
+ * runs the FP64 sweeps with host-side checks.
  *
  *   cls    uint8 class map (device, pitch g.pitch).
  *   psi    in/out FP32 field (device, pitch g.pitch): FIXED cells must hold their

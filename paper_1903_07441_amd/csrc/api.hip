@@ -480,6 +480,7 @@ int relax_device(twg_ctx *ctx, const twg_grid &g, const uint8_t *cls, float *psi
     cfg.polish = p.polish ? 1 : 0;
     cfg.check_passes = p.check_passes;
     cfg.max_rounds = kMaxRounds;
+    cfg.kept = cfg.polish && p.init == HPF_INIT_KEEP ? 1 : 0;
     rc = launch_relax_begin(ctl, cfg, st);
     if (rc) return set_err(ctx, rc, "relaxation begin launch failed");
 

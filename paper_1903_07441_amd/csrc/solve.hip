@@ -111,9 +111,10 @@ __device__ int32_t next_passes(RelaxCtl *c, double r)
     } else {
         // sweeps the measured contraction predicts, at most twice the last
         // chunk (a rate near 1 near the rounding floor must not turn into
-        // one huge chunk); the first prediction of a call aims short
+        // one huge chunk); the prediction after the FP32 solve's initial
+        // check (the first of a call, the rate still a guess) aims short
         const double want = log(c->tol_cur / r) / log(c->rate);
-        const double k = c->checks <= 1 ? 0.8 : 1.05;
+        const double k = c->h.phase == PH_PLAIN && c->solve_checks <= 1 ? 0.8 : 1.05;
         chunk = (int64_t)fmin(ceil(want * k), 1e12) + S;
         chunk = chunk > 8 * S ? chunk : 8 * S;
         if (c->last_chunk > 0) {
@@ -246,9 +247,28 @@ __device__ void on_check(RelaxCtl *c, double r, double rel)
     c->h.next_check = c->h.pass + next_passes(c, r);
 }
 
-// a defect: polish done, or the next correction round
-__device__ void on_defect(RelaxCtl *c, double r64, int32_t slot_now)
+// a defect: polish done, or the next correction round.  The first defect
+// of a kept field's polish (no check has run yet) also stands in for the
+// FP32 stage's initial check: it evaluates the same FP64 expression over
+// the same FREE cells of the same field, so when that residual meets tol the
+// FP32 stage ends as it would at that check, with no sweep; else the FP32
+// solve runs from its own initial check and the first defect comes again.
+__device__ void on_defect(RelaxCtl *c, double r64, double rel, int32_t slot_now)
 {
+    if (c->h.phase == PH_DEFECT32 && c->checks == 0 && r64 == r64 && !(r64 <= c->tol_cur)) {
+        ++c->checks;
+        c->h.phase = PH_PLAIN;
+        c->h.pass = 0;
+        c->h.run_slot = slot_now + 1;
+        c->h.next_check = 0;
+        return;
+    }
+    if (c->h.phase == PH_DEFECT32 && c->checks == 0 && r64 == r64) {
+        c->sweeps = 0;
+        c->residual32 = r64;
+        c->residual_rel = rel;
+        c->status = TWG_OK;
+    }
     ++c->checks;
     c->residual = r64;
     c->h.wide = 1;
@@ -326,7 +346,7 @@ __device__ void controller_on(RelaxCtl *c, const SlotArgs &a, int phase, int was
         break;
     }
     case PH_DEFECT32:
-    case PH_DEFECT64: on_defect(c, r, slot_now); break;
+    case PH_DEFECT64: on_defect(c, r, rel, slot_now); break;
     case PH_UPDATE:
         ++c->rounds;
         c->h.fresh = 1;
@@ -673,7 +693,7 @@ __global__ void k_relax_begin(RelaxCtl *c, RelaxConfig cfg)
     }
     if (threadIdx.x != 0) return;
     c->c = cfg;
-    c->h.phase = PH_PLAIN;
+    c->h.phase = cfg.kept ? PH_DEFECT32 : PH_PLAIN;
     c->h.parity = c->h.cparity = c->h.fresh = c->h.wide = 0;
     c->h.pass = 0;
     c->h.run_slot = 0;

@@ -187,6 +187,9 @@ struct RelaxConfig {
     int32_t polish;      // 1: FP64 defect correction after the FP32 solve
     int32_t check_passes;  // > 0: check every this many passes
     int32_t max_rounds;  // defect-correction rounds at most
+    int32_t kept;        // 1: polish of the caller's kept FP32 field, whose first
+                         // defect also checks the FP32 stage (0 sweeps when it
+                         // meets tol)
 };
 struct SlotArgs {
     const uint8_t *mask;  // free mask (0xFF on FREE cells), the grid's layout

@@ -259,6 +259,33 @@ def test_kept_field_polish_starts_from_its_fp64_defect(ctx, orc):
     assert orc.residual(cls, psi64.cpu().numpy()) * orc.wbound(nx, ny) <= 5e-7
 
 
+def test_kept_unconverged_field_polish_runs_the_fp32_stage(ctx, orc):
+    """A kept field above tol: the polish's first defect finds it unconverged,
+    the FP32 solve runs from its own initial check and the first defect comes
+    again, so the result equals, bit for bit, the same solve started from the
+    same field by HPF_INIT_ZERO (one check more for the first defect)."""
+    from paper_1903_07441_amd import twg
+    sc = scenarios.scenario("warped512", 2)
+    cls, _ = orc.rasterize(sc)
+    ny, nx = cls.shape
+    c = to_dev(cls)
+    out = {}
+    for init in (twg.INIT_KEEP, twg.INIT_ZERO):
+        psi = to_dev(np.where(cls == 3, 1.0, 0.0).astype(np.float32))
+        psi64 = to_dev(np.zeros((ny, nx)), dtype=torch.float64)
+        st = ctx.relax(c, psi, psi64, tol=1e-6, init=init, polish=1, tol_cert=5e-7)
+        torch.cuda.synchronize()
+        print(f"init={init} stats={st}", flush=True)
+        assert st["status"] == twg.OK and st["sweeps"] > 0 and st["residual32"] <= 1e-6
+        out[init] = (st, psi.cpu().numpy(), psi64.cpu().numpy())
+    (sk, pk, qk), (sz, pz, qz) = out[twg.INIT_KEEP], out[twg.INIT_ZERO]
+    assert np.array_equal(pk, pz) and np.array_equal(qk, qz)
+    for key in ("sweeps", "polish_sweeps", "residual", "residual32", "residual_rel", "polish_rounds"):
+        assert sk[key] == sz[key], key
+    assert sk["checks"] == sz["checks"] + 1
+    assert orc.residual(cls, qk) * orc.wbound(nx, ny) <= 5e-7
+
+
 def test_relax_full_size_2048_certified(ctx, orc):
     # 2048 x 2048 time-warped field with a goal reachable from the start: the
     # certificate |psi - psi*| <= r * wbound (maximum principle, any size)
