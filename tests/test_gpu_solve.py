@@ -109,6 +109,29 @@ def test_async_budget_ends_the_solve(ctx, orc, polish):
     assert sb["status"] == twg.NOT_CONVERGED and sb["sweeps"] == 4
 
 
+def test_kept_field_polish_cut_short_by_the_budget(ctx, orc):
+    # a converged FP32 field kept for the polish, with three slots: the first
+    # defect finds the field converged (no FP32 sweep), two correction passes
+    # run, the final launch ends the solve; the kept field is untouched and
+    # the FP64 field is its widened copy (no update ran)
+    from paper_1903_07441_amd import twg
+    sc, cls = _scenario_cls(orc, "warped512", 1)
+    c = to_dev(cls)
+    psi, psi64 = _fields(cls)
+    ctx.relax(c, psi, None, tol=1e-6)
+    torch.cuda.synchronize()
+    kept = psi.cpu().numpy().copy()
+    r32 = ctx.residual(c, psi=psi)
+    stats = ctx.relax_async(c, psi, psi64, slots=3, tol=1e-6, init=twg.INIT_KEEP, polish=1, tol_cert=5e-7)
+    st = twg.stats_from_device(stats)
+    print(f"kept, budget-limited: {st}", flush=True)
+    assert st["status"] == twg.NOT_CONVERGED and st["sweeps"] == 0 and st["polish_rounds"] == 0
+    assert st["residual32"] == r32
+    f = psi.cpu().numpy()
+    assert np.array_equal(f, kept)
+    np.testing.assert_array_equal(psi64.cpu().numpy(), f.astype(np.float64))
+
+
 def test_non_finite_field_is_reported(ctx):
     from paper_1903_07441_amd import twg
     rng = np.random.default_rng(4)
